@@ -175,3 +175,21 @@ def test_streaming_verifier():
     v = oracle.StreamingVerifier(cnt, minVal)
     with pytest.raises(oracle.OracleError):
         v.chunk(np.concatenate([B, B[-1:]]))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_sparse_and_offset_keys(seed):
+    """Keys that avoid the low and high ends of the declared range, with long runs
+    of absent values between them: the step writes of Alg. 3 then start at a value
+    above minVal, and Alg. 7 must skip empty bins and empty tiles."""
+    rng = np.random.default_rng(300 + seed)
+    minVal, R = int(rng.integers(-1000, 1000)), int(rng.integers(50, 3000))
+    present = rng.choice(np.arange(3, R - 3), size=int(rng.integers(1, 8)), replace=False)
+    A = minVal + rng.choice(present, size=int(rng.integers(2, 500)))
+    want = np.sort(A).astype(np.int32)
+    assert np.array_equal(oracle.sort(A, minVal, minVal + R), want)
+    P1 = np.cumsum(oracle.counts(A, minVal, minVal + R))
+    assert np.array_equal(oracle.prefix_max_output(P1, minVal, minVal + R, A.size), want)
+    for T in (1, 4, 33, R):
+        _, cdf, O = oracle.tile_intermediates(A, minVal, minVal + R, T)
+        assert np.array_equal(oracle.output_from_local_cdfs(cdf, O, minVal, minVal + R, T, A.size), want)
