@@ -1,0 +1,165 @@
+/*
+ * rtcdf.h -- C ABI of the Range-Tiled CDF sort (RT-CDF) library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * RT-CDF is the method of "Shared-Memory Range-Tiled CDF Sort for Small-Range
+ * Integer Keys on GPUs" (Sec. 3): an unstable sort of n integer keys known to
+ * lie in [minVal, maxVal).  The value range R = maxVal - minVal is split into
+ * range tiles of width T; each tile's histogram is built in on-chip memory
+ * (Alg. 5), prefix-summed into a local CDF (Alg. 4), offset by the prefix of
+ * tile totals (Alg. 6), and every value is written across its output interval
+ * (Alg. 7, Lemma 3) without reading the input again.
+ *
+ * General conventions (apply to every entry point below):
+ *  - Pointers named d_* and the key arrays are DEVICE pointers on the current
+ *    HIP device; everything else is host memory.  The caller owns all of
+ *    them; the library never frees or retains a caller pointer beyond the
+ *    call.
+ *  - Calls are asynchronous on `stream` (0 = the null stream).  Argument
+ *    errors are detected on the host and returned before any GPU work is
+ *    enqueued.  HIP launch errors return RTCDF_ERROR_HIP and the HIP code is
+ *    available from rtcdf_last_hip_error().  Errors that happen on the GPU
+ *    later surface through the usual HIP synchronisation calls.
+ *  - The range is half-open: maxVal is exclusive (Sec. 2.1).  minVal and
+ *    maxVal are int64 so that maxVal = 2^31 is expressible;
+ *    INT32_MIN <= minVal < maxVal <= 2^31 is required.
+ *  - Keys must lie in [minVal, maxVal) (a precondition, Sec. 2.1).  A key
+ *    outside the range makes the output unspecified (never an out-of-bounds
+ *    access by the library).
+ *  - The output holds the original key values in nondecreasing order.  The
+ *    sort is unstable and carries no payload; since keys are bare integers
+ *    the output is unique.
+ *  - keys_out may equal keys_in (in place): the output stage never reads the
+ *    input.  Partial overlap is rejected.
+ *  - Keys need only 4-byte alignment; the kernels peel unaligned heads/tails.
+ *  - n < 2^32 (counts are 32-bit, Sec. 3.2 workspace analysis).
+ *  - Functions are thread-safe with respect to different devices; concurrent
+ *    calls on one device that use the library's internal workspace are
+ *    serialised internally by a mutex but their GPU work is only ordered if
+ *    they share a stream.  Use rtcdf_sort_ws with separate workspaces for
+ *    concurrent streams.
+ */
+#ifndef RTCDF_H
+#define RTCDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rtcdf_status {
+  RTCDF_SUCCESS = 0,
+  RTCDF_ERROR_INVALID_VALUE = 1,    /* NULL with n > 0, maxVal <= minVal, range outside int32, bad config */
+  RTCDF_ERROR_SIZE_TOO_LARGE = 2,   /* n >= 2^32 */
+  RTCDF_ERROR_RANGE_TOO_LARGE = 3,  /* R > RTCDF_MAX_RANGE */
+  RTCDF_ERROR_OVERLAP = 4,          /* keys_in and keys_out overlap without being equal */
+  RTCDF_ERROR_OUT_OF_MEMORY = 5,    /* device workspace allocation failed */
+  RTCDF_ERROR_HIP = 6,              /* a HIP call failed; see rtcdf_last_hip_error() */
+  RTCDF_ERROR_WORKSPACE_TOO_SMALL = 7,
+  RTCDF_ERROR_NOT_SUPPORTED = 8,    /* device is not gfx950, or feature unavailable */
+  RTCDF_ERROR_NO_MODEL = 9          /* learned mode requested but no model is loaded */
+} rtcdf_status_t;
+
+/* Largest supported range.  The workspace grows with R (about 4R + 4m bytes
+ * for the histogram/local CDFs and tile offsets, Sec. 3.2), and the
+ * histogram stage rescans the input once per LDS pass. */
+#define RTCDF_MAX_RANGE (1u << 28)
+
+/* Kernel configuration (the tuning knobs of the method, Sec. 3.3):
+ *  tile_width        T, the range-tile width of the local CDFs (Sec. 3).  A
+ *                    multiple of 128 in [128, 32768].  The histogram stage
+ *                    keeps as many whole tiles per LDS pass as fit.
+ *  items_per_thread  keys handled per thread per loop iteration in the
+ *                    histogram and output stages: 4, 8 or 16.
+ *  blocks_per_tile   co-resident workgroups per compute unit working on a
+ *                    range tile: 1, 2 or 4.  Each gets 160 KiB / blocks of
+ *                    LDS, so T * 4 * blocks_per_tile <= 160 KiB is required.
+ *  flags             0 (reserved).
+ * A zeroed config (all fields 0) means "let the library choose" (the mode
+ * set by rtcdf_set_config_mode). */
+typedef struct rtcdf_config {
+  uint32_t tile_width;
+  uint32_t items_per_thread;
+  uint32_t blocks_per_tile;
+  uint32_t flags;
+} rtcdf_config_t;
+
+/* ---- Plain sort ------------------------------------------------------ */
+
+/* Sort n int32 keys from [minVal, maxVal) into keys_out (Sec. 3, Alg. 4).
+ * keys_in, keys_out: device arrays of n int32 (may be equal).
+ * Uses a per-device workspace cached by the library (allocated on first use
+ * and grown as needed; hipMalloc may therefore run inside this call).
+ * The configuration comes from the current config mode. */
+rtcdf_status_t rtcdf_sort(const int32_t* keys_in, int32_t* keys_out, size_t n,
+                          int64_t minVal, int64_t maxVal, hipStream_t stream);
+
+/* As rtcdf_sort with an explicit configuration (cfg must be valid, see
+ * rtcdf_config_t; NULL or all-zero = library choice).  Every valid config
+ * gives a byte-identical output. */
+rtcdf_status_t rtcdf_sort_with_config(const int32_t* keys_in, int32_t* keys_out, size_t n,
+                                      int64_t minVal, int64_t maxVal,
+                                      const rtcdf_config_t* cfg, hipStream_t stream);
+
+/* Bytes of device workspace rtcdf_sort_ws needs for this problem and
+ * configuration (cfg NULL = library choice), written to *bytes.  The
+ * requirement depends on n, R, the config and the alignment of keys_out
+ * modulo 16 bytes, which is why keys_out is asked for (it is not read). */
+rtcdf_status_t rtcdf_workspace_bytes(size_t n, int64_t minVal, int64_t maxVal,
+                                     const rtcdf_config_t* cfg, const int32_t* keys_out,
+                                     size_t* bytes);
+
+/* As rtcdf_sort_with_config with a caller-owned workspace: d_ws is a device
+ * buffer of ws_bytes >= rtcdf_workspace_bytes(...) bytes, 256-byte aligned.
+ * Performs no allocation and no host synchronisation, so it may be captured
+ * into a HIP graph.  The workspace contents need no initialisation and are
+ * scratch after the call; the buffer must not be used concurrently by
+ * another call. */
+rtcdf_status_t rtcdf_sort_ws(const int32_t* keys_in, int32_t* keys_out, size_t n,
+                             int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,
+                             void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Test hook for the intermediate arrays of Alg. 4-6 for tile width
+ * cfg->tile_width: d_hist[R] receives the tile histograms (Alg. 5), d_cdf[R]
+ * the local CDFs (in-place inclusive scan per tile), d_offsets[m] the tile
+ * offsets O (Alg. 6), m = ceil(R / T).  All uint32 device arrays; any may
+ * be NULL.  Uses the same kernels as rtcdf_sort_with_config. */
+rtcdf_status_t rtcdf_debug_intermediates(const int32_t* keys_in, size_t n, int64_t minVal,
+                                         int64_t maxVal, const rtcdf_config_t* cfg,
+                                         uint32_t* d_hist, uint32_t* d_cdf,
+                                         uint32_t* d_offsets, hipStream_t stream);
+
+/* ---- Configuration source --------------------------------------------- */
+
+typedef enum rtcdf_config_mode {
+  RTCDF_CONFIG_DEFAULT = 0,   /* static per-R table (selected by the geometric-mean method of Sec. 4.1) */
+  RTCDF_CONFIG_TUNED = 1,     /* nearest entry of a loaded tuning database, else DEFAULT */
+  RTCDF_CONFIG_LEARNED = 2    /* the loaded MLP picker, else TUNED/DEFAULT */
+} rtcdf_config_mode_t;
+
+rtcdf_status_t rtcdf_set_config_mode(int mode);
+int rtcdf_get_config_mode(void);
+
+/* The configuration rtcdf_sort would use for (n, R) under the current mode,
+ * written to *cfg (learned mode needs the keys for its sketch; keys_in may
+ * be NULL in the other modes).  Synchronises `stream` in learned mode. */
+rtcdf_status_t rtcdf_pick_config(const int32_t* keys_in, size_t n, int64_t minVal,
+                                 int64_t maxVal, hipStream_t stream, rtcdf_config_t* cfg);
+
+/* ---- Misc -------------------------------------------------------------- */
+
+const char* rtcdf_status_string(rtcdf_status_t status);
+/* The hipError_t of the last RTCDF_ERROR_HIP on this thread (0 if none). */
+int rtcdf_last_hip_error(void);
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int rtcdf_version(void);
+/* Frees the library's cached per-device workspaces (not needed before exit). */
+rtcdf_status_t rtcdf_release_workspaces(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTCDF_H */

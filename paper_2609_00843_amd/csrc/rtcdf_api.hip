@@ -1,0 +1,398 @@
+// rtcdf_api.hip -- host side of the RT-CDF library: argument checks, planning,
+// workspace management and the C ABI declared in include/rtcdf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "../../include/rtcdf.h"
+#include "rtcdf_internal.h"
+
+namespace rtcdf {
+
+thread_local int g_last_hip_error = 0;
+
+static rtcdf_status_t hip_fail(hipError_t e) {
+  g_last_hip_error = (int)e;
+  return RTCDF_ERROR_HIP;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------------ devices
+
+static std::mutex g_dev_mu;
+static std::map<int, DeviceInfo> g_devs;
+
+rtcdf_status_t device_info(DeviceInfo* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_devs.find(dev);
+  if (it == g_devs.end()) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e);
+    DeviceInfo d;
+    d.device = dev;
+    d.cus = prop.multiProcessorCount;
+    d.gfx950 = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    it = g_devs.emplace(dev, d).first;
+  }
+  *out = it->second;
+  if (!out->gfx950) return RTCDF_ERROR_NOT_SUPPORTED;
+  return RTCDF_SUCCESS;
+}
+
+// --------------------------------------------------------------- validation
+
+rtcdf_status_t check_problem(const int32_t* keys_in, const int32_t* keys_out, size_t n,
+                             int64_t minVal, int64_t maxVal) {
+  if (maxVal <= minVal) return RTCDF_ERROR_INVALID_VALUE;
+  if (minVal < (int64_t)INT32_MIN || maxVal > (int64_t)INT32_MAX + 1) return RTCDF_ERROR_INVALID_VALUE;
+  if ((uint64_t)(maxVal - minVal) > (uint64_t)RTCDF_MAX_RANGE) return RTCDF_ERROR_RANGE_TOO_LARGE;
+  if ((uint64_t)n > 0xffffffffull) return RTCDF_ERROR_SIZE_TOO_LARGE;
+  if (n == 0) return RTCDF_SUCCESS;
+  if (keys_in == nullptr || keys_out == nullptr) return RTCDF_ERROR_INVALID_VALUE;
+  if ((reinterpret_cast<uintptr_t>(keys_in) & 3u) || (reinterpret_cast<uintptr_t>(keys_out) & 3u))
+    return RTCDF_ERROR_INVALID_VALUE;
+  if (keys_in != keys_out) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(keys_in), b = reinterpret_cast<uintptr_t>(keys_out);
+    const uintptr_t bytes = (uintptr_t)n * 4;
+    if (a < b + bytes && b < a + bytes) return RTCDF_ERROR_OVERLAP;
+  }
+  return RTCDF_SUCCESS;
+}
+
+bool config_valid(const rtcdf_config_t& c) {
+  if (c.tile_width < 128 || c.tile_width > 32768 || (c.tile_width % 128) != 0) return false;
+  if (c.items_per_thread != 4 && c.items_per_thread != 8 && c.items_per_thread != 16) return false;
+  if (c.blocks_per_tile != 1 && c.blocks_per_tile != 2 && c.blocks_per_tile != 4) return false;
+  if ((uint64_t)c.tile_width * 4 * c.blocks_per_tile > kLdsBytes) return false;
+  if (c.flags != 0) return false;
+  return true;
+}
+
+static bool config_is_zero(const rtcdf_config_t* c) {
+  return c == nullptr ||
+         (c->tile_width == 0 && c->items_per_thread == 0 && c->blocks_per_tile == 0 && c->flags == 0);
+}
+
+// ----------------------------------------------------------------- planning
+
+// Derives every launch parameter and the workspace layout.  `out` is only
+// inspected for its alignment.
+void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& cfg,
+               const int32_t* in, const int32_t* out, const DeviceInfo& dev, Plan* p) {
+  std::memset(p, 0, sizeof(*p));
+  const uint32_t R = (uint32_t)(maxVal - minVal);
+  p->n = n;
+  p->min_u = (uint32_t)(int32_t)minVal;
+  p->R = R;
+  p->items = cfg.items_per_thread;
+  p->bpt = cfg.blocks_per_tile;
+  // Tile geometry (Sec. 3): tiles never need to be wider than the range.
+  const uint32_t Rr = (R + 127) & ~127u;
+  p->T = std::min<uint32_t>(cfg.tile_width, Rr);
+  p->m = (R + p->T - 1) / p->T;
+
+  // Histogram passes: as many whole tiles per workgroup LDS as fit, with 32-bit
+  // counters, or with two 16-bit counters per word when that needs fewer passes.
+  const uint32_t lds = kLdsBytes / p->bpt;
+  const uint32_t k32 = std::max<uint32_t>(1, lds / (4 * p->T));
+  const uint32_t k16 = std::max<uint32_t>(1, lds / (2 * p->T));
+  const uint32_t passes32 = (p->m + k32 - 1) / k32;
+  const uint32_t passes16 = (p->m + k16 - 1) / k16;
+  p->packed16 = passes16 < passes32;
+  const uint32_t k = p->packed16 ? k16 : k32;
+  p->passes = p->packed16 ? passes16 : passes32;
+  p->W = p->passes == 1 ? std::min<uint32_t>(Rr, k * p->T) : k * p->T;
+  p->row_words = p->packed16 ? p->W / 2 : p->W;
+  p->hist_block = 1024 / p->bpt;
+
+  // Input body: 16-byte aligned int4 vectors between a scalar head and tail.
+  const uintptr_t ia = reinterpret_cast<uintptr_t>(in);
+  uint64_t head = ((16 - (ia & 15)) & 15) / 4;
+  if (head > n) head = n;
+  p->in_head = (uint32_t)head;
+  p->in_n4 = (n - head) / 4;
+  // One wave of resident workgroups over all passes; chunks per pass a multiple
+  // of 8 so the XCD-aware mapping is a bijection.
+  const uint32_t V = p->items / 4;
+  uint32_t G = (uint32_t)dev.cus * p->bpt / p->passes / 8 * 8;
+  const uint64_t iters = (p->in_n4 + (uint64_t)p->hist_block * V - 1) / ((uint64_t)p->hist_block * V);
+  const uint64_t gcap = std::max<uint64_t>(8, (iters + 7) / 8 * 8);
+  G = (uint32_t)std::min<uint64_t>(std::max<uint32_t>(G, 8), gcap);
+  p->G = G;
+  p->in_per = (p->in_n4 + G - 1) / G;
+
+  p->nred = (R + kReduceBins - 1) / kReduceBins;
+
+  // Output chunks: s(0) = 0, s(k) = out_head + k * chunk.
+  const uintptr_t oa = reinterpret_cast<uintptr_t>(out);
+  p->out_head = (uint32_t)(((16 - (oa & 15)) & 15) / 4);
+  const uint32_t gran = 4 * kFillBlock * (p->items / 4);
+  uint64_t want = (n + (uint64_t)dev.cus * 8 - 1) / ((uint64_t)dev.cus * 8);
+  want = std::max<uint64_t>(want, gran);
+  want = std::min<uint64_t>(want, 65536);
+  p->chunk = (uint32_t)((want + gran - 1) / gran * gran);
+  p->nchunks = 1 + ((n >= 1 && n - 1 >= p->out_head) ? (uint32_t)((n - 1 - p->out_head) / p->chunk) : 0);
+  p->fill_grid = std::min<uint32_t>(p->nchunks, (uint32_t)dev.cus * 8);
+
+  // Workspace layout.
+  size_t off = 0;
+  p->off_partial = off;
+  off = align256(off + (size_t)p->passes * p->G * p->row_words * 4);
+  p->off_hist = off;
+  off = align256(off + (size_t)R * 4);
+  p->off_rsum = off;
+  off = align256(off + (size_t)p->nred * 4);
+  p->off_O = off;
+  off = align256(off + (size_t)p->m * 4);
+  p->off_split = off;
+  off = align256(off + ((size_t)p->nchunks + 1) * 4);
+  // Carry entries cover every bin of every pass (plus the partner of the last
+  // bin), so even keys outside the declared range stay in bounds.
+  p->carry_words = p->packed16 ? (size_t)p->passes * p->W + 2 : 0;
+  p->off_carry = off;                       // used by the caller-workspace form only
+  off = align256(off + p->carry_words * 4);
+  p->ws_bytes = off;
+}
+
+// ------------------------------------------------------------ workspaces
+
+// The library's own workspace for rtcdf_sort: one per (device, stream), so
+// sorts on different streams never share scratch memory.  The carry array of
+// the 16-bit counters lives in its own buffer that is zero between sorts
+// (zeroed when allocated, re-zeroed by the reduction after every use).
+struct Workspace {
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t* carry = nullptr;
+  size_t carry_words = 0;
+};
+
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+static rtcdf_status_t grow(Workspace& w, const Plan& p) {
+  if (w.ws_bytes < p.ws_bytes) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e);
+    if (w.ws) (void)hipFree(w.ws);
+    w.ws = nullptr;
+    w.ws_bytes = 0;
+    const size_t bytes = std::max<size_t>(p.ws_bytes, (size_t)1 << 20);
+    e = hipMalloc(&w.ws, bytes);
+    if (e != hipSuccess) {
+      w.ws = nullptr;
+      (void)hipGetLastError();
+      return RTCDF_ERROR_OUT_OF_MEMORY;
+    }
+    w.ws_bytes = bytes;
+  }
+  if (w.carry_words < p.carry_words) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e);
+    if (w.carry) (void)hipFree(w.carry);
+    w.carry = nullptr;
+    w.carry_words = 0;
+    const size_t words = std::max<size_t>(p.carry_words, 1 << 16);
+    e = hipMalloc(&w.carry, words * 4);
+    if (e != hipSuccess) {
+      w.carry = nullptr;
+      (void)hipGetLastError();
+      return RTCDF_ERROR_OUT_OF_MEMORY;
+    }
+    e = hipMemset(w.carry, 0, words * 4);
+    if (e != hipSuccess) return hip_fail(e);
+    w.carry_words = words;
+  }
+  return RTCDF_SUCCESS;
+}
+
+// Enqueue the four stages.  `carry` points at a zeroed array of p.carry_words.
+static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, uint8_t* ws,
+                              uint32_t* carry, hipStream_t s, uint32_t* dbg_hist = nullptr,
+                              uint32_t* dbg_cdf = nullptr, uint32_t* dbg_O = nullptr) {
+  const Plan& q = p;
+  hipError_t e = launch_hist(q, in, ws, carry, s);
+  if (e != hipSuccess) return hip_fail(e);
+  e = launch_reduce(q, ws, carry, s);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dbg_hist) {
+    e = hipMemcpyAsync(dbg_hist, ws + q.off_hist, (size_t)q.R * 4, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  e = launch_tilescan(q, ws, s);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dbg_cdf) {
+    e = hipMemcpyAsync(dbg_cdf, ws + q.off_hist, (size_t)q.R * 4, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (dbg_O) {
+    e = hipMemcpyAsync(dbg_O, ws + q.off_O, (size_t)q.m * 4, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (out) {
+    e = launch_fill(q, out, ws, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return RTCDF_SUCCESS;
+}
+
+rtcdf_status_t resolve_config(const rtcdf_config_t* cfg, const int32_t* keys_in, size_t n,
+                              int64_t minVal, int64_t maxVal, hipStream_t stream,
+                              rtcdf_config_t* out) {
+  if (!config_is_zero(cfg)) {
+    if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
+    *out = *cfg;
+    return RTCDF_SUCCESS;
+  }
+  return pick_config(keys_in, n, minVal, maxVal, stream, out);
+}
+
+static rtcdf_status_t sort_cached(const int32_t* in, int32_t* out, size_t n, int64_t minVal,
+                                  int64_t maxVal, const rtcdf_config_t* cfg, hipStream_t s,
+                                  uint32_t* dbg_hist, uint32_t* dbg_cdf, uint32_t* dbg_O) {
+  DeviceInfo dev;
+  rtcdf_status_t st = device_info(&dev);
+  if (st != RTCDF_SUCCESS) return st;
+  rtcdf_config_t c;
+  st = resolve_config(cfg, in, n, minVal, maxVal, s, &c);
+  if (st != RTCDF_SUCCESS) return st;
+  Plan p;
+  make_plan(n, minVal, maxVal, c, in, out ? out : in, dev, &p);
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  Workspace& w = g_ws[std::make_pair(dev.device, s)];
+  st = grow(w, p);
+  if (st != RTCDF_SUCCESS) return st;
+  return enqueue(p, in, out, static_cast<uint8_t*>(w.ws), w.carry, s, dbg_hist, dbg_cdf, dbg_O);
+}
+
+}  // namespace rtcdf
+
+using namespace rtcdf;
+
+extern "C" {
+
+rtcdf_status_t rtcdf_sort(const int32_t* keys_in, int32_t* keys_out, size_t n, int64_t minVal,
+                          int64_t maxVal, hipStream_t stream) {
+  return rtcdf_sort_with_config(keys_in, keys_out, n, minVal, maxVal, nullptr, stream);
+}
+
+rtcdf_status_t rtcdf_sort_with_config(const int32_t* keys_in, int32_t* keys_out, size_t n,
+                                      int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,
+                                      hipStream_t stream) {
+  rtcdf_status_t st = check_problem(keys_in, keys_out, n, minVal, maxVal);
+  if (st != RTCDF_SUCCESS || n == 0) return st;
+  if (!config_is_zero(cfg) && !config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
+  return sort_cached(keys_in, keys_out, n, minVal, maxVal, cfg, stream, nullptr, nullptr, nullptr);
+}
+
+rtcdf_status_t rtcdf_workspace_bytes(size_t n, int64_t minVal, int64_t maxVal,
+                                     const rtcdf_config_t* cfg, const int32_t* keys_out,
+                                     size_t* bytes) {
+  if (bytes == nullptr) return RTCDF_ERROR_INVALID_VALUE;
+  const int32_t* probe = keys_out ? keys_out : reinterpret_cast<const int32_t*>((uintptr_t)256);
+  rtcdf_status_t st = check_problem(probe, probe, n, minVal, maxVal);
+  if (st != RTCDF_SUCCESS) return st;
+  if (n == 0) {
+    *bytes = 0;
+    return RTCDF_SUCCESS;
+  }
+  DeviceInfo dev;
+  st = device_info(&dev);
+  if (st != RTCDF_SUCCESS) return st;
+  rtcdf_config_t c;
+  if (!config_is_zero(cfg)) {
+    if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
+    c = *cfg;
+  } else {
+    st = pick_config(nullptr, n, minVal, maxVal, nullptr, &c);
+    if (st != RTCDF_SUCCESS) return st;
+  }
+  Plan p;
+  // The input alignment changes only head/tail handling, not the layout.
+  make_plan(n, minVal, maxVal, c, probe, probe, dev, &p);
+  *bytes = p.ws_bytes;
+  return RTCDF_SUCCESS;
+}
+
+rtcdf_status_t rtcdf_sort_ws(const int32_t* keys_in, int32_t* keys_out, size_t n, int64_t minVal,
+                             int64_t maxVal, const rtcdf_config_t* cfg, void* d_ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  rtcdf_status_t st = check_problem(keys_in, keys_out, n, minVal, maxVal);
+  if (st != RTCDF_SUCCESS || n == 0) return st;
+  if (d_ws == nullptr || (reinterpret_cast<uintptr_t>(d_ws) & 255u)) return RTCDF_ERROR_INVALID_VALUE;
+  DeviceInfo dev;
+  st = device_info(&dev);
+  if (st != RTCDF_SUCCESS) return st;
+  rtcdf_config_t c;
+  if (!config_is_zero(cfg)) {
+    if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
+    c = *cfg;
+  } else {
+    st = pick_config(nullptr, n, minVal, maxVal, nullptr, &c);
+    if (st != RTCDF_SUCCESS) return st;
+  }
+  Plan p;
+  make_plan(n, minVal, maxVal, c, keys_in, keys_out, dev, &p);
+  if (ws_bytes < p.ws_bytes) return RTCDF_ERROR_WORKSPACE_TOO_SMALL;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  uint32_t* carry = reinterpret_cast<uint32_t*>(ws + p.off_carry);
+  if (p.carry_words) {
+    hipError_t e = launch_clear(carry, p.carry_words, stream);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return enqueue(p, keys_in, keys_out, ws, carry, stream);
+}
+
+rtcdf_status_t rtcdf_debug_intermediates(const int32_t* keys_in, size_t n, int64_t minVal,
+                                         int64_t maxVal, const rtcdf_config_t* cfg,
+                                         uint32_t* d_hist, uint32_t* d_cdf, uint32_t* d_offsets,
+                                         hipStream_t stream) {
+  rtcdf_status_t st = check_problem(keys_in, keys_in, n, minVal, maxVal);
+  if (st != RTCDF_SUCCESS) return st;
+  if (n == 0) return RTCDF_ERROR_INVALID_VALUE;
+  if (config_is_zero(cfg) || !config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
+  return sort_cached(keys_in, nullptr, n, minVal, maxVal, cfg, stream, d_hist, d_cdf, d_offsets);
+}
+
+const char* rtcdf_status_string(rtcdf_status_t s) {
+  switch (s) {
+    case RTCDF_SUCCESS: return "success";
+    case RTCDF_ERROR_INVALID_VALUE: return "invalid value";
+    case RTCDF_ERROR_SIZE_TOO_LARGE: return "n too large (n must be < 2^32)";
+    case RTCDF_ERROR_RANGE_TOO_LARGE: return "range too large";
+    case RTCDF_ERROR_OVERLAP: return "input and output overlap partially";
+    case RTCDF_ERROR_OUT_OF_MEMORY: return "out of device memory";
+    case RTCDF_ERROR_HIP: return "HIP error";
+    case RTCDF_ERROR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case RTCDF_ERROR_NOT_SUPPORTED: return "not supported on this device";
+    case RTCDF_ERROR_NO_MODEL: return "no model loaded";
+  }
+  return "unknown status";
+}
+
+int rtcdf_last_hip_error(void) { return g_last_hip_error; }
+
+int rtcdf_version(void) { return 100; }
+
+rtcdf_status_t rtcdf_release_workspaces(void) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  hipError_t e = hipDeviceSynchronize();
+  for (auto& kv : g_ws) {
+    if (kv.second.ws) (void)hipFree(kv.second.ws);
+    if (kv.second.carry) (void)hipFree(kv.second.carry);
+  }
+  g_ws.clear();
+  return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
+}
+
+}  // extern "C"

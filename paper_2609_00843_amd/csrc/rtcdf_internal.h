@@ -1,0 +1,80 @@
+// rtcdf_internal.h -- internal plan and kernel launchers of the RT-CDF library.
+// Not part of the public ABI (include/rtcdf.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rtcdf.h"
+
+namespace rtcdf {
+
+constexpr uint32_t kLdsBytes = 163840;      // LDS per workgroup/CU on gfx950
+constexpr uint32_t kReduceBins = 128;       // bins per workgroup of the partial-row reduction
+constexpr uint32_t kFillWindow = 4096;      // cumulative counts held in LDS by one output chunk
+constexpr uint32_t kFillBlock = 256;        // threads per output workgroup
+constexpr uint32_t kScanBlock = 1024;       // threads per local-CDF workgroup
+constexpr uint32_t kReduceBlock = 1024;     // threads per reduction workgroup
+
+// Everything one plain sort needs, derived on the host from (n, range, config,
+// pointer alignment, device).  Workspace offsets are in bytes from the base.
+struct Plan {
+  // problem
+  uint64_t n;
+  uint32_t min_u;        // (uint32)minVal; normalised value x = (uint32)key - min_u
+  uint32_t R;            // range size
+  // tile geometry (Sec. 3): m = ceil(R/T), tile t = [tT, tT + w_t)
+  uint32_t T, m;
+  // config knobs
+  uint32_t items, bpt;
+  // histogram passes
+  bool packed16;         // two 16-bit counters per LDS word
+  uint32_t W;            // bins per LDS pass (multiple of 128, or R rounded up when one pass)
+  uint32_t passes;       // ceil(R / W)
+  uint32_t G;            // workgroups (input chunks) per pass, multiple of 8
+  uint32_t row_words;    // 32-bit words per partial row (W or W/2)
+  uint32_t hist_block;   // threads per histogram workgroup
+  uint32_t in_head;      // keys before the 16-byte aligned input body
+  uint64_t in_n4;        // int4 vectors in the input body
+  uint64_t in_per;       // int4 vectors per input chunk
+  // reduction
+  uint32_t nred;         // ceil(R / kReduceBins)
+  // output
+  uint32_t out_head;     // output positions before the 16-byte aligned body
+  uint32_t chunk;        // output positions per chunk (multiple of 4 * kFillBlock)
+  uint32_t nchunks;
+  uint32_t fill_grid;
+  // workspace layout
+  size_t off_partial, off_hist, off_rsum, off_O, off_split, ws_bytes;
+  size_t off_carry;      // carry array inside a caller-owned workspace (rtcdf_sort_ws)
+  size_t carry_words;    // 0 unless packed16
+};
+
+struct DeviceInfo {
+  int device = -1;
+  int cus = 0;
+  bool gfx950 = false;
+};
+
+// Kernel launchers (rtcdf_kernels.hip).  All enqueue on `stream` and return the
+// hipError_t of the launch.
+hipError_t launch_clear(uint32_t* p, size_t words, hipStream_t stream);
+hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t* carry,
+                       hipStream_t stream);
+hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_t stream);
+hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t stream);
+hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream_t stream);
+
+// Host helpers shared by the C ABI translation units (rtcdf_api.hip).
+rtcdf_status_t device_info(DeviceInfo* out);
+bool config_valid(const rtcdf_config_t& c);
+void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& cfg,
+               const int32_t* in, const int32_t* out, const DeviceInfo& dev, Plan* p);
+
+// Configuration source (rtcdf_config.hip): the choice rtcdf_sort makes when the
+// caller gives no config, under the current config mode.
+rtcdf_status_t pick_config(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,
+                           hipStream_t stream, rtcdf_config_t* out);
+
+}  // namespace rtcdf

@@ -1,0 +1,217 @@
+"""Thin Python binding of librtcdf.so (the C ABI in include/rtcdf.h).
+
+Argument marshalling only: every step of the sort runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  The library
+is loaded when this module is imported; if it has not been built the import
+fails (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtcdf.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2609_00843_amd.build`")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+STATUS = {
+    0: "RTCDF_SUCCESS",
+    1: "RTCDF_ERROR_INVALID_VALUE",
+    2: "RTCDF_ERROR_SIZE_TOO_LARGE",
+    3: "RTCDF_ERROR_RANGE_TOO_LARGE",
+    4: "RTCDF_ERROR_OVERLAP",
+    5: "RTCDF_ERROR_OUT_OF_MEMORY",
+    6: "RTCDF_ERROR_HIP",
+    7: "RTCDF_ERROR_WORKSPACE_TOO_SMALL",
+    8: "RTCDF_ERROR_NOT_SUPPORTED",
+    9: "RTCDF_ERROR_NO_MODEL",
+}
+SUCCESS, INVALID_VALUE, SIZE_TOO_LARGE, RANGE_TOO_LARGE, OVERLAP = 0, 1, 2, 3, 4
+OUT_OF_MEMORY, HIP_ERROR, WORKSPACE_TOO_SMALL, NOT_SUPPORTED, NO_MODEL = 5, 6, 7, 8, 9
+MAX_RANGE = 1 << 28
+BATCH_MAX_RANGE = 1 << 16
+CONFIG_DEFAULT, CONFIG_TUNED, CONFIG_LEARNED = 0, 1, 2
+
+
+class RtcdfError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        name = STATUS.get(status, str(status))
+        extra = ""
+        if status == HIP_ERROR:
+            extra = f" (hipError {lib.rtcdf_last_hip_error()})"
+        super().__init__(f"{what}: {name}{extra}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    """rtcdf_config_t: tile width T, items per thread, blocks per tile, flags."""
+    _fields_ = [("tile_width", ctypes.c_uint32), ("items_per_thread", ctypes.c_uint32),
+                ("blocks_per_tile", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+    def as_tuple(self):
+        return (self.tile_width, self.items_per_thread, self.blocks_per_tile)
+
+    def __repr__(self):
+        return f"Config(T={self.tile_width}, items={self.items_per_thread}, bpt={self.blocks_per_tile})"
+
+
+class Segment(ctypes.Structure):
+    """rtcdf_segment_t (32 bytes, lives in device memory for the batched call)."""
+    _fields_ = [("keys_in", ctypes.c_uint64), ("keys_out", ctypes.c_uint64),
+                ("n", ctypes.c_uint32), ("minVal", ctypes.c_int32),
+                ("range", ctypes.c_uint32), ("config", ctypes.c_uint32)]
+
+
+class BatchBounds(ctypes.Structure):
+    _fields_ = [("total_keys", ctypes.c_uint64), ("max_n", ctypes.c_uint32),
+                ("max_range", ctypes.c_uint32)]
+
+
+_vp, _sz, _i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64
+_cfgp = ctypes.POINTER(Config)
+_u32p = ctypes.c_void_p
+
+_SIGS = {
+    "rtcdf_sort": [_vp, _vp, _sz, _i64, _i64, _vp],
+    "rtcdf_sort_with_config": [_vp, _vp, _sz, _i64, _i64, _cfgp, _vp],
+    "rtcdf_workspace_bytes": [_sz, _i64, _i64, _cfgp, _vp, ctypes.POINTER(ctypes.c_size_t)],
+    "rtcdf_sort_ws": [_vp, _vp, _sz, _i64, _i64, _cfgp, _vp, _sz, _vp],
+    "rtcdf_debug_intermediates": [_vp, _sz, _i64, _i64, _cfgp, _u32p, _u32p, _u32p, _vp],
+    "rtcdf_batched_workspace_bytes": [ctypes.c_uint32, ctypes.POINTER(BatchBounds),
+                                      ctypes.POINTER(ctypes.c_size_t)],
+    "rtcdf_sort_batched": [_vp, ctypes.c_uint32, ctypes.POINTER(BatchBounds), _vp, _sz, _vp],
+    "rtcdf_set_config_mode": [ctypes.c_int],
+    "rtcdf_get_config_mode": [],
+    "rtcdf_pick_config": [_vp, _sz, _i64, _i64, _vp, _cfgp],
+    "rtcdf_status_string": [ctypes.c_int],
+    "rtcdf_last_hip_error": [],
+    "rtcdf_version": [],
+    "rtcdf_release_workspaces": [],
+}
+for _name, _args in _SIGS.items():
+    if hasattr(lib, _name):
+        _f = getattr(lib, _name)
+        _f.argtypes = _args
+        _f.restype = ctypes.c_int
+lib.rtcdf_status_string.restype = ctypes.c_char_p
+
+
+def _check(st: int, what: str):
+    if st != SUCCESS:
+        raise RtcdfError(st, what)
+
+
+def make_config(tile_width: int, items_per_thread: int = 16, blocks_per_tile: int = 1) -> Config:
+    return Config(int(tile_width), int(items_per_thread), int(blocks_per_tile), 0)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _check_keys(t, what):
+    import torch
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous int32 CUDA tensor")
+
+
+def sort(keys_in, minVal: int, maxVal: int, keys_out=None, config: Config | None = None,
+         stream=None):
+    """Sort keys_in (int32 in [minVal, maxVal)) into keys_out (allocated if None).
+    Asynchronous on `stream` (default: torch's current stream)."""
+    import torch
+    _check_keys(keys_in, "keys_in")
+    if keys_out is None:
+        keys_out = torch.empty_like(keys_in)
+    _check_keys(keys_out, "keys_out")
+    if keys_out.numel() != keys_in.numel():
+        raise ValueError("keys_out must have as many elements as keys_in")
+    s = _stream_ptr(stream)
+    if config is None:
+        st = lib.rtcdf_sort(_ptr(keys_in), _ptr(keys_out), keys_in.numel(), int(minVal),
+                            int(maxVal), s)
+    else:
+        st = lib.rtcdf_sort_with_config(_ptr(keys_in), _ptr(keys_out), keys_in.numel(),
+                                        int(minVal), int(maxVal), ctypes.byref(config), s)
+    _check(st, "rtcdf_sort")
+    return keys_out
+
+
+def workspace_bytes(n: int, minVal: int, maxVal: int, config: Config | None = None,
+                    keys_out=None) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib.rtcdf_workspace_bytes(int(n), int(minVal), int(maxVal),
+                                   ctypes.byref(config) if config is not None else None,
+                                   _ptr(keys_out) if keys_out is not None else None,
+                                   ctypes.byref(out))
+    _check(st, "rtcdf_workspace_bytes")
+    return int(out.value)
+
+
+def sort_ws(keys_in, keys_out, minVal: int, maxVal: int, workspace, config: Config | None = None,
+            stream=None):
+    """Sort with a caller-owned device workspace (a uint8 CUDA tensor)."""
+    _check_keys(keys_in, "keys_in")
+    _check_keys(keys_out, "keys_out")
+    st = lib.rtcdf_sort_ws(_ptr(keys_in), _ptr(keys_out), keys_in.numel(), int(minVal),
+                           int(maxVal), ctypes.byref(config) if config is not None else None,
+                           _ptr(workspace), workspace.numel() * workspace.element_size(),
+                           _stream_ptr(stream))
+    _check(st, "rtcdf_sort_ws")
+    return keys_out
+
+
+def debug_intermediates(keys_in, minVal: int, maxVal: int, config: Config, stream=None):
+    """(tile histograms, local CDFs, tile offsets) as int32 CUDA tensors holding
+    uint32 values (Alg. 5, Alg. 4, Alg. 6)."""
+    import torch
+    _check_keys(keys_in, "keys_in")
+    R = int(maxVal) - int(minVal)
+    T = min(config.tile_width, (R + 127) // 128 * 128)
+    m = -(-R // T)
+    dev = keys_in.device
+    hist = torch.empty(R, dtype=torch.int32, device=dev)
+    cdf = torch.empty(R, dtype=torch.int32, device=dev)
+    O = torch.empty(m, dtype=torch.int32, device=dev)
+    st = lib.rtcdf_debug_intermediates(_ptr(keys_in), keys_in.numel(), int(minVal), int(maxVal),
+                                       ctypes.byref(config), _ptr(hist), _ptr(cdf), _ptr(O),
+                                       _stream_ptr(stream))
+    _check(st, "rtcdf_debug_intermediates")
+    return hist, cdf, O
+
+
+def set_config_mode(mode: int):
+    _check(lib.rtcdf_set_config_mode(int(mode)), "rtcdf_set_config_mode")
+
+
+def get_config_mode() -> int:
+    return int(lib.rtcdf_get_config_mode())
+
+
+def pick_config(n: int, minVal: int, maxVal: int, keys_in=None, stream=None) -> Config:
+    cfg = Config()
+    st = lib.rtcdf_pick_config(_ptr(keys_in) if keys_in is not None else None, int(n), int(minVal),
+                               int(maxVal), _stream_ptr(stream) if keys_in is not None else None,
+                               ctypes.byref(cfg))
+    _check(st, "rtcdf_pick_config")
+    return cfg
+
+
+def status_string(status: int) -> str:
+    return lib.rtcdf_status_string(int(status)).decode()
+
+
+def release_workspaces():
+    _check(lib.rtcdf_release_workspaces(), "rtcdf_release_workspaces")

@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point include/rtcdf.h declares, and rejects bad arguments before any GPU
+work.  The calls made here never reach a HIP API."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "rtcdf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtcdf_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def r():
+    from paper_2609_00843_amd import rtcdf
+    return rtcdf
+
+
+def test_every_declared_symbol_is_exported(r):
+    names = _declared()
+    assert "rtcdf_sort" in names and "rtcdf_sort_ws" in names
+    missing = [n for n in names if not hasattr(r.lib, n)]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def test_version_and_strings(r):
+    assert r.lib.rtcdf_version() >= 100
+    for code, name in r.STATUS.items():
+        assert r.status_string(code) and r.status_string(code) != "unknown status"
+    assert r.status_string(99) == "unknown status"
+
+
+P_IN, P_OUT = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)   # never dereferenced
+
+
+def test_argument_errors_before_gpu(r):
+    L = r.lib
+    sort = L.rtcdf_sort
+    assert sort(P_IN, P_OUT, 0, 0, 10, None) == r.SUCCESS                 # n = 0 is a no-op
+    assert sort(P_IN, P_OUT, 10, 5, 5, None) == r.INVALID_VALUE           # empty range
+    assert sort(P_IN, P_OUT, 10, 6, 5, None) == r.INVALID_VALUE
+    assert sort(P_IN, P_OUT, 10, -(2 ** 31) - 1, 0, None) == r.INVALID_VALUE
+    assert sort(P_IN, P_OUT, 10, 0, 2 ** 31 + 1, None) == r.INVALID_VALUE
+    assert sort(P_IN, P_OUT, 10, 0, (1 << 28) + 1, None) == r.RANGE_TOO_LARGE
+    assert sort(P_IN, P_OUT, 1 << 32, 0, 10, None) == r.SIZE_TOO_LARGE
+    assert sort(None, P_OUT, 10, 0, 10, None) == r.INVALID_VALUE
+    assert sort(P_IN, None, 10, 0, 10, None) == r.INVALID_VALUE
+    assert sort(ctypes.c_void_p((1 << 20) + 2), P_OUT, 10, 0, 10, None) == r.INVALID_VALUE  # not 4-byte aligned
+    # partial overlap is rejected, exact aliasing is not an argument error
+    assert sort(P_IN, ctypes.c_void_p((1 << 20) + 8), 10, 0, 10, None) == r.OVERLAP
+    assert sort(P_IN, ctypes.c_void_p((1 << 20) - 8), 10, 0, 10, None) == r.OVERLAP
+
+
+@pytest.mark.parametrize("cfg", [(100, 16, 1), (0, 16, 1), (1024, 5, 1), (1024, 16, 3),
+                                 (32768, 16, 2), (16384, 16, 4), (32896, 16, 1), (1024, 0, 1)])
+def test_invalid_configs(r, cfg):
+    c = r.make_config(*cfg)
+    assert r.lib.rtcdf_sort_with_config(P_IN, P_OUT, 10, 0, 10, ctypes.byref(c), None) == r.INVALID_VALUE
+
+
+def test_config_mode_api(r):
+    assert r.lib.rtcdf_set_config_mode(7) == r.INVALID_VALUE
+    old = r.get_config_mode()
+    r.set_config_mode(r.CONFIG_DEFAULT)
+    assert r.get_config_mode() == r.CONFIG_DEFAULT
+    r.set_config_mode(old)
+
+
+def test_load_fails_loudly_without_library(tmp_path):
+    """The binding has no fallback: without the built library the import fails."""
+    import subprocess
+    import sys
+    code = ("import sys, os; sys.path.insert(0, %r); import paper_2609_00843_amd.rtcdf as m" % str(tmp_path))
+    pkg = tmp_path / "paper_2609_00843_amd"
+    pkg.mkdir()
+    (pkg / "__init__.py").write_text("")
+    (pkg / "rtcdf.py").write_text(open(os.path.join(ROOT, "paper_2609_00843_amd", "rtcdf.py")).read())
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert res.returncode != 0 and "not built" in res.stderr

@@ -1,0 +1,229 @@
+"""GPU parity of the plain RT-CDF sort against the CPU oracle.
+
+Every comparison is element by element (the output of an unstable sort of bare
+integers is unique).  Inputs are seeded; each test prints its case before the
+GPU work so a failing run names it.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_00843_amd import inputs
+from tests.golden.load import load
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def r():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_00843_amd import rtcdf
+    return rtcdf
+
+
+def _to_dev(A, pad_front=0):
+    """Device int32 copy of A starting `pad_front` elements into its buffer
+    (pad_front in 0..3 makes the array 4/8/12 bytes off 16-byte alignment)."""
+    buf = torch.empty(A.size + pad_front + 4, dtype=torch.int32, device="cuda")
+    buf.fill_(-12345)
+    t = buf[pad_front:pad_front + A.size]
+    t.copy_(torch.from_numpy(np.ascontiguousarray(A, dtype=np.int32)))
+    return buf, t
+
+
+def _run(r, A, minVal, maxVal, cfg=None, pin=0, pout=0, inplace=False):
+    _say(f"n={A.size} min={minVal} max={maxVal} cfg={cfg} pin={pin} pout={pout} inplace={inplace}")
+    want = oracle.sort(A, minVal, maxVal)
+    bin_, tin = _to_dev(A, pin)
+    if inplace:
+        bout, tout = bin_, tin
+    else:
+        bout = torch.empty(A.size + pout + 8, dtype=torch.int32, device="cuda")
+        bout.fill_(0x5A5A5A5A)
+        tout = bout[pout:pout + A.size]
+    r.sort(tin, minVal, maxVal, keys_out=tout, config=cfg)
+    torch.cuda.synchronize()
+    got = tout.cpu().numpy()
+    assert np.array_equal(got, want), f"mismatch at {np.flatnonzero(got != want)[:8]}"
+    if not inplace:
+        # guard words around the output are untouched
+        full = bout.cpu().numpy()
+        assert np.all(full[:pout] == 0x5A5A5A5A) and np.all(full[pout + A.size:] == 0x5A5A5A5A)
+        # the input is not modified
+        assert np.array_equal(tin.cpu().numpy(), np.asarray(A, dtype=np.int32))
+
+
+def test_worked_example(r):
+    g = load("worked_example.txt")
+    _run(r, g["A"].astype(np.int32), g["minVal"], g["maxVal"], r.make_config(128, 4, 1))
+
+
+def test_small_workload_uniform_1e6(r):
+    """n = 10^6 keys, minVal 0, R = 2^7, uniform: the small single-array workload."""
+    A = inputs.uniform(10 ** 6, 0, 128, inputs.case_seed(1, 0))
+    _run(r, A, 0, 128)
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 127, 128, 129, 1000, 4097, 40961, 65535, 65536, 65537,
+                               81921, 262144])
+def test_ragged_sizes(r, R):
+    rng = np.random.default_rng(R)
+    for n in (1, 2, 3, 4, 5, 7, 8, 9, 17, 1023, 1025, 4099, 65537, 300001):
+        minVal = int(rng.integers(-10 ** 6, 10 ** 6))
+        A = rng.integers(minVal, minVal + R, size=n).astype(np.int32)
+        _run(r, A, minVal, minVal + R)
+
+
+@pytest.mark.parametrize("pin,pout", list(itertools.product(range(4), range(4))))
+def test_misaligned_pointers(r, pin, pout):
+    rng = np.random.default_rng(10 * pin + pout)
+    for n, R in ((13, 50), (5000, 3000), (70001, 70000)):
+        A = rng.integers(-7, -7 + R, size=n).astype(np.int32)
+        _run(r, A, -7, -7 + R, pin=pin, pout=pout)
+
+
+@pytest.mark.parametrize("R", [128, 70000])
+def test_in_place(r, R):
+    A = inputs.uniform(123457, 5, 5 + R, 3)
+    _run(r, A, 5, 5 + R, inplace=True)
+    _run(r, A, 5, 5 + R, pin=1, inplace=True)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "normal", "all_equal", "zipf"])
+@pytest.mark.parametrize("logR", [7, 10, 13, 16, 18])
+def test_distributions(r, dist, logR):
+    R, minVal = 1 << logR, -1000
+    A = inputs.make(dist, 2_000_003, minVal, minVal + R, inputs.case_seed(2, logR))
+    _run(r, A, minVal, minVal + R)
+
+
+def test_extreme_ranges(r):
+    i32min = -(2 ** 31)
+    A = inputs.uniform(100_001, i32min, i32min + 1000, 1)
+    _run(r, A, i32min, i32min + 1000)
+    A = inputs.uniform(100_001, 2 ** 31 - 70000, 2 ** 31, 2)
+    _run(r, A, 2 ** 31 - 70000, 2 ** 31)
+    A = np.full(1000, 2 ** 31 - 1, dtype=np.int32)
+    _run(r, A, 2 ** 31 - 1, 2 ** 31)
+
+
+@pytest.mark.parametrize("R", [1 << 16, 1 << 16 | 1, 1 << 18])
+def test_sixteen_bit_counter_overflow(r, R):
+    """More than 65535 equal keys per workgroup in 16-bit packed counters, in
+    both halves of one LDS word and in the last (phantom-paired) bin."""
+    n = 40_000_000
+    base = np.array([0, 1, 2, R - 1], dtype=np.int64)
+    rng = np.random.default_rng(R)
+    for pick in ([0], [0, 1], [1], [R - 1], [2, 3, R - 1]):
+        vals = np.asarray(pick, dtype=np.int64)
+        A = (vals[rng.integers(0, vals.size, size=n)] - 77).astype(np.int32)
+        _run(r, A, -77, -77 + R)
+    del base
+
+
+def _grid():
+    for T in (1024, 2048, 4096, 8192, 16384, 32768):
+        for items in (4, 8, 16):
+            for bpt in (1, 2, 4):
+                if T * 4 * bpt <= 163840:
+                    yield T, items, bpt
+
+
+GRID = list(_grid())
+
+
+def test_grid_has_45_valid_points():
+    assert len(GRID) == 45
+
+
+@pytest.mark.parametrize("dist,logR", [("uniform", 7), ("normal", 13), ("all_equal", 16),
+                                       ("uniform", 16), ("normal", 18)])
+def test_every_config_is_identical(r, dist, logR):
+    R, minVal = 1 << logR, 321
+    A = inputs.make(dist, 777_777, minVal, minVal + R, inputs.case_seed(5, logR))
+    want = oracle.sort(A, minVal, minVal + R)
+    _, tin = _to_dev(A, 1)
+    for T, items, bpt in GRID:
+        _say(f"config T={T} items={items} bpt={bpt} dist={dist} R={R}")
+        out = r.sort(tin, minVal, minVal + R, config=r.make_config(T, items, bpt))
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want), (T, items, bpt)
+
+
+@pytest.mark.parametrize("R,T", [(4, 128), (1000, 128), (1000, 1024), (70000, 1024),
+                                 (70000, 32768), (262144, 8192), (300000, 32768)])
+def test_intermediates_match_oracle(r, R, T):
+    """Tile histograms (Alg. 5), local CDFs (Alg. 4) and tile offsets (Alg. 6)."""
+    rng = np.random.default_rng(R + T)
+    minVal = -55
+    A = rng.integers(minVal, minVal + R, size=250_000).astype(np.int32)
+    A[:1000] = minVal + R - 1
+    Teff = min(T, (R + 127) // 128 * 128)
+    _say(f"intermediates R={R} T={T} Teff={Teff}")
+    h, c, O = oracle.tile_intermediates(A, minVal, minVal + R, Teff)
+    _, tin = _to_dev(A, 0)
+    gh, gc, gO = r.debug_intermediates(tin, minVal, minVal + R, r.make_config(T, 16, 1))
+    torch.cuda.synchronize()
+    as_u = lambda t: t.cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert np.array_equal(as_u(gh), h)
+    assert np.array_equal(as_u(gc), c)
+    assert np.array_equal(as_u(gO), O)
+
+
+def test_caller_workspace(r):
+    rng = np.random.default_rng(9)
+    for R in (100, 65536, 200000):
+        A = rng.integers(0, R, size=500_001).astype(np.int32)
+        want = oracle.sort(A, 0, R)
+        _, tin = _to_dev(A, 2)
+        out = torch.empty_like(tin)
+        nb = r.workspace_bytes(A.size, 0, R, keys_out=out)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        ws.fill_(0xAB)   # contents must not matter
+        _say(f"sort_ws R={R} bytes={nb}")
+        for _ in range(2):
+            r.sort_ws(tin, out, 0, R, ws)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want)
+        with pytest.raises(r.RtcdfError) as e:
+            r.sort_ws(tin, out, 0, R, ws[: nb // 2])
+        assert e.value.status == r.WORKSPACE_TOO_SMALL
+
+
+def test_two_streams(r):
+    A = inputs.uniform(1_000_000, 0, 70000, 4)
+    B = inputs.normal(1_000_000, 0, 300, 5)
+    wa, wb = oracle.sort(A, 0, 70000), oracle.sort(B, 0, 300)
+    _, ta = _to_dev(A)
+    _, tb = _to_dev(B)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    _say("two streams")
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            oa = r.sort(ta, 0, 70000)
+        with torch.cuda.stream(s2):
+            ob = r.sort(tb, 0, 300)
+        torch.cuda.synchronize()
+        assert np.array_equal(oa.cpu().numpy(), wa)
+        assert np.array_equal(ob.cpu().numpy(), wb)
+
+
+def test_empty_and_errors(r):
+    t = torch.empty(0, dtype=torch.int32, device="cuda")
+    assert r.sort(t, 0, 10).numel() == 0
+    x = torch.zeros(100, dtype=torch.int32, device="cuda")
+    assert r.lib.rtcdf_sort(r._ptr(x), r._ptr(x[10:]), 50, 0, 10, None) == r.OVERLAP
+    with pytest.raises(r.RtcdfError) as e:
+        r.sort(x, 0, 10, config=r.make_config(32768, 16, 2))
+    assert e.value.status == r.INVALID_VALUE
