@@ -154,6 +154,25 @@ rtcdf_status_t rtcdf_pick_config(const int32_t* keys_in, size_t n, int64_t minVa
 const char* rtcdf_status_string(rtcdf_status_t status);
 /* The hipError_t of the last RTCDF_ERROR_HIP on this thread (0 if none). */
 int rtcdf_last_hip_error(void);
+/* Per-stage timing for measurement.  While enabled, every plain sort records
+ * HIP events on its stream around its four stages (0 histogram, 1 partial-row
+ * reduction, 2 local CDF + tile offsets, 3 output); rtcdf_profile_collect
+ * waits for the recorded events, writes the summed milliseconds per stage and
+ * the number of sorts to *out, and forgets them.  Disabled by default. */
+typedef struct rtcdf_stage_stats {
+  uint64_t sorts;
+  double ms[4];
+} rtcdf_stage_stats_t;
+
+rtcdf_status_t rtcdf_profile_enable(int on);
+rtcdf_status_t rtcdf_profile_collect(rtcdf_stage_stats_t* out);
+
+/* Measurement utility: copies `bytes` (a multiple of 16) from d_src to d_dst
+ * (16-byte aligned device buffers, not overlapping) with a plain streaming
+ * kernel.  Its bandwidth is the attainable-HBM reference the sort kernels are
+ * compared with, and its HBM counters calibrate counter-derived traffic. */
+rtcdf_status_t rtcdf_stream_copy(const void* d_src, void* d_dst, size_t bytes, hipStream_t stream);
+
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int rtcdf_version(void);
 /* Frees the library's cached per-device workspaces (not needed before exit). */

@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "../../include/rtcdf.h"
 #include "rtcdf_internal.h"
@@ -85,6 +87,14 @@ static bool config_is_zero(const rtcdf_config_t* c) {
 
 // ----------------------------------------------------------------- planning
 
+// Developer overrides of launch shapes (RTCDF_DEV_*), read at every plan so a
+// measurement script can sweep them; unset means the planner's choice.
+static int64_t env_int(const char* name, int64_t dflt) {
+  const char* v = std::getenv(name);
+  if (v == nullptr || *v == 0) return dflt;
+  return std::strtoll(v, nullptr, 10);
+}
+
 // Derives every launch parameter and the workspace layout.  `out` is only
 // inspected for its alignment.
 void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& cfg,
@@ -103,17 +113,21 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
 
   // Histogram passes: as many whole tiles per workgroup LDS as fit, with 32-bit
   // counters, or with two 16-bit counters per word when that needs fewer passes.
-  const uint32_t lds = kLdsBytes / p->bpt;
+  const uint32_t lds = kLdsBytes / p->bpt - 256;   // 64 spare words for the 16-bit form
   const uint32_t k32 = std::max<uint32_t>(1, lds / (4 * p->T));
   const uint32_t k16 = std::max<uint32_t>(1, lds / (2 * p->T));
   const uint32_t passes32 = (p->m + k32 - 1) / k32;
   const uint32_t passes16 = (p->m + k16 - 1) / k16;
   p->packed16 = passes16 < passes32;
+  const int force_bits = env_int("RTCDF_DEV_COUNTER_BITS", 0);
+  if (force_bits == 16) p->packed16 = true;
+  if (force_bits == 32) p->packed16 = false;
   const uint32_t k = p->packed16 ? k16 : k32;
   p->passes = p->packed16 ? passes16 : passes32;
   p->W = p->passes == 1 ? std::min<uint32_t>(Rr, k * p->T) : k * p->T;
   p->row_words = p->packed16 ? p->W / 2 : p->W;
   p->hist_block = 1024 / p->bpt;
+  p->hist_interleave = (uint32_t)env_int("RTCDF_DEV_HIST_INTERLEAVE", 1);
 
   // Input body: 16-byte aligned int4 vectors between a scalar head and tail.
   const uintptr_t ia = reinterpret_cast<uintptr_t>(in);
@@ -136,13 +150,18 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // Output chunks: s(0) = 0, s(k) = out_head + k * chunk.
   const uintptr_t oa = reinterpret_cast<uintptr_t>(out);
   p->out_head = (uint32_t)(((16 - (oa & 15)) & 15) / 4);
-  const uint32_t gran = 4 * kFillBlock * (p->items / 4);
-  uint64_t want = (n + (uint64_t)dev.cus * 8 - 1) / ((uint64_t)dev.cus * 8);
+  const uint32_t gran = 4 * kFillBlock;
+  const uint64_t fill_per_cu = (uint64_t)env_int("RTCDF_DEV_FILL_WGS_PER_CU", 4);
+  // Chunks of 8192 positions (32 KiB of output), fewer when n is small so
+  // that every compute unit still gets work.
+  uint64_t want = (n + (uint64_t)dev.cus * 4 - 1) / ((uint64_t)dev.cus * 4);
   want = std::max<uint64_t>(want, gran);
-  want = std::min<uint64_t>(want, 65536);
+  want = std::min<uint64_t>(want, 8192);
+  const int64_t force_chunk = env_int("RTCDF_DEV_FILL_CHUNK", 0);
+  if (force_chunk > 0) want = (uint64_t)force_chunk;
   p->chunk = (uint32_t)((want + gran - 1) / gran * gran);
   p->nchunks = 1 + ((n >= 1 && n - 1 >= p->out_head) ? (uint32_t)((n - 1 - p->out_head) / p->chunk) : 0);
-  p->fill_grid = std::min<uint32_t>(p->nchunks, (uint32_t)dev.cus * 8);
+  p->fill_grid = (uint32_t)std::min<uint64_t>(p->nchunks, (uint64_t)dev.cus * fill_per_cu);
 
   // Workspace layout.
   size_t off = 0;
@@ -216,21 +235,61 @@ static rtcdf_status_t grow(Workspace& w, const Plan& p) {
   return RTCDF_SUCCESS;
 }
 
+// ------------------------------------------------------------- profiling
+
+// Optional per-stage timing: when enabled, every sort records HIP events on
+// its own stream before the histogram and after each stage.  rtcdf_profile_collect
+// waits for them and sums the elapsed time per stage.
+static std::atomic<bool> g_prof{false};
+static std::mutex g_prof_mu;
+struct StageMarks {
+  hipEvent_t ev[5];
+};
+static std::vector<StageMarks> g_prof_pending;
+static std::vector<hipEvent_t> g_prof_pool;
+
+static hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
 // Enqueue the four stages.  `carry` points at a zeroed array of p.carry_words.
 static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, uint8_t* ws,
                               uint32_t* carry, hipStream_t s, uint32_t* dbg_hist = nullptr,
                               uint32_t* dbg_cdf = nullptr, uint32_t* dbg_O = nullptr) {
   const Plan& q = p;
+  StageMarks marks;
+  bool prof = g_prof.load() && out != nullptr;
+  if (prof) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& ev : marks.ev) {
+      ev = prof_event();
+      if (ev == nullptr) prof = false;
+    }
+  }
+  auto mark = [&](int i) {
+    if (prof) (void)hipEventRecord(marks.ev[i], s);
+  };
+  mark(0);
   hipError_t e = launch_hist(q, in, ws, carry, s);
   if (e != hipSuccess) return hip_fail(e);
+  mark(1);
   e = launch_reduce(q, ws, carry, s);
   if (e != hipSuccess) return hip_fail(e);
+  mark(2);
   if (dbg_hist) {
     e = hipMemcpyAsync(dbg_hist, ws + q.off_hist, (size_t)q.R * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e);
   }
   e = launch_tilescan(q, ws, s);
   if (e != hipSuccess) return hip_fail(e);
+  mark(3);
   if (dbg_cdf) {
     e = hipMemcpyAsync(dbg_cdf, ws + q.off_hist, (size_t)q.R * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e);
@@ -242,6 +301,11 @@ static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, ui
   if (out) {
     e = launch_fill(q, out, ws, s);
     if (e != hipSuccess) return hip_fail(e);
+  }
+  mark(4);
+  if (prof) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back(marks);
   }
   return RTCDF_SUCCESS;
 }
@@ -382,7 +446,43 @@ const char* rtcdf_status_string(rtcdf_status_t s) {
 
 int rtcdf_last_hip_error(void) { return g_last_hip_error; }
 
+rtcdf_status_t rtcdf_profile_enable(int on) {
+  g_prof.store(on != 0);
+  return RTCDF_SUCCESS;
+}
+
+rtcdf_status_t rtcdf_profile_collect(rtcdf_stage_stats_t* out) {
+  if (out == nullptr) return RTCDF_ERROR_INVALID_VALUE;
+  std::memset(out, 0, sizeof(*out));
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  rtcdf_status_t st = RTCDF_SUCCESS;
+  for (StageMarks& m : g_prof_pending) {
+    hipError_t e = hipEventSynchronize(m.ev[4]);
+    if (e != hipSuccess) st = hip_fail(e);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, m.ev[i], m.ev[i + 1]) == hipSuccess) out->ms[i] += ms;
+    }
+    out->sorts += 1;
+    for (auto& ev : m.ev) g_prof_pool.push_back(ev);
+  }
+  g_prof_pending.clear();
+  return st;
+}
+
 int rtcdf_version(void) { return 100; }
+
+rtcdf_status_t rtcdf_stream_copy(const void* d_src, void* d_dst, size_t bytes, hipStream_t stream) {
+  if (bytes == 0) return RTCDF_SUCCESS;
+  if (d_src == nullptr || d_dst == nullptr || (bytes & 15u) ||
+      (reinterpret_cast<uintptr_t>(d_src) & 15u) || (reinterpret_cast<uintptr_t>(d_dst) & 15u))
+    return RTCDF_ERROR_INVALID_VALUE;
+  DeviceInfo dev;
+  rtcdf_status_t st = device_info(&dev);
+  if (st != RTCDF_SUCCESS) return st;
+  hipError_t e = launch_stream_copy(d_src, d_dst, bytes, dev.cus, stream);
+  return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
+}
 
 rtcdf_status_t rtcdf_release_workspaces(void) {
   std::lock_guard<std::mutex> lk(g_ws_mu);

@@ -18,7 +18,7 @@ struct DefaultRow {
   rtcdf_config_t cfg;
 };
 static const DefaultRow kDefaultTable[] = {
-    {1u << 28, {32768, 16, 1, 0}},
+    {1u << 28, {2048, 16, 1, 0}},
 };
 
 rtcdf_config_t default_config(size_t n, uint32_t R) {

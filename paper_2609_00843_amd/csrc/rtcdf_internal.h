@@ -35,6 +35,7 @@ struct Plan {
   uint32_t G;            // workgroups (input chunks) per pass, multiple of 8
   uint32_t row_words;    // 32-bit words per partial row (W or W/2)
   uint32_t hist_block;   // threads per histogram workgroup
+  uint32_t hist_interleave;  // 1: tiles dealt round-robin to chunks; 0: contiguous chunks
   uint32_t in_head;      // keys before the 16-byte aligned input body
   uint64_t in_n4;        // int4 vectors in the input body
   uint64_t in_per;       // int4 vectors per input chunk
@@ -60,6 +61,7 @@ struct DeviceInfo {
 // Kernel launchers (rtcdf_kernels.hip).  All enqueue on `stream` and return the
 // hipError_t of the launch.
 hipError_t launch_clear(uint32_t* p, size_t words, hipStream_t stream);
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int cus, hipStream_t stream);
 hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t* carry,
                        hipStream_t stream);
 hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_t stream);

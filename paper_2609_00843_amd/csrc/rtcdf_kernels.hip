@@ -90,53 +90,82 @@ struct HistArgs {
   uint64_t in_n4, in_per;
   uint32_t in_head, in_tail;
   uint32_t min_u, W, passes, G, row_words, R;
+  uint32_t interleave;
   uint32_t* partial;
   uint32_t* carry;
 };
 
-// Counts one normalised value x (x >= W means "not in this pass").  Lanes of a
-// wave holding the same value as the wave's first active lane are merged into
-// a single LDS atomic, so all-equal and heavily skewed keys do not serialise
-// on one LDS address.
-__device__ __forceinline__ void count_u32(uint32_t* S, uint32_t x, uint32_t W) {
-  const uint32_t lead = (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
-  const uint64_t same = __ballot(x == lead);
-  if (x == lead) {
-    if (lead < W && lane_id() == (uint32_t)(__ffsll((unsigned long long)same) - 1))
-      atomicAdd(&S[lead], (uint32_t)__popcll(same));
-  } else if (x < W) {
-    atomicAdd(&S[x], 1u);
+// Two 16-bit counters per LDS word (bin x in half x & 1 of word x >> 1).  The
+// returned old word shows whether an add of c wrapped a half; the lost 2^16
+// (and the +1 a wrap of the low half pushed into the high half) is repaired
+// exactly in the global carry array, which the reduction adds back.
+__device__ __forceinline__ void fix_u16(uint32_t old, uint32_t x, uint32_t c, uint32_t* carry,
+                                        uint32_t pass_lo) {
+  if ((x & 1u) == 0) {
+    if ((old & 0xffffu) + c > 0xffffu) {
+      const uint32_t c2 = ((old >> 16) + 1u) >> 16;  // high half wrapped by the carry
+      atomicAdd(&carry[pass_lo + x], 65536u);
+      atomicAdd(&carry[pass_lo + x + 1u], 65536u * c2 - 1u);
+    }
+  } else if ((old >> 16) + c > 0xffffu) {
+    atomicAdd(&carry[pass_lo + x], 65536u);
   }
 }
 
-// Two 16-bit counters per LDS word (bin x in half x & 1 of word x >> 1).  The
-// returned old word shows whether the add wrapped a half; the lost 2^16 (and
-// the +1 a wrap of the low half pushed into the high half) is repaired exactly
-// in the global carry array, which the reduction adds back.
-__device__ __forceinline__ void count_u16(uint32_t* S, uint32_t x, uint32_t W,
-                                          uint32_t* carry, uint32_t pass_lo) {
-  const uint32_t lead = (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
-  const uint64_t same = __ballot(x == lead);
-  uint32_t c = 1;
-  bool act;
-  if (x == lead) {
-    act = lead < W && lane_id() == (uint32_t)(__ffsll((unsigned long long)same) - 1);
-    c = (uint32_t)__popcll(same);
-  } else {
-    act = x < W;
-  }
-  if (act) {
-    const uint32_t sh = (x & 1u) << 4;
-    const uint32_t old = atomicAdd(&S[x >> 1], c << sh);
-    if (sh == 0) {
-      if ((old & 0xffffu) + c > 0xffffu) {
-        const uint32_t c2 = ((old >> 16) + 1u) >> 16;  // high half wrapped by the carry
-        atomicAdd(&carry[pass_lo + x], 65536u);
-        atomicAdd(&carry[pass_lo + x + 1u], 65536u * c2 - 1u);
-      }
-    } else if ((old >> 16) + c > 0xffffu) {
-      atomicAdd(&carry[pass_lo + x], 65536u);
+__device__ __forceinline__ void add_u16(uint32_t* S, uint32_t x, uint32_t c, uint32_t* carry,
+                                        uint32_t pass_lo) {
+  const uint32_t old = atomicAdd(&S[x >> 1], c << ((x & 1u) << 4));
+  fix_u16(old, x, c, carry, pass_lo);
+}
+
+// Counts the four keys of one vector per lane.  If every active lane of the
+// wave holds four copies of one value (all-equal or heavily skewed keys), a
+// single lane adds them with one LDS atomic instead of 4 x 64 atomics on the
+// same address.  Otherwise every key takes one LDS atomic without branching:
+// a key outside the pass adds 0 to a per-lane spare word S[spare + lane].
+// In the 16-bit form the four returning atomics are issued back to back and a
+// half that just wrapped (it held 0xffff before the +1) is repaired after a
+// single wave-wide test.
+template <bool PACKED>
+__device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32_t W,
+                                       uint32_t* carry, uint32_t pass_lo, uint32_t spare) {
+  const uint32_t x0 = (uint32_t)k.x - base, x1 = (uint32_t)k.y - base;
+  const uint32_t x2 = (uint32_t)k.z - base, x3 = (uint32_t)k.w - base;
+  const uint32_t lead = (uint32_t)__builtin_amdgcn_readfirstlane((int)x0);
+  const bool four = (x0 == lead) & (x1 == lead) & (x2 == lead) & (x3 == lead);
+  const uint64_t same = __ballot(four);
+  const uint64_t active = __ballot(1);
+  if (same == active) {
+    if (lead < W && lane_id() == (uint32_t)(__ffsll((unsigned long long)active) - 1)) {
+      const uint32_t c = 4u * (uint32_t)__popcll(active);
+      if constexpr (PACKED) add_u16(S, lead, c, carry, pass_lo);
+      else atomicAdd(&S[lead], c);
     }
+    return;
+  }
+  const uint32_t sp = spare + lane_id();
+  if constexpr (PACKED) {
+    const uint32_t s0 = (x0 & 1u) << 4, s1 = (x1 & 1u) << 4, s2 = (x2 & 1u) << 4, s3 = (x3 & 1u) << 4;
+    const uint32_t o0 = atomicAdd(&S[x0 < W ? x0 >> 1 : sp], x0 < W ? 1u << s0 : 0u);
+    const uint32_t o1 = atomicAdd(&S[x1 < W ? x1 >> 1 : sp], x1 < W ? 1u << s1 : 0u);
+    const uint32_t o2 = atomicAdd(&S[x2 < W ? x2 >> 1 : sp], x2 < W ? 1u << s2 : 0u);
+    const uint32_t o3 = atomicAdd(&S[x3 < W ? x3 >> 1 : sp], x3 < W ? 1u << s3 : 0u);
+    // The spare words only ever receive 0, so they never look wrapped.
+    const bool w0 = ((o0 >> s0) & 0xffffu) == 0xffffu && x0 < W;
+    const bool w1 = ((o1 >> s1) & 0xffffu) == 0xffffu && x1 < W;
+    const bool w2 = ((o2 >> s2) & 0xffffu) == 0xffffu && x2 < W;
+    const bool w3 = ((o3 >> s3) & 0xffffu) == 0xffffu && x3 < W;
+    if (__ballot(w0 | w1 | w2 | w3)) {
+      if (w0) fix_u16(o0, x0, 1u, carry, pass_lo);
+      if (w1) fix_u16(o1, x1, 1u, carry, pass_lo);
+      if (w2) fix_u16(o2, x2, 1u, carry, pass_lo);
+      if (w3) fix_u16(o3, x3, 1u, carry, pass_lo);
+    }
+  } else {
+    atomicAdd(&S[x0 < W ? x0 : sp], x0 < W ? 1u : 0u);
+    atomicAdd(&S[x1 < W ? x1 : sp], x1 < W ? 1u : 0u);
+    atomicAdd(&S[x2 < W ? x2 : sp], x2 < W ? 1u : 0u);
+    atomicAdd(&S[x3 < W ? x3 : sp], x3 < W ? 1u : 0u);
   }
 }
 
@@ -149,41 +178,57 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   const uint32_t wg = blockIdx.x, xcd = wg & 7u, slot = wg >> 3;
   const uint32_t pass = slot % a.passes;
   const uint32_t chunk = (slot / a.passes) * 8u + xcd;
-  for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) S[i] = 0u;
+  const uint32_t lds_words = a.row_words + 64u;   // + one spare word per lane
+  for (uint32_t i = threadIdx.x; i < lds_words; i += BLOCK) S[i] = 0u;
   __syncthreads();
 
   const uint32_t pass_lo = pass * a.W;
   const uint32_t base = a.min_u + pass_lo;   // key (as uint32) of bin 0 of this pass
   const uint32_t W = a.W;
-  auto count = [&](int32_t key) {
-    const uint32_t x = (uint32_t)key - base;
-    if constexpr (PACKED) count_u16(S, x, W, a.carry, pass_lo);
-    else count_u32(S, x, W);
-  };
 
   constexpr int V = ITEMS / 4;
   const v4i* body = reinterpret_cast<const v4i*>(a.keys + a.in_head);
-  const uint64_t c0 = (uint64_t)chunk * a.in_per;
-  const uint64_t c1 = c0 + a.in_per < a.in_n4 ? c0 + a.in_per : a.in_n4;
-  for (uint64_t i = c0 + threadIdx.x; i < c1; i += (uint64_t)BLOCK * V) {
-    v4i v[V];
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      const uint64_t idx = i + (uint64_t)j * BLOCK;
-      if (idx < c1) v[j] = __builtin_nontemporal_load(&body[idx]);
-      else v[j] = (v4i)(int)(base - 1u);   // lands outside every pass
-    }
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      count(v[j].x);
-      count(v[j].y);
-      count(v[j].z);
-      count(v[j].w);
-    }
+  const v4i outside = (v4i)(int)(base - 1u);   // lands outside every pass
+  uint64_t t0, step, end;
+  if (a.interleave) {
+    // Tiles of BLOCK * V vectors dealt round-robin to the G chunks of a pass:
+    // at any moment the whole grid reads one contiguous window of the input.
+    t0 = (uint64_t)chunk * BLOCK * V + threadIdx.x;
+    step = (uint64_t)BLOCK * V * a.G;
+    end = a.in_n4;
+  } else {
+    const uint64_t c0 = (uint64_t)chunk * a.in_per;
+    t0 = c0 + threadIdx.x;
+    step = (uint64_t)BLOCK * V;
+    end = c0 + a.in_per < a.in_n4 ? c0 + a.in_per : a.in_n4;
   }
-  if (chunk == 0 && threadIdx.x < a.in_head) count(a.keys[threadIdx.x]);
-  if (chunk == a.G - 1 && threadIdx.x < a.in_tail)
-    count(a.keys[a.in_head + 4 * a.in_n4 + threadIdx.x]);
+  // Software pipelined: the loads of the next tile are in flight while the
+  // current one is counted.
+  v4i cur[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const uint64_t idx = t0 + (uint64_t)j * BLOCK;
+    cur[j] = idx < end ? __builtin_nontemporal_load(&body[idx]) : outside;
+  }
+  while (t0 < end) {
+    const uint64_t t1 = t0 + step;
+    v4i nxt[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const uint64_t idx = t1 + (uint64_t)j * BLOCK;
+      nxt[j] = idx < end ? __builtin_nontemporal_load(&body[idx]) : outside;
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) count4<PACKED>(S, cur[j], base, W, a.carry, pass_lo, a.row_words);
+#pragma unroll
+    for (int j = 0; j < V; ++j) cur[j] = nxt[j];
+    t0 = t1;
+  }
+  // scalar head and tail keys (at most 3 each), counted by chunk 0 / chunk G-1
+  v4i e = outside;
+  if (chunk == 0 && threadIdx.x < a.in_head) e.x = a.keys[threadIdx.x];
+  if (chunk == a.G - 1 && threadIdx.x < a.in_tail) e.y = a.keys[a.in_head + 4 * a.in_n4 + threadIdx.x];
+  if (threadIdx.x < 64) count4<PACKED>(S, e, base, W, a.carry, pass_lo, a.row_words);
   __syncthreads();
 
   uint32_t* row = a.partial + ((size_t)pass * a.G + chunk) * a.row_words;
@@ -208,27 +253,46 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
   const uint32_t pass = r0 / a.W, o = r0 - pass * a.W;
   const uint32_t* rows = a.partial + (size_t)pass * a.G * a.row_words;
   const uint32_t tid = threadIdx.x;
-  if (a.packed) {
-    const uint32_t c = tid & 63u, rg = tid >> 6;   // 64 words x 16 row groups
-    uint32_t lo = 0, hi = 0;
-    for (uint32_t g = rg; g < a.G; g += 16) {
-      const uint32_t w = rows[(size_t)g * a.row_words + (o >> 1) + c];
+  // Row groups: 16 groups of 64 words (16-bit counters) or 8 groups of 128
+  // words (32-bit counters); each thread sums every NG-th row, four loads in
+  // flight at a time.
+  const uint32_t NG = a.packed ? 16u : 8u;
+  const uint32_t c = a.packed ? (tid & 63u) : (tid & 127u);
+  const uint32_t rg = a.packed ? (tid >> 6) : (tid >> 7);
+  const uint32_t col = a.packed ? (o >> 1) + c : o + c;
+  const uint32_t* src = rows + col;
+  const size_t rs = a.row_words;
+  uint32_t lo = 0, hi = 0;
+  uint32_t g = rg;
+  for (; g + 3 * NG < a.G; g += 4 * NG) {
+    const uint32_t w0 = src[(size_t)g * rs], w1 = src[(size_t)(g + NG) * rs];
+    const uint32_t w2 = src[(size_t)(g + 2 * NG) * rs], w3 = src[(size_t)(g + 3 * NG) * rs];
+    if (a.packed) {
+      lo += (w0 & 0xffffu) + (w1 & 0xffffu) + (w2 & 0xffffu) + (w3 & 0xffffu);
+      hi += (w0 >> 16) + (w1 >> 16) + (w2 >> 16) + (w3 >> 16);
+    } else {
+      lo += w0 + w1 + w2 + w3;
+    }
+  }
+  for (; g < a.G; g += NG) {
+    const uint32_t w = src[(size_t)g * rs];
+    if (a.packed) {
       lo += w & 0xffffu;
       hi += w >> 16;
+    } else {
+      lo += w;
     }
+  }
+  if (a.packed) {
     red[rg][2 * c] = lo;
     red[rg][2 * c + 1] = hi;
   } else {
-    const uint32_t c = tid & 127u, rg = tid >> 7;  // 128 words x 8 row groups
-    uint32_t s = 0;
-    for (uint32_t g = rg; g < a.G; g += 8) s += rows[(size_t)g * a.row_words + o + c];
-    red[rg][c] = s;
+    red[rg][c] = lo;
   }
   __syncthreads();
   uint32_t tot = 0;
   if (tid < kReduceBins) {
-    const uint32_t ngroups = a.packed ? 16u : 8u;
-    for (uint32_t g = 0; g < ngroups; ++g) tot += red[g][tid];
+    for (uint32_t q = 0; q < NG; ++q) tot += red[q][tid];
     const uint32_t bin = r0 + tid;
     if (a.packed && bin < a.carry_words) {
       tot += a.carry[bin];
@@ -237,8 +301,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
     if (bin < a.R) a.hist[bin] = tot;
     else tot = 0u;
   }
-  const uint32_t s = block_sum(tid < kReduceBins ? tot : 0u, wsum);
-  if (tid == 0) a.rsum[blockIdx.x] = s;
+  const uint32_t sum = block_sum(tid < kReduceBins ? tot : 0u, wsum);
+  if (tid == 0) a.rsum[blockIdx.x] = sum;
 }
 
 // ---------------------------------------------------------- local CDF + O[t]
@@ -265,6 +329,20 @@ __device__ __forceinline__ uint32_t first_chunk_at_or_after(uint64_t P, uint32_t
   return k < nchunks ? (uint32_t)k : nchunks;
 }
 
+// Local CDFs are kept in LDS with one padding word per 32 entries, so the
+// per-thread segments of the blocked scan fall into distinct banks.
+__device__ __forceinline__ uint32_t pad32(uint32_t i) { return i + (i >> 5); }
+
+// Number of entries of the nondecreasing padded array C[0..len) that are <= q.
+__device__ __forceinline__ uint32_t count_le_pad(const uint32_t* C, uint32_t len, uint32_t q) {
+  uint32_t lo = 0, hi = len;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (C[pad32(mid)] <= q) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
   extern __shared__ uint32_t C[];
   __shared__ uint32_t wsum[kScanBlock / 64];
@@ -278,35 +356,60 @@ __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
   for (uint32_t k = tid; k < b / kReduceBins; k += kScanBlock) acc += a.rsum[k];
   const uint32_t Ot = block_sum(acc, wsum);
 
-  // Alg. 4: in-place inclusive scan of H[b, b + w), 1024 bins per step.
-  uint32_t run = 0;
-  for (uint32_t r0 = 0; r0 < w; r0 += kScanBlock) {
-    const uint32_t i = r0 + tid;
-    const uint32_t v = i < w ? a.hist[b + i] : 0u;
-    uint32_t total;
-    const uint32_t inc = block_inclusive_scan(v, wsum, &total);
-    if (i < w) {
-      C[i] = run + inc;
-      a.hist[b + i] = run + inc;
-    }
-    run += total;
-  }
-  if (tid == 0) a.O[t] = Ot;
+  // Alg. 4: inclusive scan of H[b, b + w).  Coalesced copy into LDS, then
+  // each thread scans a contiguous segment of L entries, one block scan of the
+  // segment totals, and the segment prefix is added back.
+  for (uint32_t i = tid; i < w; i += kScanBlock) C[pad32(i)] = a.hist[b + i];
   __syncthreads();
-  const uint32_t Nt = run;  // = C[w - 1], the tile's population
+  const uint32_t L = (w + kScanBlock - 1) / kScanBlock;
+  const uint32_t s0 = tid * L < w ? tid * L : w;
+  const uint32_t s1 = s0 + L < w ? s0 + L : w;
+  uint32_t run = 0;
+  for (uint32_t i = s0; i < s1; ++i) {
+    run += C[pad32(i)];
+    C[pad32(i)] = run;
+  }
+  uint32_t Nt;
+  const uint32_t before = block_inclusive_scan(run, wsum, &Nt) - run;
+  for (uint32_t i = s0; i < s1; ++i) C[pad32(i)] += before;
+  __syncthreads();
+  for (uint32_t i = tid; i < w; i += kScanBlock) a.hist[b + i] = C[pad32(i)];
+  if (tid == 0) a.O[t] = Ot;
   if (Nt == 0) return;
 
   // Splitters: the value at every chunk start inside [O_t, O_t + N_t), and at
-  // position n - 1 (closes the last chunk's window).
+  // position n - 1 (closes the last chunk's window).  Chunk starts are taken
+  // in batches of 4 per thread: each thread finds its 4 consecutive starts
+  // (one bisection, then a short forward walk), stages them in LDS (behind
+  // the CDF) and the batch is written out with coalesced stores.
   const uint64_t lo = Ot, hi = (uint64_t)Ot + Nt;
   const uint32_t k0 = first_chunk_at_or_after(lo, a.out_head, a.chunk, a.nchunks);
   const uint32_t k1 = first_chunk_at_or_after(hi, a.out_head, a.chunk, a.nchunks);
-  for (uint32_t k = k0 + tid; k < k1; k += kScanBlock) {
-    const uint64_t s = k == 0 ? 0 : (uint64_t)a.out_head + (uint64_t)k * a.chunk;
-    a.split[k] = b + count_le(C, w, (uint32_t)(s - lo));
+  uint32_t* stage = C + pad32(a.T) + 1;   // 4 * kScanBlock words
+  constexpr uint32_t kPer = 4;
+  for (uint32_t kb0 = k0; kb0 < k1; kb0 += kPer * kScanBlock) {
+    const uint32_t ka = kb0 + tid * kPer;
+    uint32_t x = 0;
+    for (uint32_t j = 0; j < kPer && ka + j < k1; ++j) {
+      const uint32_t k = ka + j;
+      const uint64_t s = k == 0 ? 0 : (uint64_t)a.out_head + (uint64_t)k * a.chunk;
+      const uint32_t q = (uint32_t)(s - lo);
+      uint32_t steps = 0;
+      if (j != 0)
+        while (steps < 8u && x < w && C[pad32(x)] <= q) {
+          ++x;
+          ++steps;
+        }
+      if (j == 0 || (x < w && C[pad32(x)] <= q)) x = count_le_pad(C, w, q);
+      stage[tid * kPer + j] = b + x;
+    }
+    __syncthreads();
+    const uint32_t nbatch = min(kPer * kScanBlock, k1 - kb0);
+    for (uint32_t j = tid; j < nbatch; j += kScanBlock) a.split[kb0 + j] = stage[j];
+    __syncthreads();
   }
   if (tid == 0 && a.n - 1 >= lo && a.n - 1 < hi)
-    a.split[a.nchunks] = b + count_le(C, w, (uint32_t)(a.n - 1 - lo));
+    a.split[a.nchunks] = b + count_le_pad(C, w, (uint32_t)(a.n - 1 - lo));
 }
 
 // --------------------------------------------------------------------- output
@@ -338,72 +441,142 @@ __device__ __forceinline__ uint32_t value_at_global(const FillArgs& a, uint32_t 
   return lo;
 }
 
-template <int V>
-__global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
-  __shared__ uint32_t win[kFillWindow];
-  const uint32_t tid = threadIdx.x;
-  for (uint32_t k = blockIdx.x; k < a.nchunks; k += gridDim.x) {
-    const uint64_t p0 = k == 0 ? 0 : (uint64_t)a.out_head + (uint64_t)k * a.chunk;
-    const uint64_t p1 = k + 1 < a.nchunks ? (uint64_t)a.out_head + (uint64_t)(k + 1) * a.chunk : a.n;
-    // Splitters are always in [0, R) for keys inside the declared range; the
-    // clamps only keep every access in bounds when that precondition is broken.
-    const uint32_t v0 = min(a.split[k], a.R - 1);
-    const uint32_t v1 = min(max(a.split[k + 1], v0), a.R - 1);
-    const uint32_t nwin = v1 - v0 + 1;
-    const uint64_t q_lo = p0 > a.body_lo ? p0 : a.body_lo;
-    const uint64_t q_hi = p1 < a.body_hi ? p1 : a.body_hi;
-    v4i* body = reinterpret_cast<v4i*>(a.out + a.body_lo);
-    const uint64_t i_lo = (q_lo - a.body_lo) >> 2, i_hi = q_hi > q_lo ? (q_hi - a.body_lo) >> 2 : i_lo;
-    const int32_t base = (int32_t)(a.min_u + v0);
-    if (nwin <= kFillWindow) {
-      for (uint32_t j = tid; j < nwin; j += kFillBlock) win[j] = cum_incl(a, v0 + j);
-      __syncthreads();
-      for (uint64_t i = i_lo + tid; i < i_hi; i += (uint64_t)kFillBlock * V) {
-#pragma unroll
-        for (int u = 0; u < V; ++u) {
-          const uint64_t ii = i + (uint64_t)u * kFillBlock;
-          if (ii < i_hi) {
-            const uint32_t p = (uint32_t)(a.body_lo + 4 * ii);
-            const uint32_t last = nwin - 1;
-            uint32_t x = min(count_le(win, nwin, p), last);
-            v4i o;
-            o.x = base + (int32_t)x;
-            while (x < last && win[x] <= p + 1) ++x;
-            o.y = base + (int32_t)x;
-            while (x < last && win[x] <= p + 2) ++x;
-            o.z = base + (int32_t)x;
-            while (x < last && win[x] <= p + 3) ++x;
-            o.w = base + (int32_t)x;
-            body[ii] = o;
-          }
-        }
-      }
-      // scalar head (positions before the aligned body) and tail
-      if (k == 0)
-        for (uint64_t p = tid; p < a.body_lo; p += kFillBlock)
-          a.out[p] = base + (int32_t)count_le(win, nwin, (uint32_t)p);
-      if (k + 1 == a.nchunks)
-        for (uint64_t p = a.body_hi + tid; p < a.n; p += kFillBlock)
-          a.out[p] = base + (int32_t)count_le(win, nwin, (uint32_t)p);
-      __syncthreads();   // window is rewritten by the next chunk
+// Start position of output chunk k: s(0) = 0, s(k) = out_head + k * chunk.
+__device__ __forceinline__ uint64_t chunk_start(const FillArgs& a, uint32_t k) {
+  return k == 0 ? 0 : (uint64_t)a.out_head + (uint64_t)k * a.chunk;
+}
+
+// Writes the positions [p0, p1) of one chunk whose values lie in [v0, v0 + nwin)
+// and whose inclusive cumulative counts are in win[0, nwin).
+__device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* win, uint32_t nwin,
+                                           uint32_t v0, uint64_t p0, uint64_t p1, bool first,
+                                           bool final) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint64_t q_lo = p0 > a.body_lo ? p0 : a.body_lo;
+  const uint64_t q_hi = p1 < a.body_hi ? p1 : a.body_hi;
+  v4i* body = reinterpret_cast<v4i*>(a.out + a.body_lo);
+  const uint64_t i_lo = (q_lo - a.body_lo) >> 2, i_hi = q_hi > q_lo ? (q_hi - a.body_lo) >> 2 : i_lo;
+  const int32_t base = (int32_t)(a.min_u + v0);
+  const uint32_t last = nwin - 1;
+  // Each wave writes 64 consecutive vectors (256 positions) per step.  The
+  // wave carries the index xw of the value at its current position and that
+  // value's inclusive cumulative count `end` in registers (positions only
+  // grow), so a step whose 256 positions hold one value touches no memory but
+  // the store.  Otherwise the value boundaries inside the step are visited in
+  // order (one broadcast LDS read each) and every lane counts the boundaries
+  // at or below each of its four positions.
+  uint32_t xw = 0;
+  uint32_t end = win[0];
+  for (uint64_t ib = i_lo + (uint64_t)wave * 64; ib < i_hi; ib += kFillBlock) {
+    const uint32_t pw = (uint32_t)(a.body_lo + 4 * ib);
+    while (xw < last && end <= pw) end = win[++xw];
+    const uint64_t i = ib + lane;
+    v4i o;
+    if (xw == last || end > pw + 255u) {
+      o = (v4i)(base + (int32_t)xw);
     } else {
-      for (uint64_t i = i_lo + tid; i < i_hi; i += kFillBlock) {
-        const uint32_t p = (uint32_t)(a.body_lo + 4 * i);
-        v4i o;
-        o.x = (int32_t)(a.min_u + value_at_global(a, v0, v1, p));
-        o.y = (int32_t)(a.min_u + value_at_global(a, v0, v1, p + 1));
-        o.z = (int32_t)(a.min_u + value_at_global(a, v0, v1, p + 2));
-        o.w = (int32_t)(a.min_u + value_at_global(a, v0, v1, p + 3));
-        body[i] = o;
+      const uint32_t p = pw + 4 * lane;
+      uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+      uint32_t xb = xw, e = end;
+      while (xb < last && e <= pw + 255u) {   // boundary after value xb at position e
+        c0 += e <= p;
+        c1 += e <= p + 1;
+        c2 += e <= p + 2;
+        c3 += e <= p + 3;
+        e = win[++xb];
       }
-      if (k == 0)
-        for (uint64_t p = tid; p < a.body_lo; p += kFillBlock)
-          a.out[p] = (int32_t)(a.min_u + value_at_global(a, v0, v1, (uint32_t)p));
-      if (k + 1 == a.nchunks)
-        for (uint64_t p = a.body_hi + tid; p < a.n; p += kFillBlock)
-          a.out[p] = (int32_t)(a.min_u + value_at_global(a, v0, v1, (uint32_t)p));
+      o.x = base + (int32_t)(xw + c0);
+      o.y = base + (int32_t)(xw + c1);
+      o.z = base + (int32_t)(xw + c2);
+      o.w = base + (int32_t)(xw + c3);
     }
+    if (i < i_hi) __builtin_nontemporal_store(o, &body[i]);
   }
+  // scalar head (positions before the aligned body) and tail
+  if (first)
+    for (uint64_t p = tid; p < a.body_lo; p += kFillBlock)
+      a.out[p] = base + (int32_t)min(count_le(win, nwin, (uint32_t)p), last);
+  if (final)
+    for (uint64_t p = a.body_hi + tid; p < a.n; p += kFillBlock)
+      a.out[p] = base + (int32_t)min(count_le(win, nwin, (uint32_t)p), last);
+}
+
+// Chunk of positions whose window does not fit in LDS (very sparse values):
+// every position searches the cumulative counts in global memory.
+__device__ void fill_chunk_global(const FillArgs& a, uint32_t v0, uint32_t v1, uint64_t p0,
+                                  uint64_t p1) {
+  for (uint64_t p = p0 + threadIdx.x; p < p1; p += kFillBlock)
+    a.out[p] = (int32_t)(a.min_u + value_at_global(a, v0, v1, (uint32_t)p));
+}
+
+// Splitters of chunk k, clamped: they are always in [0, R) for keys inside
+// the declared range; the clamps only keep every access in bounds when that
+// precondition is broken.
+__device__ __forceinline__ void chunk_values(const FillArgs& a, uint32_t k, uint32_t* v0,
+                                             uint32_t* nwin) {
+  const uint32_t lo = min(a.split[k], a.R - 1);
+  const uint32_t hi = min(max(a.split[k + 1], lo), a.R - 1);
+  *v0 = lo;
+  *nwin = hi - lo + 1;
+}
+
+// Output stage.  Workgroups take chunks k = blockIdx.x + j * gridDim.x.  The
+// loop is software pipelined: while chunk k is written, the inclusive
+// cumulative counts of chunk k + G are already in flight into registers and
+// the splitters of chunk k + 2G are being fetched, so the few waves per
+// compute unit (writes are fastest with few concurrent writers) never wait
+// for global memory between chunks.
+__global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
+  __shared__ uint32_t win[2][kFillWindow];
+  const uint32_t tid = threadIdx.x, G = gridDim.x;
+  uint32_t k = blockIdx.x;
+  if (k >= a.nchunks) return;
+  uint32_t v0, nwin;
+  chunk_values(a, k, &v0, &nwin);
+  for (uint32_t j = tid; j < min(nwin, kFillWindow); j += kFillBlock) win[0][j] = cum_incl(a, v0 + j);
+  // splitters of the next chunk
+  uint32_t nv0 = 0, nnwin = 0;
+  if (k + G < a.nchunks) chunk_values(a, k + G, &nv0, &nnwin);
+  __syncthreads();
+  uint32_t buf = 0;
+  for (;;) {
+    const uint32_t kn = k + G;
+    const bool more = kn < a.nchunks;
+    // prefetch: window head of chunk k + G (one entry per thread), splitters of k + 2G
+    uint32_t pre = 0;
+    if (more && tid < nnwin && nnwin <= kFillWindow) pre = cum_incl(a, nv0 + tid);
+    uint32_t v0_2 = 0, nwin_2 = 0;
+    if (kn + G < a.nchunks) chunk_values(a, kn + G, &v0_2, &nwin_2);
+
+    const uint64_t p0 = chunk_start(a, k);
+    const uint64_t p1 = k + 1 < a.nchunks ? chunk_start(a, k + 1) : a.n;
+    if (nwin <= kFillWindow)
+      fill_chunk(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks);
+    else
+      fill_chunk_global(a, v0, v0 + nwin - 1, p0, p1);
+    if (!more) break;
+
+    // hand over to chunk k + G
+    if (nnwin <= kFillWindow) {
+      if (tid < nnwin) win[buf ^ 1][tid] = pre;
+      for (uint32_t j = kFillBlock + tid; j < nnwin; j += kFillBlock) win[buf ^ 1][j] = cum_incl(a, nv0 + j);
+    }
+    __syncthreads();   // next window complete; everyone is done with the current one
+    buf ^= 1;
+    k = kn;
+    v0 = nv0;
+    nwin = nnwin;
+    nv0 = v0_2;
+    nnwin = nwin_2;
+  }
+}
+
+// Plain 16-byte vector copy (grid-stride), the attainable-bandwidth reference
+// for the measurement of the sort kernels and the calibration of HBM counters.
+__global__ __launch_bounds__(256) void k_stream_copy(const v4i* __restrict__ src,
+                                                     v4i* __restrict__ dst, size_t n4) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (size_t)gridDim.x * 256)
+    dst[i] = __builtin_nontemporal_load(&src[i]);
 }
 
 __global__ void k_clear(uint32_t* p, size_t words) {
@@ -414,7 +587,7 @@ __global__ void k_clear(uint32_t* p, size_t words) {
 
 template <int ITEMS, bool PACKED, int BLOCK>
 hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)p.row_words * 4;
+  const size_t lds = ((size_t)p.row_words + 64) * 4;
   auto kern = k_hist<ITEMS, PACKED, BLOCK>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
@@ -443,6 +616,17 @@ hipError_t launch_hist_block(const Plan& p, const HistArgs& a, hipStream_t s) {
 
 }  // namespace
 
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int cus, hipStream_t s) {
+  const size_t n4 = bytes / 16;
+  if (n4 == 0) return hipSuccess;
+  size_t blocks = (n4 + 255) / 256;
+  const size_t cap = (size_t)cus * 4;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s,
+                     reinterpret_cast<const v4i*>(src), reinterpret_cast<v4i*>(dst), n4);
+  return hipGetLastError();
+}
+
 hipError_t launch_clear(uint32_t* ptr, size_t words, hipStream_t s) {
   if (words == 0) return hipSuccess;
   size_t blocks = (words + 255) / 256;
@@ -467,6 +651,7 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
   a.R = p.R;
   a.partial = reinterpret_cast<uint32_t*>(ws + p.off_partial);
   a.carry = carry;
+  a.interleave = p.hist_interleave;
   return p.packed16 ? launch_hist_block<true>(p, a, s) : launch_hist_block<false>(p, a, s);
 }
 
@@ -498,7 +683,7 @@ hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t s) {
   a.out_head = p.out_head;
   a.chunk = p.chunk;
   a.nchunks = p.nchunks;
-  const size_t lds = (size_t)p.T * 4;
+  const size_t lds = ((size_t)p.T + p.T / 32 + 2 + 4 * kScanBlock) * 4;
   hipError_t e = hipFuncSetAttribute((const void*)k_tilescan,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -521,11 +706,7 @@ hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream
   a.nchunks = p.nchunks;
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
   a.body_hi = a.body_lo + 4 * ((p.n - a.body_lo) / 4);
-  switch (p.items) {
-    case 4: hipLaunchKernelGGL(k_fill<1>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_fill<2>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_fill<4>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a); break;
-  }
+  hipLaunchKernelGGL(k_fill, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -143,3 +143,45 @@ def batched_segments(num: int = 4096, seed: int = None, n_lo: float = 1e3, n_hi:
         segs.append(dict(n=int(ns[i]), minVal=int(mins[i]), maxVal=int(mins[i] + Rs[i]),
                          dist=names[int(dists[i])], seed=int(case_seed(4, 1 + i, seed))))
     return segs
+
+
+def make_device(dist: str, n: int, minVal: int, maxVal: int, seed: int, device="cuda",
+                sd_div: float = 6.0, s: float = 1.1):
+    """The same four distributions generated on the GPU with torch's Philox
+    generator (seeded), for workloads too large to generate on the host in
+    reasonable time.  Returns a contiguous int32 tensor on `device`.  The
+    values differ from the host generators' (another generator), so callers
+    that compare with the oracle copy these arrays back to the host."""
+    import torch
+    R = _check_range(minVal, maxVal)
+    n = int(n)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) & ((1 << 63) - 1))
+    out = torch.empty(n, dtype=torch.int32, device=device)
+    step = 1 << 26
+    if dist == "uniform":
+        for lo in range(0, n, step):
+            hi = min(n, lo + step)
+            out[lo:hi] = torch.randint(int(minVal), int(maxVal), (hi - lo,), generator=g,
+                                       device=device, dtype=torch.int64).to(torch.int32)
+    elif dist == "normal":
+        mean, sd = float(minVal) + R / 2.0, R / float(sd_div)
+        for lo in range(0, n, step):
+            hi = min(n, lo + step)
+            x = torch.randn(hi - lo, generator=g, device=device, dtype=torch.float64)
+            x = torch.round(x * sd + mean).clamp_(float(minVal), float(maxVal - 1))
+            out[lo:hi] = x.to(torch.int64).to(torch.int32)
+    elif dist in ("all_equal", "equal"):
+        out.fill_(int(minVal) + R // 3)
+    elif dist == "zipf":
+        w = torch.arange(1, R + 1, device=device, dtype=torch.float64) ** (-float(s))
+        cdf = torch.cumsum(w, 0)
+        cdf /= cdf[-1].clone()
+        for lo in range(0, n, step):
+            hi = min(n, lo + step)
+            u = torch.rand(hi - lo, generator=g, device=device, dtype=torch.float64)
+            r = torch.searchsorted(cdf, u, right=True).clamp_(max=R - 1)
+            out[lo:hi] = (r + int(minVal)).to(torch.int32)
+    else:
+        raise ValueError(f"unknown distribution {dist!r}")
+    return out

@@ -72,6 +72,12 @@ class BatchBounds(ctypes.Structure):
                 ("max_range", ctypes.c_uint32)]
 
 
+class StageStats(ctypes.Structure):
+    _fields_ = [("sorts", ctypes.c_uint64), ("ms", ctypes.c_double * 4)]
+
+
+STAGES = ("hist", "reduce", "tilescan", "fill")
+
 _vp, _sz, _i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64
 _cfgp = ctypes.POINTER(Config)
 _u32p = ctypes.c_void_p
@@ -92,6 +98,9 @@ _SIGS = {
     "rtcdf_last_hip_error": [],
     "rtcdf_version": [],
     "rtcdf_release_workspaces": [],
+    "rtcdf_profile_enable": [ctypes.c_int],
+    "rtcdf_profile_collect": [ctypes.POINTER(StageStats)],
+    "rtcdf_stream_copy": [_vp, _vp, _sz, _vp],
 }
 for _name, _args in _SIGS.items():
     if hasattr(lib, _name):
@@ -215,3 +224,27 @@ def status_string(status: int) -> str:
 
 def release_workspaces():
     _check(lib.rtcdf_release_workspaces(), "rtcdf_release_workspaces")
+
+
+def profile_enable(on: bool = True):
+    _check(lib.rtcdf_profile_enable(1 if on else 0), "rtcdf_profile_enable")
+
+
+def profile_collect() -> dict:
+    """{'sorts': k, 'hist': ms, 'reduce': ms, 'tilescan': ms, 'fill': ms} summed
+    over the sorts recorded since the last collect."""
+    st = StageStats()
+    _check(lib.rtcdf_profile_collect(ctypes.byref(st)), "rtcdf_profile_collect")
+    d = {"sorts": int(st.sorts)}
+    for i, k in enumerate(STAGES):
+        d[k] = float(st.ms[i])
+    return d
+
+
+def stream_copy(src, dst, stream=None):
+    """Copy src into dst (same byte size, multiple of 16) with the library's
+    plain streaming kernel (the attainable-bandwidth reference)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("size mismatch")
+    _check(lib.rtcdf_stream_copy(_ptr(src), _ptr(dst), nb, _stream_ptr(stream)), "rtcdf_stream_copy")
