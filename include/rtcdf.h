@@ -132,6 +132,52 @@ rtcdf_status_t rtcdf_debug_intermediates(const int32_t* keys_in, size_t n, int64
                                          uint32_t* d_hist, uint32_t* d_cdf,
                                          uint32_t* d_offsets, hipStream_t stream);
 
+/* ---- Batched sort ---------------------------------------------------- */
+
+/* One independent array of a batch (device-resident, 32 bytes): n int32 keys
+ * at keys_in from [minVal, minVal + range), sorted into keys_out.  keys_out
+ * may equal keys_in (in place) but must not overlap any other segment's
+ * output.  1 <= range <= RTCDF_BATCH_MAX_RANGE.  config is reserved (0).
+ * A descriptor with n = 0, range = 0, range > RTCDF_BATCH_MAX_RANGE (or above
+ * the bounds' max_range) or a NULL pointer is skipped and its output left
+ * untouched. */
+typedef struct rtcdf_segment {
+  const int32_t* keys_in;
+  int32_t* keys_out;
+  uint32_t n;
+  int32_t minVal;
+  uint32_t range;
+  uint32_t config;
+} rtcdf_segment_t;
+
+/* Host-side bounds of a batch, used to size the launch and the workspace:
+ * total_keys = sum of n, max_n and max_range the largest n and range of any
+ * segment.  max_range <= RTCDF_BATCH_MAX_RANGE. */
+typedef struct rtcdf_batch_bounds {
+  uint64_t total_keys;
+  uint32_t max_n;
+  uint32_t max_range;
+} rtcdf_batch_bounds_t;
+
+#define RTCDF_BATCH_MAX_RANGE (1u << 16)
+
+/* Workspace bytes rtcdf_sort_batched needs for num_segments segments within
+ * *bounds, written to *bytes. */
+rtcdf_status_t rtcdf_batched_workspace_bytes(uint32_t num_segments,
+                                             const rtcdf_batch_bounds_t* bounds, size_t* bytes);
+
+/* Sort every segment of d_segments[num_segments] (a device array) in one
+ * persistent launch (Alg. 4 of the paper per segment, each segment handled by
+ * one workgroup, largest segments first), preceded by a one-workgroup
+ * ordering kernel.  Each segment's output equals rtcdf_sort of that segment.
+ * d_ws: caller-owned device workspace of ws_bytes bytes (>=
+ * rtcdf_batched_workspace_bytes), 256-byte aligned, no initialisation
+ * needed, not shared with a concurrent call.  No allocation and no host
+ * synchronisation: capturable into a HIP graph and replayable. */
+rtcdf_status_t rtcdf_sort_batched(const rtcdf_segment_t* d_segments, uint32_t num_segments,
+                                  const rtcdf_batch_bounds_t* bounds, void* d_ws,
+                                  size_t ws_bytes, hipStream_t stream);
+
 /* ---- Configuration source --------------------------------------------- */
 
 typedef enum rtcdf_config_mode {

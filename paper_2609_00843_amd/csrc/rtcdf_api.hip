@@ -428,6 +428,58 @@ rtcdf_status_t rtcdf_debug_intermediates(const int32_t* keys_in, size_t n, int64
   return sort_cached(keys_in, nullptr, n, minVal, maxVal, cfg, stream, d_hist, d_cdf, d_offsets);
 }
 
+// ---- batched
+
+struct BatchLayout {
+  size_t off_counters, off_order, off_scratch, bytes;
+  uint32_t grid, scratch_words;
+};
+
+static rtcdf_status_t batch_layout(uint32_t nseg, const rtcdf_batch_bounds_t* bounds, BatchLayout* L) {
+  if (bounds == nullptr) return RTCDF_ERROR_INVALID_VALUE;
+  if (bounds->max_range > RTCDF_BATCH_MAX_RANGE) return RTCDF_ERROR_RANGE_TOO_LARGE;
+  DeviceInfo dev;
+  rtcdf_status_t st = device_info(&dev);
+  if (st != RTCDF_SUCCESS) return st;
+  L->grid = (uint32_t)std::max(1, std::min<int>(dev.cus, (int)std::max<uint32_t>(nseg, 1)));
+  L->scratch_words = (uint32_t)batched_scratch_words(bounds->max_range);
+  L->off_counters = 0;
+  L->off_order = 256;
+  L->off_scratch = align256(L->off_order + (size_t)nseg * 4);
+  L->bytes = align256(L->off_scratch + (size_t)L->grid * L->scratch_words * 4);
+  return RTCDF_SUCCESS;
+}
+
+rtcdf_status_t rtcdf_batched_workspace_bytes(uint32_t num_segments, const rtcdf_batch_bounds_t* bounds,
+                                             size_t* bytes) {
+  if (bytes == nullptr) return RTCDF_ERROR_INVALID_VALUE;
+  BatchLayout L;
+  rtcdf_status_t st = batch_layout(num_segments, bounds, &L);
+  if (st != RTCDF_SUCCESS) return st;
+  *bytes = L.bytes;
+  return RTCDF_SUCCESS;
+}
+
+rtcdf_status_t rtcdf_sort_batched(const rtcdf_segment_t* d_segments, uint32_t num_segments,
+                                  const rtcdf_batch_bounds_t* bounds, void* d_ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+  if (bounds == nullptr) return RTCDF_ERROR_INVALID_VALUE;
+  if (num_segments == 0) return RTCDF_SUCCESS;
+  if (d_segments == nullptr || d_ws == nullptr || (reinterpret_cast<uintptr_t>(d_ws) & 255u) ||
+      (reinterpret_cast<uintptr_t>(d_segments) & 7u))
+    return RTCDF_ERROR_INVALID_VALUE;
+  BatchLayout L;
+  rtcdf_status_t st = batch_layout(num_segments, bounds, &L);
+  if (st != RTCDF_SUCCESS) return st;
+  if (ws_bytes < L.bytes) return RTCDF_ERROR_WORKSPACE_TOO_SMALL;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  hipError_t e = launch_batched(d_segments, num_segments, reinterpret_cast<uint32_t*>(ws + L.off_order),
+                                reinterpret_cast<uint32_t*>(ws + L.off_counters),
+                                reinterpret_cast<uint32_t*>(ws + L.off_scratch), L.scratch_words, L.grid,
+                                stream);
+  return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
+}
+
 const char* rtcdf_status_string(rtcdf_status_t s) {
   switch (s) {
     case RTCDF_SUCCESS: return "success";

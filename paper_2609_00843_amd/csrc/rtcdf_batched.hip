@@ -1,0 +1,280 @@
+// rtcdf_batched.hip -- batched RT-CDF: thousands of independent arrays with
+// uneven n and R sorted by one persistent launch.
+//
+// Each workgroup (1024 threads, 1 per compute unit, 135 KiB of LDS) takes whole
+// arrays ("segments") from a device work queue and runs every step of Alg. 4
+// of the paper for it without touching another workgroup:
+//   Alg. 5  histogram of the segment's keys in LDS (32-bit counters for
+//           R <= 2^15; two 16-bit counters per word above, with the exact
+//           wrap repair of the plain path into a per-workgroup global array);
+//   Alg. 4  local CDF of each range tile (width 2^15) by a blocked LDS scan;
+//   Alg. 6  tile offsets as the running total of the tile populations;
+//   Alg. 7  every output position gets b_t + min{x : C_t[x] >= p' + 1}; each
+//           wave writes 256 consecutive positions per step and carries the
+//           current value and its end from step to step.
+// A one-workgroup ordering kernel runs first: it buckets the segments by
+// log2(n + R) so that the queue hands out the largest segments first (longest
+// processing time first), and it resets the queue counter, so the pair of
+// launches can be captured in a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include "rtcdf_device.h"
+#include "rtcdf_internal.h"
+
+namespace rtcdf {
+namespace {
+
+using namespace dev;
+
+constexpr uint32_t kBBlock = 1024;
+constexpr uint32_t kBTile = 32768;                   // values per local CDF tile
+constexpr uint32_t kBSpare = 33792;                  // pad32(kBTile): first LDS word past any padded bin
+constexpr uint32_t kBLdsWords = kBSpare + 64;        // + one spare word per lane
+constexpr uint32_t kBBuckets = 34;
+
+struct BatchArgs {
+  const rtcdf_segment_t* segs;
+  uint32_t nseg;
+  const uint32_t* order;
+  uint32_t* counters;      // [0] next queue slot
+  uint32_t* scratch;       // per workgroup: scratch_words (16-bit counter repair / counts)
+  uint32_t scratch_words;
+};
+
+__device__ __forceinline__ uint32_t seg_bucket(const rtcdf_segment_t& d) {
+  const uint64_t size = (uint64_t)d.n + d.range + 1;
+  const uint32_t lg = 63u - (uint32_t)__clzll((long long)size);
+  return kBBuckets - 1 - (lg < kBBuckets - 1 ? lg : kBBuckets - 1);   // larger first
+}
+
+__global__ __launch_bounds__(1024) void k_batch_order(const rtcdf_segment_t* segs, uint32_t nseg,
+                                                      uint32_t* order, uint32_t* counters) {
+  __shared__ uint32_t hist[kBBuckets];
+  if (threadIdx.x < kBBuckets) hist[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nseg; i += blockDim.x) atomicAdd(&hist[seg_bucket(segs[i])], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (uint32_t b = 0; b < kBBuckets; ++b) {
+      const uint32_t c = hist[b];
+      hist[b] = run;
+      run += c;
+    }
+    counters[0] = 0;   // the queue starts empty at every launch
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nseg; i += blockDim.x)
+    order[atomicAdd(&hist[seg_bucket(segs[i])], 1u)] = i;
+}
+
+// In-place inclusive scan of the padded LDS array C[0..w); returns the total.
+__device__ uint32_t scan_tile(uint32_t* C, uint32_t w, uint32_t* wsum) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t L = (w + kBBlock - 1) / kBBlock;
+  const uint32_t s0 = tid * L < w ? tid * L : w;
+  const uint32_t s1 = s0 + L < w ? s0 + L : w;
+  uint32_t run = 0;
+  for (uint32_t i = s0; i < s1; ++i) {
+    run += C[pad32(i)];
+    C[pad32(i)] = run;
+  }
+  uint32_t total;
+  const uint32_t before = block_inclusive_scan(run, wsum, &total) - run;
+  for (uint32_t i = s0; i < s1; ++i) C[pad32(i)] += before;
+  __syncthreads();
+  return total;
+}
+
+// Writes the positions [P0, P1) of one segment's output, which hold the values
+// of the tile whose local CDF is the padded LDS array C[0..w); value x of the
+// tile is written as base + x.  body_lo is the first 16-byte aligned position
+// of the output.
+__device__ void fill_tile(int32_t* out, const uint32_t* C, uint32_t w, uint32_t base, uint32_t P0,
+                          uint32_t P1, uint32_t body_lo) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint32_t last = w - 1;
+  // aligned vectors inside [P0, P1)
+  const uint32_t a0 = P0 > body_lo ? P0 : body_lo;
+  const uint32_t q_lo = body_lo + ((a0 - body_lo + 3u) & ~3u);
+  const uint32_t q_hi = P1 > body_lo ? body_lo + ((P1 - body_lo) & ~3u) : body_lo;
+  if (q_lo < q_hi) {
+    v4i* body = reinterpret_cast<v4i*>(out + body_lo);
+    const uint32_t i_lo = (q_lo - body_lo) >> 2, i_hi = (q_hi - body_lo) >> 2;
+    uint32_t xw = 0, end = 0;
+    bool started = false;
+    for (uint32_t ib = i_lo + wave * 64; ib < i_hi; ib += kBBlock) {
+      const uint32_t lp = body_lo + 4 * ib - P0;   // tile-local position of the step's first key
+      if (!started) {
+        xw = min(count_le_pad(C, w, lp), last);
+        end = C[pad32(xw)];
+        started = true;
+      }
+      while (xw < last && end <= lp) end = C[pad32(++xw)];
+      v4i o;
+      if (xw == last || end > lp + 255u) {
+        o = (v4i)(int32_t)(base + xw);
+      } else {
+        const uint32_t p = lp + 4 * lane;
+        uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        uint32_t xb = xw, e = end;
+        while (xb < last && e <= lp + 255u) {
+          c0 += e <= p;
+          c1 += e <= p + 1;
+          c2 += e <= p + 2;
+          c3 += e <= p + 3;
+          e = C[pad32(++xb)];
+        }
+        o.x = (int32_t)(base + xw + c0);
+        o.y = (int32_t)(base + xw + c1);
+        o.z = (int32_t)(base + xw + c2);
+        o.w = (int32_t)(base + xw + c3);
+      }
+      const uint32_t i = ib + lane;
+      if (i < i_hi) __builtin_nontemporal_store(o, &body[i]);
+    }
+  }
+  // scalar positions: before the first and after the last aligned vector
+  const uint32_t s_end = q_lo < q_hi ? q_lo : P1;
+  for (uint32_t p = P0 + tid; p < s_end; p += kBBlock)
+    out[p] = (int32_t)(base + min(count_le_pad(C, w, p - P0), last));
+  if (q_lo < q_hi)
+    for (uint32_t p = q_hi + tid; p < P1; p += kBBlock)
+      out[p] = (int32_t)(base + min(count_le_pad(C, w, p - P0), last));
+}
+
+template <int V, bool PACKED>
+__device__ void count_segment(const int32_t* in, uint32_t n, uint32_t min_u, uint32_t R, uint32_t* S,
+                              uint32_t* carry) {
+  const uint32_t tid = threadIdx.x;
+  const uintptr_t ia = reinterpret_cast<uintptr_t>(in);
+  uint32_t head = (uint32_t)(((16 - (ia & 15)) & 15) / 4);
+  if (head > n) head = n;
+  const uint32_t n4 = (n - head) / 4, tail = n - head - 4 * n4;
+  const v4i* body = reinterpret_cast<const v4i*>(in + head);
+  const v4i outside = (v4i)(int)(min_u - 1u);   // normalises to 0xffffffff: never counted
+  v4i cur[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const uint32_t idx = tid + j * kBBlock;
+    cur[j] = idx < n4 ? __builtin_nontemporal_load(&body[idx]) : outside;
+  }
+  for (uint32_t t0 = tid; t0 < n4; t0 += kBBlock * V) {
+    const uint32_t t1 = t0 + kBBlock * V;
+    v4i nxt[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const uint32_t idx = t1 + j * kBBlock;
+      nxt[j] = idx < n4 ? __builtin_nontemporal_load(&body[idx]) : outside;
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) count4<PACKED, !PACKED>(S, cur[j], min_u, R, carry, 0u, kBSpare);
+#pragma unroll
+    for (int j = 0; j < V; ++j) cur[j] = nxt[j];
+  }
+  if (tid < 64) {
+    v4i e = outside;
+    if (tid < head) e.x = in[tid];
+    if (tid < tail) e.y = in[head + 4 * n4 + tid];
+    count4<PACKED, !PACKED>(S, e, min_u, R, carry, 0u, kBSpare);
+  }
+}
+
+template <int V>
+__device__ void sort_segment(const rtcdf_segment_t& d, uint32_t* S, uint32_t* wsum, uint32_t* cnt,
+                             uint32_t scratch_words) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n = d.n, R = d.range;
+  const int32_t* in = d.keys_in;
+  int32_t* out = d.keys_out;
+  // Descriptors that break the documented limits are skipped (output untouched).
+  if (n == 0 || R == 0 || R > RTCDF_BATCH_MAX_RANGE || in == nullptr || out == nullptr) return;
+  if (R > kBTile && scratch_words < R + 2) return;
+  const uint32_t min_u = (uint32_t)d.minVal;
+  const uintptr_t oa = reinterpret_cast<uintptr_t>(out);
+  uint32_t body_lo = (uint32_t)(((16 - (oa & 15)) & 15) / 4);
+  if (body_lo > n) body_lo = n;
+
+  if (R <= kBTile) {
+    // One tile: 32-bit counters in the padded layout, scanned in place.
+    const uint32_t words = pad32(R - 1) + 1;
+    for (uint32_t i = tid; i < words; i += kBBlock) S[i] = 0u;
+    if (tid < 64) S[kBSpare + tid] = 0u;
+    __syncthreads();
+    count_segment<V, false>(in, n, min_u, R, S, nullptr);
+    __syncthreads();
+    const uint32_t total = scan_tile(S, R, wsum);
+    fill_tile(out, S, R, min_u, 0u, total, body_lo);
+    __syncthreads();   // LDS is reused by the next segment
+    return;
+  }
+
+  // Two tiles: 16-bit counters, repaired and merged into the workgroup's
+  // global count array, then each tile's counts are scanned in LDS.
+  for (uint32_t i = tid; i < (R + 1) / 2; i += kBBlock) S[i] = 0u;
+  if (tid < 64) S[kBSpare + tid] = 0u;
+  for (uint32_t i = tid; i < R + 2; i += kBBlock) cnt[i] = 0u;
+  __threadfence();
+  __syncthreads();
+  count_segment<V, true>(in, n, min_u, R, S, cnt);
+  __syncthreads();
+  for (uint32_t x = tid; x < R; x += kBBlock) atomicAdd(&cnt[x], (S[x >> 1] >> ((x & 1u) << 4)) & 0xffffu);
+  __threadfence();
+  __syncthreads();
+  uint32_t O = 0;
+  for (uint32_t b = 0; b < R; b += kBTile) {
+    const uint32_t w = R - b < kBTile ? R - b : kBTile;
+    for (uint32_t i = tid; i < w; i += kBBlock)
+      S[pad32(i)] = __hip_atomic_load(&cnt[b + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint32_t Nt = scan_tile(S, w, wsum);
+    if (Nt) fill_tile(out, S, w, min_u + b, O, O + Nt, body_lo);
+    O += Nt;
+    __syncthreads();
+  }
+}
+
+template <int V>
+__global__ __launch_bounds__(kBBlock) void k_batched(BatchArgs a) {
+  extern __shared__ uint32_t S[];
+  __shared__ uint32_t wsum[kBBlock / 64];
+  __shared__ uint32_t s_q;
+  uint32_t* cnt = a.scratch + (size_t)blockIdx.x * a.scratch_words;
+  for (;;) {
+    if (threadIdx.x == 0) s_q = atomicAdd(&a.counters[0], 1u);
+    __syncthreads();
+    const uint32_t q = s_q;
+    __syncthreads();
+    if (q >= a.nseg) break;
+    const rtcdf_segment_t d = a.segs[a.order[q]];
+    sort_segment<V>(d, S, wsum, cnt, a.scratch_words);
+  }
+}
+
+}  // namespace
+
+size_t batched_scratch_words(uint32_t max_range) {
+  return max_range > kBTile ? (size_t)max_range + 2 : 0;
+}
+
+hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, uint32_t* order,
+                          uint32_t* counters, uint32_t* scratch, uint32_t scratch_words, uint32_t grid,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, segs, nseg, order, counters);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)kBLdsWords * 4;
+  e = hipFuncSetAttribute((const void*)k_batched<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  BatchArgs a;
+  a.segs = segs;
+  a.nseg = nseg;
+  a.order = order;
+  a.counters = counters;
+  a.scratch = scratch;
+  a.scratch_words = scratch_words;
+  hipLaunchKernelGGL(k_batched<4>, dim3(grid), dim3(kBBlock), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace rtcdf

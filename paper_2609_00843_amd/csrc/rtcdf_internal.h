@@ -68,6 +68,12 @@ hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_
 hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t stream);
 hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream_t stream);
 
+// Batched sort (rtcdf_batched.hip).
+size_t batched_scratch_words(uint32_t max_range);
+hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, uint32_t* order,
+                          uint32_t* counters, uint32_t* scratch, uint32_t scratch_words, uint32_t grid,
+                          hipStream_t stream);
+
 // Host helpers shared by the C ABI translation units (rtcdf_api.hip).
 rtcdf_status_t device_info(DeviceInfo* out);
 bool config_valid(const rtcdf_config_t& c);

@@ -18,70 +18,13 @@
 //               (Alg. 7 with p' = p - O[t]) as 16-byte stores.
 #include <hip/hip_runtime.h>
 
+#include "rtcdf_device.h"
 #include "rtcdf_internal.h"
 
 namespace rtcdf {
 namespace {
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-
-// ---------------------------------------------------------------- wave helpers
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
-
-// Inclusive prefix sum across a 64-lane wave with DPP row shifts and row
-// broadcasts (rows of 16 lanes, then lane 15 -> next row, lane 31 -> upper half).
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  return x;
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
-  uint32_t s = wave_inclusive_scan(x);
-  return (uint32_t)__builtin_amdgcn_readlane((int)s, 63);
-}
-
-// Block-wide inclusive scan of one value per thread (blockDim.x multiple of 64,
-// at most 1024).  Returns the inclusive prefix; *total receives the block sum.
-// wsum must hold blockDim.x / 64 words of LDS.  Contains two barriers.
-__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t* wsum,
-                                                         uint32_t* total) {
-  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  uint32_t inc = wave_inclusive_scan(v);
-  if (lane == 63) wsum[wave] = inc;
-  __syncthreads();
-  if (wave == 0) {
-    uint32_t s = lane < nw ? wsum[lane] : 0u;
-    s = wave_inclusive_scan(s);
-    if (lane < nw) wsum[lane] = s;
-  }
-  __syncthreads();
-  const uint32_t before = wave ? wsum[wave - 1] : 0u;
-  *total = wsum[nw - 1];
-  __syncthreads();  // wsum may be reused by the caller right away
-  return inc + before;
-}
-
-__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* wsum) {
-  uint32_t t;
-  (void)block_inclusive_scan(v, wsum, &t);
-  return t;
-}
-
-// Number of entries of the nondecreasing a[0..len) that are <= q.
-__device__ __forceinline__ uint32_t count_le(const uint32_t* a, uint32_t len, uint32_t q) {
-  uint32_t lo = 0, hi = len;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (a[mid] <= q) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
+using namespace dev;
 
 // ------------------------------------------------------------------ histogram
 
@@ -94,80 +37,6 @@ struct HistArgs {
   uint32_t* partial;
   uint32_t* carry;
 };
-
-// Two 16-bit counters per LDS word (bin x in half x & 1 of word x >> 1).  The
-// returned old word shows whether an add of c wrapped a half; the lost 2^16
-// (and the +1 a wrap of the low half pushed into the high half) is repaired
-// exactly in the global carry array, which the reduction adds back.
-__device__ __forceinline__ void fix_u16(uint32_t old, uint32_t x, uint32_t c, uint32_t* carry,
-                                        uint32_t pass_lo) {
-  if ((x & 1u) == 0) {
-    if ((old & 0xffffu) + c > 0xffffu) {
-      const uint32_t c2 = ((old >> 16) + 1u) >> 16;  // high half wrapped by the carry
-      atomicAdd(&carry[pass_lo + x], 65536u);
-      atomicAdd(&carry[pass_lo + x + 1u], 65536u * c2 - 1u);
-    }
-  } else if ((old >> 16) + c > 0xffffu) {
-    atomicAdd(&carry[pass_lo + x], 65536u);
-  }
-}
-
-__device__ __forceinline__ void add_u16(uint32_t* S, uint32_t x, uint32_t c, uint32_t* carry,
-                                        uint32_t pass_lo) {
-  const uint32_t old = atomicAdd(&S[x >> 1], c << ((x & 1u) << 4));
-  fix_u16(old, x, c, carry, pass_lo);
-}
-
-// Counts the four keys of one vector per lane.  If every active lane of the
-// wave holds four copies of one value (all-equal or heavily skewed keys), a
-// single lane adds them with one LDS atomic instead of 4 x 64 atomics on the
-// same address.  Otherwise every key takes one LDS atomic without branching:
-// a key outside the pass adds 0 to a per-lane spare word S[spare + lane].
-// In the 16-bit form the four returning atomics are issued back to back and a
-// half that just wrapped (it held 0xffff before the +1) is repaired after a
-// single wave-wide test.
-template <bool PACKED>
-__device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32_t W,
-                                       uint32_t* carry, uint32_t pass_lo, uint32_t spare) {
-  const uint32_t x0 = (uint32_t)k.x - base, x1 = (uint32_t)k.y - base;
-  const uint32_t x2 = (uint32_t)k.z - base, x3 = (uint32_t)k.w - base;
-  const uint32_t lead = (uint32_t)__builtin_amdgcn_readfirstlane((int)x0);
-  const bool four = (x0 == lead) & (x1 == lead) & (x2 == lead) & (x3 == lead);
-  const uint64_t same = __ballot(four);
-  const uint64_t active = __ballot(1);
-  if (same == active) {
-    if (lead < W && lane_id() == (uint32_t)(__ffsll((unsigned long long)active) - 1)) {
-      const uint32_t c = 4u * (uint32_t)__popcll(active);
-      if constexpr (PACKED) add_u16(S, lead, c, carry, pass_lo);
-      else atomicAdd(&S[lead], c);
-    }
-    return;
-  }
-  const uint32_t sp = spare + lane_id();
-  if constexpr (PACKED) {
-    const uint32_t s0 = (x0 & 1u) << 4, s1 = (x1 & 1u) << 4, s2 = (x2 & 1u) << 4, s3 = (x3 & 1u) << 4;
-    const uint32_t o0 = atomicAdd(&S[x0 < W ? x0 >> 1 : sp], x0 < W ? 1u << s0 : 0u);
-    const uint32_t o1 = atomicAdd(&S[x1 < W ? x1 >> 1 : sp], x1 < W ? 1u << s1 : 0u);
-    const uint32_t o2 = atomicAdd(&S[x2 < W ? x2 >> 1 : sp], x2 < W ? 1u << s2 : 0u);
-    const uint32_t o3 = atomicAdd(&S[x3 < W ? x3 >> 1 : sp], x3 < W ? 1u << s3 : 0u);
-    // The spare words only ever receive 0, so they never look wrapped.
-    const bool w0 = ((o0 >> s0) & 0xffffu) == 0xffffu && x0 < W;
-    const bool w1 = ((o1 >> s1) & 0xffffu) == 0xffffu && x1 < W;
-    const bool w2 = ((o2 >> s2) & 0xffffu) == 0xffffu && x2 < W;
-    const bool w3 = ((o3 >> s3) & 0xffffu) == 0xffffu && x3 < W;
-    if (__ballot(w0 | w1 | w2 | w3)) {
-      if (w0) fix_u16(o0, x0, 1u, carry, pass_lo);
-      if (w1) fix_u16(o1, x1, 1u, carry, pass_lo);
-      if (w2) fix_u16(o2, x2, 1u, carry, pass_lo);
-      if (w3) fix_u16(o3, x3, 1u, carry, pass_lo);
-    }
-  } else {
-    atomicAdd(&S[x0 < W ? x0 : sp], x0 < W ? 1u : 0u);
-    atomicAdd(&S[x1 < W ? x1 : sp], x1 < W ? 1u : 0u);
-    atomicAdd(&S[x2 < W ? x2 : sp], x2 < W ? 1u : 0u);
-    atomicAdd(&S[x3 < W ? x3 : sp], x3 < W ? 1u : 0u);
-  }
-}
 
 template <int ITEMS, bool PACKED, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
@@ -327,20 +196,6 @@ __device__ __forceinline__ uint32_t first_chunk_at_or_after(uint64_t P, uint32_t
     if (q > k) k = q;
   }
   return k < nchunks ? (uint32_t)k : nchunks;
-}
-
-// Local CDFs are kept in LDS with one padding word per 32 entries, so the
-// per-thread segments of the blocked scan fall into distinct banks.
-__device__ __forceinline__ uint32_t pad32(uint32_t i) { return i + (i >> 5); }
-
-// Number of entries of the nondecreasing padded array C[0..len) that are <= q.
-__device__ __forceinline__ uint32_t count_le_pad(const uint32_t* C, uint32_t len, uint32_t q) {
-  uint32_t lo = 0, hi = len;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (C[pad32(mid)] <= q) lo = mid + 1; else hi = mid;
-  }
-  return lo;
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {

@@ -248,3 +248,43 @@ def stream_copy(src, dst, stream=None):
     if dst.numel() * dst.element_size() != nb:
         raise ValueError("size mismatch")
     _check(lib.rtcdf_stream_copy(_ptr(src), _ptr(dst), nb, _stream_ptr(stream)), "rtcdf_stream_copy")
+
+
+# ---- batched sort
+
+def make_segments(pairs, device="cuda"):
+    """Device descriptor array and host bounds for rtcdf_sort_batched.
+
+    pairs: iterable of (keys_in, keys_out, minVal, maxVal) with int32 CUDA
+    tensors.  Returns (descriptors as a uint8 CUDA tensor, BatchBounds, count)."""
+    import torch
+    pairs = list(pairs)
+    arr = (Segment * max(len(pairs), 1))()
+    total, max_n, max_r = 0, 0, 0
+    for i, (a, b, lo, hi) in enumerate(pairs):
+        R = int(hi) - int(lo)
+        if R < 1 or R > BATCH_MAX_RANGE or lo < -(2 ** 31) or hi > 2 ** 31:
+            raise ValueError(f"segment {i}: range [{lo}, {hi}) not supported by the batched sort")
+        n = a.numel()
+        arr[i] = Segment(a.data_ptr() if n else 0, b.data_ptr() if n else 0, n, int(lo), R, 0)
+        total += n
+        max_n = max(max_n, n)
+        max_r = max(max_r, R)
+    raw = bytes(arr)[: ctypes.sizeof(Segment) * len(pairs)]
+    host = torch.frombuffer(bytearray(raw), dtype=torch.uint8) if raw else torch.zeros(0, dtype=torch.uint8)
+    return host.to(device), BatchBounds(total, max_n, max_r), len(pairs)
+
+
+def batched_workspace_bytes(num_segments: int, bounds: BatchBounds) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib.rtcdf_batched_workspace_bytes(int(num_segments), ctypes.byref(bounds), ctypes.byref(out)),
+           "rtcdf_batched_workspace_bytes")
+    return int(out.value)
+
+
+def sort_batched(d_segments, num_segments: int, bounds: BatchBounds, workspace, stream=None):
+    """rtcdf_sort_batched on a device descriptor array (uint8 CUDA tensor)."""
+    st = lib.rtcdf_sort_batched(_ptr(d_segments), int(num_segments), ctypes.byref(bounds),
+                                _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                _stream_ptr(stream))
+    _check(st, "rtcdf_sort_batched")

@@ -24,7 +24,7 @@ def r():
 
 def test_every_declared_symbol_is_exported(r):
     names = _declared()
-    assert "rtcdf_sort" in names and "rtcdf_sort_ws" in names
+    assert "rtcdf_sort" in names and "rtcdf_sort_batched" in names
     missing = [n for n in names if not hasattr(r.lib, n)]
     assert not missing, f"declared but not exported: {missing}"
 
@@ -83,3 +83,27 @@ def test_load_fails_loudly_without_library(tmp_path):
     (pkg / "rtcdf.py").write_text(open(os.path.join(ROOT, "paper_2609_00843_amd", "rtcdf.py")).read())
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert res.returncode != 0 and "not built" in res.stderr
+
+
+def test_batched_argument_errors(r):
+    L = r.lib
+    b = r.BatchBounds(10, 10, 100)
+    out = ctypes.c_size_t(0)
+    assert L.rtcdf_batched_workspace_bytes(4, None, ctypes.byref(out)) == r.INVALID_VALUE
+    assert L.rtcdf_batched_workspace_bytes(4, ctypes.byref(b), None) == r.INVALID_VALUE
+    big = r.BatchBounds(10, 10, (1 << 16) + 1)
+    assert L.rtcdf_batched_workspace_bytes(4, ctypes.byref(big), ctypes.byref(out)) == r.RANGE_TOO_LARGE
+    ws = ctypes.c_void_p(1 << 20)
+    assert L.rtcdf_sort_batched(P_IN, 0, ctypes.byref(b), ws, 1 << 20, None) == r.SUCCESS     # empty batch
+    assert L.rtcdf_sort_batched(None, 4, ctypes.byref(b), ws, 1 << 20, None) == r.INVALID_VALUE
+    assert L.rtcdf_sort_batched(P_IN, 4, None, ws, 1 << 20, None) == r.INVALID_VALUE
+    assert L.rtcdf_sort_batched(P_IN, 4, ctypes.byref(b), None, 1 << 20, None) == r.INVALID_VALUE
+    assert L.rtcdf_sort_batched(P_IN, 4, ctypes.byref(b), ctypes.c_void_p((1 << 20) + 64), 1 << 20,
+                                None) == r.INVALID_VALUE                                       # ws not 256-aligned
+    assert L.rtcdf_sort_batched(P_IN, 4, ctypes.byref(big), ws, 1 << 20, None) == r.RANGE_TOO_LARGE
+
+
+def test_segment_layout(r):
+    assert ctypes.sizeof(r.Segment) == 32
+    assert ctypes.sizeof(r.BatchBounds) == 16
+    assert ctypes.sizeof(r.Config) == 16

@@ -1,0 +1,161 @@
+"""GPU parity of the batched sort: every segment equals the oracle's sort of
+that segment, memory outside the outputs is untouched, skipped descriptors
+leave their output alone, and HIP-graph replays reproduce the eager result."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_00843_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GUARD = 0x7A7A7A7A
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def r():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_00843_amd import rtcdf
+    return rtcdf
+
+
+def _build(specs, seed, inplace_every=0):
+    """Carve every segment's input and output out of two big buffers at
+    arbitrary 4-byte offsets (so segments start at every alignment), with
+    guard words in between.  specs: list of (n, minVal, R, dist)."""
+    rng = np.random.default_rng(seed)
+    host_in, offs_in, offs_out = [], [], []
+    pos_in = pos_out = 0
+    arrays = []
+    for i, (n, lo, R, dist) in enumerate(specs):
+        A = inputs.make(dist, n, lo, lo + R, inputs.case_seed(40, seed * 100000 + i)) if n else \
+            np.zeros(0, dtype=np.int32)
+        arrays.append(A)
+        pos_in += int(rng.integers(0, 4)) + 1
+        pos_out += int(rng.integers(0, 4)) + 1
+        offs_in.append(pos_in)
+        offs_out.append(pos_out)
+        pos_in += n
+        pos_out += n
+    bin_ = np.full(pos_in + 8, GUARD, dtype=np.int32)
+    for A, o in zip(arrays, offs_in):
+        bin_[o:o + A.size] = A
+    din = torch.from_numpy(bin_).cuda()
+    dout = torch.full((pos_out + 8,), GUARD, dtype=torch.int32, device="cuda")
+    pairs = []
+    for i, ((n, lo, R, _), oi, oo) in enumerate(zip(specs, offs_in, offs_out)):
+        a = din[oi:oi + n]
+        b = a if (inplace_every and i % inplace_every == 0) else dout[oo:oo + n]
+        pairs.append((a, b, lo, lo + R))
+    return arrays, pairs, din, dout, offs_out
+
+
+def _check(arrays, specs, pairs, dout, offs_out):
+    full = dout.cpu().numpy()
+    mask = np.ones(full.size, dtype=bool)
+    for A, (n, lo, R, _), (a, b, _, _), oo in zip(arrays, specs, pairs, offs_out):
+        want = oracle.sort(A, lo, lo + R) if n else A
+        got = b.cpu().numpy()
+        assert np.array_equal(got, want), f"segment n={n} R={R} differs at {np.flatnonzero(got != want)[:5]}"
+        if b.data_ptr() != a.data_ptr():
+            mask[oo:oo + n] = False
+    assert np.all(full[mask] == GUARD), "memory outside the outputs was written"
+
+
+def _run(r, pairs):
+    d, bounds, k = r.make_segments(pairs)
+    ws = torch.empty(r.batched_workspace_bytes(k, bounds), dtype=torch.uint8, device="cuda")
+    ws.fill_(0xCD)
+    r.sort_batched(d, k, bounds, ws)
+    torch.cuda.synchronize()
+    return d, bounds, k, ws
+
+
+def test_edge_segments(r):
+    specs = []
+    for n in (0, 1, 2, 3, 4, 5, 7, 9, 17, 255, 256, 257, 1023, 1025, 4099):
+        for R in (1, 2, 3, 16, 127, 4096, 32767, 32768, 32769, 65535, 65536):
+            lo = -(2 ** 31) if (n + R) % 5 == 0 else int(np.random.default_rng(n * R).integers(-10 ** 6, 10 ** 6))
+            specs.append((n, lo, R, "uniform"))
+    _say(f"edge segments: {len(specs)}")
+    arrays, pairs, din, dout, offs = _build(specs, 1, inplace_every=7)
+    _run(r, pairs)
+    _check(arrays, specs, pairs, dout, offs)
+
+
+def test_skewed_and_large(r):
+    """All-equal and heavy segments above 65535 keys in both counter layouts."""
+    specs = [(200_000, -5, 65536, "all_equal"), (300_001, 100, 40000, "all_equal"),
+             (150_000, 0, 32768, "all_equal"), (1_000_000, -7, 65536, "normal"),
+             (999_999, 3, 50000, "zipf"), (700_000, -1_000_000, 16, "uniform"),
+             (1_000_000, 12, 65536, "uniform")]
+    _say("skewed/large")
+    arrays, pairs, din, dout, offs = _build(specs, 2)
+    _run(r, pairs)
+    _check(arrays, specs, pairs, dout, offs)
+
+
+def test_batch_workload_sample(r):
+    """The first 512 arrays of the 4096-array batch workload (n log-uniform in
+    [1e3, 1e6], minVal uniform in [-1e6, 1e6], R log-uniform in [2^4, 2^16],
+    uniform / normal sd R/6 / all-equal keys)."""
+    segs = inputs.batched_segments(4096)[:512]
+    specs = [(s["n"], s["minVal"], s["maxVal"] - s["minVal"], s["dist"]) for s in segs]
+    _say(f"workload sample: {len(specs)} segments, {sum(s[0] for s in specs)} keys")
+    arrays, pairs, din, dout, offs = _build(specs, 3)
+    _run(r, pairs)
+    _check(arrays, specs, pairs, dout, offs)
+
+
+def test_skipped_descriptors(r):
+    """range 0 or above the bounds, and NULL pointers, are skipped."""
+    import ctypes
+    A = inputs.uniform(1000, 0, 100, 5)
+    din = torch.from_numpy(A).cuda()
+    dout = torch.full((4000,), GUARD, dtype=torch.int32, device="cuda")
+    segs = (r.Segment * 4)()
+    segs[0] = r.Segment(din.data_ptr(), dout.data_ptr(), 1000, 0, 0, 0)               # range 0
+    segs[1] = r.Segment(din.data_ptr(), dout[1000:].data_ptr(), 1000, 0, 70000, 0)    # > max
+    segs[2] = r.Segment(0, dout[2000:].data_ptr(), 1000, 0, 100, 0)                   # NULL input
+    segs[3] = r.Segment(din.data_ptr(), dout[3000:].data_ptr(), 1000, 0, 100, 0)      # valid
+    d = torch.frombuffer(bytearray(bytes(segs)), dtype=torch.uint8).cuda()
+    bounds = r.BatchBounds(4000, 1000, 100)
+    ws = torch.empty(r.batched_workspace_bytes(4, bounds), dtype=torch.uint8, device="cuda")
+    _say("skipped descriptors")
+    r.sort_batched(d, 4, bounds, ws)
+    torch.cuda.synchronize()
+    out = dout.cpu().numpy()
+    assert np.all(out[:3000] == GUARD)
+    assert np.array_equal(out[3000:], oracle.sort(A, 0, 100))
+
+
+def test_graph_replay(r):
+    segs = inputs.batched_segments(64, seed=77)
+    specs = [(s["n"], s["minVal"], s["maxVal"] - s["minVal"], s["dist"]) for s in segs]
+    arrays, pairs, din, dout, offs = _build(specs, 4)
+    d, bounds, k = r.make_segments(pairs)
+    ws = torch.empty(r.batched_workspace_bytes(k, bounds), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    _say("graph capture")
+    with torch.cuda.stream(s):
+        r.sort_batched(d, k, bounds, ws, stream=s)     # eager warm-up (sets kernel attributes)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        r.sort_batched(d, k, bounds, ws, stream=s)
+    for rep in range(4):
+        dout.fill_(GUARD)          # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _say(f"replay {rep}")
+        _check(arrays, specs, pairs, dout, offs)
