@@ -189,6 +189,91 @@ typedef enum rtcdf_config_mode {
 rtcdf_status_t rtcdf_set_config_mode(int mode);
 int rtcdf_get_config_mode(void);
 
+/* The tuning grid: tile width T in {2^10 .. 2^15} x items per thread in
+ * {4, 8, 16} x blocks per tile in {1, 2, 4}; index i = 9 * log2(T / 1024) +
+ * 3 * log2(items / 4) + log2(blocks).  Points with T * 4 * blocks > 160 KiB
+ * are invalid (45 of the 54 are valid).  configs / valid: host arrays of
+ * RTCDF_GRID_SIZE entries, either may be NULL. */
+#define RTCDF_GRID_SIZE 54
+rtcdf_status_t rtcdf_config_grid(rtcdf_config_t* configs, uint8_t* valid);
+
+/* Exhaustive autotuner: times every valid grid configuration of the plain
+ * sort of keys_in into keys_out (device arrays, as rtcdf_sort_with_config)
+ * with HIP events on `stream`: `warmup` untimed sorts, then the median of
+ * `reps` timed sorts.  times_ms: host array of RTCDF_GRID_SIZE (invalid
+ * points get -1); *best (may be NULL) receives the fastest configuration.
+ * Synchronises the stream. */
+rtcdf_status_t rtcdf_autotune(const int32_t* keys_in, int32_t* keys_out, size_t n, int64_t minVal,
+                              int64_t maxVal, uint32_t warmup, uint32_t reps, float* times_ms,
+                              rtcdf_config_t* best, hipStream_t stream);
+
+/* TUNED mode table: a text file of lines "log2n log2R T items blocks" (the
+ * best configuration measured for arrays of that size and range; '#' starts
+ * a comment line).  rtcdf_sort then uses the row nearest to (log2 n, log2 R). */
+rtcdf_status_t rtcdf_load_tuned_table(const char* path);
+
+/* LEARNED mode model: a file written by paper_2609_00843_amd/learn.py
+ * ("RTCDFMLP", version 1, sizes, training ranges of log2 n and log2 R, feature
+ * mean and sd, the RTCDF_MLP_PARAMS weights, the valid-configuration mask).
+ * Arrays outside the training ranges (by more than half an octave) fall back
+ * to TUNED, then DEFAULT.  rtcdf_unload_model forgets it. */
+rtcdf_status_t rtcdf_load_model(const char* path);
+rtcdf_status_t rtcdf_unload_model(void);
+
+/* ---- Learned picker kernels (the network is trained by these) ---------- */
+
+/* Sketch features of an array: [log2 n, log2 R, fraction of S =
+ * min(RTCDF_SKETCH_SAMPLES, n) evenly spaced sample keys (key at position
+ * floor(i * n / S)) in each of RTCDF_SKETCH_BINS equal-width bins of the
+ * range].  d_features: device float[RTCDF_MLP_INPUTS]. */
+#define RTCDF_SKETCH_BINS 32
+#define RTCDF_SKETCH_SAMPLES 4096
+#define RTCDF_MLP_INPUTS 34
+#define RTCDF_MLP_HIDDEN 64
+#define RTCDF_MLP_OUTPUTS 54
+#define RTCDF_MLP_PARAMS 9910
+rtcdf_status_t rtcdf_sketch(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,
+                            float* d_features, hipStream_t stream);
+
+/* FP32 MLP y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 (34 -> 64 -> 64 -> 54).
+ * d_params: device float[RTCDF_MLP_PARAMS] laid out W1[64][34] b1 W2[64][64]
+ * b2 W3[54][64] b3.  d_X: batch x 34 (row-major), d_Y: batch x 54. */
+rtcdf_status_t rtcdf_mlp_forward(const float* d_params, const float* d_X, uint32_t batch, float* d_Y,
+                                 hipStream_t stream);
+
+/* Device workspace for rtcdf_mlp_gradient / rtcdf_mlp_train at this batch. */
+rtcdf_status_t rtcdf_mlp_workspace_bytes(uint32_t batch, size_t* bytes);
+
+/* Gradient of the masked mean squared error sum(M (Y - T)^2) / sum(M) over
+ * the batch (d_T, d_M: batch x 54; M is 0/1) into d_grad[RTCDF_MLP_PARAMS];
+ * the loss into d_loss[0] if not NULL.  Deterministic (fixed-order sums).
+ * Reads back the mask total (synchronises the stream). */
+rtcdf_status_t rtcdf_mlp_gradient(const float* d_params, const float* d_X, const float* d_T,
+                                  const float* d_M, uint32_t batch, float* d_grad, float* d_loss,
+                                  void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* One Adam step (Kingma & Ba) at step t >= 1 on the flat parameter array with
+ * moments d_m, d_v (device float[RTCDF_MLP_PARAMS], updated in place). */
+rtcdf_status_t rtcdf_mlp_adam_step(float* d_params, const float* d_grad, float* d_m, float* d_v,
+                                   uint32_t t, float lr, float beta1, float beta2, float eps,
+                                   hipStream_t stream);
+
+/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8) numbered
+ * t0 + 1 .. t0 + steps; the loss before each step goes to
+ * d_loss_history[k] when not NULL. */
+rtcdf_status_t rtcdf_mlp_train(float* d_params, float* d_m, float* d_v, uint32_t t0, const float* d_X,
+                               const float* d_T, const float* d_M, uint32_t batch, uint32_t steps,
+                               float lr, void* d_ws, size_t ws_bytes, float* d_loss_history,
+                               hipStream_t stream);
+
+/* Sketch -> standardised features ((f - mean) / sd, d_norm = mean[34] then
+ * sd[34]) -> MLP -> index of the smallest prediction among d_valid[54] != 0
+ * (lowest index on ties) into d_index[0]; predictions into d_pred[54] if not
+ * NULL.  One small launch, no host synchronisation. */
+rtcdf_status_t rtcdf_mlp_pick(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,
+                              const float* d_params, const float* d_norm, const uint8_t* d_valid,
+                              uint32_t* d_index, float* d_pred, hipStream_t stream);
+
 /* The configuration rtcdf_sort would use for (n, R) under the current mode,
  * written to *cfg (learned mode needs the keys for its sketch; keys_in may
  * be NULL in the other modes).  Synchronises `stream` in learned mode. */

@@ -18,7 +18,7 @@ namespace rtcdf {
 
 thread_local int g_last_hip_error = 0;
 
-static rtcdf_status_t hip_fail(hipError_t e) {
+rtcdf_status_t hip_fail(hipError_t e) {
   g_last_hip_error = (int)e;
   return RTCDF_ERROR_HIP;
 }

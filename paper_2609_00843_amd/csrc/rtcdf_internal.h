@@ -17,6 +17,15 @@ constexpr uint32_t kFillBlock = 256;        // threads per output workgroup
 constexpr uint32_t kScanBlock = 1024;       // threads per local-CDF workgroup
 constexpr uint32_t kReduceBlock = 1024;     // threads per reduction workgroup
 
+// Learned picker: sketch and MLP sizes (see include/rtcdf.h).
+constexpr int kSketchBins = 32;
+constexpr uint32_t kSketchSamples = 4096;
+constexpr int kMlpIn = 2 + kSketchBins;      // log2 n, log2 R, bin fractions
+constexpr int kMlpHidden = 64;
+constexpr int kMlpOut = 54;                  // the configuration grid
+constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
+                           kMlpOut * kMlpHidden + kMlpOut;
+
 // Everything one plain sort needs, derived on the host from (n, range, config,
 // pointer alignment, device).  Workspace offsets are in bytes from the base.
 struct Plan {
@@ -74,8 +83,23 @@ hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, uint32_t* 
                           uint32_t* counters, uint32_t* scratch, uint32_t scratch_words, uint32_t grid,
                           hipStream_t stream);
 
+// Learned picker (rtcdf_mlp.hip).
+hipError_t launch_sketch(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R, uint32_t samples,
+                         float* feat, hipStream_t s);
+hipError_t launch_mlp_forward(const float* P, const float* X, uint32_t B, float* Z1, float* Z2, float* Y,
+                              hipStream_t s);
+hipError_t launch_mlp_grad(const float* P, const float* X, const float* T, const float* M, uint32_t B,
+                           float inv_count, float* G, float* loss_dev, float* scratch, hipStream_t s);
+size_t mlp_grad_scratch_floats(uint32_t B);
+hipError_t launch_adam(float* P, const float* G, float* Mo, float* Vo, float lr, float b1, float b2,
+                       float eps, uint32_t t, hipStream_t s);
+hipError_t launch_pick(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R, uint32_t samples,
+                       const float* P, const float* norm, const uint8_t* valid, uint32_t* out_index,
+                       float* out_pred, hipStream_t s);
+
 // Host helpers shared by the C ABI translation units (rtcdf_api.hip).
 rtcdf_status_t device_info(DeviceInfo* out);
+rtcdf_status_t hip_fail(hipError_t e);
 bool config_valid(const rtcdf_config_t& c);
 void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& cfg,
                const int32_t* in, const int32_t* out, const DeviceInfo& dev, Plan* p);

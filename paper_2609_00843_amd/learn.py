@@ -1,0 +1,204 @@
+"""Training and evaluation of the learned configuration picker.
+
+Inputs per array: the 34 sketch features (log2 n, log2 R, 32 bin fractions)
+measured by the GPU sketch kernel.  Targets: for every valid grid
+configuration, log(median runtime) minus the array's mean over its valid
+configurations (only the ordering matters for the pick, and centring removes
+the dependence of the scale on n).  The network is trained on the GPU by the
+library's own kernels (rtcdf_mlp_train: full-batch Adam on the masked mean
+squared error).
+
+    python -m paper_2609_00843_amd.learn train --db TRAIN.jsonl --out MODEL.bin
+    python -m paper_2609_00843_amd.learn evaluate --db TEST.jsonl --model MODEL.bin
+
+A checkpoint (.npz next to the model: weights, Adam moments, step, feature
+normalisation, loss history) lets training resume.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import struct
+import sys
+
+import numpy as np
+
+from . import tune
+
+SIZES = (34, 64, 64, 54)
+
+
+def dataset(rows):
+    _, valid = tune.grid()
+    X = np.array([r["features"] for r in rows], dtype=np.float64)
+    T = np.zeros((len(rows), 54))
+    M = np.zeros((len(rows), 54))
+    for i, r in enumerate(rows):
+        t = np.array(r["times_ms"], dtype=np.float64)
+        ok = np.array(valid) & (t > 0)
+        lt = np.log(np.where(ok, t, 1.0))
+        T[i] = np.where(ok, lt - lt[ok].mean(), 0.0)
+        M[i] = ok
+    return X, T, M
+
+
+def normalisation(X):
+    mu = X.mean(axis=0)
+    sd = np.maximum(X.std(axis=0), 1e-3)
+    return mu, sd
+
+
+def init_params(seed: int):
+    """He-initialised weights from a seeded generator (flat library layout)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(3):
+        parts.append(rng.normal(0.0, math.sqrt(2.0 / SIZES[i]), size=(SIZES[i + 1], SIZES[i])).ravel())
+        parts.append(np.zeros(SIZES[i + 1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def save_model(path: str, params, mu, sd, ranges):
+    _, valid = tune.grid()
+    with open(path, "wb") as f:
+        f.write(b"RTCDFMLP")
+        f.write(struct.pack("<5I", 1, 34, 64, 54, 9910))
+        f.write(struct.pack("<4f", *ranges))
+        f.write(np.asarray(mu, dtype=np.float32).tobytes())
+        f.write(np.asarray(sd, dtype=np.float32).tobytes())
+        f.write(np.asarray(params, dtype=np.float32).tobytes())
+        f.write(bytes(1 if v else 0 for v in valid))
+
+
+def train(rows, steps: int = 6000, lr: float = 3e-3, seed: int = 2609, chunk: int = 500,
+          checkpoint: str = None, log=print):
+    import torch
+    from . import rtcdf
+    X, T, M = dataset(rows)
+    mu, sd = normalisation(X)
+    Xn = (X - mu) / sd
+    dev = torch.device("cuda:0")
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    Xd, Td, Md = f32(Xn), f32(T), f32(M)
+    state = None
+    if checkpoint and os.path.exists(checkpoint):
+        state = np.load(checkpoint)
+    P = f32(state["params"] if state is not None else init_params(seed))
+    m = f32(state["m"]) if state is not None else torch.zeros_like(P)
+    v = f32(state["v"]) if state is not None else torch.zeros_like(P)
+    t = int(state["t"]) if state is not None else 0
+    hist = list(state["loss"]) if state is not None else []
+    ws = rtcdf.mlp_workspace(X.shape[0], dev)
+    while t < steps:
+        k = min(chunk, steps - t)
+        lh = torch.empty(k, dtype=torch.float32, device=dev)
+        rtcdf.mlp_train(P, m, v, t, Xd, Td, Md, k, lr, ws=ws, loss_history=lh)
+        t += k
+        hist.extend(lh.cpu().tolist())
+        log(f"[learn] step {t}/{steps} loss {hist[-1]:.5f}")
+        if checkpoint:
+            np.savez(checkpoint, params=P.cpu().numpy(), m=m.cpu().numpy(), v=v.cpu().numpy(), t=t,
+                     mu=mu, sd=sd, loss=np.array(hist))
+    ranges = (float(X[:, 0].min()), float(X[:, 0].max()), float(X[:, 1].min()), float(X[:, 1].max()))
+    return P.cpu().numpy(), mu, sd, ranges, hist
+
+
+def predict(params, mu, sd, X):
+    """Network outputs for feature rows X, computed by the library's kernel."""
+    import torch
+    from . import rtcdf
+    dev = torch.device("cuda:0")
+    Xn = torch.from_numpy(((X - mu) / sd).astype(np.float32)).to(dev)
+    P = torch.from_numpy(np.asarray(params, dtype=np.float32)).to(dev)
+    return rtcdf.mlp_forward(P, Xn).cpu().numpy()
+
+
+def load_model_file(path: str):
+    with open(path, "rb") as f:
+        raw = f.read()
+    assert raw[:8] == b"RTCDFMLP"
+    o = 8 + 20
+    ranges = struct.unpack("<4f", raw[o:o + 16])
+    o += 16
+    mu = np.frombuffer(raw, dtype=np.float32, count=34, offset=o).astype(np.float64)
+    o += 136
+    sd = np.frombuffer(raw, dtype=np.float32, count=34, offset=o).astype(np.float64)
+    o += 136
+    params = np.frombuffer(raw, dtype=np.float32, count=9910, offset=o).copy()
+    return params, mu, sd, ranges
+
+
+def evaluate(rows, model_path: str):
+    """Regret of the learned pick against the exhaustive optimum of the same
+    (independent) timing run, and its gain over the static default table."""
+    from . import rtcdf
+    params, mu, sd, _ = load_model_file(model_path)
+    pts, valid = tune.grid()
+    X = np.array([r["features"] for r in rows], dtype=np.float64)
+    Y = predict(params, mu, sd, X)
+    idx_of = {p: i for i, p in enumerate(pts)}
+    old_mode = rtcdf.get_config_mode()
+    rtcdf.set_config_mode(rtcdf.CONFIG_DEFAULT)
+    regrets, gains, per = [], [], []
+    try:
+        for r, y in zip(rows, Y):
+            t = np.array(r["times_ms"])
+            ok = np.array(valid) & (t > 0)
+            pick = min((y[j], j) for j in range(54) if ok[j])[1]
+            static = idx_of[rtcdf.pick_config(r["n"], r["minVal"], r["minVal"] + r["R"]).as_tuple()]
+            best = float(t[ok].min())
+            regrets.append(t[pick] / best - 1.0)
+            gains.append(t[static] / t[pick])
+            per.append({"key": r["key"], "dist": r["dist"], "n": r["n"], "R": r["R"], "pick": pts[pick],
+                        "static": pts[static], "t_pick": float(t[pick]), "t_static": float(t[static]),
+                        "t_best": best})
+    finally:
+        rtcdf.set_config_mode(old_mode)
+    reg = np.array(regrets)
+    res = {"arrays": len(rows),
+           "regret_mean": float(reg.mean()), "regret_median": float(np.median(reg)),
+           "regret_p95": float(np.percentile(reg, 95)), "regret_max": float(reg.max()),
+           "gain_geomean_vs_static": float(np.exp(np.mean(np.log(gains)))),
+           "static_regret_mean": float(np.mean([p["t_static"] / p["t_best"] - 1 for p in per]))}
+    by_dist = {}
+    for p, g, rg in zip(per, gains, regrets):
+        by_dist.setdefault(p["dist"], []).append((g, rg))
+    res["by_dist"] = {d: {"gain_geomean": float(np.exp(np.mean(np.log([g for g, _ in v])))),
+                          "regret_mean": float(np.mean([rg for _, rg in v])), "arrays": len(v)}
+                      for d, v in by_dist.items()}
+    return res, per
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--db", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--steps", type=int, default=6000)
+    t.add_argument("--lr", type=float, default=3e-3)
+    t.add_argument("--seed", type=int, default=2609)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--db", required=True)
+    e.add_argument("--model", required=True)
+    e.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    if args.cmd == "train":
+        rows = tune.load_db(args.db)
+        params, mu, sd, ranges, hist = train(rows, steps=args.steps, lr=args.lr, seed=args.seed,
+                                             checkpoint=os.path.splitext(args.out)[0] + "_ckpt.npz")
+        save_model(args.out, params, mu, sd, ranges)
+        print(json.dumps({"rows": len(rows), "final_loss": hist[-1], "first_loss": hist[0],
+                          "model": args.out}))
+    else:
+        res, per = evaluate(tune.load_db(args.db), args.model)
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump({"summary": res, "arrays": per}, f)
+        print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

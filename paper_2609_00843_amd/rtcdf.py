@@ -288,3 +288,131 @@ def sort_batched(d_segments, num_segments: int, bounds: BatchBounds, workspace, 
                                 _ptr(workspace), workspace.numel() * workspace.element_size(),
                                 _stream_ptr(stream))
     _check(st, "rtcdf_sort_batched")
+
+
+# ---- configuration grid, autotuner, learned picker
+
+GRID_SIZE = 54
+MLP_INPUTS, MLP_HIDDEN, MLP_OUTPUTS, MLP_PARAMS = 34, 64, 54, 9910
+SKETCH_BINS, SKETCH_SAMPLES = 32, 4096
+
+_fp = ctypes.c_void_p
+for _name, _args in {
+    "rtcdf_config_grid": [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_uint8)],
+    "rtcdf_autotune": [_vp, _vp, _sz, _i64, _i64, ctypes.c_uint32, ctypes.c_uint32,
+                       ctypes.POINTER(ctypes.c_float), _cfgp, _vp],
+    "rtcdf_load_tuned_table": [ctypes.c_char_p],
+    "rtcdf_load_model": [ctypes.c_char_p],
+    "rtcdf_unload_model": [],
+    "rtcdf_sketch": [_vp, _sz, _i64, _i64, _fp, _vp],
+    "rtcdf_mlp_forward": [_fp, _fp, ctypes.c_uint32, _fp, _vp],
+    "rtcdf_mlp_workspace_bytes": [ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)],
+    "rtcdf_mlp_gradient": [_fp, _fp, _fp, _fp, ctypes.c_uint32, _fp, _fp, _vp, _sz, _vp],
+    "rtcdf_mlp_adam_step": [_fp, _fp, _fp, _fp, ctypes.c_uint32, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, ctypes.c_float, _vp],
+    "rtcdf_mlp_train": [_fp, _fp, _fp, ctypes.c_uint32, _fp, _fp, _fp, ctypes.c_uint32,
+                        ctypes.c_uint32, ctypes.c_float, _vp, _sz, _fp, _vp],
+    "rtcdf_mlp_pick": [_vp, _sz, _i64, _i64, _fp, _fp, _vp, _vp, _fp, _vp],
+}.items():
+    if hasattr(lib, _name):
+        getattr(lib, _name).argtypes = _args
+        getattr(lib, _name).restype = ctypes.c_int
+
+
+def config_grid():
+    """[(T, items, blocks)] * 54 and the validity mask."""
+    cfgs = (Config * GRID_SIZE)()
+    valid = (ctypes.c_uint8 * GRID_SIZE)()
+    _check(lib.rtcdf_config_grid(cfgs, valid), "rtcdf_config_grid")
+    return [c.as_tuple() for c in cfgs], [bool(v) for v in valid]
+
+
+def autotune(keys_in, minVal: int, maxVal: int, keys_out=None, warmup: int = 2, reps: int = 5,
+             stream=None):
+    """Median ms of every grid configuration (-1 for invalid ones) and the best config."""
+    import torch
+    if keys_out is None:
+        keys_out = torch.empty_like(keys_in)
+    times = (ctypes.c_float * GRID_SIZE)()
+    best = Config()
+    _check(lib.rtcdf_autotune(_ptr(keys_in), _ptr(keys_out), keys_in.numel(), int(minVal), int(maxVal),
+                              int(warmup), int(reps), times, ctypes.byref(best), _stream_ptr(stream)),
+           "rtcdf_autotune")
+    return [float(t) for t in times], best
+
+
+def load_tuned_table(path: str):
+    _check(lib.rtcdf_load_tuned_table(os.fsencode(path)), "rtcdf_load_tuned_table")
+
+
+def load_model(path: str):
+    _check(lib.rtcdf_load_model(os.fsencode(path)), "rtcdf_load_model")
+
+
+def unload_model():
+    _check(lib.rtcdf_unload_model(), "rtcdf_unload_model")
+
+
+def sketch(keys_in, minVal: int, maxVal: int, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty(MLP_INPUTS, dtype=torch.float32, device=keys_in.device)
+    _check(lib.rtcdf_sketch(_ptr(keys_in), keys_in.numel(), int(minVal), int(maxVal), _ptr(out),
+                            _stream_ptr(stream)), "rtcdf_sketch")
+    return out
+
+
+def mlp_forward(params, X, stream=None):
+    import torch
+    B = X.shape[0]
+    Y = torch.empty((B, MLP_OUTPUTS), dtype=torch.float32, device=X.device)
+    _check(lib.rtcdf_mlp_forward(_ptr(params), _ptr(X), B, _ptr(Y), _stream_ptr(stream)),
+           "rtcdf_mlp_forward")
+    return Y
+
+
+def mlp_workspace(batch: int, device="cuda"):
+    import torch
+    nb = ctypes.c_size_t(0)
+    _check(lib.rtcdf_mlp_workspace_bytes(int(batch), ctypes.byref(nb)), "rtcdf_mlp_workspace_bytes")
+    return torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+
+
+def mlp_gradient(params, X, T, M, ws=None, stream=None):
+    """(gradient, loss) of the masked MSE at params."""
+    import torch
+    B = X.shape[0]
+    if ws is None:
+        ws = mlp_workspace(B, X.device)
+    G = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+    L = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(lib.rtcdf_mlp_gradient(_ptr(params), _ptr(X), _ptr(T), _ptr(M), B, _ptr(G), _ptr(L), _ptr(ws),
+                                  ws.numel(), _stream_ptr(stream)), "rtcdf_mlp_gradient")
+    return G, L
+
+
+def mlp_adam_step(params, grad, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib.rtcdf_mlp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), lr, beta1, beta2,
+                                   eps, _stream_ptr(stream)), "rtcdf_mlp_adam_step")
+
+
+def mlp_train(params, m, v, t0: int, X, T, M, steps: int, lr: float, ws=None, loss_history=None,
+              stream=None):
+    B = X.shape[0]
+    if ws is None:
+        ws = mlp_workspace(B, X.device)
+    _check(lib.rtcdf_mlp_train(_ptr(params), _ptr(m), _ptr(v), int(t0), _ptr(X), _ptr(T), _ptr(M), B,
+                               int(steps), float(lr), _ptr(ws), ws.numel(),
+                               _ptr(loss_history) if loss_history is not None else None,
+                               _stream_ptr(stream)), "rtcdf_mlp_train")
+
+
+def mlp_pick(keys_in, minVal: int, maxVal: int, params, norm, valid, stream=None):
+    """(index tensor[1], predictions tensor[54]) on the device."""
+    import torch
+    idx = torch.empty(1, dtype=torch.int32, device=keys_in.device)
+    pred = torch.empty(MLP_OUTPUTS, dtype=torch.float32, device=keys_in.device)
+    _check(lib.rtcdf_mlp_pick(_ptr(keys_in), keys_in.numel(), int(minVal), int(maxVal), _ptr(params),
+                              _ptr(norm), _ptr(valid), _ptr(idx), _ptr(pred), _stream_ptr(stream)),
+           "rtcdf_mlp_pick")
+    return idx, pred

@@ -1,0 +1,212 @@
+"""Autotuning database, static default table and tuned table.
+
+The database is append-only JSON lines, one row per measured array:
+    {"key": ..., "n": ..., "minVal": ..., "R": ..., "dist": ..., "sd_div": ...,
+     "features": [34 floats from the GPU sketch kernel],
+     "times_ms": [54 medians from rtcdf_autotune, -1 for invalid grid points]}
+Rows are keyed by the array's seed, so an interrupted collection resumes where
+it stopped.
+
+The static default table follows the selection rule of Sec. 4.1 of the paper:
+for every range class, the configuration with the smallest geometric mean of
+t(config) / t_best over the arrays of that class.
+
+Run ``python -m paper_2609_00843_amd.tune collect --set train --count 2000 --db PATH``
+on a GPU, then ``python -m paper_2609_00843_amd.tune table --db PATH`` to write
+csrc/rtcdf_default_table.h and the tuned table.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import inputs
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+DATA = os.path.join(PKG, "data")
+TABLE_H = os.path.join(PKG, "csrc", "rtcdf_default_table.h")
+
+GRID_T = [1024 << i for i in range(6)]
+GRID_ITEMS = [4, 8, 16]
+GRID_BPT = [1, 2, 4]
+
+
+def grid():
+    """The 54 grid points (T, items, blocks) in library order and their validity."""
+    pts, valid = [], []
+    for T in GRID_T:
+        for it in GRID_ITEMS:
+            for b in GRID_BPT:
+                pts.append((T, it, b))
+                valid.append(T * 4 * b <= 163840)
+    return pts, valid
+
+
+def specs(which: str, count: int, seed: int = None):
+    """Arrays like the single-array workloads: n log-uniform in [1e6, 1e9], R
+    log-uniform in [2^7, 2^18] (rounded), minVal 0, keys uniform, normal with
+    sd R/6, normal with sd R/64 or all equal; the held-out set adds Zipf(1.1)."""
+    if seed is None:
+        seed = inputs.case_seed(5, 0 if which == "train" else 1)
+    rng = np.random.Generator(np.random.Philox(np.random.SeedSequence([seed, 5])))
+    dists = [("uniform", 6.0), ("normal", 6.0), ("normal", 64.0), ("all_equal", 6.0)]
+    if which == "test":
+        dists.append(("zipf", 6.0))
+    out = []
+    for i in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(1e6), math.log(1e9)))))
+        R = int(round(2.0 ** rng.uniform(7.0, 18.0)))
+        d, sd = dists[int(rng.integers(0, len(dists)))]
+        out.append({"key": f"{which}-{seed}-{i}", "n": n, "minVal": 0, "R": R, "dist": d, "sd_div": sd,
+                    "seed": int(inputs.case_seed(6, i, seed))})
+    return out
+
+
+def load_db(path: str):
+    rows = []
+    if os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                line = line.strip()
+                if line:
+                    rows.append(json.loads(line))
+    return rows
+
+
+def collect(db: str, which: str, count: int, warmup: int = 2, reps: int = 5, start: int = 0,
+            stop: int = None, budget_s: float = None):
+    """Measure every not-yet-measured array of the set; prints one line per array."""
+    import torch
+    from . import rtcdf
+    done = {r["key"] for r in load_db(db)}
+    todo = [s for s in specs(which, count)[start:stop] if s["key"] not in done]
+    print(f"[tune] {len(done)} rows present, {len(todo)} to measure -> {db}", flush=True)
+    os.makedirs(os.path.dirname(os.path.abspath(db)), exist_ok=True)
+    dev = torch.device("cuda:0")
+    t_start = time.time()
+    with open(db, "a") as f:
+        for k, s in enumerate(todo):
+            if budget_s is not None and time.time() - t_start > budget_s:
+                print(f"[tune] time budget reached after {k} arrays", flush=True)
+                break
+            a = inputs.make_device(s["dist"], s["n"], s["minVal"], s["minVal"] + s["R"], s["seed"],
+                                   device=dev, sd_div=s["sd_div"])
+            b = torch.empty_like(a)
+            feats = rtcdf.sketch(a, s["minVal"], s["minVal"] + s["R"]).cpu().tolist()
+            times, best = rtcdf.autotune(a, s["minVal"], s["minVal"] + s["R"], keys_out=b, warmup=warmup,
+                                         reps=reps)
+            row = dict(s)
+            row["features"] = feats
+            row["times_ms"] = times
+            f.write(json.dumps(row) + "\n")
+            f.flush()
+            print(f"[tune] {k + 1}/{len(todo)} n={s['n']} R={s['R']} {s['dist']}/{s['sd_div']:g} "
+                  f"best={best.as_tuple()} {min(t for t in times if t > 0):.4f} ms", flush=True)
+            del a, b
+
+
+def range_class(R: int) -> int:
+    return int(round(math.log2(R)))
+
+
+def select_static(rows):
+    """{range class: grid index} by the smallest geometric mean of t / t_best."""
+    _, valid = grid()
+    by_class = {}
+    for r in rows:
+        by_class.setdefault(range_class(r["R"]), []).append(r)
+    table = {}
+    for c, rs in sorted(by_class.items()):
+        scores = []
+        for i in range(54):
+            if not valid[i]:
+                scores.append(math.inf)
+                continue
+            logs = [math.log(r["times_ms"][i] / min(t for t, v in zip(r["times_ms"], valid) if v))
+                    for r in rs]
+            scores.append(sum(logs) / len(logs))
+        table[c] = int(np.argmin(scores))
+    return table
+
+
+def write_default_table(table, path: str = TABLE_H, source: str = ""):
+    pts, _ = grid()
+    classes = sorted(table)
+    lines = []
+    for j, c in enumerate(classes):
+        # class c covers R up to the geometric midpoint towards class c + 1
+        bound = "1u << 28" if j == len(classes) - 1 else f"{int(math.floor(2.0 ** (c + 0.5)))}u"
+        T, it, b = pts[table[c]]
+        lines.append(f"    {{{bound}, {{{T}, {it}, {b}, 0}}}},   // log2 R ~ {c}")
+    body = "\n".join(lines)
+    src = f"\n// Source: {source}" if source else ""
+    text = f"""// rtcdf_default_table.h -- static default configuration per range class.
+// Written by paper_2609_00843_amd/tune.py from measured tuning rows (the
+// geometric mean of relative times per range, as in Sec. 4.1 of the paper);
+// rows are ordered by max_range and the first row with R <= max_range applies.{src}
+#pragma once
+
+#include "../../include/rtcdf.h"
+
+namespace rtcdf {{
+
+struct DefaultRow {{
+  uint32_t max_range;
+  rtcdf_config_t cfg;
+}};
+
+static const DefaultRow kDefaultTable[] = {{
+{body}
+}};
+
+}}  // namespace rtcdf
+"""
+    with open(path, "w") as f:
+        f.write(text)
+
+
+def write_tuned_table(rows, path: str):
+    """One line per measured array: log2 n, log2 R and its fastest configuration."""
+    pts, valid = grid()
+    with open(path, "w") as f:
+        f.write("# log2n log2R T items blocks  (fastest measured configuration per array)\n")
+        for r in rows:
+            i = min((t, j) for j, t in enumerate(r["times_ms"]) if valid[j] and t > 0)[1]
+            T, it, b = pts[i]
+            f.write(f"{math.log2(r['n']):.4f} {math.log2(r['R']):.4f} {T} {it} {b}\n")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect")
+    c.add_argument("--set", default="train", choices=["train", "test"])
+    c.add_argument("--count", type=int, default=2000)
+    c.add_argument("--db", required=True)
+    c.add_argument("--start", type=int, default=0)
+    c.add_argument("--stop", type=int, default=None)
+    c.add_argument("--budget-s", type=float, default=None)
+    c.add_argument("--reps", type=int, default=5)
+    t = sub.add_parser("table")
+    t.add_argument("--db", required=True)
+    t.add_argument("--tuned-out", default=os.path.join(DATA, "tuned_table.txt"))
+    args = ap.parse_args(argv)
+    if args.cmd == "collect":
+        collect(args.db, args.set, args.count, reps=args.reps, start=args.start, stop=args.stop,
+                budget_s=args.budget_s)
+    else:
+        rows = load_db(args.db)
+        table = select_static(rows)
+        write_default_table(table, source=f"{os.path.basename(args.db)}, {len(rows)} arrays")
+        write_tuned_table(rows, args.tuned_out)
+        print(json.dumps({str(k): grid()[0][v] for k, v in table.items()}))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,148 @@
+"""GPU parity of the learned picker's kernels against the float64 reference
+(oracle/mlp_ref.py): sketch, forward, gradient, Adam, training determinism and
+the masked argmin pick.  FP32 against float64: relative tolerance 1e-4 on
+outputs and gradients (sums of at most 2000 x 64 products, fp32 unit
+roundoff 6e-8), exact bin counts."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as M
+from paper_2609_00843_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+SIZES = (34, 64, 64, 54)
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def r():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_00843_amd import rtcdf
+    return rtcdf
+
+
+def _init(seed):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for i in range(3):
+        p[f"W{i + 1}"] = rng.normal(0, np.sqrt(2.0 / SIZES[i]), size=(SIZES[i + 1], SIZES[i]))
+        p[f"b{i + 1}"] = rng.normal(0, 0.05, size=SIZES[i + 1])
+    return p
+
+
+def _flat(p):
+    return np.concatenate([p[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def _unflat(v):
+    out, o = {}, 0
+    for i in range(3):
+        for k, shape in ((f"W{i + 1}", (SIZES[i + 1], SIZES[i])), (f"b{i + 1}", (SIZES[i + 1],))):
+            sz = int(np.prod(shape))
+            out[k] = v[o:o + sz].reshape(shape)
+            o += sz
+    return out
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _batch(seed, B):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(B, 34))
+    T = rng.normal(size=(B, 54))
+    Mk = np.ones((B, 54))
+    Mk[:, [38, 41, 44, 46, 47, 49, 50, 52, 53]] = 0.0      # the invalid grid points
+    Mk[rng.random(size=(B, 54)) < 0.05] = 0.0
+    return X, T, Mk
+
+
+@pytest.mark.parametrize("dist,n,R", [("uniform", 10 ** 6, 128), ("normal", 3_000_001, 70000),
+                                      ("all_equal", 5000, 1 << 18), ("zipf", 777, 1000),
+                                      ("uniform", 4096, 33), ("normal", 12345, 1 << 28)])
+def test_sketch(r, dist, n, R):
+    lo = -12345
+    A = inputs.make(dist, n, lo, lo + R, 11)
+    _say(f"sketch {dist} n={n} R={R}")
+    got = r.sketch(torch.from_numpy(A).cuda(), lo, lo + R).cpu().numpy().astype(np.float64)
+    want = M.sketch(A, lo, lo + R, samples=4096, bins=32)
+    assert np.allclose(got[:2], want[:2], rtol=1e-6, atol=0)
+    S = min(4096, n)
+    assert np.array_equal(np.rint(got[2:] * S), np.rint(want[2:] * S))   # identical bin counts
+
+
+def test_forward_and_gradient(r):
+    p = _init(1)
+    X, T, Mk = _batch(2, 300)
+    P = _dev(_flat(p))
+    _say("forward")
+    Y = r.mlp_forward(P, _dev(X)).cpu().numpy()
+    Yr, cache = M.forward(p, X)
+    assert np.allclose(Y, Yr, rtol=1e-4, atol=1e-4 * np.abs(Yr).max())
+    _say("gradient")
+    G, L = r.mlp_gradient(P, _dev(X), _dev(T), _dev(Mk))
+    gr = _flat(M.backward(p, cache, Yr, T, Mk))
+    g = G.cpu().numpy()
+    assert np.allclose(g, gr, rtol=1e-3, atol=1e-4 * np.abs(gr).max())
+    assert float(L.cpu()[0]) == pytest.approx(M.loss(Yr, T, Mk), rel=1e-4)
+
+
+def test_adam_step(r):
+    rng = np.random.default_rng(3)
+    p = {"w": rng.normal(size=9910)}
+    g = {"w": rng.normal(size=9910)}
+    m = {"w": rng.normal(size=9910) * 0.1}
+    v = {"w": np.abs(rng.normal(size=9910)) * 0.01}
+    P, Gd, Md, Vd = _dev(p["w"]), _dev(g["w"]), _dev(m["w"]), _dev(v["w"])
+    _say("adam")
+    r.mlp_adam_step(P, Gd, Md, Vd, 7, lr=1e-2)
+    M.adam_step(p, g, m, v, 7, lr=1e-2)
+    assert np.allclose(P.cpu().numpy(), p["w"], rtol=1e-5, atol=1e-6)
+    assert np.allclose(Md.cpu().numpy(), m["w"], rtol=1e-5, atol=1e-7)
+    assert np.allclose(Vd.cpu().numpy(), v["w"], rtol=1e-5, atol=1e-9)
+
+
+def test_training_is_deterministic_and_learns(r):
+    p0 = _flat(_init(4))
+    X, T, Mk = _batch(5, 500)
+    Xd, Td, Md = _dev(X), _dev(T * 0.1 + X[:, :1] * 0.5), _dev(Mk)
+    finals = []
+    for rep in range(2):
+        P = _dev(p0)
+        m = torch.zeros_like(P)
+        v = torch.zeros_like(P)
+        hist = torch.empty(200, dtype=torch.float32, device="cuda")
+        _say(f"train run {rep}")
+        r.mlp_train(P, m, v, 0, Xd, Td, Md, 200, 3e-3, loss_history=hist)
+        torch.cuda.synchronize()
+        h = hist.cpu().numpy()
+        assert h[-1] < 0.5 * h[0]
+        finals.append(P.cpu().numpy())
+    assert np.array_equal(finals[0], finals[1])
+
+
+def test_pick(r):
+    p = _init(6)
+    rng = np.random.default_rng(7)
+    norm = np.concatenate([rng.normal(size=34) * 0.1, 0.5 + rng.random(size=34)])
+    _, valid = r.config_grid()
+    validd = torch.tensor(np.array(valid, dtype=np.uint8), device="cuda")
+    for dist, n, R in (("uniform", 100_000, 4096), ("normal", 50_000, 300), ("zipf", 9999, 65536)):
+        A = inputs.make(dist, n, 0, R, 8)
+        _say(f"pick {dist}")
+        idx, pred = r.mlp_pick(torch.from_numpy(A).cuda(), 0, R, _dev(_flat(p)), _dev(norm), validd)
+        pred = pred.cpu().numpy()
+        f = (M.sketch(A, 0, R) - norm[:34]) / norm[34:]
+        want, _ = M.forward(p, f[None, :])
+        assert np.allclose(pred, want[0], rtol=1e-4, atol=1e-4 * np.abs(want).max())
+        # the argmin is taken in the kernel's precision: compare on its own outputs
+        assert int(idx.cpu()[0]) == M.pick(pred, valid)
