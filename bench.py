@@ -56,6 +56,136 @@ def load_traffic(stage: str):
     return float(v) if v is not None else None
 
 
+def bench_batched(torch, rtcdf, inputs, steps, check):
+    """The 4096-array batch workload: one HIP-graph launch of the batched sort
+    against the same arrays sorted by 4096 plain calls (eagerly, and captured in
+    one graph through the caller-workspace entry point)."""
+    import numpy as np
+    segs = inputs.batched_segments(4096)
+    total = sum(s["n"] for s in segs)
+    dev = torch.device("cuda:0")
+    din = torch.empty(total, dtype=torch.int32, device=dev)
+    dout = torch.empty(total, dtype=torch.int32, device=dev)
+    pairs, o = [], 0
+    for s in segs:
+        n = s["n"]
+        din[o:o + n] = inputs.make_device(s["dist"], n, s["minVal"], s["maxVal"], s["seed"], device=dev)
+        pairs.append((din[o:o + n], dout[o:o + n], s["minVal"], s["maxVal"]))
+        o += n
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    d, bounds, k = rtcdf.make_segments(pairs)
+    ws = torch.empty(rtcdf.batched_workspace_bytes(k, bounds), dtype=torch.uint8, device=dev)
+    with torch.cuda.stream(stream):
+        rtcdf.sort_batched(d, k, bounds, ws, stream=stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        rtcdf.sort_batched(d, k, bounds, ws, stream=stream)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_batched = timed(g.replay, steps)
+    parity = "not checked"
+    if check:
+        import oracle
+        outs = dout.cpu().numpy()
+        ins = din.cpu().numpy()
+        bad, o = 0, 0
+        for s in segs:
+            n = s["n"]
+            if not np.array_equal(outs[o:o + n], oracle.sort(ins[o:o + n], s["minVal"], s["maxVal"])):
+                bad += 1
+            o += n
+        parity = "bit-exact on all 4096 arrays" if bad == 0 else f"MISMATCH in {bad} arrays"
+        del outs, ins
+
+    def plain_loop():
+        for a, b, lo, hi in pairs:
+            rtcdf.sort(a, lo, hi, keys_out=b, stream=stream)
+
+    t_plain = timed(plain_loop, max(1, steps // 5))
+    # the same plain sorts in one captured graph, sharing one caller workspace
+    wsz = max(rtcdf.workspace_bytes(a.numel(), lo, hi, keys_out=b) for a, b, lo, hi in pairs)
+    pws = torch.empty(wsz, dtype=torch.uint8, device=dev)
+    with torch.cuda.stream(stream):
+        for a, b, lo, hi in pairs:
+            rtcdf.sort_ws(a, b, lo, hi, pws, stream=stream)
+    torch.cuda.synchronize()
+    pg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(pg, stream=stream):
+        for a, b, lo, hi in pairs:
+            rtcdf.sort_ws(a, b, lo, hi, pws, stream=stream)
+    t_plain_graph = timed(pg.replay, max(1, steps // 5))
+    gk = lambda ms: round(total / (ms * 1e-3) / 1e9, 2)
+    return {"workload": "4096 int32 arrays: n log-uniform in [1e3,1e6], minVal uniform in [-1e6,1e6], "
+                        "R log-uniform in [2^4,2^16], uniform / normal sd R/6 / all-equal",
+            "keys": total, "ms_batched_graph": round(t_batched, 4), "gkeys_per_s": gk(t_batched),
+            "frac_8B_roofline": round(8.0 * total / (t_batched * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "ms_plain_calls": round(t_plain, 4), "gkeys_per_s_plain_calls": gk(t_plain),
+            "ms_plain_graph": round(t_plain_graph, 4), "gkeys_per_s_plain_graph": gk(t_plain_graph),
+            "speedup_vs_plain_calls": round(t_plain / t_batched, 2),
+            "speedup_vs_plain_graph": round(t_plain_graph / t_batched, 2), "parity": parity}
+
+
+def bench_learned(torch, rtcdf, cases, ins, outs, steps):
+    """Plain sorts of the sweep with the configuration picked by the learned
+    model against the static default table, plus the held-out evaluation."""
+    model = os.path.join(ROOT, "paper_2609_00843_amd", "data", "model.bin")
+    res = {}
+    ev = os.path.join(ROOT, "paper_2609_00843_amd", "data", "learned_eval.json")
+    if os.path.exists(ev):
+        res["held_out"] = json.load(open(ev)).get("summary")
+    if not os.path.exists(model):
+        res["status"] = "no model file"
+        return res
+    rtcdf.load_model(model)
+    stream = torch.cuda.current_stream()
+    rows = []
+    old = rtcdf.get_config_mode()
+    try:
+        for (lr, d), a, b in zip(cases, ins, outs):
+            R = 1 << lr
+            t = {}
+            for mode in (rtcdf.CONFIG_DEFAULT, rtcdf.CONFIG_LEARNED):
+                rtcdf.set_config_mode(mode)
+                cfg = rtcdf.pick_config(N, MIN_VAL, MIN_VAL + R, keys_in=a)
+                for _ in range(2):
+                    rtcdf.sort(a, MIN_VAL, MIN_VAL + R, keys_out=b, config=cfg)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(steps):
+                    rtcdf.sort(a, MIN_VAL, MIN_VAL + R, keys_out=b, config=cfg)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t[mode] = (e0.elapsed_time(e1) / steps, cfg.as_tuple())
+            # pick cost: sketch + MLP + argmin kernel and the read-back, per call
+            rtcdf.set_config_mode(rtcdf.CONFIG_LEARNED)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                rtcdf.pick_config(N, MIN_VAL, MIN_VAL + R, keys_in=a)
+            pick_ms = (time.perf_counter() - t0) * 1e3 / steps
+            rows.append({"R": R, "dist": d, "ms_static": round(t[0][0], 5), "cfg_static": t[0][1],
+                         "ms_learned": round(t[2][0], 5), "cfg_learned": t[2][1],
+                         "pick_ms": round(pick_ms, 4)})
+    finally:
+        rtcdf.set_config_mode(old)
+    import math
+    res["sweep"] = rows
+    res["sweep_gain_geomean"] = round(math.exp(sum(math.log(r["ms_static"] / r["ms_learned"])
+                                                   for r in rows) / len(rows)), 4)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,12 +193,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cases", default="", help="comma list like 16:uniform,7:normal (default all)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="only run warmup + timed steps (for rocprofv3 runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(the sort shards with one histogram all-reduce, see DESIGN.md)", file=sys.stderr)
+              f"(the sort would shard by one 4R-byte histogram all-reduce)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -199,6 +331,20 @@ def main():
                          f"{os.cpu_count()} host cores visible"}
         log(f"[bench] oracle {cpu['value']} Gkeys/s on 1 core; parity: {parity}")
 
+    learned = None
+    if not args.no_learned:
+        log("[bench] learned picker vs static table on the sweep")
+        learned = bench_learned(torch, rtcdf, cases, ins, outs, max(3, args.steps // 2))
+    batched = None
+    if not args.no_batched:
+        del ins, outs
+        torch.cuda.empty_cache()
+        log("[bench] batched workload")
+        batched = bench_batched(torch, rtcdf, inputs, args.steps, not args.no_cpu_baseline)
+        log(f"[bench] batched: {batched['gkeys_per_s']} Gkeys/s in one graph launch, "
+            f"{batched['speedup_vs_plain_calls']}x plain calls, {batched['speedup_vs_plain_graph']}x "
+            f"plain graph; parity {batched['parity']}")
+
     tgt = [c for c in per_case if c["R"] <= (1 << 16)]
     rec = {
         "metric": METRIC,
@@ -226,6 +372,8 @@ def main():
         "parity": parity,
         "stage_ms_per_sort": {k: round(v, 5) for k, v in stage_ms.items()},
         "cases": per_case,
+        "batched": batched,
+        "learned": learned,
     }
     print(json.dumps(rec))
 

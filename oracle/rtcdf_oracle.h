@@ -11,7 +11,7 @@
  * against the paper by eye.  Sections cited are those of the paper
  * "Shared-Memory Range-Tiled CDF Sort for Small-Range Integer Keys on GPUs".
  *
- * Conventions (readings of the paper, listed in the design doc):
+ * Conventions (readings of the paper where it leaves a choice open):
  *   - keys are int32, the range is the half-open [minVal, maxVal) (Sec. 2.1);
  *     minVal/maxVal are int64 so that maxVal = 2^31 is expressible;
  *   - R = maxVal - minVal; the paper subtracts minVal "for notation" only

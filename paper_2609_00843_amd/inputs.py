@@ -6,7 +6,8 @@ piece the tests, the benchmark and the oracle's callers share.
 
 Distributions (the paper's evaluation uses synthetic uniform, normal and
 all-equal keys, Sec. 4.1 and Sec. 4.2; the parameters below are those of the
-measured workloads, and their readings are listed in the design doc):
+measured workloads, which differ from the paper's normal sd of R/8 and
+all-zero keys):
   uniform    i.i.d. integers in [minVal, maxVal)
   normal     real N(minVal + R/2, (R/sd_div)^2), rounded half-to-even, clamped
              to [minVal, maxVal - 1]
