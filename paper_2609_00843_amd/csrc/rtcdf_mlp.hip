@@ -9,6 +9,8 @@
 // gradient is a fixed-order sum over the samples by one thread.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "rtcdf_device.h"
 #include "rtcdf_internal.h"
 
@@ -174,13 +176,16 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(const float* X, const float* 
 
 // One Adam step (Kingma & Ba): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
 // p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+// The coefficients 1 - b1 and 1 - b2 come from the host in double precision
+// (1.f - 0.999f is 1.3e-5 off in float).
 __global__ __launch_bounds__(256) void k_adam(float* P, const float* G, float* Mo, float* Vo, float lr,
-                                              float b1, float b2, float eps, float c1, float c2) {
+                                              float b1, float b2, float omb1, float omb2, float eps,
+                                              float c1, float c2) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= NPARAM) return;
   const float g = G[p];
-  const float m = b1 * Mo[p] + (1.f - b1) * g;
-  const float v = b2 * Vo[p] + (1.f - b2) * g * g;
+  const float m = b1 * Mo[p] + omb1 * g;
+  const float v = b2 * Vo[p] + omb2 * g * g;
   Mo[p] = m;
   Vo[p] = v;
   P[p] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
@@ -277,9 +282,10 @@ size_t mlp_grad_scratch_floats(uint32_t B) { return (size_t)B * (4 * H + 2 * D3 
 
 hipError_t launch_adam(float* P, const float* G, float* Mo, float* Vo, float lr, float b1, float b2,
                        float eps, uint32_t t, hipStream_t s) {
-  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
-  hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, P, G, Mo, Vo, lr, b1, b2, eps,
-                     c1, c2);
+  const double db1 = b1, db2 = b2;
+  const float c1 = (float)(1.0 - std::pow(db1, (double)t)), c2 = (float)(1.0 - std::pow(db2, (double)t));
+  hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, P, G, Mo, Vo, lr, b1, b2,
+                     (float)(1.0 - db1), (float)(1.0 - db2), eps, c1, c2);
   return hipGetLastError();
 }
 

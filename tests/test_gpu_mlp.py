@@ -105,7 +105,9 @@ def test_adam_step(r):
     P, Gd, Md, Vd = _dev(p["w"]), _dev(g["w"]), _dev(m["w"]), _dev(v["w"])
     _say("adam")
     r.mlp_adam_step(P, Gd, Md, Vd, 7, lr=1e-2)
-    M.adam_step(p, g, m, v, 7, lr=1e-2)
+    # the kernel receives float hyperparameters: give the reference the same values
+    f32 = lambda x: float(np.float32(x))
+    M.adam_step(p, g, m, v, 7, lr=f32(1e-2), beta1=f32(0.9), beta2=f32(0.999), eps=f32(1e-8))
     assert np.allclose(P.cpu().numpy(), p["w"], rtol=1e-5, atol=1e-6)
     assert np.allclose(Md.cpu().numpy(), m["w"], rtol=1e-5, atol=1e-7)
     assert np.allclose(Vd.cpu().numpy(), v["w"], rtol=1e-5, atol=1e-9)
