@@ -152,22 +152,27 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   p->out_head = (uint32_t)(((16 - (oa & 15)) & 15) / 4);
   const uint32_t gran = 4 * kFillBlock;
   const uint64_t fill_per_cu = (uint64_t)env_int("RTCDF_DEV_FILL_WGS_PER_CU", 4);
-  // Chunks of 8192 positions (32 KiB of output), fewer when n is small so
-  // that every compute unit still gets work.
-  uint64_t want = (n + (uint64_t)dev.cus * 4 - 1) / ((uint64_t)dev.cus * 4);
-  want = std::max<uint64_t>(want, gran);
-  want = std::min<uint64_t>(want, 8192);
+  // Chunks of 2048 positions (8 KiB of output): the workgroups interleave
+  // chunk by chunk, so the whole chip writes one narrow moving window.
+  uint64_t want = 2048;
   const int64_t force_chunk = env_int("RTCDF_DEV_FILL_CHUNK", 0);
   if (force_chunk > 0) want = (uint64_t)force_chunk;
   p->chunk = (uint32_t)((want + gran - 1) / gran * gran);
   p->nchunks = 1 + ((n >= 1 && n - 1 >= p->out_head) ? (uint32_t)((n - 1 - p->out_head) / p->chunk) : 0);
   p->fill_grid = (uint32_t)std::min<uint64_t>(p->nchunks, (uint64_t)dev.cus * fill_per_cu);
+  // Enough workgroups in the local-CDF stage to spread the splitters of a
+  // single tile over the chip, but no more than one per 256 chunk boundaries.
+  const uint32_t want_parts = std::max<uint32_t>(1, (uint32_t)dev.cus / p->m);
+  const uint32_t by_work = std::max<uint32_t>(1, p->nchunks / std::max<uint32_t>(1, p->m) / 256);
+  p->scan_parts = std::min<uint32_t>(want_parts, by_work);
 
   // Workspace layout.
   size_t off = 0;
   p->off_partial = off;
   off = align256(off + (size_t)p->passes * p->G * p->row_words * 4);
   p->off_hist = off;
+  off = align256(off + (size_t)R * 4);
+  p->off_cdf = off;
   off = align256(off + (size_t)R * 4);
   p->off_rsum = off;
   off = align256(off + (size_t)p->nred * 4);
@@ -291,7 +296,7 @@ static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, ui
   if (e != hipSuccess) return hip_fail(e);
   mark(3);
   if (dbg_cdf) {
-    e = hipMemcpyAsync(dbg_cdf, ws + q.off_hist, (size_t)q.R * 4, hipMemcpyDeviceToDevice, s);
+    e = hipMemcpyAsync(dbg_cdf, ws + q.off_cdf, (size_t)q.R * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e);
   }
   if (dbg_O) {

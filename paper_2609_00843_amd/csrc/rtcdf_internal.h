@@ -55,8 +55,9 @@ struct Plan {
   uint32_t chunk;        // output positions per chunk (multiple of 4 * kFillBlock)
   uint32_t nchunks;
   uint32_t fill_grid;
+  uint32_t scan_parts;   // workgroups per tile in the local-CDF stage
   // workspace layout
-  size_t off_partial, off_hist, off_rsum, off_O, off_split, ws_bytes;
+  size_t off_partial, off_hist, off_cdf, off_rsum, off_O, off_split, ws_bytes;
   size_t off_carry;      // carry array inside a caller-owned workspace (rtcdf_sort_ws)
   size_t carry_words;    // 0 unless packed16
 };

@@ -7,11 +7,13 @@
 //               the per-bin global atomics of Alg. 5.
 //   k_reduce    sums the partial rows of each bin -> H[R], plus per-128-bin
 //               block totals used for the tile offsets.
-//   k_tilescan  one workgroup per range tile: local CDF by inclusive scan
+//   k_tilescan  S workgroups per range tile: local CDF by inclusive scan
 //               (Alg. 4), tile offset O[t] (Alg. 6, as a sum of the block
 //               totals before the tile), and the value found at each output
 //               chunk boundary ("splitters", by bisection in the local CDF as in
-//               Alg. 7).
+//               Alg. 7).  Every workgroup of a tile scans the tile in its own
+//               LDS; the first one writes the CDF and O[t], and each takes 1/S
+//               of the tile's chunk boundaries.
 //   k_fill      one workgroup per output chunk: loads the inclusive cumulative
 //               counts O[t] + C_t[x] of the values that cover the chunk into LDS
 //               and writes every position p the value b_t + min{x : C_t[x] >= p'+1}
@@ -177,12 +179,13 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
 // ---------------------------------------------------------- local CDF + O[t]
 
 struct ScanArgs {
-  uint32_t* hist;         // in: H; out: local CDFs (in place)
+  const uint32_t* hist;   // H (tile histograms)
+  uint32_t* cdf;          // out: local CDFs
   const uint32_t* rsum;
   uint32_t* O;
   uint32_t* split;
   uint64_t n;
-  uint32_t R, T, out_head, chunk, nchunks;
+  uint32_t R, T, out_head, chunk, nchunks, S;
 };
 
 // First output chunk whose start position s(k) is >= P, where s(0) = 0 and
@@ -201,7 +204,7 @@ __device__ __forceinline__ uint32_t first_chunk_at_or_after(uint64_t P, uint32_t
 __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
   extern __shared__ uint32_t C[];
   __shared__ uint32_t wsum[kScanBlock / 64];
-  const uint32_t t = blockIdx.x, tid = threadIdx.x;
+  const uint32_t t = blockIdx.x / a.S, part = blockIdx.x % a.S, tid = threadIdx.x;
   const uint32_t b = t * a.T;
   const uint32_t w = a.R - b < a.T ? a.R - b : a.T;
 
@@ -228,18 +231,23 @@ __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
   const uint32_t before = block_inclusive_scan(run, wsum, &Nt) - run;
   for (uint32_t i = s0; i < s1; ++i) C[pad32(i)] += before;
   __syncthreads();
-  for (uint32_t i = tid; i < w; i += kScanBlock) a.hist[b + i] = C[pad32(i)];
-  if (tid == 0) a.O[t] = Ot;
+  if (part == 0) {
+    for (uint32_t i = tid; i < w; i += kScanBlock) a.cdf[b + i] = C[pad32(i)];
+    if (tid == 0) a.O[t] = Ot;
+  }
   if (Nt == 0) return;
 
   // Splitters: the value at every chunk start inside [O_t, O_t + N_t), and at
-  // position n - 1 (closes the last chunk's window).  Chunk starts are taken
-  // in batches of 4 per thread: each thread finds its 4 consecutive starts
-  // (one bisection, then a short forward walk), stages them in LDS (behind
-  // the CDF) and the batch is written out with coalesced stores.
+  // position n - 1 (closes the last chunk's window); this workgroup takes part
+  // `part` of S.  Chunk starts are taken in batches of 4 per thread: each
+  // thread finds its 4 consecutive starts (one bisection, then a short forward
+  // walk), stages them in LDS (behind the CDF) and the batch is written out
+  // with coalesced stores.
   const uint64_t lo = Ot, hi = (uint64_t)Ot + Nt;
-  const uint32_t k0 = first_chunk_at_or_after(lo, a.out_head, a.chunk, a.nchunks);
-  const uint32_t k1 = first_chunk_at_or_after(hi, a.out_head, a.chunk, a.nchunks);
+  const uint32_t kt0 = first_chunk_at_or_after(lo, a.out_head, a.chunk, a.nchunks);
+  const uint32_t kt1 = first_chunk_at_or_after(hi, a.out_head, a.chunk, a.nchunks);
+  const uint32_t per = (kt1 - kt0 + a.S - 1) / a.S;
+  const uint32_t k0 = min(kt0 + part * per, kt1), k1 = min(k0 + per, kt1);
   uint32_t* stage = C + pad32(a.T) + 1;   // 4 * kScanBlock words
   constexpr uint32_t kPer = 4;
   for (uint32_t kb0 = k0; kb0 < k1; kb0 += kPer * kScanBlock) {
@@ -263,7 +271,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
     for (uint32_t j = tid; j < nbatch; j += kScanBlock) a.split[kb0 + j] = stage[j];
     __syncthreads();
   }
-  if (tid == 0 && a.n - 1 >= lo && a.n - 1 < hi)
+  if (part == 0 && tid == 0 && a.n - 1 >= lo && a.n - 1 < hi)
     a.split[a.nchunks] = b + count_le_pad(C, w, (uint32_t)(a.n - 1 - lo));
 }
 
@@ -528,7 +536,9 @@ hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_
 
 hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t s) {
   ScanArgs a;
-  a.hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
+  a.hist = reinterpret_cast<const uint32_t*>(ws + p.off_hist);
+  a.cdf = reinterpret_cast<uint32_t*>(ws + p.off_cdf);
+  a.S = p.scan_parts;
   a.rsum = reinterpret_cast<const uint32_t*>(ws + p.off_rsum);
   a.O = reinterpret_cast<uint32_t*>(ws + p.off_O);
   a.split = reinterpret_cast<uint32_t*>(ws + p.off_split);
@@ -542,14 +552,14 @@ hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)k_tilescan,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_tilescan, dim3(p.m), dim3(kScanBlock), lds, s, a);
+  hipLaunchKernelGGL(k_tilescan, dim3(p.m * p.scan_parts), dim3(kScanBlock), lds, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream_t s) {
   FillArgs a;
   a.out = out;
-  a.cdf = reinterpret_cast<const uint32_t*>(ws + p.off_hist);
+  a.cdf = reinterpret_cast<const uint32_t*>(ws + p.off_cdf);
   a.O = reinterpret_cast<const uint32_t*>(ws + p.off_O);
   a.split = reinterpret_cast<const uint32_t*>(ws + p.off_split);
   a.n = p.n;
