@@ -304,6 +304,28 @@ rtcdf_status_t rtcdf_profile_collect(rtcdf_stage_stats_t* out);
  * compared with, and its HBM counters calibrate counter-derived traffic. */
 rtcdf_status_t rtcdf_stream_copy(const void* d_src, void* d_dst, size_t bytes, hipStream_t stream);
 
+/* The launch plan rtcdf_sort_with_config would use (cfg NULL = library
+ * choice; keys_in / keys_out are only inspected for alignment and may be
+ * NULL), for measurement and tests. */
+typedef struct rtcdf_plan_info {
+  uint32_t tile_width;       /* effective T */
+  uint32_t tiles;            /* m = ceil(R / T) */
+  uint32_t counter_bits;     /* 32, 16 (two per LDS word) or 8 (four per word) */
+  uint32_t passes;           /* LDS passes over the input */
+  uint32_t pass_bins;        /* bins per pass */
+  uint32_t hist_workgroups;  /* passes x chunks */
+  uint32_t hist_threads;
+  uint32_t items_per_thread;
+  uint32_t scan_workgroups;  /* tiles x workgroups per tile */
+  uint32_t out_chunk;        /* output positions per chunk */
+  uint32_t out_chunks;
+  uint32_t fill_workgroups;
+  uint64_t workspace_bytes;
+} rtcdf_plan_info_t;
+
+rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,
+                               const int32_t* keys_in, const int32_t* keys_out, rtcdf_plan_info_t* out);
+
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int rtcdf_version(void);
 /* Frees the library's cached per-device workspaces (not needed before exit). */

@@ -112,20 +112,22 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   p->m = (R + p->T - 1) / p->T;
 
   // Histogram passes: as many whole tiles per workgroup LDS as fit, with 32-bit
-  // counters, or with two 16-bit counters per word when that needs fewer passes.
-  const uint32_t lds = kLdsBytes / p->bpt - 256;   // 64 spare words for the 16-bit form
+  // counters, or with two 16-bit or four 8-bit counters per word when that
+  // needs fewer passes over the input.
+  const uint32_t lds = kLdsBytes / p->bpt - 256;   // 64 spare words
   const uint32_t k32 = std::max<uint32_t>(1, lds / (4 * p->T));
   const uint32_t k16 = std::max<uint32_t>(1, lds / (2 * p->T));
+  const uint32_t k8 = std::max<uint32_t>(1, (lds - 512) / p->T);   // 512 B wrap table
   const uint32_t passes32 = (p->m + k32 - 1) / k32;
   const uint32_t passes16 = (p->m + k16 - 1) / k16;
-  p->packed16 = passes16 < passes32;
+  const uint32_t passes8 = (p->m + k8 - 1) / k8;
+  p->bits = passes8 < passes16 ? 8 : (passes16 < passes32 ? 16 : 32);
   const int force_bits = env_int("RTCDF_DEV_COUNTER_BITS", 0);
-  if (force_bits == 16) p->packed16 = true;
-  if (force_bits == 32) p->packed16 = false;
-  const uint32_t k = p->packed16 ? k16 : k32;
-  p->passes = p->packed16 ? passes16 : passes32;
+  if (force_bits == 8 || force_bits == 16 || force_bits == 32) p->bits = (uint32_t)force_bits;
+  const uint32_t k = p->bits == 8 ? k8 : (p->bits == 16 ? k16 : k32);
+  p->passes = (p->m + k - 1) / k;
   p->W = p->passes == 1 ? std::min<uint32_t>(Rr, k * p->T) : k * p->T;
-  p->row_words = p->packed16 ? p->W / 2 : p->W;
+  p->row_words = p->W / (32 / p->bits);
   p->hist_block = 1024 / p->bpt;
   p->hist_interleave = (uint32_t)env_int("RTCDF_DEV_HIST_INTERLEAVE", 1);
 
@@ -182,7 +184,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   off = align256(off + ((size_t)p->nchunks + 1) * 4);
   // Carry entries cover every bin of every pass (plus the partner of the last
   // bin), so even keys outside the declared range stay in bounds.
-  p->carry_words = p->packed16 ? (size_t)p->passes * p->W + 2 : 0;
+  p->carry_words = p->bits < 32 ? (size_t)p->passes * p->W + 4 : 0;
   p->off_carry = off;                       // used by the caller-workspace form only
   off = align256(off + p->carry_words * 4);
   p->ws_bytes = off;
@@ -528,6 +530,41 @@ rtcdf_status_t rtcdf_profile_collect(rtcdf_stage_stats_t* out) {
 }
 
 int rtcdf_version(void) { return 100; }
+
+rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,
+                               const int32_t* keys_in, const int32_t* keys_out, rtcdf_plan_info_t* out) {
+  if (out == nullptr || n == 0) return RTCDF_ERROR_INVALID_VALUE;
+  const int32_t* probe = reinterpret_cast<const int32_t*>((uintptr_t)256);
+  rtcdf_status_t st = check_problem(probe, probe, n, minVal, maxVal);
+  if (st != RTCDF_SUCCESS) return st;
+  DeviceInfo dev;
+  st = device_info(&dev);
+  if (st != RTCDF_SUCCESS) return st;
+  rtcdf_config_t c;
+  if (!config_is_zero(cfg)) {
+    if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
+    c = *cfg;
+  } else {
+    st = pick_config(nullptr, n, minVal, maxVal, nullptr, &c);
+    if (st != RTCDF_SUCCESS) return st;
+  }
+  Plan p;
+  make_plan(n, minVal, maxVal, c, keys_in ? keys_in : probe, keys_out ? keys_out : probe, dev, &p);
+  out->tile_width = p.T;
+  out->tiles = p.m;
+  out->counter_bits = p.bits;
+  out->passes = p.passes;
+  out->pass_bins = p.W;
+  out->hist_workgroups = p.passes * p.G;
+  out->hist_threads = p.hist_block;
+  out->items_per_thread = p.items;
+  out->scan_workgroups = p.m * p.scan_parts;
+  out->out_chunk = p.chunk;
+  out->out_chunks = p.nchunks;
+  out->fill_workgroups = p.fill_grid;
+  out->workspace_bytes = p.ws_bytes;
+  return RTCDF_SUCCESS;
+}
 
 rtcdf_status_t rtcdf_stream_copy(const void* d_src, void* d_dst, size_t bytes, hipStream_t stream) {
   if (bytes == 0) return RTCDF_SUCCESS;

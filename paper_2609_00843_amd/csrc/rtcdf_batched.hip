@@ -153,6 +153,7 @@ __device__ void count_segment(const int32_t* in, uint32_t n, uint32_t min_u, uin
   const uint32_t n4 = (n - head) / 4, tail = n - head - 4 * n4;
   const v4i* body = reinterpret_cast<const v4i*>(in + head);
   const v4i outside = (v4i)(int)(min_u - 1u);   // normalises to 0xffffffff: never counted
+  HotBin hot;                                    // unused by the 32- and 16-bit forms
   v4i cur[V];
 #pragma unroll
   for (int j = 0; j < V; ++j) {
@@ -168,7 +169,7 @@ __device__ void count_segment(const int32_t* in, uint32_t n, uint32_t min_u, uin
       nxt[j] = idx < n4 ? __builtin_nontemporal_load(&body[idx]) : outside;
     }
 #pragma unroll
-    for (int j = 0; j < V; ++j) count4<PACKED, !PACKED>(S, cur[j], min_u, R, carry, 0u, kBSpare);
+    for (int j = 0; j < V; ++j) count4<PACKED ? 16 : 32, !PACKED>(S, cur[j], min_u, R, carry, 0u, kBSpare, nullptr, hot);
 #pragma unroll
     for (int j = 0; j < V; ++j) cur[j] = nxt[j];
   }
@@ -176,7 +177,7 @@ __device__ void count_segment(const int32_t* in, uint32_t n, uint32_t min_u, uin
     v4i e = outside;
     if (tid < head) e.x = in[tid];
     if (tid < tail) e.y = in[head + 4 * n4 + tid];
-    count4<PACKED, !PACKED>(S, e, min_u, R, carry, 0u, kBSpare);
+    count4<PACKED ? 16 : 32, !PACKED>(S, e, min_u, R, carry, 0u, kBSpare, nullptr, hot);
   }
 }
 

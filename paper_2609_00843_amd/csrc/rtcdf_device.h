@@ -106,17 +106,78 @@ __device__ __forceinline__ void add_u16(uint32_t* S, uint32_t x, uint32_t c, uin
   fix_u16(old, x, c, carry, pass_lo);
 }
 
-// Counts the four keys of one vector per lane.  If every active lane of the
-// wave holds four copies of one value (all-equal or heavily skewed keys), a
-// single lane adds them with one LDS atomic instead of 4 x 64 atomics on the
-// same address.  Otherwise every key takes one LDS atomic without branching:
-// a key outside the pass adds 0 to a per-lane spare word S[spare + lane].
-// In the 16-bit form the four returning atomics are issued back to back and a
-// half that just wrapped (it held 0xffff before the +1) is repaired after a
-// single wave-wide test.
-template <bool PACKED, bool PAD = false>
+// Wrap table of the 8-bit form: kWrapSlots (bin, amount) pairs in LDS that
+// collect the repairs of one workgroup, so that a heavily hit bin costs one
+// global atomic per workgroup at the end instead of one per wrap.  Slot
+// bin % kWrapSlots belongs to the first bin that claims it; a repair whose slot
+// is held by another bin goes straight to the global carry array.
+constexpr uint32_t kWrapSlots = 64;
+constexpr uint32_t kWrapEmpty = 0xffffffffu;
+
+__device__ __forceinline__ void wrap_add(uint32_t* tab, uint32_t bin, uint32_t d, uint32_t* carry,
+                                         uint32_t pass_lo) {
+  uint32_t* slot = tab + (bin & (kWrapSlots - 1));
+  const uint32_t prev = atomicCAS(slot, kWrapEmpty, bin);
+  if (prev == kWrapEmpty || prev == bin) atomicAdd(slot + kWrapSlots, d);
+  else atomicAdd(&carry[pass_lo + bin], d);
+}
+
+// Moves the table's amounts to the global carry array (one thread per slot,
+// after the workgroup's last count).
+__device__ __forceinline__ void wrap_flush(const uint32_t* tab, uint32_t* carry, uint32_t pass_lo,
+                                           uint32_t t) {
+  if (t < kWrapSlots) {
+    const uint32_t bin = tab[t], d = tab[t + kWrapSlots];
+    if (bin != kWrapEmpty && d != 0u) atomicAdd(&carry[pass_lo + bin], d);
+  }
+}
+
+// Wave-uniform accumulator of the 8-bit form's all-equal fast path: a wave
+// whose four keys per lane are one value adds them to this register (an add
+// of up to 256 would wrap a byte counter every time); it goes to the wrap
+// table when the value changes and at the end.
+struct HotBin {
+  uint32_t bin = kWrapEmpty;
+  uint32_t cnt = 0;
+};
+
+__device__ __forceinline__ void hot_flush(HotBin& hot, uint32_t* tab, uint32_t* carry, uint32_t pass_lo) {
+  if (hot.cnt && lane_id() == (uint32_t)(__ffsll((unsigned long long)__ballot(1)) - 1))
+    wrap_add(tab, hot.bin, hot.cnt, carry, pass_lo);
+  hot.cnt = 0;
+}
+
+// Four 8-bit counters per LDS word (bin x in byte x & 3 of word x >> 2).  An
+// add of c << 8s changes the bytes above s through carries; every byte whose
+// represented change differs from its true change (c for byte s, 0 above) is
+// repaired, modulo 2^32, through the wrap table.  Rare for spread-out keys.
+__device__ __forceinline__ void fix_u8(uint32_t old, uint32_t x, uint32_t c, uint32_t* tab,
+                                       uint32_t* carry, uint32_t pass_lo) {
+  const uint32_t s = x & 3u, s8 = s << 3;
+  const uint32_t nw = old + (c << s8);
+  const uint32_t base = x & ~3u;
+  for (uint32_t j = s; j < 4; ++j) {
+    const int32_t rep = (int32_t)((nw >> (8 * j)) & 0xffu) - (int32_t)((old >> (8 * j)) & 0xffu);
+    const int32_t tru = j == s ? (int32_t)c : 0;
+    if (rep != tru) wrap_add(tab, base + j, (uint32_t)(tru - rep), carry, pass_lo);
+  }
+}
+
+// Counts the four keys of one vector per lane with BITS-bit LDS counters (32,
+// 16 or 8).  If every active lane of the wave holds four copies of one value
+// (all-equal or heavily skewed keys), a single lane adds them with one LDS
+// atomic instead of 4 x 64 atomics on the same address (8-bit form: into the
+// wave's hot-bin register, since such adds would wrap a byte).  Otherwise
+// every key takes one LDS atomic without branching: a key outside the pass
+// adds 0 to a per-lane spare word S[spare + lane].  In the narrow forms the
+// four returning atomics are issued back to back and a counter that just
+// wrapped is repaired after a single wave-wide test.  PAD selects the padded
+// 32-bit layout (bin x at x + x / 32).  `tab` and `hot` (the wrap table and
+// the hot-bin register) are used by the 8-bit form only.
+template <int BITS, bool PAD = false>
 __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32_t W,
-                                       uint32_t* carry, uint32_t pass_lo, uint32_t spare) {
+                                       uint32_t* carry, uint32_t pass_lo, uint32_t spare, uint32_t* tab,
+                                       HotBin& hot) {
   const uint32_t x0 = (uint32_t)k.x - base, x1 = (uint32_t)k.y - base;
   const uint32_t x2 = (uint32_t)k.z - base, x3 = (uint32_t)k.w - base;
   const uint32_t lead = (uint32_t)__builtin_amdgcn_readfirstlane((int)x0);
@@ -124,30 +185,49 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
   const uint64_t same = __ballot(four);
   const uint64_t active = __ballot(1);
   if (same == active) {
-    if (lead < W && lane_id() == (uint32_t)(__ffsll((unsigned long long)active) - 1)) {
+    if (lead < W) {
       const uint32_t c = 4u * (uint32_t)__popcll(active);
-      if constexpr (PACKED) add_u16(S, lead, c, carry, pass_lo);
-      else atomicAdd(&S[PAD ? pad32(lead) : lead], c);
+      if constexpr (BITS == 8) {
+        if (lead != hot.bin) {
+          hot_flush(hot, tab, carry, pass_lo);
+          hot.bin = lead;
+        }
+        hot.cnt += c;
+      } else if (lane_id() == (uint32_t)(__ffsll((unsigned long long)active) - 1)) {
+        if constexpr (BITS == 16) add_u16(S, lead, c, carry, pass_lo);
+        else atomicAdd(&S[PAD ? pad32(lead) : lead], c);
+      }
     }
     return;
   }
   const uint32_t sp = spare + lane_id();
-  if constexpr (PACKED) {
-    const uint32_t s0 = (x0 & 1u) << 4, s1 = (x1 & 1u) << 4, s2 = (x2 & 1u) << 4, s3 = (x3 & 1u) << 4;
-    const uint32_t o0 = atomicAdd(&S[x0 < W ? x0 >> 1 : sp], x0 < W ? 1u << s0 : 0u);
-    const uint32_t o1 = atomicAdd(&S[x1 < W ? x1 >> 1 : sp], x1 < W ? 1u << s1 : 0u);
-    const uint32_t o2 = atomicAdd(&S[x2 < W ? x2 >> 1 : sp], x2 < W ? 1u << s2 : 0u);
-    const uint32_t o3 = atomicAdd(&S[x3 < W ? x3 >> 1 : sp], x3 < W ? 1u << s3 : 0u);
+  if constexpr (BITS == 16 || BITS == 8) {
+    // bin x is field x & MASK of word x >> LOG; a field is 1 << SH bits wide
+    constexpr uint32_t LOG = BITS == 16 ? 1 : 2, MASK = BITS == 16 ? 1 : 3, SH = BITS == 16 ? 4 : 3;
+    constexpr uint32_t FULL = BITS == 16 ? 0xffffu : 0xffu;
+    const uint32_t s0 = (x0 & MASK) << SH, s1 = (x1 & MASK) << SH;
+    const uint32_t s2 = (x2 & MASK) << SH, s3 = (x3 & MASK) << SH;
+    const uint32_t o0 = atomicAdd(&S[x0 < W ? x0 >> LOG : sp], x0 < W ? 1u << s0 : 0u);
+    const uint32_t o1 = atomicAdd(&S[x1 < W ? x1 >> LOG : sp], x1 < W ? 1u << s1 : 0u);
+    const uint32_t o2 = atomicAdd(&S[x2 < W ? x2 >> LOG : sp], x2 < W ? 1u << s2 : 0u);
+    const uint32_t o3 = atomicAdd(&S[x3 < W ? x3 >> LOG : sp], x3 < W ? 1u << s3 : 0u);
     // The spare words only ever receive 0, so they never look wrapped.
-    const bool w0 = ((o0 >> s0) & 0xffffu) == 0xffffu && x0 < W;
-    const bool w1 = ((o1 >> s1) & 0xffffu) == 0xffffu && x1 < W;
-    const bool w2 = ((o2 >> s2) & 0xffffu) == 0xffffu && x2 < W;
-    const bool w3 = ((o3 >> s3) & 0xffffu) == 0xffffu && x3 < W;
+    const bool w0 = ((o0 >> s0) & FULL) == FULL && x0 < W;
+    const bool w1 = ((o1 >> s1) & FULL) == FULL && x1 < W;
+    const bool w2 = ((o2 >> s2) & FULL) == FULL && x2 < W;
+    const bool w3 = ((o3 >> s3) & FULL) == FULL && x3 < W;
     if (__ballot(w0 | w1 | w2 | w3)) {
-      if (w0) fix_u16(o0, x0, 1u, carry, pass_lo);
-      if (w1) fix_u16(o1, x1, 1u, carry, pass_lo);
-      if (w2) fix_u16(o2, x2, 1u, carry, pass_lo);
-      if (w3) fix_u16(o3, x3, 1u, carry, pass_lo);
+      if constexpr (BITS == 16) {
+        if (w0) fix_u16(o0, x0, 1u, carry, pass_lo);
+        if (w1) fix_u16(o1, x1, 1u, carry, pass_lo);
+        if (w2) fix_u16(o2, x2, 1u, carry, pass_lo);
+        if (w3) fix_u16(o3, x3, 1u, carry, pass_lo);
+      } else {
+        if (w0) fix_u8(o0, x0, 1u, tab, carry, pass_lo);
+        if (w1) fix_u8(o1, x1, 1u, tab, carry, pass_lo);
+        if (w2) fix_u8(o2, x2, 1u, tab, carry, pass_lo);
+        if (w3) fix_u8(o3, x3, 1u, tab, carry, pass_lo);
+      }
     }
   } else {
     const uint32_t y0 = PAD ? pad32(x0) : x0, y1 = PAD ? pad32(x1) : x1;

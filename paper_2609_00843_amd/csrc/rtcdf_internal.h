@@ -38,11 +38,11 @@ struct Plan {
   // config knobs
   uint32_t items, bpt;
   // histogram passes
-  bool packed16;         // two 16-bit counters per LDS word
+  uint32_t bits;         // LDS counter width: 32, 16 (two per word) or 8 (four per word)
   uint32_t W;            // bins per LDS pass (multiple of 128, or R rounded up when one pass)
   uint32_t passes;       // ceil(R / W)
   uint32_t G;            // workgroups (input chunks) per pass, multiple of 8
-  uint32_t row_words;    // 32-bit words per partial row (W or W/2)
+  uint32_t row_words;    // 32-bit words per partial row (W * bits / 32)
   uint32_t hist_block;   // threads per histogram workgroup
   uint32_t hist_interleave;  // 1: tiles dealt round-robin to chunks; 0: contiguous chunks
   uint32_t in_head;      // keys before the 16-byte aligned input body
@@ -59,7 +59,7 @@ struct Plan {
   // workspace layout
   size_t off_partial, off_hist, off_cdf, off_rsum, off_O, off_split, ws_bytes;
   size_t off_carry;      // carry array inside a caller-owned workspace (rtcdf_sort_ws)
-  size_t carry_words;    // 0 unless packed16
+  size_t carry_words;    // 0 for 32-bit counters
 };
 
 struct DeviceInfo {

@@ -40,7 +40,7 @@ struct HistArgs {
   uint32_t* carry;
 };
 
-template <int ITEMS, bool PACKED, int BLOCK>
+template <int ITEMS, int BITS, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   extern __shared__ uint32_t S[];
   // XCD-aware mapping: workgroup ids are dealt round-robin to the 8 XCDs, so
@@ -49,8 +49,14 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   const uint32_t wg = blockIdx.x, xcd = wg & 7u, slot = wg >> 3;
   const uint32_t pass = slot % a.passes;
   const uint32_t chunk = (slot / a.passes) * 8u + xcd;
-  const uint32_t lds_words = a.row_words + 64u;   // + one spare word per lane
+  // LDS: the counters, one spare word per lane, then (8-bit form) the wrap
+  // table's bins and amounts.
+  const uint32_t lds_words = a.row_words + 64u;
+  uint32_t* tab = S + lds_words;
   for (uint32_t i = threadIdx.x; i < lds_words; i += BLOCK) S[i] = 0u;
+  if constexpr (BITS == 8) {
+    if (threadIdx.x < 2 * kWrapSlots) tab[threadIdx.x] = threadIdx.x < kWrapSlots ? kWrapEmpty : 0u;
+  }
   __syncthreads();
 
   const uint32_t pass_lo = pass * a.W;
@@ -60,6 +66,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   constexpr int V = ITEMS / 4;
   const v4i* body = reinterpret_cast<const v4i*>(a.keys + a.in_head);
   const v4i outside = (v4i)(int)(base - 1u);   // lands outside every pass
+  HotBin hot;                                  // 8-bit form only
   uint64_t t0, step, end;
   if (a.interleave) {
     // Tiles of BLOCK * V vectors dealt round-robin to the G chunks of a pass:
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
       nxt[j] = idx < end ? __builtin_nontemporal_load(&body[idx]) : outside;
     }
 #pragma unroll
-    for (int j = 0; j < V; ++j) count4<PACKED>(S, cur[j], base, W, a.carry, pass_lo, a.row_words);
+    for (int j = 0; j < V; ++j) count4<BITS>(S, cur[j], base, W, a.carry, pass_lo, a.row_words, tab, hot);
 #pragma unroll
     for (int j = 0; j < V; ++j) cur[j] = nxt[j];
     t0 = t1;
@@ -99,8 +106,10 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   v4i e = outside;
   if (chunk == 0 && threadIdx.x < a.in_head) e.x = a.keys[threadIdx.x];
   if (chunk == a.G - 1 && threadIdx.x < a.in_tail) e.y = a.keys[a.in_head + 4 * a.in_n4 + threadIdx.x];
-  if (threadIdx.x < 64) count4<PACKED>(S, e, base, W, a.carry, pass_lo, a.row_words);
+  if (threadIdx.x < 64) count4<BITS>(S, e, base, W, a.carry, pass_lo, a.row_words, tab, hot);
+  if constexpr (BITS == 8) hot_flush(hot, tab, a.carry, pass_lo);
   __syncthreads();
+  if constexpr (BITS == 8) wrap_flush(tab, a.carry, pass_lo, threadIdx.x);
 
   uint32_t* row = a.partial + ((size_t)pass * a.G + chunk) * a.row_words;
   for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) row[i] = S[i];
@@ -113,59 +122,78 @@ struct ReduceArgs {
   uint32_t* carry;
   uint32_t* hist;
   uint32_t* rsum;
-  uint32_t R, W, G, row_words, carry_words;
-  bool packed;
+  uint32_t R, W, G, row_words, carry_words, bits;
 };
 
+// Adds rows g0, g0 + NG, ... < G of the column src (stride rs words), split
+// into 32 / BITS counters per word, into acc[0 .. 32 / BITS).
+template <int BITS>
+__device__ __forceinline__ void sum_rows(const uint32_t* src, size_t rs, uint32_t g0, uint32_t G,
+                                         uint32_t NG, uint32_t* acc) {
+  uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  auto add = [&](uint32_t w) {
+    if constexpr (BITS == 32) {
+      a0 += w;
+    } else if constexpr (BITS == 16) {
+      a0 += w & 0xffffu;
+      a1 += w >> 16;
+    } else {
+      a0 += w & 0xffu;
+      a1 += (w >> 8) & 0xffu;
+      a2 += (w >> 16) & 0xffu;
+      a3 += w >> 24;
+    }
+  };
+  uint32_t g = g0;
+  for (; g + 3 * NG < G; g += 4 * NG) {
+    const uint32_t w0 = src[(size_t)g * rs], w1 = src[(size_t)(g + NG) * rs];
+    const uint32_t w2 = src[(size_t)(g + 2 * NG) * rs], w3 = src[(size_t)(g + 3 * NG) * rs];
+    add(w0);
+    add(w1);
+    add(w2);
+    add(w3);
+  }
+  for (; g < G; g += NG) add(src[(size_t)g * rs]);
+  acc[0] = a0;
+  acc[1] = a1;
+  acc[2] = a2;
+  acc[3] = a3;
+}
+
+// Sums, for the 128 bins of one block, the G partial rows of the block's pass
+// (counters of `bits` bits, 32 / bits per word), adds the carry array (narrow
+// counters) and re-zeroes it, and writes H and the block total.
 __global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
-  __shared__ uint32_t red[16][kReduceBins + 1];
+  __shared__ uint32_t red[32][kReduceBins + 1];
   __shared__ uint32_t wsum[kReduceBlock / 64];
   const uint32_t r0 = blockIdx.x * kReduceBins;
   const uint32_t pass = r0 / a.W, o = r0 - pass * a.W;
   const uint32_t* rows = a.partial + (size_t)pass * a.G * a.row_words;
   const uint32_t tid = threadIdx.x;
-  // Row groups: 16 groups of 64 words (16-bit counters) or 8 groups of 128
-  // words (32-bit counters); each thread sums every NG-th row, four loads in
+  // A block's 128 bins are 128 / per words of each row; the 1024 threads are
+  // (row group, word) pairs and each sums every NG-th row, four loads in
   // flight at a time.
-  const uint32_t NG = a.packed ? 16u : 8u;
-  const uint32_t c = a.packed ? (tid & 63u) : (tid & 127u);
-  const uint32_t rg = a.packed ? (tid >> 6) : (tid >> 7);
-  const uint32_t col = a.packed ? (o >> 1) + c : o + c;
-  const uint32_t* src = rows + col;
+  const uint32_t per = 32 / a.bits, words = kReduceBins / per, NG = kReduceBlock / words;
+  const uint32_t c = tid % words, rg = tid / words;
+  const uint32_t* src = rows + o / per + c;
   const size_t rs = a.row_words;
-  uint32_t lo = 0, hi = 0;
-  uint32_t g = rg;
-  for (; g + 3 * NG < a.G; g += 4 * NG) {
-    const uint32_t w0 = src[(size_t)g * rs], w1 = src[(size_t)(g + NG) * rs];
-    const uint32_t w2 = src[(size_t)(g + 2 * NG) * rs], w3 = src[(size_t)(g + 3 * NG) * rs];
-    if (a.packed) {
-      lo += (w0 & 0xffffu) + (w1 & 0xffffu) + (w2 & 0xffffu) + (w3 & 0xffffu);
-      hi += (w0 >> 16) + (w1 >> 16) + (w2 >> 16) + (w3 >> 16);
-    } else {
-      lo += w0 + w1 + w2 + w3;
-    }
-  }
-  for (; g < a.G; g += NG) {
-    const uint32_t w = src[(size_t)g * rs];
-    if (a.packed) {
-      lo += w & 0xffffu;
-      hi += w >> 16;
-    } else {
-      lo += w;
-    }
-  }
-  if (a.packed) {
-    red[rg][2 * c] = lo;
-    red[rg][2 * c + 1] = hi;
-  } else {
-    red[rg][c] = lo;
+  uint32_t acc[4] = {0, 0, 0, 0};
+  if (a.bits == 32) sum_rows<32>(src, rs, rg, a.G, NG, acc);
+  else if (a.bits == 16) sum_rows<16>(src, rs, rg, a.G, NG, acc);
+  else sum_rows<8>(src, rs, rg, a.G, NG, acc);
+  const uint32_t acc0 = acc[0], acc1 = acc[1], acc2 = acc[2], acc3 = acc[3];
+  red[rg][per * c] = acc0;
+  if (per > 1) red[rg][per * c + 1] = acc1;
+  if (per > 2) {
+    red[rg][per * c + 2] = acc2;
+    red[rg][per * c + 3] = acc3;
   }
   __syncthreads();
   uint32_t tot = 0;
   if (tid < kReduceBins) {
     for (uint32_t q = 0; q < NG; ++q) tot += red[q][tid];
     const uint32_t bin = r0 + tid;
-    if (a.packed && bin < a.carry_words) {
+    if (a.bits < 32 && bin < a.carry_words) {
       tot += a.carry[bin];
       a.carry[bin] = 0u;   // keep the carry array zero between sorts
     }
@@ -448,10 +476,10 @@ __global__ void k_clear(uint32_t* p, size_t words) {
     p[i] = 0u;
 }
 
-template <int ITEMS, bool PACKED, int BLOCK>
+template <int ITEMS, int BITS, int BLOCK>
 hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
-  const size_t lds = ((size_t)p.row_words + 64) * 4;
-  auto kern = k_hist<ITEMS, PACKED, BLOCK>;
+  const size_t lds = ((size_t)p.row_words + 64 + (BITS == 8 ? 2 * kWrapSlots : 0)) * 4;
+  auto kern = k_hist<ITEMS, BITS, BLOCK>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -459,21 +487,21 @@ hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <bool PACKED, int BLOCK>
+template <int BITS, int BLOCK>
 hipError_t launch_hist_items(const Plan& p, const HistArgs& a, hipStream_t s) {
   switch (p.items) {
-    case 4: return launch_hist_t<4, PACKED, BLOCK>(p, a, s);
-    case 8: return launch_hist_t<8, PACKED, BLOCK>(p, a, s);
-    default: return launch_hist_t<16, PACKED, BLOCK>(p, a, s);
+    case 4: return launch_hist_t<4, BITS, BLOCK>(p, a, s);
+    case 8: return launch_hist_t<8, BITS, BLOCK>(p, a, s);
+    default: return launch_hist_t<16, BITS, BLOCK>(p, a, s);
   }
 }
 
-template <bool PACKED>
+template <int BITS>
 hipError_t launch_hist_block(const Plan& p, const HistArgs& a, hipStream_t s) {
   switch (p.hist_block) {
-    case 1024: return launch_hist_items<PACKED, 1024>(p, a, s);
-    case 512: return launch_hist_items<PACKED, 512>(p, a, s);
-    default: return launch_hist_items<PACKED, 256>(p, a, s);
+    case 1024: return launch_hist_items<BITS, 1024>(p, a, s);
+    case 512: return launch_hist_items<BITS, 512>(p, a, s);
+    default: return launch_hist_items<BITS, 256>(p, a, s);
   }
 }
 
@@ -515,7 +543,11 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
   a.partial = reinterpret_cast<uint32_t*>(ws + p.off_partial);
   a.carry = carry;
   a.interleave = p.hist_interleave;
-  return p.packed16 ? launch_hist_block<true>(p, a, s) : launch_hist_block<false>(p, a, s);
+  switch (p.bits) {
+    case 8: return launch_hist_block<8>(p, a, s);
+    case 16: return launch_hist_block<16>(p, a, s);
+    default: return launch_hist_block<32>(p, a, s);
+  }
 }
 
 hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_t s) {
@@ -529,7 +561,7 @@ hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_
   a.G = p.G;
   a.row_words = p.row_words;
   a.carry_words = (uint32_t)p.carry_words;
-  a.packed = p.packed16;
+  a.bits = p.bits;
   hipLaunchKernelGGL(k_reduce, dim3(p.nred), dim3(kReduceBlock), 0, s, a);
   return hipGetLastError();
 }

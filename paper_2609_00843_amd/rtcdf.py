@@ -416,3 +416,29 @@ def mlp_pick(keys_in, minVal: int, maxVal: int, params, norm, valid, stream=None
                               _ptr(norm), _ptr(valid), _ptr(idx), _ptr(pred), _stream_ptr(stream)),
            "rtcdf_mlp_pick")
     return idx, pred
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint32) for k in (
+        "tile_width", "tiles", "counter_bits", "passes", "pass_bins", "hist_workgroups",
+        "hist_threads", "items_per_thread", "scan_workgroups", "out_chunk", "out_chunks",
+        "fill_workgroups")] + [("workspace_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+if hasattr(lib, "rtcdf_plan_info"):
+    lib.rtcdf_plan_info.argtypes = [_sz, _i64, _i64, _cfgp, _vp, _vp, ctypes.POINTER(PlanInfo)]
+    lib.rtcdf_plan_info.restype = ctypes.c_int
+
+
+def plan_info(n: int, minVal: int, maxVal: int, config: Config | None = None, keys_in=None,
+              keys_out=None) -> dict:
+    out = PlanInfo()
+    _check(lib.rtcdf_plan_info(int(n), int(minVal), int(maxVal),
+                               ctypes.byref(config) if config is not None else None,
+                               _ptr(keys_in) if keys_in is not None else None,
+                               _ptr(keys_out) if keys_out is not None else None, ctypes.byref(out)),
+           "rtcdf_plan_info")
+    return out.as_dict()

@@ -107,3 +107,5 @@ def test_segment_layout(r):
     assert ctypes.sizeof(r.Segment) == 32
     assert ctypes.sizeof(r.BatchBounds) == 16
     assert ctypes.sizeof(r.Config) == 16
+    assert ctypes.sizeof(r.PlanInfo) == 56
+    assert ctypes.sizeof(r.StageStats) == 40

@@ -118,18 +118,50 @@ def test_extreme_ranges(r):
     _run(r, A, 2 ** 31 - 1, 2 ** 31)
 
 
-@pytest.mark.parametrize("R", [1 << 16, 1 << 16 | 1, 1 << 18])
-def test_sixteen_bit_counter_overflow(r, R):
-    """More than 65535 equal keys per workgroup in 16-bit packed counters, in
-    both halves of one LDS word and in the last (phantom-paired) bin."""
+@pytest.mark.parametrize("R", [1 << 16, 1 << 16 | 1, 79873, 1 << 17, 1 << 18])
+def test_packed_counter_overflow(r, R):
+    """More equal keys per workgroup than a packed LDS counter holds (65535 in
+    16-bit, 255 in 8-bit counters), in every byte / half of one LDS word and in
+    the last (phantom-paired) bin; R = 2^16 and 65537 take 16-bit counters,
+    79873, 2^17 and 2^18 take 8-bit ones at the default tile width."""
     n = 40_000_000
-    base = np.array([0, 1, 2, R - 1], dtype=np.int64)
     rng = np.random.default_rng(R)
-    for pick in ([0], [0, 1], [1], [R - 1], [2, 3, R - 1]):
+    for pick in ([0], [0, 1], [1], [R - 1], [2, 3, R - 1], [0, 1, 2, 3], [4, 6, 7]):
         vals = np.asarray(pick, dtype=np.int64)
         A = (vals[rng.integers(0, vals.size, size=n)] - 77).astype(np.int32)
         _run(r, A, -77, -77 + R)
-    del base
+
+
+@pytest.mark.parametrize("k", [97, 1024, 20000])
+def test_few_distinct_values_wide_range(r, k):
+    """k distinct values spread over R = 2^18: each of them wraps 8-bit
+    counters a few times (k = 97, 1024) or about once (k = 20000) per
+    workgroup."""
+    R = 1 << 18
+    rng = np.random.default_rng(k)
+    vals = rng.choice(R, size=k, replace=False)
+    A = vals[rng.integers(0, k, size=20_000_000)].astype(np.int32)
+    _run(r, A, 0, R)
+
+
+@pytest.mark.parametrize("bits", [8, 16, 32])
+@pytest.mark.parametrize("dist,R", [("zipf", 1000), ("normal", 65537), ("uniform", 1 << 18),
+                                    ("all_equal", 1 << 17)])
+def test_forced_counter_width(r, monkeypatch, bits, dist, R):
+    """Every counter width gives the same output on every range, whichever the
+    plan would choose by itself."""
+    monkeypatch.setenv("RTCDF_DEV_COUNTER_BITS", str(bits))
+    A = inputs.make(dist, 3_000_017, 9, 9 + R, inputs.case_seed(4, R))
+    info = r.plan_info(A.size, 9, 9 + R)
+    assert info["counter_bits"] == bits
+    _run(r, A, 9, 9 + R)
+
+
+def test_plan_counter_width_choice(r):
+    """The plan takes the narrowest counters only when they save a pass."""
+    widths = {R: r.plan_info(10 ** 8, 0, R)["counter_bits"] for R in (128, 65536, 1 << 17, 1 << 18)}
+    assert widths[128] == 32 and widths[65536] == 16
+    assert widths[1 << 17] == 8 and widths[1 << 18] == 8
 
 
 def _grid():
