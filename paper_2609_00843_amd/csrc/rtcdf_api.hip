@@ -114,7 +114,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // Histogram passes: as many whole tiles per workgroup LDS as fit, with 32-bit
   // counters, or with two 16-bit or four 8-bit counters per word when that
   // needs fewer passes over the input.
-  const uint32_t lds = kLdsBytes / p->bpt - 256;   // 64 spare words
+  const uint32_t lds = kLdsBytes / p->bpt;
   const uint32_t k32 = std::max<uint32_t>(1, lds / (4 * p->T));
   const uint32_t k16 = std::max<uint32_t>(1, lds / (2 * p->T));
   const uint32_t k8 = std::max<uint32_t>(1, (lds - 512) / p->T);   // 512 B wrap table
@@ -162,11 +162,20 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   p->chunk = (uint32_t)((want + gran - 1) / gran * gran);
   p->nchunks = 1 + ((n >= 1 && n - 1 >= p->out_head) ? (uint32_t)((n - 1 - p->out_head) / p->chunk) : 0);
   p->fill_grid = (uint32_t)std::min<uint64_t>(p->nchunks, (uint64_t)dev.cus * fill_per_cu);
-  // Enough workgroups in the local-CDF stage to spread the splitters of a
-  // single tile over the chip, but no more than one per 256 chunk boundaries.
-  const uint32_t want_parts = std::max<uint32_t>(1, (uint32_t)dev.cus / p->m);
-  const uint32_t by_work = std::max<uint32_t>(1, p->nchunks / std::max<uint32_t>(1, p->m) / 256);
-  p->scan_parts = std::min<uint32_t>(want_parts, by_work);
+  // Local-CDF stage: enough workgroups to spread the splitters over the chip,
+  // but no more than one per 256 chunk starts.  With at most kScanBlock tiles
+  // and 8 * kScanBlock block totals the kernel assigns the workgroups to tiles
+  // by their share of chunk starts (it sees the counts); otherwise every tile
+  // gets the same number of workgroups.
+  const uint32_t by_work = std::max<uint32_t>(1, p->nchunks / 256);
+  if (p->m <= kScanBlock && p->nred <= 8 * kScanBlock) {
+    p->scan_parts = 1;
+    p->scan_grid = std::max<uint32_t>(p->m, std::min<uint32_t>((uint32_t)dev.cus, by_work));
+  } else {
+    const uint32_t want_parts = std::max<uint32_t>(1, (uint32_t)dev.cus / p->m);
+    p->scan_parts = std::min<uint32_t>(want_parts, std::max<uint32_t>(1, by_work / p->m));
+    p->scan_grid = p->m * p->scan_parts;
+  }
 
   // Workspace layout.
   size_t off = 0;
@@ -558,7 +567,7 @@ rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const r
   out->hist_workgroups = p.passes * p.G;
   out->hist_threads = p.hist_block;
   out->items_per_thread = p.items;
-  out->scan_workgroups = p.m * p.scan_parts;
+  out->scan_workgroups = p.scan_grid;
   out->out_chunk = p.chunk;
   out->out_chunks = p.nchunks;
   out->fill_workgroups = p.fill_grid;

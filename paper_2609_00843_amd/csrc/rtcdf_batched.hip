@@ -28,8 +28,7 @@ using namespace dev;
 
 constexpr uint32_t kBBlock = 1024;
 constexpr uint32_t kBTile = 32768;                   // values per local CDF tile
-constexpr uint32_t kBSpare = 33792;                  // pad32(kBTile): first LDS word past any padded bin
-constexpr uint32_t kBLdsWords = kBSpare + 64;        // + one spare word per lane
+constexpr uint32_t kBLdsWords = 33792;               // pad32(kBTile): LDS words of one padded tile
 constexpr uint32_t kBBuckets = 34;
 
 struct BatchArgs {
@@ -169,7 +168,7 @@ __device__ void count_segment(const int32_t* in, uint32_t n, uint32_t min_u, uin
       nxt[j] = idx < n4 ? __builtin_nontemporal_load(&body[idx]) : outside;
     }
 #pragma unroll
-    for (int j = 0; j < V; ++j) count4<PACKED ? 16 : 32, !PACKED>(S, cur[j], min_u, R, carry, 0u, kBSpare, nullptr, hot);
+    for (int j = 0; j < V; ++j) count4<PACKED ? 16 : 32, !PACKED>(S, cur[j], min_u, R, carry, 0u, nullptr, hot);
 #pragma unroll
     for (int j = 0; j < V; ++j) cur[j] = nxt[j];
   }
@@ -177,7 +176,7 @@ __device__ void count_segment(const int32_t* in, uint32_t n, uint32_t min_u, uin
     v4i e = outside;
     if (tid < head) e.x = in[tid];
     if (tid < tail) e.y = in[head + 4 * n4 + tid];
-    count4<PACKED ? 16 : 32, !PACKED>(S, e, min_u, R, carry, 0u, kBSpare, nullptr, hot);
+    count4<PACKED ? 16 : 32, !PACKED>(S, e, min_u, R, carry, 0u, nullptr, hot);
   }
 }
 
@@ -200,7 +199,6 @@ __device__ void sort_segment(const rtcdf_segment_t& d, uint32_t* S, uint32_t* ws
     // One tile: 32-bit counters in the padded layout, scanned in place.
     const uint32_t words = pad32(R - 1) + 1;
     for (uint32_t i = tid; i < words; i += kBBlock) S[i] = 0u;
-    if (tid < 64) S[kBSpare + tid] = 0u;
     __syncthreads();
     count_segment<V, false>(in, n, min_u, R, S, nullptr);
     __syncthreads();
@@ -213,7 +211,6 @@ __device__ void sort_segment(const rtcdf_segment_t& d, uint32_t* S, uint32_t* ws
   // Two tiles: 16-bit counters, repaired and merged into the workgroup's
   // global count array, then each tile's counts are scanned in LDS.
   for (uint32_t i = tid; i < (R + 1) / 2; i += kBBlock) S[i] = 0u;
-  if (tid < 64) S[kBSpare + tid] = 0u;
   for (uint32_t i = tid; i < R + 2; i += kBBlock) cnt[i] = 0u;
   __threadfence();
   __syncthreads();

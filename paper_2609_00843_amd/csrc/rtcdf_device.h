@@ -168,16 +168,15 @@ __device__ __forceinline__ void fix_u8(uint32_t old, uint32_t x, uint32_t c, uin
 // (all-equal or heavily skewed keys), a single lane adds them with one LDS
 // atomic instead of 4 x 64 atomics on the same address (8-bit form: into the
 // wave's hot-bin register, since such adds would wrap a byte).  Otherwise
-// every key takes one LDS atomic without branching: a key outside the pass
-// adds 0 to a per-lane spare word S[spare + lane].  In the narrow forms the
-// four returning atomics are issued back to back and a counter that just
-// wrapped is repaired after a single wave-wide test.  PAD selects the padded
-// 32-bit layout (bin x at x + x / 32).  `tab` and `hot` (the wrap table and
-// the hot-bin register) are used by the 8-bit form only.
+// every key inside the pass takes one LDS atomic; keys outside it are masked
+// off.  In the narrow forms the four returning atomics are issued back to
+// back and a counter that just wrapped is repaired after a single wave-wide
+// test.  PAD selects the padded 32-bit layout (bin x at x + x / 32).  `tab`
+// and `hot` (the wrap table and the hot-bin register) are used by the 8-bit
+// form only.
 template <int BITS, bool PAD = false>
 __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32_t W,
-                                       uint32_t* carry, uint32_t pass_lo, uint32_t spare, uint32_t* tab,
-                                       HotBin& hot) {
+                                       uint32_t* carry, uint32_t pass_lo, uint32_t* tab, HotBin& hot) {
   const uint32_t x0 = (uint32_t)k.x - base, x1 = (uint32_t)k.y - base;
   const uint32_t x2 = (uint32_t)k.z - base, x3 = (uint32_t)k.w - base;
   const uint32_t lead = (uint32_t)__builtin_amdgcn_readfirstlane((int)x0);
@@ -200,18 +199,17 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
     }
     return;
   }
-  const uint32_t sp = spare + lane_id();
   if constexpr (BITS == 16 || BITS == 8) {
     // bin x is field x & MASK of word x >> LOG; a field is 1 << SH bits wide
     constexpr uint32_t LOG = BITS == 16 ? 1 : 2, MASK = BITS == 16 ? 1 : 3, SH = BITS == 16 ? 4 : 3;
     constexpr uint32_t FULL = BITS == 16 ? 0xffffu : 0xffu;
     const uint32_t s0 = (x0 & MASK) << SH, s1 = (x1 & MASK) << SH;
     const uint32_t s2 = (x2 & MASK) << SH, s3 = (x3 & MASK) << SH;
-    const uint32_t o0 = atomicAdd(&S[x0 < W ? x0 >> LOG : sp], x0 < W ? 1u << s0 : 0u);
-    const uint32_t o1 = atomicAdd(&S[x1 < W ? x1 >> LOG : sp], x1 < W ? 1u << s1 : 0u);
-    const uint32_t o2 = atomicAdd(&S[x2 < W ? x2 >> LOG : sp], x2 < W ? 1u << s2 : 0u);
-    const uint32_t o3 = atomicAdd(&S[x3 < W ? x3 >> LOG : sp], x3 < W ? 1u << s3 : 0u);
-    // The spare words only ever receive 0, so they never look wrapped.
+    uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+    if (x0 < W) o0 = atomicAdd(&S[x0 >> LOG], 1u << s0);
+    if (x1 < W) o1 = atomicAdd(&S[x1 >> LOG], 1u << s1);
+    if (x2 < W) o2 = atomicAdd(&S[x2 >> LOG], 1u << s2);
+    if (x3 < W) o3 = atomicAdd(&S[x3 >> LOG], 1u << s3);
     const bool w0 = ((o0 >> s0) & FULL) == FULL && x0 < W;
     const bool w1 = ((o1 >> s1) & FULL) == FULL && x1 < W;
     const bool w2 = ((o2 >> s2) & FULL) == FULL && x2 < W;
@@ -232,10 +230,10 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
   } else {
     const uint32_t y0 = PAD ? pad32(x0) : x0, y1 = PAD ? pad32(x1) : x1;
     const uint32_t y2 = PAD ? pad32(x2) : x2, y3 = PAD ? pad32(x3) : x3;
-    atomicAdd(&S[x0 < W ? y0 : sp], x0 < W ? 1u : 0u);
-    atomicAdd(&S[x1 < W ? y1 : sp], x1 < W ? 1u : 0u);
-    atomicAdd(&S[x2 < W ? y2 : sp], x2 < W ? 1u : 0u);
-    atomicAdd(&S[x3 < W ? y3 : sp], x3 < W ? 1u : 0u);
+    if (x0 < W) atomicAdd(&S[y0], 1u);
+    if (x1 < W) atomicAdd(&S[y1], 1u);
+    if (x2 < W) atomicAdd(&S[y2], 1u);
+    if (x3 < W) atomicAdd(&S[y3], 1u);
   }
 }
 

@@ -55,7 +55,8 @@ struct Plan {
   uint32_t chunk;        // output positions per chunk (multiple of 4 * kFillBlock)
   uint32_t nchunks;
   uint32_t fill_grid;
-  uint32_t scan_parts;   // workgroups per tile in the local-CDF stage
+  uint32_t scan_parts;   // workgroups per tile in the local-CDF stage (fixed split)
+  uint32_t scan_grid;    // workgroups of the local-CDF stage; > m: split by chunk counts
   // workspace layout
   size_t off_partial, off_hist, off_cdf, off_rsum, off_O, off_split, ws_bytes;
   size_t off_carry;      // carry array inside a caller-owned workspace (rtcdf_sort_ws)

@@ -7,13 +7,15 @@
 //               the per-bin global atomics of Alg. 5.
 //   k_reduce    sums the partial rows of each bin -> H[R], plus per-128-bin
 //               block totals used for the tile offsets.
-//   k_tilescan  S workgroups per range tile: local CDF by inclusive scan
-//               (Alg. 4), tile offset O[t] (Alg. 6, as a sum of the block
+//   k_tilescan  one or more workgroups per range tile: local CDF by inclusive
+//               scan (Alg. 4), tile offset O[t] (Alg. 6, as a sum of the block
 //               totals before the tile), and the value found at each output
 //               chunk boundary ("splitters", by bisection in the local CDF as in
 //               Alg. 7).  Every workgroup of a tile scans the tile in its own
-//               LDS; the first one writes the CDF and O[t], and each takes 1/S
-//               of the tile's chunk boundaries.
+//               LDS; the first one writes the CDF and O[t], and each takes an
+//               equal share of the tile's chunk boundaries.  With few tiles the
+//               workgroups are given to tiles in proportion to their chunk
+//               boundaries, which the kernel reads from the block totals.
 //   k_fill      one workgroup per output chunk: loads the inclusive cumulative
 //               counts O[t] + C_t[x] of the values that cover the chunk into LDS
 //               and writes every position p the value b_t + min{x : C_t[x] >= p'+1}
@@ -49,11 +51,9 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   const uint32_t wg = blockIdx.x, xcd = wg & 7u, slot = wg >> 3;
   const uint32_t pass = slot % a.passes;
   const uint32_t chunk = (slot / a.passes) * 8u + xcd;
-  // LDS: the counters, one spare word per lane, then (8-bit form) the wrap
-  // table's bins and amounts.
-  const uint32_t lds_words = a.row_words + 64u;
-  uint32_t* tab = S + lds_words;
-  for (uint32_t i = threadIdx.x; i < lds_words; i += BLOCK) S[i] = 0u;
+  // LDS: the counters, then (8-bit form) the wrap table's bins and amounts.
+  uint32_t* tab = S + a.row_words;
+  for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) S[i] = 0u;
   if constexpr (BITS == 8) {
     if (threadIdx.x < 2 * kWrapSlots) tab[threadIdx.x] = threadIdx.x < kWrapSlots ? kWrapEmpty : 0u;
   }
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
       nxt[j] = idx < end ? __builtin_nontemporal_load(&body[idx]) : outside;
     }
 #pragma unroll
-    for (int j = 0; j < V; ++j) count4<BITS>(S, cur[j], base, W, a.carry, pass_lo, a.row_words, tab, hot);
+    for (int j = 0; j < V; ++j) count4<BITS>(S, cur[j], base, W, a.carry, pass_lo, tab, hot);
 #pragma unroll
     for (int j = 0; j < V; ++j) cur[j] = nxt[j];
     t0 = t1;
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   v4i e = outside;
   if (chunk == 0 && threadIdx.x < a.in_head) e.x = a.keys[threadIdx.x];
   if (chunk == a.G - 1 && threadIdx.x < a.in_tail) e.y = a.keys[a.in_head + 4 * a.in_n4 + threadIdx.x];
-  if (threadIdx.x < 64) count4<BITS>(S, e, base, W, a.carry, pass_lo, a.row_words, tab, hot);
+  if (threadIdx.x < 64) count4<BITS>(S, e, base, W, a.carry, pass_lo, tab, hot);
   if constexpr (BITS == 8) hot_flush(hot, tab, a.carry, pass_lo);
   __syncthreads();
   if constexpr (BITS == 8) wrap_flush(tab, a.carry, pass_lo, threadIdx.x);
@@ -214,6 +214,7 @@ struct ScanArgs {
   uint32_t* split;
   uint64_t n;
   uint32_t R, T, out_head, chunk, nchunks, S;
+  uint32_t m, grid;   // tiles; workgroups (grid > m: assigned by chunk counts)
 };
 
 // First output chunk whose start position s(k) is >= P, where s(0) = 0 and
@@ -232,15 +233,72 @@ __device__ __forceinline__ uint32_t first_chunk_at_or_after(uint64_t P, uint32_t
 __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
   extern __shared__ uint32_t C[];
   __shared__ uint32_t wsum[kScanBlock / 64];
-  const uint32_t t = blockIdx.x / a.S, part = blockIdx.x % a.S, tid = threadIdx.x;
+  __shared__ uint32_t tiles[kScanBlock];
+  __shared__ uint32_t sel[4];
+  const uint32_t tid = threadIdx.x;
+  uint32_t t, part, S, Ot;
+  if (a.m == 1) {
+    t = 0;
+    part = blockIdx.x;
+    S = gridDim.x;
+    Ot = 0;
+  } else if (a.grid > a.m) {
+    // At most kScanBlock tiles and 8 * kScanBlock block totals: every
+    // workgroup derives the same assignment of the grid to tiles, one
+    // workgroup per tile plus the spare ones in proportion to the number of
+    // output chunks that start inside each tile (all-equal keys put every
+    // chunk in one tile).  Tile totals first (nb, a power of two, block totals
+    // per tile), then thread i handles tile i.
+    const uint32_t nb = a.T / kReduceBins, nred = (a.R + kReduceBins - 1) / kReduceBins;
+    tiles[tid] = 0u;
+    __syncthreads();
+    for (uint32_t k0 = 0; k0 < nred; k0 += kScanBlock) {
+      const uint32_t k = k0 + tid;
+      const uint32_t v = k < nred ? a.rsum[k] : 0u;
+      if (nb >= 64) {   // a wave's 64 totals belong to one tile
+        const uint32_t ws = wave_sum(v);
+        if (lane_id() == 0 && k < nred) atomicAdd(&tiles[k / nb], ws);
+      } else if (k < nred) {
+        atomicAdd(&tiles[k / nb], v);
+      }
+    }
+    __syncthreads();
+    const uint32_t Ni = tid < a.m ? tiles[tid] : 0u;
+    uint32_t total;
+    const uint32_t Oi = block_inclusive_scan(Ni, wsum, &total) - Ni;   // Alg. 6
+    uint32_t ci = 0;
+    if (tid < a.m && Ni > 0)
+      ci = first_chunk_at_or_after((uint64_t)Oi + Ni, a.out_head, a.chunk, a.nchunks) -
+           first_chunk_at_or_after(Oi, a.out_head, a.chunk, a.nchunks);
+    const uint64_t extra = a.grid - a.m;
+    const uint32_t Si = tid < a.m ? 1u + (uint32_t)(extra * ci / a.nchunks) : 0u;
+    uint32_t used;
+    const uint32_t start = block_inclusive_scan(Si, wsum, &used) - Si;
+    if (tid == 0 && blockIdx.x >= used) sel[0] = 0xffffffffu;
+    if (tid < a.m && blockIdx.x >= start && blockIdx.x < start + Si) {
+      sel[0] = tid;
+      sel[1] = blockIdx.x - start;
+      sel[2] = Si;
+      sel[3] = Oi;
+    }
+    __syncthreads();
+    t = sel[0];
+    if (t == 0xffffffffu) return;   // a spare workgroup left over by the rounding
+    part = sel[1];
+    S = sel[2];
+    Ot = sel[3];
+  } else {
+    t = blockIdx.x / a.S;
+    part = blockIdx.x % a.S;
+    S = a.S;
+    // Alg. 6: O[t] = number of keys below b_t = sum of the 128-bin block
+    // totals before the tile (b_t is a multiple of 128).
+    uint32_t acc = 0;
+    for (uint32_t k = tid; k < t * a.T / kReduceBins; k += kScanBlock) acc += a.rsum[k];
+    Ot = block_sum(acc, wsum);
+  }
   const uint32_t b = t * a.T;
   const uint32_t w = a.R - b < a.T ? a.R - b : a.T;
-
-  // Alg. 6: O[t] = number of keys below b_t = sum of the 128-bin block totals
-  // before the tile (b_t is a multiple of 128).
-  uint32_t acc = 0;
-  for (uint32_t k = tid; k < b / kReduceBins; k += kScanBlock) acc += a.rsum[k];
-  const uint32_t Ot = block_sum(acc, wsum);
 
   // Alg. 4: inclusive scan of H[b, b + w).  Coalesced copy into LDS, then
   // each thread scans a contiguous segment of L entries, one block scan of the
@@ -274,10 +332,11 @@ __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
   const uint64_t lo = Ot, hi = (uint64_t)Ot + Nt;
   const uint32_t kt0 = first_chunk_at_or_after(lo, a.out_head, a.chunk, a.nchunks);
   const uint32_t kt1 = first_chunk_at_or_after(hi, a.out_head, a.chunk, a.nchunks);
-  const uint32_t per = (kt1 - kt0 + a.S - 1) / a.S;
+  const uint32_t per = (kt1 - kt0 + S - 1) / S;
   const uint32_t k0 = min(kt0 + part * per, kt1), k1 = min(k0 + per, kt1);
   uint32_t* stage = C + pad32(a.T) + 1;   // 4 * kScanBlock words
-  constexpr uint32_t kPer = 4;
+  // 1 to 4 starts per thread: as few as cover this workgroup's share at once
+  const uint32_t kPer = min(4u, max(1u, (k1 - k0 + kScanBlock - 1) / kScanBlock));
   for (uint32_t kb0 = k0; kb0 < k1; kb0 += kPer * kScanBlock) {
     const uint32_t ka = kb0 + tid * kPer;
     uint32_t x = 0;
@@ -478,7 +537,7 @@ __global__ void k_clear(uint32_t* p, size_t words) {
 
 template <int ITEMS, int BITS, int BLOCK>
 hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
-  const size_t lds = ((size_t)p.row_words + 64 + (BITS == 8 ? 2 * kWrapSlots : 0)) * 4;
+  const size_t lds = ((size_t)p.row_words + (BITS == 8 ? 2 * kWrapSlots : 0)) * 4;
   auto kern = k_hist<ITEMS, BITS, BLOCK>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
@@ -571,6 +630,8 @@ hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t s) {
   a.hist = reinterpret_cast<const uint32_t*>(ws + p.off_hist);
   a.cdf = reinterpret_cast<uint32_t*>(ws + p.off_cdf);
   a.S = p.scan_parts;
+  a.m = p.m;
+  a.grid = p.scan_grid;
   a.rsum = reinterpret_cast<const uint32_t*>(ws + p.off_rsum);
   a.O = reinterpret_cast<uint32_t*>(ws + p.off_O);
   a.split = reinterpret_cast<uint32_t*>(ws + p.off_split);
@@ -584,7 +645,7 @@ hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)k_tilescan,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_tilescan, dim3(p.m * p.scan_parts), dim3(kScanBlock), lds, s, a);
+  hipLaunchKernelGGL(k_tilescan, dim3(p.scan_grid), dim3(kScanBlock), lds, s, a);
   return hipGetLastError();
 }
 

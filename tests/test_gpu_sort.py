@@ -118,12 +118,12 @@ def test_extreme_ranges(r):
     _run(r, A, 2 ** 31 - 1, 2 ** 31)
 
 
-@pytest.mark.parametrize("R", [1 << 16, 1 << 16 | 1, 79873, 1 << 17, 1 << 18])
+@pytest.mark.parametrize("R", [1 << 16, 1 << 16 | 1, 81921, 1 << 17, 1 << 18])
 def test_packed_counter_overflow(r, R):
     """More equal keys per workgroup than a packed LDS counter holds (65535 in
     16-bit, 255 in 8-bit counters), in every byte / half of one LDS word and in
     the last (phantom-paired) bin; R = 2^16 and 65537 take 16-bit counters,
-    79873, 2^17 and 2^18 take 8-bit ones at the default tile width."""
+    81921, 2^17 and 2^18 take 8-bit ones at the default tile width."""
     n = 40_000_000
     rng = np.random.default_rng(R)
     for pick in ([0], [0, 1], [1], [R - 1], [2, 3, R - 1], [0, 1, 2, 3], [4, 6, 7]):
