@@ -118,8 +118,13 @@ __device__ __forceinline__ void wrap_add(uint32_t* tab, uint32_t bin, uint32_t d
                                          uint32_t pass_lo) {
   uint32_t* slot = tab + (bin & (kWrapSlots - 1));
   const uint32_t prev = atomicCAS(slot, kWrapEmpty, bin);
-  if (prev == kWrapEmpty || prev == bin) atomicAdd(slot + kWrapSlots, d);
-  else atomicAdd(&carry[pass_lo + bin], d);
+  // Workgroup scope for the LDS add, device scope for the global one: the
+  // compiler then keeps them apart instead of merging them into one flat
+  // atomic, whose counters would stop it from pipelining the input loads.
+  if (prev == kWrapEmpty || prev == bin)
+    __hip_atomic_fetch_add(slot + kWrapSlots, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else
+    __hip_atomic_fetch_add(&carry[pass_lo + bin], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Moves the table's amounts to the global carry array (one thread per slot,
@@ -180,8 +185,8 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
   const uint32_t x0 = (uint32_t)k.x - base, x1 = (uint32_t)k.y - base;
   const uint32_t x2 = (uint32_t)k.z - base, x3 = (uint32_t)k.w - base;
   const uint32_t lead = (uint32_t)__builtin_amdgcn_readfirstlane((int)x0);
-  const bool four = (x0 == lead) & (x1 == lead) & (x2 == lead) & (x3 == lead);
-  const uint64_t same = __ballot(four);
+  const uint64_t same = __ballot(x0 == lead) & __ballot(x1 == lead) & __ballot(x2 == lead) &
+                        __ballot(x3 == lead);
   const uint64_t active = __ballot(1);
   if (same == active) {
     if (lead < W) {
@@ -200,20 +205,21 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
     return;
   }
   if constexpr (BITS == 16 || BITS == 8) {
-    // bin x is field x & MASK of word x >> LOG; a field is 1 << SH bits wide
-    constexpr uint32_t LOG = BITS == 16 ? 1 : 2, MASK = BITS == 16 ? 1 : 3, SH = BITS == 16 ? 4 : 3;
+    // Bin x is the field at bit (x & (32 / BITS - 1)) * BITS of word x >> LOG.
+    // That offset is (x << SH) & 31, and the hardware shifts and bit-field
+    // extracts read only the low 5 bits of an offset, so the masks fold away.
+    constexpr uint32_t LOG = BITS == 16 ? 1 : 2, SH = BITS == 16 ? 4 : 3;
     constexpr uint32_t FULL = BITS == 16 ? 0xffffu : 0xffu;
-    const uint32_t s0 = (x0 & MASK) << SH, s1 = (x1 & MASK) << SH;
-    const uint32_t s2 = (x2 & MASK) << SH, s3 = (x3 & MASK) << SH;
+    const uint32_t s0 = x0 << SH, s1 = x1 << SH, s2 = x2 << SH, s3 = x3 << SH;
     uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-    if (x0 < W) o0 = atomicAdd(&S[x0 >> LOG], 1u << s0);
-    if (x1 < W) o1 = atomicAdd(&S[x1 >> LOG], 1u << s1);
-    if (x2 < W) o2 = atomicAdd(&S[x2 >> LOG], 1u << s2);
-    if (x3 < W) o3 = atomicAdd(&S[x3 >> LOG], 1u << s3);
-    const bool w0 = ((o0 >> s0) & FULL) == FULL && x0 < W;
-    const bool w1 = ((o1 >> s1) & FULL) == FULL && x1 < W;
-    const bool w2 = ((o2 >> s2) & FULL) == FULL && x2 < W;
-    const bool w3 = ((o3 >> s3) & FULL) == FULL && x3 < W;
+    if (x0 < W) o0 = atomicAdd(&S[x0 >> LOG], 1u << (s0 & 31u));
+    if (x1 < W) o1 = atomicAdd(&S[x1 >> LOG], 1u << (s1 & 31u));
+    if (x2 < W) o2 = atomicAdd(&S[x2 >> LOG], 1u << (s2 & 31u));
+    if (x3 < W) o3 = atomicAdd(&S[x3 >> LOG], 1u << (s3 & 31u));
+    const bool w0 = __builtin_amdgcn_ubfe(o0, s0, BITS) == FULL && x0 < W;
+    const bool w1 = __builtin_amdgcn_ubfe(o1, s1, BITS) == FULL && x1 < W;
+    const bool w2 = __builtin_amdgcn_ubfe(o2, s2, BITS) == FULL && x2 < W;
+    const bool w3 = __builtin_amdgcn_ubfe(o3, s3, BITS) == FULL && x3 < W;
     if (__ballot(w0 | w1 | w2 | w3)) {
       if constexpr (BITS == 16) {
         if (w0) fix_u16(o0, x0, 1u, carry, pass_lo);

@@ -34,7 +34,7 @@ using namespace dev;
 
 struct HistArgs {
   const int32_t* keys;
-  uint64_t in_n4, in_per;
+  uint32_t in_n4, in_per;   // n < 2^32 keys: vector indices fit 32 bits
   uint32_t in_head, in_tail;
   uint32_t min_u, W, passes, G, row_words, R;
   uint32_t interleave;
@@ -44,7 +44,10 @@ struct HistArgs {
 
 template <int ITEMS, int BITS, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
-  extern __shared__ uint32_t S[];
+  // The planner's LDS budget: kLdsBytes per 1024 threads (one workgroup per
+  // compute unit at 1024 threads, two at 512, four at 256).  A static array
+  // lets the compiler fold its base into the LDS instructions.
+  __shared__ uint32_t S[kLdsBytes / 4 / (1024 / BLOCK)];
   // XCD-aware mapping: workgroup ids are dealt round-robin to the 8 XCDs, so
   // the `passes` workgroups that read the same input chunk get consecutive
   // slots on one XCD and the rescans of later passes can hit that XCD's L2.
@@ -67,45 +70,55 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   const v4i* body = reinterpret_cast<const v4i*>(a.keys + a.in_head);
   const v4i outside = (v4i)(int)(base - 1u);   // lands outside every pass
   HotBin hot;                                  // 8-bit form only
-  uint64_t t0, step, end;
+  uint32_t t0, step, end;
   if (a.interleave) {
     // Tiles of BLOCK * V vectors dealt round-robin to the G chunks of a pass:
     // at any moment the whole grid reads one contiguous window of the input.
-    t0 = (uint64_t)chunk * BLOCK * V + threadIdx.x;
-    step = (uint64_t)BLOCK * V * a.G;
+    t0 = chunk * BLOCK * V + threadIdx.x;
+    step = BLOCK * V * a.G;
     end = a.in_n4;
   } else {
-    const uint64_t c0 = (uint64_t)chunk * a.in_per;
+    const uint32_t c0 = chunk * a.in_per;
     t0 = c0 + threadIdx.x;
-    step = (uint64_t)BLOCK * V;
+    step = BLOCK * V;
     end = c0 + a.in_per < a.in_n4 ? c0 + a.in_per : a.in_n4;
   }
   // Software pipelined: the loads of the next tile are in flight while the
-  // current one is counted.
-  v4i cur[V];
+  // current one is counted.  Every load is issued unconditionally from an
+  // index clamped into [0, end), so that the compiler can wait for the
+  // current tile's loads alone rather than for all loads in flight; in the
+  // workgroup's last, partial tile the lanes past the end count `outside`.
+  if (end > 0) {
+    const uint32_t last = end - 1;
+    // first vector of the workgroup's tile (uniform: kept in a scalar register)
+    uint32_t tb = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t0 - threadIdx.x));
+    v4i cur[V];
 #pragma unroll
-  for (int j = 0; j < V; ++j) {
-    const uint64_t idx = t0 + (uint64_t)j * BLOCK;
-    cur[j] = idx < end ? __builtin_nontemporal_load(&body[idx]) : outside;
-  }
-  while (t0 < end) {
-    const uint64_t t1 = t0 + step;
-    v4i nxt[V];
+    for (int j = 0; j < V; ++j) cur[j] = __builtin_nontemporal_load(&body[min(t0 + j * BLOCK, last)]);
+    while (tb < end) {
+      const uint32_t t1 = t0 + step;
+      v4i nxt[V];
 #pragma unroll
-    for (int j = 0; j < V; ++j) {
-      const uint64_t idx = t1 + (uint64_t)j * BLOCK;
-      nxt[j] = idx < end ? __builtin_nontemporal_load(&body[idx]) : outside;
+      for (int j = 0; j < V; ++j) nxt[j] = __builtin_nontemporal_load(&body[min(t1 + j * BLOCK, last)]);
+      if (tb + V * BLOCK <= end) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) count4<BITS>(S, cur[j], base, W, a.carry, pass_lo, tab, hot);
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          count4<BITS>(S, t0 + j * BLOCK < end ? cur[j] : outside, base, W, a.carry, pass_lo, tab, hot);
+      }
+#pragma unroll
+      for (int j = 0; j < V; ++j) cur[j] = nxt[j];
+      t0 = t1;
+      tb += step;
     }
-#pragma unroll
-    for (int j = 0; j < V; ++j) count4<BITS>(S, cur[j], base, W, a.carry, pass_lo, tab, hot);
-#pragma unroll
-    for (int j = 0; j < V; ++j) cur[j] = nxt[j];
-    t0 = t1;
   }
   // scalar head and tail keys (at most 3 each), counted by chunk 0 / chunk G-1
   v4i e = outside;
   if (chunk == 0 && threadIdx.x < a.in_head) e.x = a.keys[threadIdx.x];
-  if (chunk == a.G - 1 && threadIdx.x < a.in_tail) e.y = a.keys[a.in_head + 4 * a.in_n4 + threadIdx.x];
+  if (chunk == a.G - 1 && threadIdx.x < a.in_tail)
+    e.y = a.keys[a.in_head + 4 * (size_t)a.in_n4 + threadIdx.x];
   if (threadIdx.x < 64) count4<BITS>(S, e, base, W, a.carry, pass_lo, tab, hot);
   if constexpr (BITS == 8) hot_flush(hot, tab, a.carry, pass_lo);
   __syncthreads();
@@ -537,12 +550,10 @@ __global__ void k_clear(uint32_t* p, size_t words) {
 
 template <int ITEMS, int BITS, int BLOCK>
 hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
+  // the counters (and the 8-bit form's wrap table) fit the static LDS array
   const size_t lds = ((size_t)p.row_words + (BITS == 8 ? 2 * kWrapSlots : 0)) * 4;
-  auto kern = k_hist<ITEMS, BITS, BLOCK>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(p.passes * p.G), dim3(BLOCK), lds, s, a);
+  if (lds > kLdsBytes / (1024 / BLOCK)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_hist<ITEMS, BITS, BLOCK>), dim3(p.passes * p.G), dim3(BLOCK), 0, s, a);
   return hipGetLastError();
 }
 
@@ -589,8 +600,8 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
                        hipStream_t s) {
   HistArgs a;
   a.keys = keys;
-  a.in_n4 = p.in_n4;
-  a.in_per = p.in_per;
+  a.in_n4 = (uint32_t)p.in_n4;     // n < 2^32: at most 2^30 vectors
+  a.in_per = (uint32_t)p.in_per;
   a.in_head = p.in_head;
   a.in_tail = (uint32_t)(p.n - p.in_head - 4 * p.in_n4);
   a.min_u = p.min_u;

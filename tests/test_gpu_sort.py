@@ -108,6 +108,19 @@ def test_distributions(r, dist, logR):
     _run(r, A, minVal, minVal + R)
 
 
+@pytest.mark.parametrize("logR,dist", [(20, "normal"), (20, "all_equal"), (21, "uniform"),
+                                       (21, "all_equal"), (22, "zipf"), (24, "normal")])
+def test_wide_ranges(r, logR, dist):
+    """Ranges with up to 1024 tiles and 8192 block totals (the local-CDF stage
+    assigns its workgroups by chunk counts) and beyond (fixed split), at the
+    default tile width."""
+    R = 1 << logR
+    A = inputs.make(dist, 3_000_001, -R // 2, R - R // 2, inputs.case_seed(5, logR))
+    info = r.plan_info(A.size, -R // 2, R - R // 2)
+    assert info["tiles"] == (R + info["tile_width"] - 1) // info["tile_width"]
+    _run(r, A, -R // 2, R - R // 2)
+
+
 def test_extreme_ranges(r):
     i32min = -(2 ** 31)
     A = inputs.uniform(100_001, i32min, i32min + 1000, 1)
