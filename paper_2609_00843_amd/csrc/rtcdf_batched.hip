@@ -26,6 +26,13 @@ namespace {
 
 using namespace dev;
 
+// Segment keys are reached through pointers read from device memory, which
+// the compiler cannot place in an address space; these global (address space
+// 1) types keep their loads and stores out of the flat form, whose counters
+// would make every LDS wait also wait for them.
+typedef __attribute__((address_space(1))) int32_t g_i32;
+typedef __attribute__((address_space(1))) v4i g_v4i;
+
 constexpr uint32_t kBBlock = 1024;
 constexpr uint32_t kBTile = 32768;                   // values per local CDF tile
 constexpr uint32_t kBLdsWords = 33792;               // pad32(kBTile): LDS words of one padded tile
@@ -89,7 +96,7 @@ __device__ uint32_t scan_tile(uint32_t* C, uint32_t w, uint32_t* wsum) {
 // of the tile whose local CDF is the padded LDS array C[0..w); value x of the
 // tile is written as base + x.  body_lo is the first 16-byte aligned position
 // of the output.
-__device__ void fill_tile(int32_t* out, const uint32_t* C, uint32_t w, uint32_t base, uint32_t P0,
+__device__ void fill_tile(g_i32* out, const uint32_t* C, uint32_t w, uint32_t base, uint32_t P0,
                           uint32_t P1, uint32_t body_lo) {
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t last = w - 1;
@@ -98,7 +105,7 @@ __device__ void fill_tile(int32_t* out, const uint32_t* C, uint32_t w, uint32_t 
   const uint32_t q_lo = body_lo + ((a0 - body_lo + 3u) & ~3u);
   const uint32_t q_hi = P1 > body_lo ? body_lo + ((P1 - body_lo) & ~3u) : body_lo;
   if (q_lo < q_hi) {
-    v4i* body = reinterpret_cast<v4i*>(out + body_lo);
+    g_v4i* body = (g_v4i*)(out + body_lo);
     const uint32_t i_lo = (q_lo - body_lo) >> 2, i_hi = (q_hi - body_lo) >> 2;
     uint32_t xw = 0, end = 0;
     bool started = false;
@@ -109,7 +116,14 @@ __device__ void fill_tile(int32_t* out, const uint32_t* C, uint32_t w, uint32_t 
         end = C[pad32(xw)];
         started = true;
       }
-      while (xw < last && end <= lp) end = C[pad32(++xw)];
+      // as in the plain output stage: a walk of at most kWalk boundaries,
+      // bisection beyond that (sparse segments)
+      constexpr uint32_t kWalk = 8;
+      for (uint32_t s = 0; s < kWalk && xw < last && end <= lp; ++s) end = C[pad32(++xw)];
+      if (xw < last && end <= lp) {
+        xw = upper_in_pad(C, xw, last, lp);
+        end = C[pad32(xw)];
+      }
       v4i o;
       if (xw == last || end > lp + 255u) {
         o = (v4i)(int32_t)(base + xw);
@@ -117,17 +131,24 @@ __device__ void fill_tile(int32_t* out, const uint32_t* C, uint32_t w, uint32_t 
         const uint32_t p = lp + 4 * lane;
         uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
         uint32_t xb = xw, e = end;
-        while (xb < last && e <= lp + 255u) {
+        for (uint32_t s = 0; s < kWalk && xb < last && e <= lp + 255u; ++s) {
           c0 += e <= p;
           c1 += e <= p + 1;
           c2 += e <= p + 2;
           c3 += e <= p + 3;
           e = C[pad32(++xb)];
         }
-        o.x = (int32_t)(base + xw + c0);
-        o.y = (int32_t)(base + xw + c1);
-        o.z = (int32_t)(base + xw + c2);
-        o.w = (int32_t)(base + xw + c3);
+        if (xb < last && e <= lp + 255u) {
+          o.x = (int32_t)(base + upper_in_pad(C, xw, last, p));
+          o.y = (int32_t)(base + upper_in_pad(C, xw, last, p + 1));
+          o.z = (int32_t)(base + upper_in_pad(C, xw, last, p + 2));
+          o.w = (int32_t)(base + upper_in_pad(C, xw, last, p + 3));
+        } else {
+          o.x = (int32_t)(base + xw + c0);
+          o.y = (int32_t)(base + xw + c1);
+          o.z = (int32_t)(base + xw + c2);
+          o.w = (int32_t)(base + xw + c3);
+        }
       }
       const uint32_t i = ib + lane;
       if (i < i_hi) __builtin_nontemporal_store(o, &body[i]);
@@ -143,34 +164,41 @@ __device__ void fill_tile(int32_t* out, const uint32_t* C, uint32_t w, uint32_t 
 }
 
 template <int V, bool PACKED>
-__device__ void count_segment(const int32_t* in, uint32_t n, uint32_t min_u, uint32_t R, uint32_t* S,
+__device__ void count_segment(const g_i32* in, uint32_t n, uint32_t min_u, uint32_t R, uint32_t* S,
                               uint32_t* carry) {
   const uint32_t tid = threadIdx.x;
-  const uintptr_t ia = reinterpret_cast<uintptr_t>(in);
+  const uintptr_t ia = (uintptr_t)in;
   uint32_t head = (uint32_t)(((16 - (ia & 15)) & 15) / 4);
   if (head > n) head = n;
   const uint32_t n4 = (n - head) / 4, tail = n - head - 4 * n4;
-  const v4i* body = reinterpret_cast<const v4i*>(in + head);
+  const g_v4i* body = (const g_v4i*)(in + head);
   const v4i outside = (v4i)(int)(min_u - 1u);   // normalises to 0xffffffff: never counted
   HotBin hot;                                    // unused by the 32- and 16-bit forms
-  v4i cur[V];
+  // Pipelined as in the plain histogram: unconditional loads from indices
+  // clamped into [0, n4), `outside` for lanes past the end of the last tile.
+  if (n4 > 0) {
+    const uint32_t last = n4 - 1;
+    v4i cur[V];
 #pragma unroll
-  for (int j = 0; j < V; ++j) {
-    const uint32_t idx = tid + j * kBBlock;
-    cur[j] = idx < n4 ? __builtin_nontemporal_load(&body[idx]) : outside;
-  }
-  for (uint32_t t0 = tid; t0 < n4; t0 += kBBlock * V) {
-    const uint32_t t1 = t0 + kBBlock * V;
-    v4i nxt[V];
+    for (int j = 0; j < V; ++j) cur[j] = __builtin_nontemporal_load(&body[min(tid + j * kBBlock, last)]);
+    for (uint32_t tb = 0, t0 = tid; tb < n4; tb += kBBlock * V, t0 += kBBlock * V) {
+      const uint32_t t1 = t0 + kBBlock * V;
+      v4i nxt[V];
 #pragma unroll
-    for (int j = 0; j < V; ++j) {
-      const uint32_t idx = t1 + j * kBBlock;
-      nxt[j] = idx < n4 ? __builtin_nontemporal_load(&body[idx]) : outside;
+      for (int j = 0; j < V; ++j) nxt[j] = __builtin_nontemporal_load(&body[min(t1 + j * kBBlock, last)]);
+      if (tb + kBBlock * V <= n4) {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          count4<PACKED ? 16 : 32, !PACKED>(S, cur[j], min_u, R, carry, 0u, nullptr, hot);
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          count4<PACKED ? 16 : 32, !PACKED>(S, t0 + j * kBBlock < n4 ? cur[j] : outside, min_u, R, carry,
+                                            0u, nullptr, hot);
+      }
+#pragma unroll
+      for (int j = 0; j < V; ++j) cur[j] = nxt[j];
     }
-#pragma unroll
-    for (int j = 0; j < V; ++j) count4<PACKED ? 16 : 32, !PACKED>(S, cur[j], min_u, R, carry, 0u, nullptr, hot);
-#pragma unroll
-    for (int j = 0; j < V; ++j) cur[j] = nxt[j];
   }
   if (tid < 64) {
     v4i e = outside;
@@ -185,13 +213,14 @@ __device__ void sort_segment(const rtcdf_segment_t& d, uint32_t* S, uint32_t* ws
                              uint32_t scratch_words) {
   const uint32_t tid = threadIdx.x;
   const uint32_t n = d.n, R = d.range;
-  const int32_t* in = d.keys_in;
-  int32_t* out = d.keys_out;
   // Descriptors that break the documented limits are skipped (output untouched).
-  if (n == 0 || R == 0 || R > RTCDF_BATCH_MAX_RANGE || in == nullptr || out == nullptr) return;
+  if (n == 0 || R == 0 || R > RTCDF_BATCH_MAX_RANGE || d.keys_in == nullptr || d.keys_out == nullptr)
+    return;
+  const g_i32* in = (const g_i32*)d.keys_in;
+  g_i32* out = (g_i32*)d.keys_out;
   if (R > kBTile && scratch_words < R + 2) return;
   const uint32_t min_u = (uint32_t)d.minVal;
-  const uintptr_t oa = reinterpret_cast<uintptr_t>(out);
+  const uintptr_t oa = (uintptr_t)out;
   uint32_t body_lo = (uint32_t)(((16 - (oa & 15)) & 15) / 4);
   if (body_lo > n) body_lo = n;
 

@@ -69,9 +69,39 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t* a, uint32_t len, ui
   return lo;
 }
 
+// First index x in [lo, hi] with a[x] > q in the nondecreasing a, or hi if
+// there is none.
+__device__ __forceinline__ uint32_t upper_in(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t q) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] <= q) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 // Local CDFs are kept in LDS with one padding word per 32 entries, so the
 // per-thread segments of the blocked scan fall into distinct banks.
 __device__ __forceinline__ uint32_t pad32(uint32_t i) { return i + (i >> 5); }
+
+// upper_in for a wave-uniform search: every probe is read into a scalar
+// register, so the loop runs on the scalar unit.
+__device__ __forceinline__ uint32_t upper_in_uniform(const uint32_t* a, uint32_t lo, uint32_t hi,
+                                                     uint32_t q) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if ((uint32_t)__builtin_amdgcn_readfirstlane((int)a[mid]) <= q) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// upper_in over the padded array C.
+__device__ __forceinline__ uint32_t upper_in_pad(const uint32_t* C, uint32_t lo, uint32_t hi, uint32_t q) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (C[pad32(mid)] <= q) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
 
 // Number of entries of the nondecreasing padded array C[0..len) that are <= q.
 __device__ __forceinline__ uint32_t count_le_pad(const uint32_t* C, uint32_t len, uint32_t q) {

@@ -410,7 +410,9 @@ __device__ __forceinline__ uint64_t chunk_start(const FillArgs& a, uint32_t k) {
 }
 
 // Writes the positions [p0, p1) of one chunk whose values lie in [v0, v0 + nwin)
-// and whose inclusive cumulative counts are in win[0, nwin).
+// and whose inclusive cumulative counts are in win[0, nwin).  SPARSE selects
+// the form for windows of many values per step (see below).
+template <bool SPARSE>
 __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* win, uint32_t nwin,
                                            uint32_t v0, uint64_t p0, uint64_t p1, bool first,
                                            bool final) {
@@ -427,17 +429,33 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
   // grow), so a step whose 256 positions hold one value touches no memory but
   // the store.  Otherwise the value boundaries inside the step are visited in
   // order (one broadcast LDS read each) and every lane counts the boundaries
-  // at or below each of its four positions.
+  // at or below each of its four positions.  In the SPARSE form, where more
+  // than kWalk values end before the step or inside it (most of them empty),
+  // one look-ahead read shows it and the window is bisected instead.
+  constexpr uint32_t kWalk = 8;
   uint32_t xw = 0;
   uint32_t end = win[0];
   for (uint64_t ib = i_lo + (uint64_t)wave * 64; ib < i_hi; ib += kFillBlock) {
     const uint32_t pw = (uint32_t)(a.body_lo + 4 * ib);
-    while (xw < last && end <= pw) end = win[++xw];
+    if (!SPARSE) {
+      while (xw < last && end <= pw) end = win[++xw];
+    } else if (xw < last && end <= pw) {
+      // the look-ahead and the next end are read together
+      const uint32_t far = win[min(xw + kWalk, last)], e1 = win[xw + 1];
+      if (far <= pw) {
+        xw = upper_in(win, xw, last, pw);
+        end = win[xw];
+      } else {
+        ++xw;
+        end = e1;
+        while (end <= pw) end = win[++xw];
+      }
+    }
     const uint64_t i = ib + lane;
     v4i o;
     if (xw == last || end > pw + 255u) {
       o = (v4i)(base + (int32_t)xw);
-    } else {
+    } else if constexpr (!SPARSE) {
       const uint32_t p = pw + 4 * lane;
       uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
       uint32_t xb = xw, e = end;
@@ -452,6 +470,30 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
       o.y = base + (int32_t)(xw + c1);
       o.z = base + (int32_t)(xw + c2);
       o.w = base + (int32_t)(xw + c3);
+    } else {
+      const uint32_t p = pw + 4 * lane;
+      const uint32_t far = win[min(xw + kWalk, last)], e1 = win[xw + 1];
+      if (far <= pw + 255u) {
+        o.x = base + (int32_t)upper_in(win, xw, last, p);
+        o.y = base + (int32_t)upper_in(win, xw, last, p + 1);
+        o.z = base + (int32_t)upper_in(win, xw, last, p + 2);
+        o.w = base + (int32_t)upper_in(win, xw, last, p + 3);
+      } else {
+        // boundary after value xw at position end, then after xw + 1 at e1, ...
+        uint32_t c0 = end <= p, c1 = end <= p + 1, c2 = end <= p + 2, c3 = end <= p + 3;
+        uint32_t xb = xw + 1, e = e1;
+        while (xb < last && e <= pw + 255u) {
+          c0 += e <= p;
+          c1 += e <= p + 1;
+          c2 += e <= p + 2;
+          c3 += e <= p + 3;
+          e = win[++xb];
+        }
+        o.x = base + (int32_t)(xw + c0);
+        o.y = base + (int32_t)(xw + c1);
+        o.z = base + (int32_t)(xw + c2);
+        o.w = base + (int32_t)(xw + c3);
+      }
     }
     if (i < i_hi) __builtin_nontemporal_store(o, &body[i]);
   }
@@ -489,6 +531,7 @@ __device__ __forceinline__ void chunk_values(const FillArgs& a, uint32_t k, uint
 // the splitters of chunk k + 2G are being fetched, so the few waves per
 // compute unit (writes are fastest with few concurrent writers) never wait
 // for global memory between chunks.
+template <bool SPARSE>
 __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
   __shared__ uint32_t win[2][kFillWindow];
   const uint32_t tid = threadIdx.x, G = gridDim.x;
@@ -514,7 +557,7 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
     const uint64_t p0 = chunk_start(a, k);
     const uint64_t p1 = k + 1 < a.nchunks ? chunk_start(a, k + 1) : a.n;
     if (nwin <= kFillWindow)
-      fill_chunk(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks);
+      fill_chunk<SPARSE>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks);
     else
       fill_chunk_global(a, v0, v0 + nwin - 1, p0, p1);
     if (!more) break;
@@ -675,7 +718,12 @@ hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream
   a.nchunks = p.nchunks;
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
   a.body_hi = a.body_lo + 4 * ((p.n - a.body_lo) / 4);
-  hipLaunchKernelGGL(k_fill, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a);
+  // The sparse form (look-ahead and bisection in the window) when the values
+  // average fewer than 64 output positions each; the plain walk otherwise.
+  if (p.n < (uint64_t)64 * p.R)
+    hipLaunchKernelGGL(k_fill<true>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_fill<false>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a);
   return hipGetLastError();
 }
 
