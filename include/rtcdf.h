@@ -213,10 +213,17 @@ rtcdf_status_t rtcdf_autotune(const int32_t* keys_in, int32_t* keys_out, size_t 
 rtcdf_status_t rtcdf_load_tuned_table(const char* path);
 
 /* LEARNED mode model: a file written by paper_2609_00843_amd/learn.py
- * ("RTCDFMLP", version 1, sizes, training ranges of log2 n and log2 R, feature
- * mean and sd, the RTCDF_MLP_PARAMS weights, the valid-configuration mask).
- * Arrays outside the training ranges (by more than half an octave) fall back
- * to TUNED, then DEFAULT.  rtcdf_unload_model forgets it. */
+ * ("RTCDFMLP", version 1 or 2, sizes, training ranges of log2 n and log2 R,
+ * version 2 only: the decision margin and the trusted feature range zmax,
+ * feature mean and sd, the RTCDF_MLP_PARAMS weights, the valid-configuration
+ * mask).  The network predicts a centred log run time per grid configuration;
+ * its choice is used only when it predicts at least `margin` (natural-log
+ * units) less than for the configuration TUNED/DEFAULT would give, else that
+ * one is kept (version 1: margin 0).  Arrays outside the training ranges of
+ * log2 n and log2 R (by more than half an octave), or whose sketch features
+ * lie more than zmax standard deviations from the training mean in some
+ * feature (zmax 0: no such limit), fall back to TUNED, then DEFAULT.
+ * rtcdf_unload_model forgets it. */
 rtcdf_status_t rtcdf_load_model(const char* path);
 rtcdf_status_t rtcdf_unload_model(void);
 

@@ -116,8 +116,8 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // needs fewer passes over the input.
   const uint32_t lds = kLdsBytes / p->bpt;
   const uint32_t k32 = std::max<uint32_t>(1, lds / (4 * p->T));
-  const uint32_t k16 = std::max<uint32_t>(1, lds / (2 * p->T));
-  const uint32_t k8 = std::max<uint32_t>(1, (lds - 512) / p->T);   // 512 B wrap table
+  const uint32_t k16 = std::max<uint32_t>(1, (lds - 512) / (2 * p->T));   // 512 B wrap table
+  const uint32_t k8 = std::max<uint32_t>(1, (lds - 512) / p->T);
   const uint32_t passes32 = (p->m + k32 - 1) / k32;
   const uint32_t passes16 = (p->m + k16 - 1) / k16;
   const uint32_t passes8 = (p->m + k8 - 1) / k8;

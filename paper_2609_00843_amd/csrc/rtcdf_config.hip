@@ -74,13 +74,18 @@ struct Model {
   std::vector<float> params, norm;      // norm: mean[34] then sd[34]
   std::vector<uint8_t> valid;           // per grid point
   float log2n_lo = 0, log2n_hi = 0, log2r_lo = 0, log2r_hi = 0;   // training ranges
+  float margin = 0;                     // least predicted log-time gain that is acted on
+  float zmax = 0;                       // feature range trusted (0: no limit)
 };
+// Pick results: word 0 the argmin index, words 1..kMlpOut the predictions,
+// then the largest |normalised feature|.
+constexpr int kPickWords = 2 + kMlpOut;
 struct DeviceModel {
   float* params = nullptr;
   float* norm = nullptr;
   uint8_t* valid = nullptr;
-  uint32_t* index = nullptr;
-  uint32_t* host_index = nullptr;       // pinned
+  uint32_t* out = nullptr;              // kPickWords
+  uint32_t* host_out = nullptr;         // pinned, kPickWords
   uint64_t generation = 0;
 };
 static Model g_model;
@@ -89,12 +94,12 @@ static std::map<int, DeviceModel> g_dev_models;
 
 static rtcdf_status_t upload_model(int dev, DeviceModel** out) {
   DeviceModel& d = g_dev_models[dev];
-  if (d.index == nullptr) {
+  if (d.out == nullptr) {
     hipError_t e = hipMalloc(&d.params, sizeof(float) * kMlpParams);
     if (e == hipSuccess) e = hipMalloc(&d.norm, sizeof(float) * 2 * kMlpIn);
     if (e == hipSuccess) e = hipMalloc(&d.valid, kMlpOut);
-    if (e == hipSuccess) e = hipMalloc(&d.index, sizeof(uint32_t));
-    if (e == hipSuccess) e = hipHostMalloc(&d.host_index, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&d.out, sizeof(uint32_t) * kPickWords);
+    if (e == hipSuccess) e = hipHostMalloc(&d.host_out, sizeof(uint32_t) * kPickWords);
     if (e != hipSuccess) return hip_fail(e);
   }
   if (d.generation != g_model_generation) {
@@ -109,9 +114,27 @@ static rtcdf_status_t upload_model(int dev, DeviceModel** out) {
   return RTCDF_SUCCESS;
 }
 
+static int grid_index(const rtcdf_config_t& c) {
+  for (int i = 0; i < kMlpOut; ++i) {
+    const rtcdf_config_t g = grid_config(i);
+    if (g.tile_width == c.tile_width && g.items_per_thread == c.items_per_thread &&
+        g.blocks_per_tile == c.blocks_per_tile)
+      return i;
+  }
+  return -1;
+}
+
+// The configuration used when the learned model does not decide.
+static rtcdf_config_t static_config(size_t n, uint32_t R, int mode) {
+  rtcdf_config_t c;
+  if (mode != RTCDF_CONFIG_DEFAULT && tuned_config(n, R, &c)) return c;
+  return default_config(n, R);
+}
+
 static rtcdf_status_t learned_config(const int32_t* keys, size_t n, int64_t minVal, int64_t maxVal,
                                      hipStream_t stream, rtcdf_config_t* out, bool* used) {
   *used = false;
+  const rtcdf_config_t fallback = static_config(n, (uint32_t)(maxVal - minVal), RTCDF_CONFIG_TUNED);
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   if (!g_model.loaded || keys == nullptr || n == 0) return RTCDF_SUCCESS;
   const double a = std::log2((double)n), b = std::log2((double)(maxVal - minVal));
@@ -126,15 +149,27 @@ static rtcdf_status_t learned_config(const int32_t* keys, size_t n, int64_t minV
   rtcdf_status_t st = upload_model(dev, &d);
   if (st != RTCDF_SUCCESS) return st;
   e = launch_pick(keys, n, minVal, (uint64_t)(maxVal - minVal), kSketchSamples, d->params, d->norm, d->valid,
-                  d->index, nullptr, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(d->host_index, d->index, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+                  d->out, reinterpret_cast<float*>(d->out + 1),
+                  reinterpret_cast<float*>(d->out + 1 + kMlpOut), stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d->host_out, d->out, sizeof(uint32_t) * kPickWords, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e);
-  const uint32_t idx = *d->host_index;
-  if (idx < (uint32_t)kMlpOut && grid_valid((int)idx)) {
-    *out = grid_config((int)idx);
-    *used = true;
-  }
+  const uint32_t idx = d->host_out[0];
+  if (idx >= (uint32_t)kMlpOut || !grid_valid((int)idx)) return RTCDF_SUCCESS;
+  // Keys whose sketch lies outside the features the network was trained on
+  // (farther than zmax sd from the training mean in some feature) are left to
+  // the static configuration, like arrays outside the trained n and R ranges.
+  float z;
+  std::memcpy(&z, d->host_out + 1 + kMlpOut, sizeof(float));
+  if (g_model.zmax > 0.f && !(z <= g_model.zmax)) return RTCDF_SUCCESS;
+  // Act on the prediction only where it promises at least the margin over
+  // the configuration that would be used otherwise.
+  const float* pred = reinterpret_cast<const float*>(d->host_out + 1);
+  const int si = grid_index(fallback);
+  if (si >= 0 && g_model.valid[si] && pred[si] - pred[idx] < g_model.margin) return RTCDF_SUCCESS;
+  *out = grid_config((int)idx);
+  *used = true;
   return RTCDF_SUCCESS;
 }
 
@@ -212,9 +247,10 @@ rtcdf_status_t rtcdf_load_tuned_table(const char* path) {
   return RTCDF_SUCCESS;
 }
 
-// Model file: "RTCDFMLP" | u32 version 1 | u32 inputs, hidden, outputs, params |
-// f32 log2n_lo, log2n_hi, log2r_lo, log2r_hi | f32 mean[inputs] | f32 sd[inputs] |
-// f32 params[params] | u8 valid[outputs].
+// Model file: "RTCDFMLP" | u32 version (1 or 2) | u32 inputs, hidden, outputs,
+// params | f32 log2n_lo, log2n_hi, log2r_lo, log2r_hi | version 2: f32 margin,
+// f32 zmax | f32 mean[inputs] | f32 sd[inputs] | f32 params[params] |
+// u8 valid[outputs].
 rtcdf_status_t rtcdf_load_model(const char* path) {
   if (path == nullptr) return RTCDF_ERROR_INVALID_VALUE;
   FILE* f = std::fopen(path, "rb");
@@ -223,10 +259,12 @@ rtcdf_status_t rtcdf_load_model(const char* path) {
   char magic[8];
   uint32_t hdr[5];
   float ranges[4];
+  float gate[2] = {0.f, 0.f};   // margin, zmax
   bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "RTCDFMLP", 8) == 0 &&
-            std::fread(hdr, 4, 5, f) == 5 && hdr[0] == 1 && hdr[1] == (uint32_t)kMlpIn &&
+            std::fread(hdr, 4, 5, f) == 5 && (hdr[0] == 1 || hdr[0] == 2) && hdr[1] == (uint32_t)kMlpIn &&
             hdr[2] == (uint32_t)kMlpHidden && hdr[3] == (uint32_t)kMlpOut && hdr[4] == (uint32_t)kMlpParams &&
-            std::fread(ranges, 4, 4, f) == 4;
+            std::fread(ranges, 4, 4, f) == 4 && (hdr[0] == 1 || std::fread(gate, 4, 2, f) == 2);
+  ok = ok && std::isfinite(gate[0]) && gate[0] >= 0.f && std::isfinite(gate[1]) && gate[1] >= 0.f;
   if (ok) {
     m.norm.resize(2 * kMlpIn);
     m.params.resize(kMlpParams);
@@ -247,6 +285,8 @@ rtcdf_status_t rtcdf_load_model(const char* path) {
   m.log2n_hi = ranges[1];
   m.log2r_lo = ranges[2];
   m.log2r_hi = ranges[3];
+  m.margin = gate[0];
+  m.zmax = gate[1];
   m.loaded = true;
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   g_model = m;
@@ -393,7 +433,7 @@ rtcdf_status_t rtcdf_mlp_pick(const int32_t* keys_in, size_t n, int64_t minVal, 
   if (!keys_in || n == 0 || maxVal <= minVal || !d_params || !d_norm || !d_valid || !d_index)
     return RTCDF_ERROR_INVALID_VALUE;
   hipError_t e = launch_pick(keys_in, n, minVal, (uint64_t)(maxVal - minVal), kSketchSamples, d_params, d_norm,
-                             d_valid, d_index, d_pred, stream);
+                             d_valid, d_index, d_pred, nullptr, stream);
   return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
 }
 

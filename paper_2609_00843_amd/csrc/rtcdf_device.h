@@ -167,10 +167,11 @@ __device__ __forceinline__ void wrap_flush(const uint32_t* tab, uint32_t* carry,
   }
 }
 
-// Wave-uniform accumulator of the 8-bit form's all-equal fast path: a wave
+// Wave-uniform accumulator of the narrow forms' all-equal fast path: a wave
 // whose four keys per lane are one value adds them to this register (an add
-// of up to 256 would wrap a byte counter every time); it goes to the wrap
-// table when the value changes and at the end.
+// of 256 would wrap a byte counter every time, and a returning LDS atomic per
+// vector would stall the wave); it goes to the wrap table when the value
+// changes and at the end.
 struct HotBin {
   uint32_t bin = kWrapEmpty;
   uint32_t cnt = 0;
@@ -202,13 +203,13 @@ __device__ __forceinline__ void fix_u8(uint32_t old, uint32_t x, uint32_t c, uin
 // 16 or 8).  If every active lane of the wave holds four copies of one value
 // (all-equal or heavily skewed keys), a single lane adds them with one LDS
 // atomic instead of 4 x 64 atomics on the same address (8-bit form: into the
-// wave's hot-bin register, since such adds would wrap a byte).  Otherwise
+// wave's hot-bin register in the narrow forms).  Otherwise
 // every key inside the pass takes one LDS atomic; keys outside it are masked
 // off.  In the narrow forms the four returning atomics are issued back to
 // back and a counter that just wrapped is repaired after a single wave-wide
 // test.  PAD selects the padded 32-bit layout (bin x at x + x / 32).  `tab`
-// and `hot` (the wrap table and the hot-bin register) are used by the 8-bit
-// form only.
+// and `hot` (the wrap table and the hot-bin register) are used by the 8- and
+// 16-bit forms; the 16-bit form may run without a table (tab == nullptr).
 template <int BITS, bool PAD = false>
 __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32_t W,
                                        uint32_t* carry, uint32_t pass_lo, uint32_t* tab, HotBin& hot) {
@@ -221,15 +222,18 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
   if (same == active) {
     if (lead < W) {
       const uint32_t c = 4u * (uint32_t)__popcll(active);
-      if constexpr (BITS == 8) {
-        if (lead != hot.bin) {
-          hot_flush(hot, tab, carry, pass_lo);
-          hot.bin = lead;
+      if constexpr (BITS < 32) {
+        if (tab != nullptr) {
+          if (lead != hot.bin) {
+            hot_flush(hot, tab, carry, pass_lo);
+            hot.bin = lead;
+          }
+          hot.cnt += c;
+        } else if (lane_id() == (uint32_t)(__ffsll((unsigned long long)active) - 1)) {
+          add_u16(S, lead, c, carry, pass_lo);   // 16-bit form without a wrap table
         }
-        hot.cnt += c;
       } else if (lane_id() == (uint32_t)(__ffsll((unsigned long long)active) - 1)) {
-        if constexpr (BITS == 16) add_u16(S, lead, c, carry, pass_lo);
-        else atomicAdd(&S[PAD ? pad32(lead) : lead], c);
+        atomicAdd(&S[PAD ? pad32(lead) : lead], c);
       }
     }
     return;

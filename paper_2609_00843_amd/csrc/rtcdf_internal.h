@@ -95,9 +95,11 @@ hipError_t launch_mlp_grad(const float* P, const float* X, const float* T, const
 size_t mlp_grad_scratch_floats(uint32_t B);
 hipError_t launch_adam(float* P, const float* G, float* Mo, float* Vo, float lr, float b1, float b2,
                        float eps, uint32_t t, hipStream_t s);
+// out_pred (54 predictions) and out_zmax (the largest |normalised feature|)
+// may be null.
 hipError_t launch_pick(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R, uint32_t samples,
                        const float* P, const float* norm, const uint8_t* valid, uint32_t* out_index,
-                       float* out_pred, hipStream_t s);
+                       float* out_pred, float* out_zmax, hipStream_t s);
 
 // Host helpers shared by the C ABI translation units (rtcdf_api.hip).
 rtcdf_status_t device_info(DeviceInfo* out);

@@ -54,10 +54,10 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   const uint32_t wg = blockIdx.x, xcd = wg & 7u, slot = wg >> 3;
   const uint32_t pass = slot % a.passes;
   const uint32_t chunk = (slot / a.passes) * 8u + xcd;
-  // LDS: the counters, then (8-bit form) the wrap table's bins and amounts.
+  // LDS: the counters, then (narrow forms) the wrap table's bins and amounts.
   uint32_t* tab = S + a.row_words;
   for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) S[i] = 0u;
-  if constexpr (BITS == 8) {
+  if constexpr (BITS < 32) {
     if (threadIdx.x < 2 * kWrapSlots) tab[threadIdx.x] = threadIdx.x < kWrapSlots ? kWrapEmpty : 0u;
   }
   __syncthreads();
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   constexpr int V = ITEMS / 4;
   const v4i* body = reinterpret_cast<const v4i*>(a.keys + a.in_head);
   const v4i outside = (v4i)(int)(base - 1u);   // lands outside every pass
-  HotBin hot;                                  // 8-bit form only
+  HotBin hot;                                  // narrow forms only
   uint32_t t0, step, end;
   if (a.interleave) {
     // Tiles of BLOCK * V vectors dealt round-robin to the G chunks of a pass:
@@ -120,9 +120,9 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   if (chunk == a.G - 1 && threadIdx.x < a.in_tail)
     e.y = a.keys[a.in_head + 4 * (size_t)a.in_n4 + threadIdx.x];
   if (threadIdx.x < 64) count4<BITS>(S, e, base, W, a.carry, pass_lo, tab, hot);
-  if constexpr (BITS == 8) hot_flush(hot, tab, a.carry, pass_lo);
+  if constexpr (BITS < 32) hot_flush(hot, tab, a.carry, pass_lo);
   __syncthreads();
-  if constexpr (BITS == 8) wrap_flush(tab, a.carry, pass_lo, threadIdx.x);
+  if constexpr (BITS < 32) wrap_flush(tab, a.carry, pass_lo, threadIdx.x);
 
   uint32_t* row = a.partial + ((size_t)pass * a.G + chunk) * a.row_words;
   for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) row[i] = S[i];
@@ -593,8 +593,8 @@ __global__ void k_clear(uint32_t* p, size_t words) {
 
 template <int ITEMS, int BITS, int BLOCK>
 hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
-  // the counters (and the 8-bit form's wrap table) fit the static LDS array
-  const size_t lds = ((size_t)p.row_words + (BITS == 8 ? 2 * kWrapSlots : 0)) * 4;
+  // the counters (and the narrow forms' wrap table) fit the static LDS array
+  const size_t lds = ((size_t)p.row_words + (BITS < 32 ? 2 * kWrapSlots : 0)) * 4;
   if (lds > kLdsBytes / (1024 / BLOCK)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_hist<ITEMS, BITS, BLOCK>), dim3(p.passes * p.G), dim3(BLOCK), 0, s, a);
   return hipGetLastError();

@@ -205,7 +205,8 @@ __global__ void k_sum_loss(const float* lossterm, uint32_t B, float inv_count, f
 // configurations (lowest index on ties).  One workgroup of 256 threads.
 __global__ __launch_bounds__(256) void k_pick(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R,
                                               uint32_t samples, const float* P, const float* norm,
-                                              const uint8_t* valid, uint32_t* out_index, float* out_pred) {
+                                              const uint8_t* valid, uint32_t* out_index, float* out_pred,
+                                              float* out_zmax) {
   __shared__ uint32_t bins[kSketchBins];
   __shared__ float f[D0];
   __shared__ float h[2 * H];
@@ -213,6 +214,11 @@ __global__ __launch_bounds__(256) void k_pick(const int32_t* keys, uint64_t n, i
   sketch_block(keys, n, minVal, R, samples, f, bins);
   if (threadIdx.x < D0) f[threadIdx.x] = (f[threadIdx.x] - norm[threadIdx.x]) / norm[D0 + threadIdx.x];
   __syncthreads();
+  if (out_zmax && threadIdx.x == 0) {   // distance from the training features, in sd units
+    float z = 0.f;
+    for (int i = 0; i < D0; ++i) z = fmaxf(z, fabsf(f[i]));
+    out_zmax[0] = z;
+  }
   // All 256 threads take part in the barriers; the first 64 compute.
   const int j = threadIdx.x;
   if (j < H) {
@@ -291,9 +297,9 @@ hipError_t launch_adam(float* P, const float* G, float* Mo, float* Vo, float lr,
 
 hipError_t launch_pick(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R, uint32_t samples,
                        const float* P, const float* norm, const uint8_t* valid, uint32_t* out_index,
-                       float* out_pred, hipStream_t s) {
+                       float* out_pred, float* out_zmax, hipStream_t s) {
   hipLaunchKernelGGL(k_pick, dim3(1), dim3(256), 0, s, keys, n, minVal, R, samples, P, norm, valid,
-                     out_index, out_pred);
+                     out_index, out_pred, out_zmax);
   return hipGetLastError();
 }
 

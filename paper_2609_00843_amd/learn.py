@@ -13,6 +13,16 @@ squared error).
 
 A checkpoint (.npz next to the model: weights, Adam moments, step, feature
 normalisation, loss history) lets training resume.
+
+The network's choice replaces the static table's only where it predicts at
+least `margin` (natural-log units) less run time, and only for arrays whose
+features lie within `zmax` standard deviations of the training mean in every
+feature (zmax is twice the largest such distance among the fitting rows, the
+factor fixed in advance): outside that the network is extrapolating and the
+static table is kept.  The network is fitted on a seeded 80 % of the training
+rows; on the other 20 % the margin with the best geometric-mean gain over the
+static table is chosen (the larger one on ties).  The held-out test rows are
+never used for fitting, for zmax or for the margin.
 """
 from __future__ import annotations
 
@@ -60,12 +70,25 @@ def init_params(seed: int):
     return np.concatenate(parts).astype(np.float32)
 
 
-def save_model(path: str, params, mu, sd, ranges):
+MARGINS = tuple(round(0.005 * i, 3) for i in range(41))   # 0 .. 0.2
+
+
+ZMAX_FACTOR = 2.0
+
+
+def zmax_of(X, mu, sd) -> float:
+    """Largest |normalised feature| over the rows of X."""
+    return float(np.abs((np.asarray(X, dtype=np.float64) - mu) / sd).max())
+
+
+def save_model(path: str, params, mu, sd, ranges, margin: float = 0.0, zmax: float = 0.0):
+    """Model file version 2 (version 1 has no margin and zmax fields)."""
     _, valid = tune.grid()
     with open(path, "wb") as f:
         f.write(b"RTCDFMLP")
-        f.write(struct.pack("<5I", 1, 34, 64, 54, 9910))
+        f.write(struct.pack("<5I", 2, 34, 64, 54, 9910))
         f.write(struct.pack("<4f", *ranges))
+        f.write(struct.pack("<2f", margin, zmax))
         f.write(np.asarray(mu, dtype=np.float32).tobytes())
         f.write(np.asarray(sd, dtype=np.float32).tobytes())
         f.write(np.asarray(params, dtype=np.float32).tobytes())
@@ -116,48 +139,106 @@ def predict(params, mu, sd, X):
 
 
 def load_model_file(path: str):
+    """(params, mean, sd, ranges, margin, zmax) of a model file of version 1 or 2."""
     with open(path, "rb") as f:
         raw = f.read()
     assert raw[:8] == b"RTCDFMLP"
+    version = struct.unpack("<I", raw[8:12])[0]
+    assert version in (1, 2)
     o = 8 + 20
     ranges = struct.unpack("<4f", raw[o:o + 16])
     o += 16
+    margin = zmax = 0.0
+    if version == 2:
+        margin, zmax = struct.unpack("<2f", raw[o:o + 8])
+        o += 8
     mu = np.frombuffer(raw, dtype=np.float32, count=34, offset=o).astype(np.float64)
     o += 136
     sd = np.frombuffer(raw, dtype=np.float32, count=34, offset=o).astype(np.float64)
     o += 136
     params = np.frombuffer(raw, dtype=np.float32, count=9910, offset=o).copy()
-    return params, mu, sd, ranges
+    return params, mu, sd, ranges, margin, zmax
+
+
+def static_indices(rows):
+    """Grid index of the static table's configuration for every row (the
+    library's DEFAULT pick, host logic only)."""
+    from . import rtcdf
+    pts, _ = tune.grid()
+    idx_of = {p: i for i, p in enumerate(pts)}
+    old = rtcdf.get_config_mode()
+    rtcdf.set_config_mode(rtcdf.CONFIG_DEFAULT)
+    try:
+        return [idx_of[rtcdf.pick_config(r["n"], r["minVal"], r["minVal"] + r["R"]).as_tuple()]
+                for r in rows]
+    finally:
+        rtcdf.set_config_mode(old)
+
+
+def decide(y, ok, static: int, margin: float, trusted: bool = True) -> int:
+    """The network's masked argmin where the array's features are trusted and
+    it predicts at least `margin` less than for the static choice, else the
+    static choice."""
+    if not trusted:
+        return static
+    pick = min((y[j], j) for j in range(54) if ok[j])[1]
+    if ok[static] and y[static] - y[pick] < margin:
+        return static
+    return pick
+
+
+def margin_gains(Y, rows, statics, trusted=None):
+    """Geometric-mean gain over the static choice, on the rows' measured
+    times, of every margin in MARGINS."""
+    _, valid = tune.grid()
+    trusted = trusted if trusted is not None else [True] * len(rows)
+    out = []
+    for mg in MARGINS:
+        logs = []
+        for r, y, si, tr in zip(rows, Y, statics, trusted):
+            t = np.array(r["times_ms"])
+            ok = np.array(valid) & (t > 0)
+            logs.append(math.log(t[si] / t[decide(y, ok, si, mg, tr)]))
+        out.append(math.exp(sum(logs) / len(logs)))
+    return out
+
+
+def choose_margin(Y, rows, statics, trusted=None):
+    """The margin (from MARGINS) with the best geometric-mean gain over the
+    static choice on the rows' measured times; the larger margin on ties."""
+    gains = margin_gains(Y, rows, statics, trusted)
+    best = (None, -1.0)
+    for mg, g in zip(MARGINS, gains):
+        if g >= best[1]:
+            best = (mg, g)
+    return best
 
 
 def evaluate(rows, model_path: str):
     """Regret of the learned pick against the exhaustive optimum of the same
-    (independent) timing run, and its gain over the static default table."""
-    from . import rtcdf
-    params, mu, sd, _ = load_model_file(model_path)
+    (independent) timing run, and its gain over the static default table,
+    with the model's margin and feature gate applied."""
+    params, mu, sd, _, margin, zmax = load_model_file(model_path)
     pts, valid = tune.grid()
     X = np.array([r["features"] for r in rows], dtype=np.float64)
     Y = predict(params, mu, sd, X)
-    idx_of = {p: i for i, p in enumerate(pts)}
-    old_mode = rtcdf.get_config_mode()
-    rtcdf.set_config_mode(rtcdf.CONFIG_DEFAULT)
+    statics = static_indices(rows)
+    trusted = [zmax <= 0 or zmax_of(x[None, :], mu, sd) <= zmax for x in X]
     regrets, gains, per = [], [], []
-    try:
-        for r, y in zip(rows, Y):
-            t = np.array(r["times_ms"])
-            ok = np.array(valid) & (t > 0)
-            pick = min((y[j], j) for j in range(54) if ok[j])[1]
-            static = idx_of[rtcdf.pick_config(r["n"], r["minVal"], r["minVal"] + r["R"]).as_tuple()]
-            best = float(t[ok].min())
-            regrets.append(t[pick] / best - 1.0)
-            gains.append(t[static] / t[pick])
-            per.append({"key": r["key"], "dist": r["dist"], "n": r["n"], "R": r["R"], "pick": pts[pick],
-                        "static": pts[static], "t_pick": float(t[pick]), "t_static": float(t[static]),
-                        "t_best": best})
-    finally:
-        rtcdf.set_config_mode(old_mode)
+    for r, y, static, tr in zip(rows, Y, statics, trusted):
+        t = np.array(r["times_ms"])
+        ok = np.array(valid) & (t > 0)
+        pick = decide(y, ok, static, margin, tr)
+        best = float(t[ok].min())
+        regrets.append(t[pick] / best - 1.0)
+        gains.append(t[static] / t[pick])
+        per.append({"key": r["key"], "dist": r["dist"], "n": r["n"], "R": r["R"], "pick": pts[pick],
+                    "static": pts[static], "t_pick": float(t[pick]), "t_static": float(t[static]),
+                    "t_best": best, "trusted": bool(tr)})
     reg = np.array(regrets)
-    res = {"arrays": len(rows),
+    res = {"arrays": len(rows), "margin": margin, "zmax": zmax,
+           "within_zmax": float(np.mean(trusted)),
+           "learned_choice_used": float(np.mean([p["pick"] != p["static"] for p in per])),
            "regret_mean": float(reg.mean()), "regret_median": float(np.median(reg)),
            "regret_p95": float(np.percentile(reg, 95)), "regret_max": float(reg.max()),
            "gain_geomean_vs_static": float(np.exp(np.mean(np.log(gains)))),
@@ -187,11 +268,20 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.cmd == "train":
         rows = tune.load_db(args.db)
-        params, mu, sd, ranges, hist = train(rows, steps=args.steps, lr=args.lr, seed=args.seed,
+        order = np.random.default_rng(args.seed).permutation(len(rows))
+        n_val = len(rows) // 5
+        val = [rows[i] for i in order[:n_val]]
+        fit = [rows[i] for i in order[n_val:]]
+        params, mu, sd, ranges, hist = train(fit, steps=args.steps, lr=args.lr, seed=args.seed,
                                              checkpoint=os.path.splitext(args.out)[0] + "_ckpt.npz")
-        save_model(args.out, params, mu, sd, ranges)
-        print(json.dumps({"rows": len(rows), "final_loss": hist[-1], "first_loss": hist[0],
-                          "model": args.out}))
+        zmax = ZMAX_FACTOR * zmax_of([r["features"] for r in fit], mu, sd)
+        Xv = np.array([r["features"] for r in val], dtype=np.float64)
+        trusted = [zmax_of(x[None, :], mu, sd) <= zmax for x in Xv]
+        margin, gain = choose_margin(predict(params, mu, sd, Xv), val, static_indices(val), trusted)
+        save_model(args.out, params, mu, sd, ranges, margin, zmax)
+        print(json.dumps({"rows_fit": len(fit), "rows_validation": len(val), "final_loss": hist[-1],
+                          "first_loss": hist[0], "margin": margin, "zmax": zmax,
+                          "validation_gain": gain, "model": args.out}))
     else:
         res, per = evaluate(tune.load_db(args.db), args.model)
         if args.out:

@@ -17,6 +17,14 @@ LIB_PATH = os.path.join(_HERE, "librtcdf.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2609_00843_amd.build`")
 
+# torch ships its own HIP runtime (libamdhip64.so) next to its libraries; the
+# library's own dependency is the system libamdhip64.so.7.  Importing torch
+# first puts torch's runtime in the global symbol scope, so the library's HIP
+# calls bind to the same runtime that owns torch's streams and allocations.
+# Loaded the other way round, the process would hold two HIP runtimes and
+# torch's stream handles would reach the wrong one.
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 
 STATUS = {

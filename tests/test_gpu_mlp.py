@@ -148,3 +148,69 @@ def test_pick(r):
         assert np.allclose(pred, want[0], rtol=1e-4, atol=1e-4 * np.abs(want).max())
         # the argmin is taken in the kernel's precision: compare on its own outputs
         assert int(idx.cpu()[0]) == M.pick(pred, valid)
+
+
+@pytest.mark.parametrize("margin", [0.0, 0.02, 1e30])
+def test_learned_pick_applies_margin(r, tmp_path, margin):
+    """LEARNED mode keeps the static configuration unless the network predicts
+    at least the model's margin of gain: the library's choice equals
+    learn.decide applied to the pick kernel's own predictions."""
+    from paper_2609_00843_amd import learn, tune
+    p = _flat(_init(8))
+    rng = np.random.default_rng(9)
+    mu, sd = rng.normal(size=34) * 0.1, 0.5 + rng.random(size=34)
+    path = str(tmp_path / "m.bin")
+    learn.save_model(path, p, mu, sd, (10.0, 30.0, 4.0, 20.0), margin=margin, zmax=0.0)
+    pts, valid = tune.grid()
+    r.load_model(path)
+    old = r.get_config_mode()
+    try:
+        for dist, n, R in (("uniform", 2_000_000, 4096), ("normal", 1_500_000, 70000), ("zipf", 3_000_000, 300)):
+            A = inputs.make(dist, n, 0, R, 10)
+            d = torch.from_numpy(A).cuda()
+            _say(f"learned pick {dist} margin={margin}")
+            r.set_config_mode(r.CONFIG_DEFAULT)
+            static = pts.index(r.pick_config(n, 0, R).as_tuple())
+            r.set_config_mode(r.CONFIG_LEARNED)
+            got = pts.index(r.pick_config(n, 0, R, keys_in=d).as_tuple())
+            norm = np.concatenate([mu, sd])
+            validd = torch.tensor(np.array(valid, dtype=np.uint8), device="cuda")
+            _, pred = r.mlp_pick(d, 0, R, _dev(p), _dev(norm), validd)
+            # the library compares in FP32: so does the reference here
+            want = learn.decide(pred.cpu().numpy(), np.array(valid), static, np.float32(margin))
+            assert got == want
+            if margin >= 1e30:
+                assert got == static
+    finally:
+        r.set_config_mode(old)
+        r.unload_model()
+
+
+def test_learned_pick_feature_gate(r, tmp_path):
+    """A sketch farther than zmax from the training mean keeps the static
+    configuration whatever the network prefers; within it the network decides."""
+    from paper_2609_00843_amd import learn, tune
+    p = _flat(_init(8))
+    pts, valid = tune.grid()
+    A = inputs.make("zipf", 2_000_000, 0, 50000, 12)
+    d = torch.from_numpy(A).cuda()
+    feats = M.sketch(A, 0, 50000)
+    mu, sd = np.zeros(34), np.ones(34)
+    z = float(np.abs(feats - mu).max())          # the array's distance in sd units
+    old = r.get_config_mode()
+    try:
+        r.set_config_mode(r.CONFIG_DEFAULT)
+        static = pts.index(r.pick_config(A.size, 0, 50000).as_tuple())
+        _, pred = r.mlp_pick(d, 0, 50000, _dev(p), _dev(np.concatenate([mu, sd])),
+                             torch.tensor(np.array(valid, dtype=np.uint8), device="cuda"))
+        free = learn.decide(pred.cpu().numpy(), np.array(valid), static, np.float32(0.0))
+        for zmax, want in ((z * 0.5, static), (z * 2.0, free)):
+            path = str(tmp_path / f"m{zmax}.bin")
+            learn.save_model(path, p, mu, sd, (10.0, 30.0, 4.0, 20.0), margin=0.0, zmax=zmax)
+            r.load_model(path)
+            r.set_config_mode(r.CONFIG_LEARNED)
+            _say(f"feature gate zmax={zmax:.3f} (array at {z:.3f})")
+            assert pts.index(r.pick_config(A.size, 0, 50000, keys_in=d).as_tuple()) == want
+            r.unload_model()
+    finally:
+        r.set_config_mode(old)

@@ -67,12 +67,25 @@ def test_model_file_round_trip(tmp_path):
     p = learn.init_params(5)
     mu, sd = np.zeros(34), np.ones(34)
     path = str(tmp_path / "m.bin")
-    learn.save_model(path, p, mu, sd, (20.0, 30.0, 7.0, 18.0))
+    learn.save_model(path, p, mu, sd, (20.0, 30.0, 7.0, 18.0), margin=0.025, zmax=5.5)
     rtcdf.load_model(path)
-    p2, mu2, sd2, ranges = learn.load_model_file(path)
+    p2, mu2, sd2, ranges, margin, zmax = learn.load_model_file(path)
     assert np.array_equal(p2, p) and ranges == (20.0, 30.0, 7.0, 18.0)
+    assert margin == pytest.approx(0.025) and zmax == pytest.approx(5.5)
     rtcdf.unload_model()
     raw = bytearray(open(path, "rb").read())
+    # version 1: no margin and zmax fields
+    v1 = bytearray(raw[:44]) + raw[52:]
+    v1[8] = 1
+    (tmp_path / "v1.bin").write_bytes(bytes(v1))
+    rtcdf.load_model(str(tmp_path / "v1.bin"))
+    assert learn.load_model_file(str(tmp_path / "v1.bin"))[4:] == (0.0, 0.0)
+    rtcdf.unload_model()
+    neg = bytearray(raw)
+    neg[44:48] = np.float32(-0.1).tobytes()      # a negative margin is refused
+    (tmp_path / "neg.bin").write_bytes(bytes(neg))
+    with pytest.raises(rtcdf.RtcdfError):
+        rtcdf.load_model(str(tmp_path / "neg.bin"))
     raw[8] = 7                                  # unknown version
     (tmp_path / "v.bin").write_bytes(bytes(raw))
     with pytest.raises(rtcdf.RtcdfError):
@@ -80,6 +93,30 @@ def test_model_file_round_trip(tmp_path):
     (tmp_path / "short.bin").write_bytes(bytes(raw[:100]))
     with pytest.raises(rtcdf.RtcdfError):
         rtcdf.load_model(str(tmp_path / "short.bin"))
+
+
+def test_decision_margin():
+    """The network's choice replaces the static one only with at least the
+    margin of predicted gain; the margin is chosen on measured times."""
+    _, valid = tune.grid()
+    ok = np.array(valid)
+    y = np.zeros(54)
+    y[5] = -0.03                                  # predicted 3% faster than everything else
+    assert learn.decide(y, ok, 0, 0.02) == 5
+    assert learn.decide(y, ok, 0, 0.05) == 0
+    assert learn.decide(y, ok, 5, 0.0) == 5
+    assert learn.decide(y, ok, 0, 0.0, trusted=False) == 0
+    rows = []
+    for g in (1.10, 0.90, 1.02):                # static / picked time ratio per row
+        t = np.ones(54)
+        t[5] = 1.0 / g
+        t[~ok] = -1.0
+        rows.append({"times_ms": t.tolist()})
+    Y = np.zeros((3, 54))
+    Y[:, 5] = [-0.2, -0.01, -0.05]               # the network is confident where it is right
+    mg, gain = learn.choose_margin(Y, rows, [0, 0, 0])
+    # margins in (0.01, 0.05] keep rows 0 and 2 and drop row 1; the largest wins the tie
+    assert mg == pytest.approx(0.05) and gain == pytest.approx((1.10 * 1.02) ** (1 / 3))
 
 
 def test_dataset_targets_are_centred():
