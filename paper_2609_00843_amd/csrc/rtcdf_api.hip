@@ -112,16 +112,19 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   p->m = (R + p->T - 1) / p->T;
 
   // Histogram passes: as many whole tiles per workgroup LDS as fit, with 32-bit
-  // counters, or with two 16-bit or four 8-bit counters per word when that
-  // needs fewer passes over the input.
+  // counters, or with four 8-bit counters per word when that needs fewer
+  // passes over the input.
   const uint32_t lds = kLdsBytes / p->bpt;
   const uint32_t k32 = std::max<uint32_t>(1, lds / (4 * p->T));
   const uint32_t k16 = std::max<uint32_t>(1, (lds - 512) / (2 * p->T));   // 512 B wrap table
   const uint32_t k8 = std::max<uint32_t>(1, (lds - 512) / p->T);
   const uint32_t passes32 = (p->m + k32 - 1) / k32;
-  const uint32_t passes16 = (p->m + k16 - 1) / k16;
   const uint32_t passes8 = (p->m + k8 - 1) / k8;
-  p->bits = passes8 < passes16 ? 8 : (passes16 < passes32 ? 16 : 32);
+  // 32-bit counters where they need no more passes (no wraps, no returning
+  // atomics); otherwise four 8-bit counters per word (measured faster than
+  // two 16-bit ones at equal passes: half the partial-row traffic, wraps of hot
+  // bins gathered in LDS).  16-bit counters stay selectable for measurement.
+  p->bits = passes32 <= passes8 ? 32 : 8;
   const int force_bits = env_int("RTCDF_DEV_COUNTER_BITS", 0);
   if (force_bits == 8 || force_bits == 16 || force_bits == 32) p->bits = (uint32_t)force_bits;
   const uint32_t k = p->bits == 8 ? k8 : (p->bits == 16 ? k16 : k32);
@@ -170,7 +173,8 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   const uint32_t by_work = std::max<uint32_t>(1, p->nchunks / 256);
   if (p->m <= kScanBlock && p->nred <= 8 * kScanBlock) {
     p->scan_parts = 1;
-    p->scan_grid = std::max<uint32_t>(p->m, std::min<uint32_t>((uint32_t)dev.cus, by_work));
+    // one per tile plus up to 64 spares (all-equal keys: ~760 splitters each at n = 10^8)
+    p->scan_grid = p->m + std::min<uint32_t>(64u, by_work);
   } else {
     const uint32_t want_parts = std::max<uint32_t>(1, (uint32_t)dev.cus / p->m);
     p->scan_parts = std::min<uint32_t>(want_parts, std::max<uint32_t>(1, by_work / p->m));
@@ -191,6 +195,8 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   off = align256(off + (size_t)p->m * 4);
   p->off_split = off;
   off = align256(off + ((size_t)p->nchunks + 1) * 4);
+  p->off_flags = off;                       // [0]: some output chunk is sparse
+  off = align256(off + 4);
   // Carry entries cover every bin of every pass (plus the partner of the last
   // bin), so even keys outside the declared range stay in bounds.
   p->carry_words = p->bits < 32 ? (size_t)p->passes * p->W + 4 : 0;

@@ -58,7 +58,7 @@ struct Plan {
   uint32_t scan_parts;   // workgroups per tile in the local-CDF stage (fixed split)
   uint32_t scan_grid;    // workgroups of the local-CDF stage; > m: split by chunk counts
   // workspace layout
-  size_t off_partial, off_hist, off_cdf, off_rsum, off_O, off_split, ws_bytes;
+  size_t off_partial, off_hist, off_cdf, off_rsum, off_O, off_split, off_flags, ws_bytes;
   size_t off_carry;      // carry array inside a caller-owned workspace (rtcdf_sort_ws)
   size_t carry_words;    // 0 for 32-bit counters
 };

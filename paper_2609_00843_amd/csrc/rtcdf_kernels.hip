@@ -135,6 +135,7 @@ struct ReduceArgs {
   uint32_t* carry;
   uint32_t* hist;
   uint32_t* rsum;
+  uint32_t* flags;   // cleared here for the local-CDF stage
   uint32_t R, W, G, row_words, carry_words, bits;
 };
 
@@ -215,6 +216,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
   }
   const uint32_t sum = block_sum(tid < kReduceBins ? tot : 0u, wsum);
   if (tid == 0) a.rsum[blockIdx.x] = sum;
+  if (blockIdx.x == 0 && tid == 0) a.flags[0] = 0u;
 }
 
 // ---------------------------------------------------------- local CDF + O[t]
@@ -228,6 +230,7 @@ struct ScanArgs {
   uint64_t n;
   uint32_t R, T, out_head, chunk, nchunks, S;
   uint32_t m, grid;   // tiles; workgroups (grid > m: assigned by chunk counts)
+  uint32_t* flags;    // [0] set if some chunk's window holds over chunk / 64 values
 };
 
 // First output chunk whose start position s(k) is >= P, where s(0) = 0 and
@@ -368,8 +371,12 @@ __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
     }
     __syncthreads();
     const uint32_t nbatch = min(kPer * kScanBlock, k1 - kb0);
-    for (uint32_t j = tid; j < nbatch; j += kScanBlock) a.split[kb0 + j] = stage[j];
-    __syncthreads();
+    bool sparse = false;
+    for (uint32_t j = tid; j < nbatch; j += kScanBlock) {
+      a.split[kb0 + j] = stage[j];
+      if (j + 1 < nbatch) sparse |= (uint64_t)(stage[j + 1] - stage[j] + 1) * 64 > a.chunk;
+    }
+    if (__syncthreads_or(sparse) && tid == 0) a.flags[0] = 1u;
   }
   if (part == 0 && tid == 0 && a.n - 1 >= lo && a.n - 1 < hi)
     a.split[a.nchunks] = b + count_le_pad(C, w, (uint32_t)(a.n - 1 - lo));
@@ -385,6 +392,7 @@ struct FillArgs {
   uint64_t n;
   uint32_t min_u, R, T, out_head, chunk, nchunks;
   uint64_t body_lo, body_hi;   // positions [body_lo, body_hi) are 16-byte aligned int4s
+  const uint32_t* flags;       // [0]: some chunk is sparse (local-CDF stage)
 };
 
 // Inclusive cumulative count of value v over the whole range: O[t] + C_t[x].
@@ -525,18 +533,20 @@ __device__ __forceinline__ void chunk_values(const FillArgs& a, uint32_t k, uint
   *nwin = hi - lo + 1;
 }
 
-// Output stage.  Workgroups take chunks k = blockIdx.x + j * gridDim.x.  The
-// loop is software pipelined: while chunk k is written, the inclusive
-// cumulative counts of chunk k + G are already in flight into registers and
-// the splitters of chunk k + 2G are being fetched, so the few waves per
-// compute unit (writes are fastest with few concurrent writers) never wait
-// for global memory between chunks.
-template <bool SPARSE>
-__global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
-  __shared__ uint32_t win[2][kFillWindow];
+// Output stage.  Workgroups take chunks k = blockIdx.x + j * gridDim.x.  At
+// the start of chunk k the workgroup loads the head of chunk k + G's window
+// and the splitters of chunk k + 2G, so a chunk's window is complete in LDS
+// when its turn comes; the four resident workgroups per compute unit cover
+// each other's load latency (more workgroups per unit were measured not to
+// write faster).
+// MODE 0: every chunk in the dense form; 1: every chunk in the sparse form;
+// 2: per chunk, the sparse form where the window holds more than one value
+// per 64 positions (a sort whose keys leave stretches of the range nearly
+// empty, such as the tails of a narrow normal distribution).
+template <int MODE>
+__device__ __forceinline__ void fill_loop(const FillArgs& a, uint32_t (*win)[kFillWindow]) {
   const uint32_t tid = threadIdx.x, G = gridDim.x;
   uint32_t k = blockIdx.x;
-  if (k >= a.nchunks) return;
   uint32_t v0, nwin;
   chunk_values(a, k, &v0, &nwin);
   for (uint32_t j = tid; j < min(nwin, kFillWindow); j += kFillBlock) win[0][j] = cum_incl(a, v0 + j);
@@ -556,10 +566,12 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
 
     const uint64_t p0 = chunk_start(a, k);
     const uint64_t p1 = k + 1 < a.nchunks ? chunk_start(a, k + 1) : a.n;
-    if (nwin <= kFillWindow)
-      fill_chunk<SPARSE>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks);
-    else
+    if (nwin > kFillWindow)
       fill_chunk_global(a, v0, v0 + nwin - 1, p0, p1);
+    else if (MODE == 1 || (MODE == 2 && (uint64_t)nwin * 64 > p1 - p0))
+      fill_chunk<true>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks);
+    else
+      fill_chunk<false>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks);
     if (!more) break;
 
     // hand over to chunk k + G
@@ -575,6 +587,18 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
     nv0 = v0_2;
     nnwin = nwin_2;
   }
+}
+
+// SPARSE: the sort's keys average under 64 per value, so every chunk takes the
+// sparse form.  Otherwise the dense form, unless the local-CDF stage flagged a
+// sparse chunk, in which case each chunk takes the form its window calls for.
+template <bool SPARSE>
+__global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
+  __shared__ uint32_t win[2][kFillWindow];
+  if (blockIdx.x >= a.nchunks) return;
+  if (SPARSE) fill_loop<1>(a, win);
+  else if (a.flags[0] == 0u) fill_loop<0>(a, win);
+  else fill_loop<2>(a, win);
 }
 
 // Plain 16-byte vector copy (grid-stride), the attainable-bandwidth reference
@@ -669,6 +693,7 @@ hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_
   a.carry = carry;
   a.hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
   a.rsum = reinterpret_cast<uint32_t*>(ws + p.off_rsum);
+  a.flags = reinterpret_cast<uint32_t*>(ws + p.off_flags);
   a.R = p.R;
   a.W = p.W;
   a.G = p.G;
@@ -686,6 +711,7 @@ hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t s) {
   a.S = p.scan_parts;
   a.m = p.m;
   a.grid = p.scan_grid;
+  a.flags = reinterpret_cast<uint32_t*>(ws + p.off_flags);
   a.rsum = reinterpret_cast<const uint32_t*>(ws + p.off_rsum);
   a.O = reinterpret_cast<uint32_t*>(ws + p.off_O);
   a.split = reinterpret_cast<uint32_t*>(ws + p.off_split);
@@ -718,6 +744,7 @@ hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream
   a.nchunks = p.nchunks;
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
   a.body_hi = a.body_lo + 4 * ((p.n - a.body_lo) / 4);
+  a.flags = reinterpret_cast<const uint32_t*>(ws + p.off_flags);
   // The sparse form (look-ahead and bisection in the window) when the values
   // average fewer than 64 output positions each; the plain walk otherwise.
   if (p.n < (uint64_t)64 * p.R)

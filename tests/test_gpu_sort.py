@@ -133,10 +133,10 @@ def test_extreme_ranges(r):
 
 @pytest.mark.parametrize("R", [1 << 16, 1 << 16 | 1, 81921, 1 << 17, 1 << 18])
 def test_packed_counter_overflow(r, R):
-    """More equal keys per workgroup than a packed LDS counter holds (65535 in
-    16-bit, 255 in 8-bit counters), in every byte / half of one LDS word and in
-    the last (phantom-paired) bin; R = 2^16 and 65537 take 16-bit counters,
-    81921, 2^17 and 2^18 take 8-bit ones at the default tile width."""
+    """More equal keys per workgroup than an 8-bit LDS counter holds (255), in
+    every byte of one LDS word and in the last bin, with the counter width the
+    plan chooses (8-bit for all of these ranges); 16-bit counters are covered
+    by the forced-width test below and by the batched sort."""
     n = 40_000_000
     rng = np.random.default_rng(R)
     for pick in ([0], [0, 1], [1], [R - 1], [2, 3, R - 1], [0, 1, 2, 3], [4, 6, 7]):
@@ -171,9 +171,10 @@ def test_forced_counter_width(r, monkeypatch, bits, dist, R):
 
 
 def test_plan_counter_width_choice(r):
-    """The plan takes the narrowest counters only when they save a pass."""
+    """The plan takes 32-bit counters where they need no more passes, else
+    8-bit ones."""
     widths = {R: r.plan_info(10 ** 8, 0, R)["counter_bits"] for R in (128, 65536, 1 << 17, 1 << 18)}
-    assert widths[128] == 32 and widths[65536] == 16
+    assert widths[128] == 32 and widths[65536] == 8
     assert widths[1 << 17] == 8 and widths[1 << 18] == 8
 
 
