@@ -36,6 +36,7 @@ typedef __attribute__((address_space(1))) v4i g_v4i;
 constexpr uint32_t kBBlock = 1024;
 constexpr uint32_t kBTile = 32768;                   // values per local CDF tile
 constexpr uint32_t kBLdsWords = 33792;               // pad32(kBTile): LDS words of one padded tile
+constexpr uint32_t kBStageWords = kBBlock / 64 * 256;  // per-wave output staging (sparse steps)
 constexpr uint32_t kBBuckets = 34;
 
 struct BatchArgs {
@@ -97,7 +98,7 @@ __device__ uint32_t scan_tile(uint32_t* C, uint32_t w, uint32_t* wsum) {
 // tile is written as base + x.  body_lo is the first 16-byte aligned position
 // of the output.
 __device__ void fill_tile(g_i32* out, const uint32_t* C, uint32_t w, uint32_t base, uint32_t P0,
-                          uint32_t P1, uint32_t body_lo) {
+                          uint32_t P1, uint32_t body_lo, uint32_t* stage) {
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t last = w - 1;
   // aligned vectors inside [P0, P1)
@@ -139,10 +140,10 @@ __device__ void fill_tile(g_i32* out, const uint32_t* C, uint32_t w, uint32_t ba
           e = C[pad32(++xb)];
         }
         if (xb < last && e <= lp + 255u) {
-          o.x = (int32_t)(base + upper_in_pad(C, xw, last, p));
-          o.y = (int32_t)(base + upper_in_pad(C, xw, last, p + 1));
-          o.z = (int32_t)(base + upper_in_pad(C, xw, last, p + 2));
-          o.w = (int32_t)(base + upper_in_pad(C, xw, last, p + 3));
+          uint32_t* st = stage + wave * 256u;
+          scatter_step([&](uint32_t x) { return C[pad32(x)]; }, xw, last, lp, st);
+          const v4i sv = *reinterpret_cast<const v4i*>(st + 4 * lane);
+          o = (v4i)(int32_t)base + sv;
         } else {
           o.x = (int32_t)(base + xw + c0);
           o.y = (int32_t)(base + xw + c1);
@@ -232,21 +233,26 @@ __device__ void sort_segment(const rtcdf_segment_t& d, uint32_t* S, uint32_t* ws
     count_segment<V, false>(in, n, min_u, R, S, nullptr);
     __syncthreads();
     const uint32_t total = scan_tile(S, R, wsum);
-    fill_tile(out, S, R, min_u, 0u, total, body_lo);
+    fill_tile(out, S, R, min_u, 0u, total, body_lo, S + kBLdsWords);
     __syncthreads();   // LDS is reused by the next segment
     return;
   }
 
   // Two tiles: 16-bit counters, repaired and merged into the workgroup's
-  // global count array, then each tile's counts are scanned in LDS.
+  // global count array, then each tile's counts are scanned in LDS.  The count
+  // array belongs to this workgroup alone, so workgroup-scope ordering is
+  // enough between its phases (every store and atomic has reached L2 before
+  // the barrier; the reads below bypass L1).  A device-scope fence here would
+  // write back the whole L2 of the XCD, once per segment.
   for (uint32_t i = tid; i < (R + 1) / 2; i += kBBlock) S[i] = 0u;
   for (uint32_t i = tid; i < R + 2; i += kBBlock) cnt[i] = 0u;
-  __threadfence();
+  __threadfence_block();
   __syncthreads();
   count_segment<V, true>(in, n, min_u, R, S, cnt);
+  __threadfence_block();
   __syncthreads();
   for (uint32_t x = tid; x < R; x += kBBlock) atomicAdd(&cnt[x], (S[x >> 1] >> ((x & 1u) << 4)) & 0xffffu);
-  __threadfence();
+  __threadfence_block();
   __syncthreads();
   uint32_t O = 0;
   for (uint32_t b = 0; b < R; b += kBTile) {
@@ -255,7 +261,7 @@ __device__ void sort_segment(const rtcdf_segment_t& d, uint32_t* S, uint32_t* ws
       S[pad32(i)] = __hip_atomic_load(&cnt[b + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const uint32_t Nt = scan_tile(S, w, wsum);
-    if (Nt) fill_tile(out, S, w, min_u + b, O, O + Nt, body_lo);
+    if (Nt) fill_tile(out, S, w, min_u + b, O, O + Nt, body_lo, S + kBLdsWords);
     O += Nt;
     __syncthreads();
   }
@@ -290,7 +296,7 @@ hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, uint32_t* 
   hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, segs, nseg, order, counters);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)kBLdsWords * 4;
+  const size_t lds = (size_t)(kBLdsWords + kBStageWords) * 4;
   e = hipFuncSetAttribute((const void*)k_batched<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   BatchArgs a;

@@ -79,6 +79,39 @@ __device__ __forceinline__ uint32_t upper_in(const uint32_t* a, uint32_t lo, uin
   return lo;
 }
 
+// Writes, for one wave, the value index of each of the 256 positions
+// [q, q + 256) into stage[0, 256) (this wave's LDS staging area).  E(x) is
+// the inclusive cumulative count of value x, so value x occupies positions
+// [E(x - 1), E(x)); x0 is the value at position q and last the last value
+// index (E(last) is past every position asked for).  The lanes take 64
+// consecutive values at a time and each writes its value over its positions
+// inside the step: about two LDS reads per 64 values, however many of them
+// are empty, where a search per position would read log2(last) entries in
+// sequence.
+template <typename GetE>
+__device__ __forceinline__ void scatter_step(GetE E, uint32_t x0, uint32_t last, uint32_t q,
+                                             uint32_t* stage) {
+  const uint32_t lane = lane_id();
+  uint32_t xb = x0, start = q;   // start: where the run of value xb begins, clipped to q
+  for (;;) {
+    const uint32_t x = xb + lane;
+    const uint32_t e = x <= last ? E(x) : 0xffffffffu;
+    const uint32_t s = lane == 0 ? start : (x <= last ? E(x - 1) : 0xffffffffu);
+    const uint32_t lo = s > q ? s : q, hi = e < q + 256u ? e : q + 256u;
+    for (uint32_t p = lo; p < hi; ++p) stage[p - q] = x;
+    const uint32_t e63 = (uint32_t)__builtin_amdgcn_readlane((int)e, 63);
+    if (xb + 63u >= last || e63 >= q + 256u) break;
+    start = e63;
+    xb += 64u;
+  }
+  // all lanes' writes are ordered before the reads that follow (LDS operations
+  // of one wave execute in order); the fence only keeps the compiler from
+  // moving them
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Local CDFs are kept in LDS with one padding word per 32 entries, so the
 // per-thread segments of the blocked scan fall into distinct banks.
 __device__ __forceinline__ uint32_t pad32(uint32_t i) { return i + (i >> 5); }

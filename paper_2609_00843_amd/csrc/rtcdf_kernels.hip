@@ -423,7 +423,7 @@ __device__ __forceinline__ uint64_t chunk_start(const FillArgs& a, uint32_t k) {
 template <bool SPARSE>
 __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* win, uint32_t nwin,
                                            uint32_t v0, uint64_t p0, uint64_t p1, bool first,
-                                           bool final) {
+                                           bool final, uint32_t* stage) {
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint64_t q_lo = p0 > a.body_lo ? p0 : a.body_lo;
   const uint64_t q_hi = p1 < a.body_hi ? p1 : a.body_hi;
@@ -439,7 +439,8 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
   // order (one broadcast LDS read each) and every lane counts the boundaries
   // at or below each of its four positions.  In the SPARSE form, where more
   // than kWalk values end before the step or inside it (most of them empty),
-  // one look-ahead read shows it and the window is bisected instead.
+  // one look-ahead read shows it: the wave then bisects for its position or
+  // scatters the step's values over an LDS stage (scatter_step).
   constexpr uint32_t kWalk = 8;
   uint32_t xw = 0;
   uint32_t end = win[0];
@@ -482,10 +483,10 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
       const uint32_t p = pw + 4 * lane;
       const uint32_t far = win[min(xw + kWalk, last)], e1 = win[xw + 1];
       if (far <= pw + 255u) {
-        o.x = base + (int32_t)upper_in(win, xw, last, p);
-        o.y = base + (int32_t)upper_in(win, xw, last, p + 1);
-        o.z = base + (int32_t)upper_in(win, xw, last, p + 2);
-        o.w = base + (int32_t)upper_in(win, xw, last, p + 3);
+        uint32_t* st = stage + (tid >> 6) * 256u;
+        scatter_step([&](uint32_t x) { return win[x]; }, xw, last, pw, st);
+        const v4i sv = *reinterpret_cast<const v4i*>(st + 4 * lane);
+        o = (v4i)base + sv;
       } else {
         // boundary after value xw at position end, then after xw + 1 at e1, ...
         uint32_t c0 = end <= p, c1 = end <= p + 1, c2 = end <= p + 2, c3 = end <= p + 3;
@@ -544,7 +545,8 @@ __device__ __forceinline__ void chunk_values(const FillArgs& a, uint32_t k, uint
 // per 64 positions (a sort whose keys leave stretches of the range nearly
 // empty, such as the tails of a narrow normal distribution).
 template <int MODE>
-__device__ __forceinline__ void fill_loop(const FillArgs& a, uint32_t (*win)[kFillWindow]) {
+__device__ __forceinline__ void fill_loop(const FillArgs& a, uint32_t (*win)[kFillWindow],
+                                          uint32_t* stage) {
   const uint32_t tid = threadIdx.x, G = gridDim.x;
   uint32_t k = blockIdx.x;
   uint32_t v0, nwin;
@@ -569,9 +571,9 @@ __device__ __forceinline__ void fill_loop(const FillArgs& a, uint32_t (*win)[kFi
     if (nwin > kFillWindow)
       fill_chunk_global(a, v0, v0 + nwin - 1, p0, p1);
     else if (MODE == 1 || (MODE == 2 && (uint64_t)nwin * 64 > p1 - p0))
-      fill_chunk<true>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks);
+      fill_chunk<true>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
     else
-      fill_chunk<false>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks);
+      fill_chunk<false>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
     if (!more) break;
 
     // hand over to chunk k + G
@@ -595,10 +597,11 @@ __device__ __forceinline__ void fill_loop(const FillArgs& a, uint32_t (*win)[kFi
 template <bool SPARSE>
 __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
   __shared__ uint32_t win[2][kFillWindow];
+  __shared__ __align__(16) uint32_t stage[kFillBlock / 64 * 256];   // per wave (sparse steps)
   if (blockIdx.x >= a.nchunks) return;
-  if (SPARSE) fill_loop<1>(a, win);
-  else if (a.flags[0] == 0u) fill_loop<0>(a, win);
-  else fill_loop<2>(a, win);
+  if (SPARSE) fill_loop<1>(a, win, stage);
+  else if (a.flags[0] == 0u) fill_loop<0>(a, win, stage);
+  else fill_loop<2>(a, win, stage);
 }
 
 // Plain 16-byte vector copy (grid-stride), the attainable-bandwidth reference
