@@ -110,45 +110,61 @@ __device__ void fill_tile(g_i32* out, const uint32_t* C, uint32_t w, uint32_t ba
     const uint32_t i_lo = (q_lo - body_lo) >> 2, i_hi = (q_hi - body_lo) >> 2;
     uint32_t xw = 0, end = 0;
     bool started = false;
-    for (uint32_t ib = i_lo + wave * 64; ib < i_hi; ib += kBBlock) {
+    // Each wave writes a contiguous run of 64-vector steps, so the value index
+    // it carries from step to step moves by one step's worth of values.
+    const uint32_t steps = (i_hi - i_lo + 63) / 64, per_wave = (steps + kBBlock / 64 - 1) / (kBBlock / 64);
+    const uint32_t ib0 = i_lo + wave * per_wave * 64;
+    const uint32_t ib1 = min(i_hi, ib0 + per_wave * 64);
+    for (uint32_t ib = ib0; ib < ib1; ib += 64) {
       const uint32_t lp = body_lo + 4 * ib - P0;   // tile-local position of the step's first key
       if (!started) {
         xw = min(count_le_pad(C, w, lp), last);
         end = C[pad32(xw)];
         started = true;
       }
-      // as in the plain output stage: a walk of at most kWalk boundaries,
-      // bisection beyond that (sparse segments)
+      // The carried value may end before this step (the previous step carried
+      // the value at its last position).  A step crosses at most kWalk value
+      // ends by a walk; where a look-ahead read shows more (sparse values,
+      // most of them empty) it bisects or scatters instead.
       constexpr uint32_t kWalk = 8;
-      for (uint32_t s = 0; s < kWalk && xw < last && end <= lp; ++s) end = C[pad32(++xw)];
       if (xw < last && end <= lp) {
-        xw = upper_in_pad(C, xw, last, lp);
-        end = C[pad32(xw)];
+        if (C[pad32(min(xw + kWalk, last))] <= lp) {
+          xw = upper_in_pad(C, xw, last, lp);
+          end = C[pad32(xw)];
+        } else {
+          while (end <= lp) end = C[pad32(++xw)];
+        }
       }
       v4i o;
       if (xw == last || end > lp + 255u) {
         o = (v4i)(int32_t)(base + xw);
       } else {
-        const uint32_t p = lp + 4 * lane;
-        uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-        uint32_t xb = xw, e = end;
-        for (uint32_t s = 0; s < kWalk && xb < last && e <= lp + 255u; ++s) {
-          c0 += e <= p;
-          c1 += e <= p + 1;
-          c2 += e <= p + 2;
-          c3 += e <= p + 3;
-          e = C[pad32(++xb)];
-        }
-        if (xb < last && e <= lp + 255u) {
+        // the look-ahead and the next end are read together
+        const uint32_t far = C[pad32(min(xw + kWalk, last))], e1 = C[pad32(xw + 1)];
+        if (far <= lp + 255u) {
           uint32_t* st = stage + wave * 256u;
           scatter_step([&](uint32_t x) { return C[pad32(x)]; }, xw, last, lp, st);
           const v4i sv = *reinterpret_cast<const v4i*>(st + 4 * lane);
           o = (v4i)(int32_t)base + sv;
+          xw = min(st[255], last);   // the value at the step's last position
+          end = C[pad32(xw)];
         } else {
+          const uint32_t p = lp + 4 * lane;
+          uint32_t c0 = end <= p, c1 = end <= p + 1, c2 = end <= p + 2, c3 = end <= p + 3;
+          uint32_t xb = xw + 1, e = e1;
+          while (xb < last && e <= lp + 255u) {   // fewer than kWalk more ends
+            c0 += e <= p;
+            c1 += e <= p + 1;
+            c2 += e <= p + 2;
+            c3 += e <= p + 3;
+            e = C[pad32(++xb)];
+          }
           o.x = (int32_t)(base + xw + c0);
           o.y = (int32_t)(base + xw + c1);
           o.z = (int32_t)(base + xw + c2);
           o.w = (int32_t)(base + xw + c3);
+          xw = xb;                   // the value at the step's last position
+          end = e;
         }
       }
       const uint32_t i = ib + lane;
