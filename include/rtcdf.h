@@ -294,7 +294,8 @@ const char* rtcdf_status_string(rtcdf_status_t status);
 int rtcdf_last_hip_error(void);
 /* Per-stage timing for measurement.  While enabled, every plain sort records
  * HIP events on its stream around its four stages (0 histogram, 1 partial-row
- * reduction, 2 local CDF + tile offsets, 3 output); rtcdf_profile_collect
+ * reduction, 2 local CDF + tile offsets, 3 output; stages 1 and 2 take no
+ * time on the single-tile fast path, whose output stage does both); rtcdf_profile_collect
  * waits for the recorded events, writes the summed milliseconds per stage and
  * the number of sorts to *out, and forgets them.  Disabled by default. */
 typedef struct rtcdf_stage_stats {
@@ -323,7 +324,9 @@ typedef struct rtcdf_plan_info {
   uint32_t hist_workgroups;  /* passes x chunks */
   uint32_t hist_threads;
   uint32_t items_per_thread;
-  uint32_t scan_workgroups;  /* tiles x workgroups per tile */
+  uint32_t scan_workgroups;  /* local-CDF workgroups; 0 on the single-tile fast
+                                path (one tile, one pass of 32-bit counters, R <= 2048),
+                                where the output stage reduces and scans the counts */
   uint32_t out_chunk;        /* output positions per chunk */
   uint32_t out_chunks;
   uint32_t fill_workgroups;

@@ -181,6 +181,21 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
     p->scan_grid = p->m * p->scan_parts;
   }
 
+  // Single-tile fast path: one tile, one pass of 32-bit counters and at most
+  // kFastMaxRange bins.  The histogram adds into accumulation rows of the
+  // fast-path area and the output stage sums and scans them itself.  Rows
+  // spread the atomics of the histogram workgroups over more addresses; every
+  // output workgroup reads rows * stride <= kFastRegionWords words.
+  p->fast = p->m == 1 && p->bits == 32 && p->passes == 1 && R <= kFastMaxRange &&
+            env_int("RTCDF_DEV_FAST", 1) != 0;
+  if (p->fast) {
+    p->fast_stride = Rr;
+    const int64_t force_rows = env_int("RTCDF_DEV_FAST_ROWS", 0);
+    const uint32_t max_rows = std::max<uint32_t>(1u, kFastRegionWords / Rr);
+    p->fast_rows = force_rows > 0 ? (uint32_t)std::min<int64_t>(force_rows, max_rows)
+                                  : std::min<uint32_t>(16u, max_rows);
+  }
+
   // Workspace layout.
   size_t off = 0;
   p->off_partial = off;
@@ -200,6 +215,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // Carry entries cover every bin of every pass (plus the partner of the last
   // bin), so even keys outside the declared range stay in bounds.
   p->carry_words = p->bits < 32 ? (size_t)p->passes * p->W + 4 : 0;
+  if (p->fast) p->carry_words = kFastAreaWords;   // the fast-path area
   p->off_carry = off;                       // used by the caller-workspace form only
   off = align256(off + p->carry_words * 4);
   p->ws_bytes = off;
@@ -216,6 +232,11 @@ struct Workspace {
   size_t ws_bytes = 0;
   uint32_t* carry = nullptr;
   size_t carry_words = 0;
+  // The single-tile fast path's accumulation area (zeroed when allocated; the
+  // kernels keep its state consistent from sort to sort).  Set dirty when a
+  // sort could not enqueue all its stages, which re-zeroes it before the next.
+  uint32_t* fast = nullptr;
+  bool fast_dirty = false;
 };
 
 static std::mutex g_ws_mu;
@@ -237,7 +258,17 @@ static rtcdf_status_t grow(Workspace& w, const Plan& p) {
     }
     w.ws_bytes = bytes;
   }
-  if (w.carry_words < p.carry_words) {
+  if (p.fast && w.fast == nullptr) {
+    hipError_t e = hipMalloc(&w.fast, (size_t)kFastAreaWords * 4);
+    if (e != hipSuccess) {
+      w.fast = nullptr;
+      (void)hipGetLastError();
+      return RTCDF_ERROR_OUT_OF_MEMORY;
+    }
+    e = hipMemset(w.fast, 0, (size_t)kFastAreaWords * 4);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (!p.fast && w.carry_words < p.carry_words) {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e);
     if (w.carry) (void)hipFree(w.carry);
@@ -281,7 +312,8 @@ static hipEvent_t prof_event() {
   return e;
 }
 
-// Enqueue the four stages.  `carry` points at a zeroed array of p.carry_words.
+// Enqueue the four stages (two on the fast path).  `carry` points at a zeroed
+// array of p.carry_words, or at the fast-path area on the fast path.
 static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, uint8_t* ws,
                               uint32_t* carry, hipStream_t s, uint32_t* dbg_hist = nullptr,
                               uint32_t* dbg_cdf = nullptr, uint32_t* dbg_O = nullptr) {
@@ -302,6 +334,18 @@ static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, ui
   hipError_t e = launch_hist(q, in, ws, carry, s);
   if (e != hipSuccess) return hip_fail(e);
   mark(1);
+  if (q.fast) {   // the output stage does the reduction and the scan
+    mark(2);
+    mark(3);
+    e = launch_fill_fast(q, out, carry, s);
+    if (e != hipSuccess) return hip_fail(e);
+    mark(4);
+    if (prof) {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_prof_pending.push_back(marks);
+    }
+    return RTCDF_SUCCESS;
+  }
   e = launch_reduce(q, ws, carry, s);
   if (e != hipSuccess) return hip_fail(e);
   mark(2);
@@ -354,11 +398,22 @@ static rtcdf_status_t sort_cached(const int32_t* in, int32_t* out, size_t n, int
   if (st != RTCDF_SUCCESS) return st;
   Plan p;
   make_plan(n, minVal, maxVal, c, in, out ? out : in, dev, &p);
+  // The intermediates are only materialised by the staged path.
+  if (out == nullptr) p.fast = false;
   std::lock_guard<std::mutex> lk(g_ws_mu);
   Workspace& w = g_ws[std::make_pair(dev.device, s)];
   st = grow(w, p);
   if (st != RTCDF_SUCCESS) return st;
-  return enqueue(p, in, out, static_cast<uint8_t*>(w.ws), w.carry, s, dbg_hist, dbg_cdf, dbg_O);
+  if (!p.fast)
+    return enqueue(p, in, out, static_cast<uint8_t*>(w.ws), w.carry, s, dbg_hist, dbg_cdf, dbg_O);
+  if (w.fast_dirty) {
+    hipError_t e = launch_clear(w.fast, kFastAreaWords, s);
+    if (e != hipSuccess) return hip_fail(e);
+    w.fast_dirty = false;
+  }
+  st = enqueue(p, in, out, static_cast<uint8_t*>(w.ws), w.fast, s);
+  if (st != RTCDF_SUCCESS) w.fast_dirty = true;
+  return st;
 }
 
 }  // namespace rtcdf
@@ -573,7 +628,7 @@ rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const r
   out->hist_workgroups = p.passes * p.G;
   out->hist_threads = p.hist_block;
   out->items_per_thread = p.items;
-  out->scan_workgroups = p.scan_grid;
+  out->scan_workgroups = p.fast ? 0 : p.scan_grid;
   out->out_chunk = p.chunk;
   out->out_chunks = p.nchunks;
   out->fill_workgroups = p.fill_grid;
@@ -599,6 +654,7 @@ rtcdf_status_t rtcdf_release_workspaces(void) {
   for (auto& kv : g_ws) {
     if (kv.second.ws) (void)hipFree(kv.second.ws);
     if (kv.second.carry) (void)hipFree(kv.second.carry);
+    if (kv.second.fast) (void)hipFree(kv.second.fast);
   }
   g_ws.clear();
   return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);

@@ -10,6 +10,7 @@ namespace rtcdf {
 namespace dev {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- wave helpers
 

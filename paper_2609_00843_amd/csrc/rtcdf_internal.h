@@ -17,6 +17,20 @@ constexpr uint32_t kFillBlock = 256;        // threads per output workgroup
 constexpr uint32_t kScanBlock = 1024;       // threads per local-CDF workgroup
 constexpr uint32_t kReduceBlock = 1024;     // threads per reduction workgroup
 
+// Single-tile fast path (one tile, one pass of 32-bit counters, R <= 2048).
+// Its accumulation area holds two regions of kFastRegionWords and two parity
+// words.  Between sorts, region par[...] and region 1 - par are zero.  The
+// histogram adds into region `par`, its workgroup 0 zeroes the other region
+// and stores cur = par; the output stage reads region `cur` and its
+// workgroup 0 stores par = cur ^ 1.  No word is written while the other
+// kernel's workgroups read it, and all state is on the device, so a captured
+// graph replays correctly.
+constexpr uint32_t kFastMaxRange = 2048;
+constexpr uint32_t kFastRegionWords = 4096;
+constexpr uint32_t kFastPar = 2 * kFastRegionWords;        // word read by the histogram
+constexpr uint32_t kFastCur = 2 * kFastRegionWords + 32;   // word read by the output stage
+constexpr uint32_t kFastAreaWords = 2 * kFastRegionWords + 64;
+
 // Learned picker: sketch and MLP sizes (see include/rtcdf.h).
 constexpr int kSketchBins = 32;
 constexpr uint32_t kSketchSamples = 4096;
@@ -55,12 +69,17 @@ struct Plan {
   uint32_t chunk;        // output positions per chunk (multiple of 4 * kFillBlock)
   uint32_t nchunks;
   uint32_t fill_grid;
+  // Single-tile fast path: the histogram accumulates into fast_rows rows of
+  // fast_stride words of the fast-path area and the output stage scans them
+  // itself; no reduction or local-CDF launch.
+  bool fast;
+  uint32_t fast_rows, fast_stride;
   uint32_t scan_parts;   // workgroups per tile in the local-CDF stage (fixed split)
   uint32_t scan_grid;    // workgroups of the local-CDF stage; > m: split by chunk counts
   // workspace layout
   size_t off_partial, off_hist, off_cdf, off_rsum, off_O, off_split, off_flags, ws_bytes;
   size_t off_carry;      // carry array inside a caller-owned workspace (rtcdf_sort_ws)
-  size_t carry_words;    // 0 for 32-bit counters
+  size_t carry_words;    // 0 for 32-bit counters; the fast-path area on the fast path
 };
 
 struct DeviceInfo {
@@ -78,6 +97,9 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
 hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_t stream);
 hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t stream);
 hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream_t stream);
+// Single-tile fast path: output stage from the counts the histogram left in the
+// fast-path area `area` (kFastAreaWords, whose state the launch advances).
+hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStream_t stream);
 
 // Batched sort (rtcdf_batched.hip).
 size_t batched_scratch_words(uint32_t max_range);

@@ -40,6 +40,10 @@ struct HistArgs {
   uint32_t interleave;
   uint32_t* partial;
   uint32_t* carry;
+  // Single-tile fast path (merge != 0): add the counts into row
+  // blockIdx % merge (rows of merge_stride words) of the current region of the
+  // fast-path area in `carry` instead of writing a partial row.
+  uint32_t merge, merge_stride;
 };
 
 template <int ITEMS, int BITS, int BLOCK>
@@ -124,6 +128,21 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   __syncthreads();
   if constexpr (BITS < 32) wrap_flush(tab, a.carry, pass_lo, threadIdx.x);
 
+  if (BITS == 32 && a.merge) {
+    // Few bins (the fast path): the workgroup adds its counts to one of
+    // several rows of the current region, zero on entry, instead of writing a
+    // partial row; the rows spread the atomics over more addresses.
+    const uint32_t par = a.carry[kFastPar] & 1u;
+    uint32_t* acc = a.carry + par * kFastRegionWords + (blockIdx.x % a.merge) * a.merge_stride;
+    for (uint32_t i = threadIdx.x; i < a.R; i += BLOCK)
+      if (S[i] != 0u) atomicAdd(&acc[i], S[i]);
+    if (blockIdx.x == 0) {   // the previous sort's region: zero for the next sort
+      uint32_t* other = a.carry + (par ^ 1u) * kFastRegionWords;
+      for (uint32_t i = threadIdx.x; i < kFastRegionWords; i += BLOCK) other[i] = 0u;
+      if (threadIdx.x == 0) a.carry[kFastCur] = par;
+    }
+    return;
+  }
   uint32_t* row = a.partial + ((size_t)pass * a.G + chunk) * a.row_words;
   for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) row[i] = S[i];
 }
@@ -604,6 +623,114 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
   else fill_loop<2>(a, win, stage);
 }
 
+// Output stage of the single-tile fast path (R <= kFastMaxRange, one LDS pass
+// of 32-bit counters).  The histogram left the counts in `rows` rows of
+// `stride` words of region `cur` of the fast-path area; every workgroup sums
+// the rows and scans the sums into its own LDS (the cumulative counts of the
+// whole range, so any chunk's window is a slice of them) and finds the values
+// at its chunks' boundaries itself, so no reduction or local-CDF launch is
+// needed.
+constexpr uint32_t kFastSplit = kFillBlock;   // chunk boundaries found per batch
+
+// Numbers of entries <= q0 and <= q1 in the nondecreasing C[0, len): two
+// branch-free binary liftings advanced together (independent LDS reads).
+__device__ __forceinline__ void count_le2(const uint32_t* C, uint32_t len, uint32_t q0, uint32_t q1,
+                                          uint32_t* r0, uint32_t* r1) {
+  uint32_t a = 0, b = 0;
+  for (uint32_t step = len ? 1u << (31 - __builtin_clz(len)) : 0u; step; step >>= 1) {
+    const uint32_t xa = a + step <= len ? C[a + step - 1] : ~0u;
+    const uint32_t xb = b + step <= len ? C[b + step - 1] : ~0u;
+    if (xa <= q0) a += step;
+    if (xb <= q1) b += step;
+  }
+  *r0 = a;
+  *r1 = b;
+}
+
+template <bool SPARSE>
+__global__ __launch_bounds__(kFillBlock) void k_fill_small(FillArgs a, uint32_t* area, uint32_t rows,
+                                                           uint32_t stride) {
+  __shared__ __align__(16) uint32_t C[kFastMaxRange];
+  __shared__ __align__(16) uint32_t rowbuf[kFastRegionWords];
+  __shared__ uint32_t v_lo[kFastSplit], v_hi[kFastSplit];
+  __shared__ uint32_t wsum[kFillBlock / 64];
+  __shared__ __align__(16) uint32_t stage[kFillBlock / 64 * 256];
+  const uint32_t tid = threadIdx.x, R = a.R;
+  const uint32_t cur = area[kFastCur] & 1u;
+  if (blockIdx.x == 0 && tid == 0) area[kFastPar] = cur ^ 1u;   // the next sort's region
+  const uint32_t* acc = area + cur * kFastRegionWords;
+  const uint32_t words = rows * stride;
+  // all rows at once: every (clamped) load is issued before the first use
+  constexpr uint32_t kLoads = kFastRegionWords / kFillBlock;
+  uint32_t ld[kLoads];
+#pragma unroll
+  for (uint32_t j = 0; j < kLoads; ++j) ld[j] = acc[min(tid + j * kFillBlock, words - 1)];
+#pragma unroll
+  for (uint32_t j = 0; j < kLoads; ++j)
+    if (tid + j * kFillBlock < words) rowbuf[tid + j * kFillBlock] = ld[j];
+  __syncthreads();
+  // Column sums and their inclusive scan in one pass: thread t owns the eight
+  // columns [8t, 8t + 8) (stride, a multiple of 128, is at most 2048; columns
+  // in [R, stride) are zero).
+  static_assert(8 * kFillBlock == kFastMaxRange, "eight columns per thread");
+  const uint32_t c0 = 8 * tid;
+  uint32_t x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (c0 < stride) {
+#pragma unroll 4
+    for (uint32_t r = 0; r < rows; ++r) {
+      const v4u lo = *reinterpret_cast<const v4u*>(rowbuf + r * stride + c0);
+      const v4u hi = *reinterpret_cast<const v4u*>(rowbuf + r * stride + c0 + 4);
+      x[0] += lo.x; x[1] += lo.y; x[2] += lo.z; x[3] += lo.w;
+      x[4] += hi.x; x[5] += hi.y; x[6] += hi.z; x[7] += hi.w;
+    }
+#pragma unroll
+    for (int q = 1; q < 8; ++q) x[q] += x[q - 1];
+  }
+  uint32_t total;
+  const uint32_t before = block_inclusive_scan(x[7], wsum, &total) - x[7];
+  if (c0 < stride) {
+    const v4u lo = {x[0], x[1], x[2], x[3]}, hi = {x[4], x[5], x[6], x[7]};
+    *reinterpret_cast<v4u*>(C + c0) = lo + before;
+    *reinterpret_cast<v4u*>(C + c0 + 4) = hi + before;
+  }
+  __syncthreads();
+  const uint32_t last = R - 1, G = gridDim.x;
+  for (uint32_t k0 = blockIdx.x; k0 < a.nchunks; k0 += kFastSplit * G) {
+    // values at the first and last position of up to kFastSplit of this
+    // workgroup's chunks, one bisection each
+    const uint32_t kt = k0 + tid * G;
+    if (kt < a.nchunks) {
+      const uint64_t p0 = chunk_start(a, kt);
+      const uint64_t p1 = kt + 1 < a.nchunks ? chunk_start(a, kt + 1) : a.n;
+      uint32_t lo, hi;
+      count_le2(C, R, (uint32_t)p0, (uint32_t)(p1 - 1), &lo, &hi);
+      v_lo[tid] = min(lo, last);
+      v_hi[tid] = min(hi, last);
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < kFastSplit && k0 + j * G < a.nchunks; ++j) {
+      const uint32_t k = k0 + j * G;
+      const uint64_t p0 = chunk_start(a, k);
+      const uint64_t p1 = k + 1 < a.nchunks ? chunk_start(a, k + 1) : a.n;
+      // uniform: the walk of fill_chunk is then steered by scalar registers
+      const uint32_t v0 = __builtin_amdgcn_readfirstlane(v_lo[j]);
+      const uint32_t nwin = __builtin_amdgcn_readfirstlane(v_hi[j]) - v0 + 1;
+      if (SPARSE || (uint64_t)nwin * 64 > p1 - p0)   // as the per-chunk mode of fill_loop
+        fill_chunk<true>(a, C + v0, nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
+      else
+        fill_chunk<false>(a, C + v0, nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
+      // Every wave waits for its stores, then the workgroup meets, once per
+      // chunk.  A loop of bare stores lets the oldest workgroups on a compute
+      // unit take the store path (the youngest ended ~30 us after the oldest
+      // at n = 10^8); this keeps the four in step, as the window loads of
+      // k_fill do.
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+}
+
 // Plain 16-byte vector copy (grid-stride), the attainable-bandwidth reference
 // for the measurement of the sort kernels and the calibration of HBM counters.
 __global__ __launch_bounds__(256) void k_stream_copy(const v4i* __restrict__ src,
@@ -683,6 +810,8 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
   a.partial = reinterpret_cast<uint32_t*>(ws + p.off_partial);
   a.carry = carry;
   a.interleave = p.hist_interleave;
+  a.merge = p.fast ? p.fast_rows : 0u;
+  a.merge_stride = p.fast_stride;
   switch (p.bits) {
     case 8: return launch_hist_block<8>(p, a, s);
     case 16: return launch_hist_block<16>(p, a, s);
@@ -754,6 +883,30 @@ hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream
     hipLaunchKernelGGL(k_fill<true>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a);
   else
     hipLaunchKernelGGL(k_fill<false>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStream_t s) {
+  if (p.R > kFastMaxRange || p.m != 1 || p.fast_rows == 0 || p.fast_stride < p.R ||
+      (uint64_t)p.fast_rows * p.fast_stride > kFastRegionWords)
+    return hipErrorInvalidValue;
+  FillArgs a = {};
+  a.out = out;
+  a.n = p.n;
+  a.min_u = p.min_u;
+  a.R = p.R;
+  a.T = p.T;
+  a.out_head = p.out_head;
+  a.chunk = p.chunk;
+  a.nchunks = p.nchunks;
+  a.body_lo = p.out_head < p.n ? p.out_head : p.n;
+  a.body_hi = a.body_lo + 4 * ((p.n - a.body_lo) / 4);
+  if (p.n < (uint64_t)64 * p.R)
+    hipLaunchKernelGGL(k_fill_small<true>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a, area,
+                       p.fast_rows, p.fast_stride);
+  else
+    hipLaunchKernelGGL(k_fill_small<false>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a, area,
+                       p.fast_rows, p.fast_stride);
   return hipGetLastError();
 }
 

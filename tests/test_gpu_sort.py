@@ -273,3 +273,86 @@ def test_empty_and_errors(r):
     with pytest.raises(r.RtcdfError) as e:
         r.sort(x, 0, 10, config=r.make_config(32768, 16, 2))
     assert e.value.status == r.INVALID_VALUE
+
+
+def test_fast_path_plan(r):
+    """One tile, one pass of 32-bit counters and R <= 2048 take the fast path
+    (histogram and output stage only: no local-CDF workgroups); other plans
+    keep every stage."""
+    for R in (1, 128, 1000, 2048, 2049, 5000, 1 << 16):
+        info = r.plan_info(10_000_000, 0, R)
+        _say(f"plan R={R} {info}")
+        fast = info["tiles"] == 1 and info["counter_bits"] == 32 and info["passes"] == 1 and R <= 2048
+        assert (info["scan_workgroups"] == 0) == fast
+        if R <= 128:
+            assert fast
+
+
+def test_fast_path_sequence(r):
+    """Fast, staged and narrow-counter sorts interleaved on one stream: the
+    fast path's accumulation area must be left consistent by every sort."""
+    rng = np.random.default_rng(31)
+    s = torch.cuda.Stream()
+    cases = [
+        (1_000_000, 128, "uniform", None),
+        (300_000, 2048, "normal", None),
+        (500_000, 70_000, "uniform", None),        # 8-bit counters, staged
+        (1000, 1, "uniform", None),
+        (10, 2000, "uniform", None),               # fewer keys than values
+        (2_000_001, 300, "zipf", None),
+        (400_000, 2048, "uniform", r.make_config(1024, 16, 1)),   # two tiles: staged
+        (1_000_000, 128, "all_equal", None),
+        (77_777, 1500, "normal", None),
+    ]
+    for rep in range(2):
+        for i, (n, R, dist, cfg) in enumerate(cases):
+            lo = int(rng.integers(-5000, 5000))
+            A = inputs.make(dist, n, lo, lo + R, 1000 * rep + i)
+            want = oracle.sort(A, lo, lo + R)
+            _, tin = _to_dev(A, i % 4)
+            _say(f"sequence rep={rep} n={n} R={R} {dist} cfg={cfg}")
+            with torch.cuda.stream(s):
+                out = r.sort(tin, lo, lo + R, config=cfg, stream=s)
+            s.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_fast_path_graph_replay(r):
+    """Captured fast-path sorts (library workspace and caller workspace)
+    replay correctly with new inputs between replays: the fast path keeps its
+    state on the device."""
+    n, R = 300_001, 1000
+    s = torch.cuda.Stream()
+    tin = torch.empty(n, dtype=torch.int32, device="cuda")
+    out1 = torch.empty_like(tin)
+    out2 = torch.empty_like(tin)
+    ws = torch.empty(r.workspace_bytes(n, 0, R, keys_out=out2), dtype=torch.uint8, device="cuda")
+    ws.fill_(0xCD)
+    tin.copy_(torch.from_numpy(inputs.uniform(n, 0, R, 5)))
+    _say("fast path graph: warm-up")
+    with torch.cuda.stream(s):
+        r.sort(tin, 0, R, keys_out=out1, stream=s)    # allocates the library workspace
+        r.sort_ws(tin, out2, 0, R, ws, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        r.sort(tin, 0, R, keys_out=out1, stream=s)
+        r.sort_ws(tin, out2, 0, R, ws, stream=s)
+    for rep in range(4):
+        dist = ("uniform", "normal", "zipf", "all_equal")[rep]
+        A = inputs.make(dist, n, 0, R, 50 + rep)
+        want = oracle.sort(A, 0, R)
+        tin.copy_(torch.from_numpy(A))
+        out1.fill_(-1)
+        out2.fill_(-1)
+        torch.cuda.synchronize()
+        _say(f"fast path graph: replay {rep} {dist}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out1.cpu().numpy(), want)
+        assert np.array_equal(out2.cpu().numpy(), want)
+        # an eager sort on the same stream between replays
+        with torch.cuda.stream(s):
+            r.sort(tin, 0, R, keys_out=out1, stream=s)
+        s.synchronize()
+        assert np.array_equal(out1.cpu().numpy(), want)
