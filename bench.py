@@ -359,9 +359,14 @@ def main():
         st = rtcdf.profile_collect()
         rtcdf.profile_enable(False)
         nsorts += st["sorts"]
-        fill_name = f"k_fill<{'true' if N < 64 * R else 'false'}>"   # sparse form below 64 keys per value
-        for stg, name in (("hist", hist_name), ("reduce", "k_reduce"), ("tilescan", "k_tilescan"),
-                          ("fill", fill_name)):
+        sparse = "true" if N < 64 * R else "false"   # sparse form below 64 keys per value
+        if info["scan_workgroups"] == 0:
+            # single-tile fast path: two launches, the output stage reduces and scans
+            stages = (("hist", hist_name), ("fill", f"k_fill_small<{sparse}>"))
+        else:
+            stages = (("hist", hist_name), ("reduce", "k_reduce"), ("tilescan", "k_tilescan"),
+                      ("fill", f"k_fill<{sparse}>"))
+        for stg, name in stages:
             stage_tot[stg] += st[stg]
             kern_ms[name] = kern_ms.get(name, 0.0) + st[stg]
             kern_n[name] = kern_n.get(name, 0) + st["sorts"]
