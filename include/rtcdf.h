@@ -60,7 +60,8 @@ typedef enum rtcdf_status {
   RTCDF_ERROR_HIP = 6,              /* a HIP call failed; see rtcdf_last_hip_error() */
   RTCDF_ERROR_WORKSPACE_TOO_SMALL = 7,
   RTCDF_ERROR_NOT_SUPPORTED = 8,    /* device is not gfx950, or feature unavailable */
-  RTCDF_ERROR_NO_MODEL = 9          /* learned mode requested but no model is loaded */
+  RTCDF_ERROR_NO_MODEL = 9,         /* learned mode requested but no model is loaded */
+  RTCDF_ERROR_KEY_OUT_OF_RANGE = 10 /* checked mode only: some key lies outside [minVal, maxVal) */
 } rtcdf_status_t;
 
 /* Largest supported range.  The workspace grows with R (about 4R + 4m bytes
@@ -103,6 +104,26 @@ rtcdf_status_t rtcdf_sort(const int32_t* keys_in, int32_t* keys_out, size_t n,
 rtcdf_status_t rtcdf_sort_with_config(const int32_t* keys_in, int32_t* keys_out, size_t n,
                                       int64_t minVal, int64_t maxVal,
                                       const rtcdf_config_t* cfg, hipStream_t stream);
+
+/* Checked mode.  The keys lying in [minVal, maxVal) is a precondition of the
+ * method (Sec. 2.1) that the sort itself does not test.  These two calls test
+ * it, at the price of one more read of the keys (4 B per key):
+ *
+ * rtcdf_count_out_of_range: writes to *d_count (a device uint64, 8-byte
+ * aligned) the number of keys[i], i < n, outside [minVal, maxVal).
+ * Asynchronous on `stream`; argument errors as for rtcdf_sort (keys_out is
+ * not involved).
+ *
+ * rtcdf_sort_checked: as rtcdf_sort_with_config (cfg NULL = library choice),
+ * but first counts the out-of-range keys and waits for the count (a host
+ * synchronisation with `stream`).  If any key is out of range it returns
+ * RTCDF_ERROR_KEY_OUT_OF_RANGE and enqueues nothing more (keys_out is left
+ * unchanged); otherwise it enqueues the sort and returns without waiting. */
+rtcdf_status_t rtcdf_count_out_of_range(const int32_t* keys, size_t n, int64_t minVal, int64_t maxVal,
+                                        uint64_t* d_count, hipStream_t stream);
+rtcdf_status_t rtcdf_sort_checked(const int32_t* keys_in, int32_t* keys_out, size_t n,
+                                  int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,
+                                  hipStream_t stream);
 
 /* Bytes of device workspace rtcdf_sort_ws needs for this problem and
  * configuration (cfg NULL = library choice), written to *bytes.  The

@@ -237,6 +237,7 @@ struct Workspace {
   // sort could not enqueue all its stages, which re-zeroes it before the next.
   uint32_t* fast = nullptr;
   bool fast_dirty = false;
+  uint64_t* check = nullptr;   // checked mode: the out-of-range count
 };
 
 static std::mutex g_ws_mu;
@@ -436,6 +437,49 @@ rtcdf_status_t rtcdf_sort_with_config(const int32_t* keys_in, int32_t* keys_out,
   return sort_cached(keys_in, keys_out, n, minVal, maxVal, cfg, stream, nullptr, nullptr, nullptr);
 }
 
+rtcdf_status_t rtcdf_count_out_of_range(const int32_t* keys, size_t n, int64_t minVal, int64_t maxVal,
+                                        uint64_t* d_count, hipStream_t stream) {
+  if (d_count == nullptr || (reinterpret_cast<uintptr_t>(d_count) & 7u)) return RTCDF_ERROR_INVALID_VALUE;
+  rtcdf_status_t st = check_problem(keys, keys, n, minVal, maxVal);
+  if (st != RTCDF_SUCCESS) return st;
+  DeviceInfo dev;
+  st = device_info(&dev);
+  if (st != RTCDF_SUCCESS) return st;
+  const hipError_t e = launch_count_out_of_range(keys, n, (uint32_t)(int32_t)minVal,
+                                                 (uint32_t)(maxVal - minVal), d_count, dev.cus, stream);
+  return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
+}
+
+rtcdf_status_t rtcdf_sort_checked(const int32_t* keys_in, int32_t* keys_out, size_t n, int64_t minVal,
+                                  int64_t maxVal, const rtcdf_config_t* cfg, hipStream_t stream) {
+  rtcdf_status_t st = check_problem(keys_in, keys_out, n, minVal, maxVal);
+  if (st != RTCDF_SUCCESS || n == 0) return st;
+  if (!config_is_zero(cfg) && !config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
+  DeviceInfo dev;
+  st = device_info(&dev);
+  if (st != RTCDF_SUCCESS) return st;
+  uint64_t bad = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace& w = g_ws[std::make_pair(dev.device, stream)];
+    if (w.check == nullptr) {
+      hipError_t e = hipMalloc(&w.check, 256);
+      if (e != hipSuccess) {
+        w.check = nullptr;
+        (void)hipGetLastError();
+        return RTCDF_ERROR_OUT_OF_MEMORY;
+      }
+    }
+    hipError_t e = launch_count_out_of_range(keys_in, n, (uint32_t)(int32_t)minVal,
+                                             (uint32_t)(maxVal - minVal), w.check, dev.cus, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, w.check, sizeof(bad), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (bad != 0) return RTCDF_ERROR_KEY_OUT_OF_RANGE;
+  return sort_cached(keys_in, keys_out, n, minVal, maxVal, cfg, stream, nullptr, nullptr, nullptr);
+}
+
 rtcdf_status_t rtcdf_workspace_bytes(size_t n, int64_t minVal, int64_t maxVal,
                                      const rtcdf_config_t* cfg, const int32_t* keys_out,
                                      size_t* bytes) {
@@ -569,6 +613,7 @@ const char* rtcdf_status_string(rtcdf_status_t s) {
     case RTCDF_ERROR_WORKSPACE_TOO_SMALL: return "workspace too small";
     case RTCDF_ERROR_NOT_SUPPORTED: return "not supported on this device";
     case RTCDF_ERROR_NO_MODEL: return "no model loaded";
+    case RTCDF_ERROR_KEY_OUT_OF_RANGE: return "a key lies outside [minVal, maxVal)";
   }
   return "unknown status";
 }
@@ -655,6 +700,7 @@ rtcdf_status_t rtcdf_release_workspaces(void) {
     if (kv.second.ws) (void)hipFree(kv.second.ws);
     if (kv.second.carry) (void)hipFree(kv.second.carry);
     if (kv.second.fast) (void)hipFree(kv.second.fast);
+    if (kv.second.check) (void)hipFree(kv.second.check);
   }
   g_ws.clear();
   return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);

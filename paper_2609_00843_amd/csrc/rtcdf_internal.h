@@ -91,6 +91,10 @@ struct DeviceInfo {
 // Kernel launchers (rtcdf_kernels.hip).  All enqueue on `stream` and return the
 // hipError_t of the launch.
 hipError_t launch_clear(uint32_t* p, size_t words, hipStream_t stream);
+// Checked mode: *count (zeroed first) = number of keys[0, n) with
+// (uint32)key - min_u >= R.
+hipError_t launch_count_out_of_range(const int32_t* keys, uint64_t n, uint32_t min_u, uint32_t R,
+                                     uint64_t* count, int cus, hipStream_t stream);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int cus, hipStream_t stream);
 hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t* carry,
                        hipStream_t stream);

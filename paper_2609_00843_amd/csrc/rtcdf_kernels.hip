@@ -20,6 +20,11 @@
 //               counts O[t] + C_t[x] of the values that cover the chunk into LDS
 //               and writes every position p the value b_t + min{x : C_t[x] >= p'+1}
 //               (Alg. 7 with p' = p - O[t]) as 16-byte stores.
+//   k_fill_small  single-tile fast path (one tile, one LDS pass of 32-bit
+//               counters, R <= 2048): the histogram workgroups add their counts
+//               into accumulation rows with global atomics, and every output
+//               workgroup sums and scans those counts in its own LDS and finds
+//               its chunks' boundaries itself (no k_reduce / k_tilescan launch).
 #include <hip/hip_runtime.h>
 
 #include "rtcdf_device.h"

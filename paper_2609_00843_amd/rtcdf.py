@@ -38,9 +38,11 @@ STATUS = {
     7: "RTCDF_ERROR_WORKSPACE_TOO_SMALL",
     8: "RTCDF_ERROR_NOT_SUPPORTED",
     9: "RTCDF_ERROR_NO_MODEL",
+    10: "RTCDF_ERROR_KEY_OUT_OF_RANGE",
 }
 SUCCESS, INVALID_VALUE, SIZE_TOO_LARGE, RANGE_TOO_LARGE, OVERLAP = 0, 1, 2, 3, 4
 OUT_OF_MEMORY, HIP_ERROR, WORKSPACE_TOO_SMALL, NOT_SUPPORTED, NO_MODEL = 5, 6, 7, 8, 9
+KEY_OUT_OF_RANGE = 10
 MAX_RANGE = 1 << 28
 BATCH_MAX_RANGE = 1 << 16
 CONFIG_DEFAULT, CONFIG_TUNED, CONFIG_LEARNED = 0, 1, 2
@@ -109,6 +111,8 @@ _SIGS = {
     "rtcdf_profile_enable": [ctypes.c_int],
     "rtcdf_profile_collect": [ctypes.POINTER(StageStats)],
     "rtcdf_stream_copy": [_vp, _vp, _sz, _vp],
+    "rtcdf_count_out_of_range": [_vp, _sz, _i64, _i64, _vp, _vp],
+    "rtcdf_sort_checked": [_vp, _vp, _sz, _i64, _i64, _cfgp, _vp],
 }
 for _name, _args in _SIGS.items():
     if hasattr(lib, _name):
@@ -163,6 +167,37 @@ def sort(keys_in, minVal: int, maxVal: int, keys_out=None, config: Config | None
         st = lib.rtcdf_sort_with_config(_ptr(keys_in), _ptr(keys_out), keys_in.numel(),
                                         int(minVal), int(maxVal), ctypes.byref(config), s)
     _check(st, "rtcdf_sort")
+    return keys_out
+
+
+def count_out_of_range(keys, minVal: int, maxVal: int, out=None, stream=None):
+    """Number of keys outside [minVal, maxVal), as a one-element int64 CUDA
+    tensor filled asynchronously on `stream` (checked mode)."""
+    import torch
+    _check_keys(keys, "keys")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=keys.device)
+    st = lib.rtcdf_count_out_of_range(_ptr(keys), keys.numel(), int(minVal), int(maxVal), _ptr(out),
+                                      _stream_ptr(stream))
+    _check(st, "rtcdf_count_out_of_range")
+    return out
+
+
+def sort_checked(keys_in, minVal: int, maxVal: int, keys_out=None, config: Config | None = None,
+                 stream=None):
+    """sort() that first verifies every key lies in [minVal, maxVal) (waits for
+    that count); raises RtcdfError with status KEY_OUT_OF_RANGE otherwise,
+    leaving keys_out unchanged."""
+    import torch
+    _check_keys(keys_in, "keys_in")
+    if keys_out is None:
+        keys_out = torch.empty_like(keys_in)
+    _check_keys(keys_out, "keys_out")
+    if keys_out.numel() != keys_in.numel():
+        raise ValueError("keys_out must have as many elements as keys_in")
+    st = lib.rtcdf_sort_checked(_ptr(keys_in), _ptr(keys_out), keys_in.numel(), int(minVal), int(maxVal),
+                                ctypes.byref(config) if config is not None else None, _stream_ptr(stream))
+    _check(st, "rtcdf_sort_checked")
     return keys_out
 
 

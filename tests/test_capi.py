@@ -57,6 +57,23 @@ def test_argument_errors_before_gpu(r):
     assert sort(P_IN, ctypes.c_void_p((1 << 20) - 8), 10, 0, 10, None) == r.OVERLAP
 
 
+def test_checked_mode_argument_errors(r):
+    L = r.lib
+    cnt = ctypes.c_void_p(1 << 24)                                        # never dereferenced
+    assert L.rtcdf_count_out_of_range(P_IN, 10, 0, 10, None, None) == r.INVALID_VALUE
+    assert L.rtcdf_count_out_of_range(P_IN, 10, 0, 10, ctypes.c_void_p((1 << 24) + 4), None) == r.INVALID_VALUE
+    assert L.rtcdf_count_out_of_range(P_IN, 10, 5, 5, cnt, None) == r.INVALID_VALUE
+    assert L.rtcdf_count_out_of_range(None, 10, 0, 10, cnt, None) == r.INVALID_VALUE
+    assert L.rtcdf_count_out_of_range(P_IN, 1 << 32, 0, 10, cnt, None) == r.SIZE_TOO_LARGE
+    sc = L.rtcdf_sort_checked
+    assert sc(P_IN, P_OUT, 0, 0, 10, None, None) == r.SUCCESS                # n = 0 is a no-op
+    assert sc(P_IN, P_OUT, 10, 0, (1 << 28) + 1, None, None) == r.RANGE_TOO_LARGE
+    assert sc(P_IN, ctypes.c_void_p((1 << 20) + 8), 10, 0, 10, None, None) == r.OVERLAP
+    bad = r.Config(100, 16, 1, 0)
+    assert sc(P_IN, P_OUT, 10, 0, 10, ctypes.byref(bad), None) == r.INVALID_VALUE
+    assert r.status_string(r.KEY_OUT_OF_RANGE) == "a key lies outside [minVal, maxVal)"
+
+
 @pytest.mark.parametrize("cfg", [(100, 16, 1), (0, 16, 1), (1024, 5, 1), (1024, 16, 3),
                                  (32768, 16, 2), (16384, 16, 4), (32896, 16, 1), (1024, 0, 1)])
 def test_invalid_configs(r, cfg):

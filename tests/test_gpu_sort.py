@@ -356,3 +356,45 @@ def test_fast_path_graph_replay(r):
             r.sort(tin, 0, R, keys_out=out1, stream=s)
         s.synchronize()
         assert np.array_equal(out1.cpu().numpy(), want)
+
+
+def test_checked_mode(r):
+    """Checked mode counts the keys outside [minVal, maxVal) (in the scalar head,
+    the vector body and the tail of unaligned arrays; on both sides of the
+    range; int32 extremes) and refuses to sort them, leaving the output
+    untouched, as the oracle refuses them; in-range keys sort as usual."""
+    rng = np.random.default_rng(77)
+    I32 = np.iinfo(np.int32)
+    lo, R = -50, 300
+    for n, pin in ((1, 0), (3, 1), (7, 2), (1000, 3), (1_000_003, 1)):
+        A = rng.integers(lo, lo + R, size=n).astype(np.int32)
+        _, tin = _to_dev(A, pin)
+        _say(f"checked n={n} pin={pin} in range")
+        c = r.count_out_of_range(tin, lo, lo + R)
+        torch.cuda.synchronize()
+        assert int(c.item()) == 0
+        out = r.sort_checked(tin, lo, lo + R)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), oracle.sort(A, lo, lo + R))
+        # keys planted at the first and last position and a few in between
+        B = A.copy()
+        idx = sorted(set([0, n - 1] + [int(i) for i in rng.integers(0, n, size=min(n, 5))]))
+        vals = [lo - 1, lo + R, I32.min, I32.max, lo - 1000]
+        for j, i in enumerate(idx):
+            B[i] = vals[j % len(vals)]
+        wide = B.astype(np.int64)
+        want_bad = int(np.count_nonzero((wide < lo) | (wide >= lo + R)))
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.sort(B, lo, lo + R)
+        assert e.value.code == oracle.ORC_KEY_OUT_OF_RANGE
+        _, tb = _to_dev(B, pin)
+        _say(f"checked n={n} pin={pin} out of range: {want_bad}")
+        c = r.count_out_of_range(tb, lo, lo + R)
+        torch.cuda.synchronize()
+        assert int(c.item()) == want_bad
+        out = torch.full_like(tb, 0x5A5A5A5A)
+        with pytest.raises(r.RtcdfError) as e:
+            r.sort_checked(tb, lo, lo + R, keys_out=out)
+        assert e.value.status == r.KEY_OUT_OF_RANGE
+        torch.cuda.synchronize()
+        assert np.all(out.cpu().numpy() == 0x5A5A5A5A)
