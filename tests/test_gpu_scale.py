@@ -1,7 +1,8 @@
-"""Full-size parity at n = 10^9 keys (4 GB in, 4 GB out), minVal 0, R = 2^18:
-uniform, all-equal and normal with sd R/64.  The output is checked element by
-element against the oracle's counts with the streaming verifier (no second
-4 GB host copy), in the launch configuration the library picks by default."""
+"""Full-size parity: n = 10^9 keys (4 GB in, 4 GB out), minVal 0, R = 2^18
+(uniform, all-equal and normal with sd R/64), and the fifteen n = 10^8 arrays
+of the range sweep.  Every output is checked element by element against the
+oracle's counts with the streaming verifier (no second full-size host copy),
+in the launch configuration the library picks by default."""
 import sys
 
 import numpy as np
@@ -43,3 +44,29 @@ def test_billion_keys(r, dist, sd_div):
     for lo in range(0, N, CHUNK):
         v.chunk(b[lo:lo + CHUNK].cpu().numpy())
     v.end(N)
+
+
+SWEEP_N = 100_000_000
+SWEEP_MIN = -1000
+
+
+@pytest.mark.parametrize("i,logR,dist", [(i, lr, d) for i, (lr, d) in enumerate(
+    (lr, d) for lr in (7, 10, 13, 16, 18) for d in ("uniform", "normal", "all_equal"))])
+def test_range_sweep_full_size(r, i, logR, dist):
+    """The 15 arrays of the n = 10^8 range sweep, generated as the benchmark
+    generates them (same seeds) and sorted in the launch configuration it
+    times (library default); every output element is compared with the
+    oracle's counts."""
+    R = 1 << logR
+    print(f"[case] n=1e8 R=2^{logR} {dist} minVal={SWEEP_MIN}", flush=True)
+    sys.stdout.flush()
+    a = inputs.make_device(dist, SWEEP_N, SWEEP_MIN, SWEEP_MIN + R, inputs.case_seed(2, i))
+    b = torch.empty_like(a)
+    r.sort(a, SWEEP_MIN, SWEEP_MIN + R, keys_out=b)
+    torch.cuda.synchronize()
+    cnt = oracle.counts(a.cpu().numpy(), SWEEP_MIN, SWEEP_MIN + R)
+    del a
+    v = oracle.StreamingVerifier(cnt, SWEEP_MIN)
+    for lo in range(0, SWEEP_N, CHUNK):
+        v.chunk(b[lo:lo + CHUNK].cpu().numpy())
+    v.end(SWEEP_N)
