@@ -344,6 +344,18 @@ def main():
     if args.profile_only:
         print(json.dumps({"ms_per_step": ms_step, "value": value, "copy_ms": copy_ms}))
         return
+    # Attainable write-only bandwidth (the output stage's traffic): torch's
+    # vectorised fill of one output array, timed the same way.
+    wr0, wr1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        outs[0].fill_(7)
+    wr0.record(stream)
+    for _ in range(args.steps):
+        outs[0].fill_(7)
+    wr1.record(stream)
+    torch.cuda.synchronize()
+    write_gbs = 4.0 * N / (wr0.elapsed_time(wr1) / args.steps * 1e-3) / 1e9
+    log(f"[bench] write-only fill of {4 * N} bytes: {write_gbs:.0f} GB/s")
 
     # Per-case times (same launches, one case at a time).
     per_case = []
@@ -494,6 +506,7 @@ def main():
                    "parallelism": "single GPU"},
         "frac_8B_roofline_step": round(8.0 * keys_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "stream_copy_GBps": round(copy_gbs, 1),
+        "write_fill_GBps": round(write_gbs, 1),
         "min_frac_8B_roofline_R_le_2^16": round(min(c["frac_8B_roofline"] for c in tgt), 4) if tgt else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
