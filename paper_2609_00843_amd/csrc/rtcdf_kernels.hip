@@ -163,75 +163,64 @@ struct ReduceArgs {
   uint32_t R, W, G, row_words, carry_words, bits;
 };
 
-// Adds rows g0, g0 + NG, ... < G of the column src (stride rs words), split
-// into 32 / BITS counters per word, into acc[0 .. 32 / BITS).
+// One workgroup per 128-bin block of one pass: the block is 128 / (32 / bits)
+// words of every partial row of the pass.  Threads are 32 row groups x NQ word
+// quads (NQ = 32, 16, 8 for 32-, 16-, 8-bit counters: 1024, 512, 256 threads);
+// each thread adds the 16-byte quad of every 32nd row, four loads in flight,
+// and splits the words into their counters.  The row groups are summed in LDS;
+// every bin adds (and re-zeroes) its carry entry (narrow counters), and the
+// workgroup writes H and the block total.
+constexpr uint32_t kReduceGroups = 32;
+
 template <int BITS>
-__device__ __forceinline__ void sum_rows(const uint32_t* src, size_t rs, uint32_t g0, uint32_t G,
-                                         uint32_t NG, uint32_t* acc) {
-  uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-  auto add = [&](uint32_t w) {
-    if constexpr (BITS == 32) {
-      a0 += w;
-    } else if constexpr (BITS == 16) {
-      a0 += w & 0xffffu;
-      a1 += w >> 16;
-    } else {
-      a0 += w & 0xffu;
-      a1 += (w >> 8) & 0xffu;
-      a2 += (w >> 16) & 0xffu;
-      a3 += w >> 24;
+__device__ __forceinline__ void reduce_block(const ReduceArgs& a, uint32_t (*red)[kReduceBins + 1],
+                                             uint32_t* wsum) {
+  constexpr uint32_t per = 32 / BITS, NQ = kReduceBins / per / 4;
+  const uint32_t tid = threadIdx.x, q = tid % NQ, rg = tid / NQ;
+  const uint32_t r0 = blockIdx.x * kReduceBins;   // first bin (passes hold W bins, W % 128 == 0)
+  const uint32_t pass = r0 / a.W, w0 = (r0 - pass * a.W) / per;
+  const size_t rs4 = a.row_words / 4;
+  const v4u* src = reinterpret_cast<const v4u*>(a.partial + (size_t)pass * a.G * a.row_words + w0) + q;
+  uint32_t acc[4 * per];
+#pragma unroll
+  for (uint32_t k = 0; k < 4 * per; ++k) acc[k] = 0;
+  auto add = [&](const v4u w) {
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      if constexpr (BITS == 32) {
+        acc[j] += ws[j];
+      } else if constexpr (BITS == 16) {
+        acc[2 * j] += ws[j] & 0xffffu;
+        acc[2 * j + 1] += ws[j] >> 16;
+      } else {
+        acc[4 * j] += ws[j] & 0xffu;
+        acc[4 * j + 1] += (ws[j] >> 8) & 0xffu;
+        acc[4 * j + 2] += (ws[j] >> 16) & 0xffu;
+        acc[4 * j + 3] += ws[j] >> 24;
+      }
     }
   };
-  uint32_t g = g0;
+  uint32_t g = rg;
+  const uint32_t G = a.G, NG = kReduceGroups;
   for (; g + 3 * NG < G; g += 4 * NG) {
-    const uint32_t w0 = src[(size_t)g * rs], w1 = src[(size_t)(g + NG) * rs];
-    const uint32_t w2 = src[(size_t)(g + 2 * NG) * rs], w3 = src[(size_t)(g + 3 * NG) * rs];
-    add(w0);
-    add(w1);
-    add(w2);
-    add(w3);
+    const v4u x0 = src[(size_t)g * rs4], x1 = src[(size_t)(g + NG) * rs4];
+    const v4u x2 = src[(size_t)(g + 2 * NG) * rs4], x3 = src[(size_t)(g + 3 * NG) * rs4];
+    add(x0);
+    add(x1);
+    add(x2);
+    add(x3);
   }
-  for (; g < G; g += NG) add(src[(size_t)g * rs]);
-  acc[0] = a0;
-  acc[1] = a1;
-  acc[2] = a2;
-  acc[3] = a3;
-}
-
-// Sums, for the 128 bins of one block, the G partial rows of the block's pass
-// (counters of `bits` bits, 32 / bits per word), adds the carry array (narrow
-// counters) and re-zeroes it, and writes H and the block total.
-__global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
-  __shared__ uint32_t red[32][kReduceBins + 1];
-  __shared__ uint32_t wsum[kReduceBlock / 64];
-  const uint32_t r0 = blockIdx.x * kReduceBins;
-  const uint32_t pass = r0 / a.W, o = r0 - pass * a.W;
-  const uint32_t* rows = a.partial + (size_t)pass * a.G * a.row_words;
-  const uint32_t tid = threadIdx.x;
-  // A block's 128 bins are 128 / per words of each row; the 1024 threads are
-  // (row group, word) pairs and each sums every NG-th row, four loads in
-  // flight at a time.
-  const uint32_t per = 32 / a.bits, words = kReduceBins / per, NG = kReduceBlock / words;
-  const uint32_t c = tid % words, rg = tid / words;
-  const uint32_t* src = rows + o / per + c;
-  const size_t rs = a.row_words;
-  uint32_t acc[4] = {0, 0, 0, 0};
-  if (a.bits == 32) sum_rows<32>(src, rs, rg, a.G, NG, acc);
-  else if (a.bits == 16) sum_rows<16>(src, rs, rg, a.G, NG, acc);
-  else sum_rows<8>(src, rs, rg, a.G, NG, acc);
-  const uint32_t acc0 = acc[0], acc1 = acc[1], acc2 = acc[2], acc3 = acc[3];
-  red[rg][per * c] = acc0;
-  if (per > 1) red[rg][per * c + 1] = acc1;
-  if (per > 2) {
-    red[rg][per * c + 2] = acc2;
-    red[rg][per * c + 3] = acc3;
-  }
+  for (; g < G; g += NG) add(src[(size_t)g * rs4]);
+  // bin 4 * per * q + k of the block = counter k % per of word 4q + k / per
+#pragma unroll
+  for (uint32_t k = 0; k < 4 * per; ++k) red[rg][4 * per * q + k] = acc[k];
   __syncthreads();
   uint32_t tot = 0;
   if (tid < kReduceBins) {
-    for (uint32_t q = 0; q < NG; ++q) tot += red[q][tid];
+    for (uint32_t r = 0; r < kReduceGroups; ++r) tot += red[r][tid];
     const uint32_t bin = r0 + tid;
-    if (a.bits < 32 && bin < a.carry_words) {
+    if (BITS < 32 && bin < a.carry_words) {
       tot += a.carry[bin];
       a.carry[bin] = 0u;   // keep the carry array zero between sorts
     }
@@ -240,7 +229,15 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
   }
   const uint32_t sum = block_sum(tid < kReduceBins ? tot : 0u, wsum);
   if (tid == 0) a.rsum[blockIdx.x] = sum;
-  if (blockIdx.x == 0 && tid == 0) a.flags[0] = 0u;
+}
+
+__global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
+  __shared__ uint32_t red[kReduceGroups][kReduceBins + 1];
+  __shared__ uint32_t wsum[kReduceBlock / 64];
+  if (a.bits == 32) reduce_block<32>(a, red, wsum);
+  else if (a.bits == 16) reduce_block<16>(a, red, wsum);
+  else reduce_block<8>(a, red, wsum);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.flags[0] = 0u;
 }
 
 // ---------------------------------------------------------- local CDF + O[t]
@@ -837,7 +834,11 @@ hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_
   a.row_words = p.row_words;
   a.carry_words = (uint32_t)p.carry_words;
   a.bits = p.bits;
-  hipLaunchKernelGGL(k_reduce, dim3(p.nred), dim3(kReduceBlock), 0, s, a);
+  // 128-bin blocks never straddle passes (W % 128 == 0), and a block's words
+  // are whole 16-byte quads of 16-byte aligned rows
+  if (p.W % kReduceBins != 0 || p.row_words % 4 != 0) return hipErrorInvalidValue;
+  const uint32_t threads = kReduceGroups * (kReduceBins / (32 / p.bits) / 4);
+  hipLaunchKernelGGL(k_reduce, dim3(p.nred), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
