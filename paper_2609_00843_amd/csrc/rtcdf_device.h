@@ -244,16 +244,26 @@ __device__ __forceinline__ void fix_u8(uint32_t old, uint32_t x, uint32_t c, uin
 // test.  PAD selects the padded 32-bit layout (bin x at x + x / 32).  `tab`
 // and `hot` (the wrap table and the hot-bin register) are used by the 8- and
 // 16-bit forms; the 16-bit form may run without a table (tab == nullptr).
+// 1 << (s mod 32): the hardware shift reads only the low five bits of the
+// amount, so no mask is needed (the compiler emits one when it can prove the
+// amount's low bits are zero, as for x << 3).
+__device__ __forceinline__ uint32_t shl1(uint32_t s) {
+  uint32_t r;
+  asm("v_lshlrev_b32_e64 %0, %1, 1" : "=v"(r) : "v"(s));
+  return r;
+}
+
 template <int BITS, bool PAD = false>
 __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32_t W,
                                        uint32_t* carry, uint32_t pass_lo, uint32_t* tab, HotBin& hot) {
   const uint32_t x0 = (uint32_t)k.x - base, x1 = (uint32_t)k.y - base;
   const uint32_t x2 = (uint32_t)k.z - base, x3 = (uint32_t)k.w - base;
   const uint32_t lead = (uint32_t)__builtin_amdgcn_readfirstlane((int)x0);
-  const uint64_t same = __ballot(x0 == lead) & __ballot(x1 == lead) & __ballot(x2 == lead) &
-                        __ballot(x3 == lead);
   const uint64_t active = __ballot(1);
-  if (same == active) {
+  // the other three keys are compared only when every first key matches
+  bool all_same = __ballot(x0 == lead) == active;
+  if (all_same) all_same = (__ballot(x1 == lead) & __ballot(x2 == lead) & __ballot(x3 == lead)) == active;
+  if (all_same) {
     if (lead < W) {
       const uint32_t c = 4u * (uint32_t)__popcll(active);
       if constexpr (BITS < 32) {
@@ -280,15 +290,16 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
     constexpr uint32_t FULL = BITS == 16 ? 0xffffu : 0xffu;
     const uint32_t s0 = x0 << SH, s1 = x1 << SH, s2 = x2 << SH, s3 = x3 << SH;
     uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-    if (x0 < W) o0 = atomicAdd(&S[x0 >> LOG], 1u << (s0 & 31u));
-    if (x1 < W) o1 = atomicAdd(&S[x1 >> LOG], 1u << (s1 & 31u));
-    if (x2 < W) o2 = atomicAdd(&S[x2 >> LOG], 1u << (s2 & 31u));
-    if (x3 < W) o3 = atomicAdd(&S[x3 >> LOG], 1u << (s3 & 31u));
-    const bool w0 = __builtin_amdgcn_ubfe(o0, s0, BITS) == FULL && x0 < W;
-    const bool w1 = __builtin_amdgcn_ubfe(o1, s1, BITS) == FULL && x1 < W;
-    const bool w2 = __builtin_amdgcn_ubfe(o2, s2, BITS) == FULL && x2 < W;
-    const bool w3 = __builtin_amdgcn_ubfe(o3, s3, BITS) == FULL && x3 < W;
-    if (__ballot(w0 | w1 | w2 | w3)) {
+    if (x0 < W) o0 = atomicAdd(&S[x0 >> LOG], shl1(s0));
+    if (x1 < W) o1 = atomicAdd(&S[x1 >> LOG], shl1(s1));
+    if (x2 < W) o2 = atomicAdd(&S[x2 >> LOG], shl1(s2));
+    if (x3 < W) o3 = atomicAdd(&S[x3 >> LOG], shl1(s3));
+    // One test for the four: a counter wrapped iff its old field was FULL.
+    // Keys outside the pass kept o = 0, whose fields are 0.
+    const uint32_t f0 = __builtin_amdgcn_ubfe(o0, s0, BITS), f1 = __builtin_amdgcn_ubfe(o1, s1, BITS);
+    const uint32_t f2 = __builtin_amdgcn_ubfe(o2, s2, BITS), f3 = __builtin_amdgcn_ubfe(o3, s3, BITS);
+    if (__ballot(max(max(f0, f1), max(f2, f3)) == FULL)) {
+      const bool w0 = f0 == FULL, w1 = f1 == FULL, w2 = f2 == FULL, w3 = f3 == FULL;
       if constexpr (BITS == 16) {
         if (w0) fix_u16(o0, x0, 1u, carry, pass_lo);
         if (w1) fix_u16(o1, x1, 1u, carry, pass_lo);
