@@ -144,6 +144,20 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // of 8 so the XCD-aware mapping is a bijection.
   const uint32_t V = p->items / 4;
   uint32_t G = (uint32_t)dev.cus * p->bpt / p->passes / 8 * 8;
+  if (p->bits == 8) {
+    // Bound the keys per workgroup to 10 R, so that values up to ~25 x denser
+    // than uniform stay below the 256 hits at which a byte counter wraps (a
+    // wrap takes the slow repair path; n = 10^9 normal keys with sd R/64 spent
+    // two thirds of their histogram time there).  More workgroups mean more
+    // partial rows: their traffic (written once, read once) is capped at 1/32
+    // of the 8 bytes per key.
+    const uint64_t want = (n + 10ull * R - 1) / (10ull * R);
+    const uint64_t cap = n / (32ull * p->passes * p->row_words);
+    const uint64_t g = std::min<uint64_t>(want, cap);
+    if (g > G) G = (uint32_t)std::min<uint64_t>((g + 7) / 8 * 8, 1u << 16);
+  }
+  const int64_t gmul = env_int("RTCDF_DEV_HIST_GMUL", 1);
+  if (gmul > 1 && gmul <= 64) G *= (uint32_t)gmul;
   const uint64_t iters = (p->in_n4 + (uint64_t)p->hist_block * V - 1) / ((uint64_t)p->hist_block * V);
   const uint64_t gcap = std::max<uint64_t>(8, (iters + 7) / 8 * 8);
   G = (uint32_t)std::min<uint64_t>(std::max<uint32_t>(G, 8), gcap);
