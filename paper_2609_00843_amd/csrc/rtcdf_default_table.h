@@ -15,17 +15,17 @@ struct DefaultRow {
 };
 
 static const DefaultRow kDefaultTable[] = {
-    {181u, {4096, 8, 2, 0}},   // log2 R ~ 7
+    {181u, {2048, 8, 2, 0}},   // log2 R ~ 7
     {362u, {1024, 8, 2, 0}},   // log2 R ~ 8
     {724u, {1024, 8, 2, 0}},   // log2 R ~ 9
     {1448u, {32768, 8, 1, 0}},   // log2 R ~ 10
-    {2896u, {4096, 8, 1, 0}},   // log2 R ~ 11
+    {2896u, {8192, 8, 1, 0}},   // log2 R ~ 11
     {5792u, {1024, 8, 1, 0}},   // log2 R ~ 12
     {11585u, {1024, 8, 1, 0}},   // log2 R ~ 13
-    {23170u, {1024, 16, 1, 0}},   // log2 R ~ 14
+    {23170u, {1024, 8, 1, 0}},   // log2 R ~ 14
     {46340u, {1024, 16, 1, 0}},   // log2 R ~ 15
-    {92681u, {1024, 8, 1, 0}},   // log2 R ~ 16
-    {185363u, {1024, 8, 1, 0}},   // log2 R ~ 17
+    {92681u, {1024, 16, 1, 0}},   // log2 R ~ 16
+    {185363u, {1024, 16, 1, 0}},   // log2 R ~ 17
     {1u << 28, {1024, 8, 1, 0}},   // log2 R ~ 18
 };
 
