@@ -88,7 +88,8 @@ def test_ragged_sizes(r, R):
 @pytest.mark.parametrize("pin,pout", list(itertools.product(range(4), range(4))))
 def test_misaligned_pointers(r, pin, pout):
     rng = np.random.default_rng(10 * pin + pout)
-    for n, R in ((13, 50), (5000, 3000), (70001, 70000)):
+    # fast path (sparse and dense), staged 32-bit, one-pass 8-bit
+    for n, R in ((13, 50), (300001, 1500), (5000, 3000), (70001, 70000)):
         A = rng.integers(-7, -7 + R, size=n).astype(np.int32)
         _run(r, A, -7, -7 + R, pin=pin, pout=pout)
 
