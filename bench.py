@@ -101,6 +101,7 @@ def bench_batched(torch, rtcdf, inputs, steps, check):
     dout.fill_(0)
     t_batched = timed(g.replay, steps)
     parity = "not checked"
+    # Part of the CPU (oracle) leg: skipped together with it by --no-cpu-baseline.
     if check:
         import oracle
         outs = dout.cpu().numpy()
