@@ -399,3 +399,18 @@ def test_checked_mode(r):
         assert e.value.status == r.KEY_OUT_OF_RANGE
         torch.cuda.synchronize()
         assert np.all(out.cpu().numpy() == 0x5A5A5A5A)
+
+
+def test_release_workspaces_between_sorts(r):
+    """Released library workspaces (plain, carry and fast-path areas) are
+    re-created zeroed: sorts before and after a release agree with the oracle."""
+    rng = np.random.default_rng(123)
+    for rep in range(2):
+        for R in (100, 2000, 70000):
+            A = rng.integers(0, R, size=200_003).astype(np.int32)
+            _, tin = _to_dev(A, rep)
+            _say(f"release rep={rep} R={R}")
+            out = r.sort(tin, 0, R)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), oracle.sort(A, 0, R))
+        assert r.lib.rtcdf_release_workspaces() == r.SUCCESS
