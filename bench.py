@@ -433,10 +433,16 @@ def main():
 
     # CPU oracle on this host over the same arrays; doubles as a full parity check.
     cpu = None
+    cpu_parallel = None
     parity = "not checked"
     if not args.no_cpu_baseline:
         import oracle
         t_cpu, k_cpu, bad, host = 0.0, 0, [], []
+        # the multi-threaded CPU counting sort runs on this process's CPU share
+        par_threads = len(os.sched_getaffinity(0))
+        if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+            par_threads = min(par_threads, int(os.environ["OMP_NUM_THREADS"]))
+        par_bad, par_used = [], 0
         for (lr, d), a, b in zip(cases, ins, outs):
             R = 1 << lr
             A = a.cpu().numpy()
@@ -446,8 +452,11 @@ def main():
             k_cpu += A.size
             if not np.array_equal(b.cpu().numpy(), B):
                 bad.append(f"2^{lr}:{d}")
+            P, par_used = oracle.parallel_sort(A, MIN_VAL, MIN_VAL + R, par_threads)
+            if not np.array_equal(P, B):
+                par_bad.append(f"2^{lr}:{d}")
             host.append((A, R))
-            del B
+            del B, P
         parity = "bit-exact on all cases" if not bad else f"MISMATCH in {bad}"
         # further whole passes over the same arrays until about 10 s of CPU work
         passes = 1
@@ -458,7 +467,27 @@ def main():
                 t_cpu += time.perf_counter() - t
                 k_cpu += A.size
             passes += 1
-        del host
+        # multi-threaded CPU counting sort: whole passes until about 3 s
+        buf = np.empty(max(A.size for A, _ in host), dtype=np.int32)
+        t_par, k_par, par_passes = 0.0, 0, 0
+        while t_par < 3.0:
+            for A, R in host:
+                t = time.perf_counter()
+                oracle.parallel_sort(A, MIN_VAL, MIN_VAL + R, par_threads, out=buf[:A.size])
+                t_par += time.perf_counter() - t
+                k_par += A.size
+            par_passes += 1
+        del host, buf
+        cpu_parallel = {
+            "value": round(k_par / t_par / 1e9, 4), "unit": "Gkeys/s", "cores": par_used,
+            "kind": "multi-threaded counting sort",
+            "parity": "bit-exact vs oracle on all cases" if not par_bad else f"MISMATCH in {par_bad}",
+            "sample": f"all {len(cases)} arrays of the sweep, {par_passes} passes ({k_par} keys, "
+                      f"{t_par:.1f} s), per-thread histograms + parallel fill, {par_used} threads "
+                      f"(process affinity {len(os.sched_getaffinity(0))}, "
+                      f"{os.cpu_count()} host CPUs)"}
+        log(f"[bench] parallel CPU sort {cpu_parallel['value']} Gkeys/s on {par_used} threads; "
+            f"{cpu_parallel['parity']}")
         cpu = {"value": round(k_cpu / t_cpu / 1e9, 4), "unit": "Gkeys/s", "cores": 1,
                "kind": "oracle",
                "sample": f"all {len(cases)} arrays of the sweep at full size, {passes} passes "
@@ -511,6 +540,7 @@ def main():
         "min_frac_8B_roofline_R_le_2^16": round(min(c["frac_8B_roofline"] for c in tgt), 4) if tgt else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_parallel": cpu_parallel,
         "parity": parity,
         "stage_ms_per_sort": {k: round(v, 5) for k, v in stage_ms.items()},
         "kernels": kernels,

@@ -6,6 +6,10 @@ shares no code with the HIP path.  The arithmetic lives in plain C
 (``rtcdf_oracle.c``, built with gcc into ``liboracle.so``) and in
 ``mlp_ref.py`` / ``tune_ref.py``; this module is argument marshalling.
 
+``parallel_sort`` is not an oracle: it wraps ``cpu_parallel.cc``, the
+multi-threaded CPU counting sort that the benchmark times beside the oracle
+and that the tests check against it.
+
 Each wrapper names the passage of the paper it follows (sections of
 "Shared-Memory Range-Tiled CDF Sort for Small-Range Integer Keys on GPUs").
 """
@@ -21,6 +25,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # RTCDF_ORACLE_LIB lets the mutation test load a deliberately broken copy.
 _SO = os.environ.get("RTCDF_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "rtcdf_oracle.c")
+# The multi-threaded CPU counting sort timed beside the oracle (not an oracle).
+_PAR_SO = os.path.join(_HERE, "libcpu_parallel.so")
+_PAR_SRC = os.path.join(_HERE, "cpu_parallel.cc")
 
 ORC_OK = 0
 ORC_INVALID_ARGUMENT = 1
@@ -34,13 +41,23 @@ class OracleError(RuntimeError):
         self.code = code
 
 
+def _stale(so: str, src: str) -> bool:
+    return not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src)
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain C, -O2, no vectorisation tricks)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+    """Compile the oracle with gcc (plain C, -O2, no vectorisation tricks), and
+    the multi-threaded CPU baseline with g++."""
+    if force or _stale(_SO, _SRC):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
                                "-o", tmp, _SRC])
         os.replace(tmp, _SO)
+    if force or _stale(_PAR_SO, _PAR_SRC):
+        tmp = _PAR_SO + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-Wall", "-Wextra", "-pthread", "-shared",
+                               "-fPIC", "-o", tmp, _PAR_SRC])
+        os.replace(tmp, _PAR_SO)
     return _SO
 
 
@@ -71,6 +88,24 @@ def _load():
         lib.oracle_verify_begin.restype = None
         _lib = lib
     return _lib
+
+
+_par_lib = None
+
+
+def _load_parallel():
+    global _par_lib
+    if _par_lib is None:
+        if not os.path.exists(_PAR_SO):
+            build()
+        lib = ctypes.CDLL(_PAR_SO)
+        lib.cpu_parallel_sort.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_uint64,
+                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int)]
+        lib.cpu_parallel_sort.restype = ctypes.c_int
+        _par_lib = lib
+    return _par_lib
 
 
 def _i32(a) -> np.ndarray:
@@ -106,6 +141,22 @@ def sort(A, minVal: int, maxVal: int) -> np.ndarray:
                              _p(B, ctypes.c_int32))
     _check(rc, "oracle_sort")
     return B
+
+
+def parallel_sort(A, minVal: int, maxVal: int, threads: int, out=None):
+    """Measurement baseline, not an oracle: the counting sort of Sec. 2.1 on
+    `threads` host threads (per-thread histograms, parallel merge, parallel
+    fill by output position).  Returns (B, threads actually used)."""
+    A = _i32(A)
+    B = np.empty(A.size, dtype=np.int32) if out is None else out
+    if B.dtype != np.int32 or B.size != A.size or not B.flags.c_contiguous:
+        raise OracleError(ORC_INVALID_ARGUMENT, "parallel_sort: out")
+    used = ctypes.c_int(0)
+    rc = _load_parallel().cpu_parallel_sort(_p(A, ctypes.c_int32), A.size, int(minVal),
+                                            int(maxVal), int(threads), _p(B, ctypes.c_int32),
+                                            ctypes.byref(used))
+    _check(rc, "cpu_parallel_sort")
+    return B, used.value
 
 
 def tile_intermediates(A, minVal: int, maxVal: int, T: int):
