@@ -143,13 +143,13 @@ def bench_batched(torch, rtcdf, inputs, steps, check):
             "speedup_vs_plain_graph": round(t_plain_graph / t_batched, 2), "parity": parity}
 
 
-def timed_sorts(torch, rtcdf, a, b, lo, hi, reps, stream):
+def timed_sorts(torch, rtcdf, a, b, lo, hi, reps, stream, config=None):
     for _ in range(3):
-        rtcdf.sort(a, lo, hi, keys_out=b, stream=stream)
+        rtcdf.sort(a, lo, hi, keys_out=b, stream=stream, config=config)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        rtcdf.sort(a, lo, hi, keys_out=b, stream=stream)
+        rtcdf.sort(a, lo, hi, keys_out=b, stream=stream, config=config)
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
@@ -192,6 +192,41 @@ def bench_small(torch, rtcdf, inputs, steps):
             "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 2), "timing": "warm (HIP events, mean)",
             "ms_flushed": round(med(flushed), 5),
             "ms_wall_with_workspace_alloc": round(med(wall), 4)}
+
+
+def bench_output_methods(torch, rtcdf, inputs, steps):
+    """The paper's two output methods on the same inputs and configuration:
+    the search of the local CDFs (Alg. 7, the library's path) and step writes
+    plus a prefix maximum (Alg. 3, RTCDF_FLAG_OUTPUT_PREFIX_MAX).  Uniform
+    keys, n from 10^5 to 10^8, R from 2^7 to 2^22 (the paper saw Alg. 3 win
+    at small n and large R), warm, HIP events; both outputs are compared."""
+    stream = torch.cuda.current_stream()
+    old = rtcdf.get_config_mode()
+    rtcdf.set_config_mode(rtcdf.CONFIG_DEFAULT)
+    rows, same, faster = [], True, []
+    try:
+        for i, n in enumerate((10 ** 5, 10 ** 6, 10 ** 7, 10 ** 8)):
+            for logR in (7, 13, 18, 22):
+                R = 1 << logR
+                a = inputs.make_device("uniform", n, 0, R, inputs.case_seed(6, 10 * i + logR))
+                b = torch.empty_like(a)
+                c = torch.empty_like(a)
+                base = rtcdf.pick_config(n, 0, R)
+                pm = rtcdf.make_config(base.tile_width, base.items_per_thread, base.blocks_per_tile,
+                                       flags=rtcdf.FLAG_OUTPUT_PREFIX_MAX)
+                reps = max(steps, 20)
+                t_fill = timed_sorts(torch, rtcdf, a, b, 0, R, reps, stream, config=base)
+                t_pmax = timed_sorts(torch, rtcdf, a, c, 0, R, reps, stream, config=pm)
+                same = same and bool(torch.equal(b, c))
+                if t_pmax < t_fill:
+                    faster.append(f"n={n} R=2^{logR}")
+                rows.append({"n": n, "R": R, "ms_search": round(t_fill, 5), "ms_prefix_max": round(t_pmax, 5),
+                             "prefix_max_over_search": round(t_pmax / t_fill, 3)})
+                del a, b, c
+    finally:
+        rtcdf.set_config_mode(old)
+    return {"rows": rows, "outputs_identical": same, "prefix_max_faster_at": faster,
+            "timing": "warm, HIP events, mean over repetitions, default-mode configuration for both"}
 
 
 def bench_scale(torch, rtcdf, inputs, steps):
@@ -281,7 +316,12 @@ def main():
                     help="skip the 1e6-key and 1e9-key timings")
     ap.add_argument("--profile-only", action="store_true",
                     help="only run warmup + timed steps (for rocprofv3 runs)")
+    ap.add_argument("--output-method", choices=("search", "prefix_max"), default="search",
+                    help="with --profile-only: sort with the prefix-maximum output (Alg. 3) instead "
+                         "of the local-CDF search (Alg. 7)")
     args = ap.parse_args()
+    if args.output_method != "search" and not args.profile_only:
+        ap.error("--output-method prefix_max is a profiling mode; it needs --profile-only")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
               f"(the sort would shard by one 4R-byte histogram all-reduce)", file=sys.stderr)
@@ -306,9 +346,16 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 
+    cfgs = [None] * len(cases)
+    if args.output_method == "prefix_max":
+        for i, (lr, _) in enumerate(cases):
+            c = rtcdf.pick_config(N, MIN_VAL, MIN_VAL + (1 << lr))
+            cfgs[i] = rtcdf.make_config(c.tile_width, c.items_per_thread, c.blocks_per_tile,
+                                        flags=rtcdf.FLAG_OUTPUT_PREFIX_MAX)
+
     def step():
-        for (lr, _), a, b in zip(cases, ins, outs):
-            rtcdf.sort(a, MIN_VAL, MIN_VAL + (1 << lr), keys_out=b, stream=stream)
+        for (lr, _), a, b, c in zip(cases, ins, outs, cfgs):
+            rtcdf.sort(a, MIN_VAL, MIN_VAL + (1 << lr), keys_out=b, stream=stream, config=c)
 
     log(f"[bench] warmup {args.warmup} steps")
     for _ in range(args.warmup):
@@ -509,11 +556,15 @@ def main():
             f"{batched['speedup_vs_plain_calls']}x plain calls, {batched['speedup_vs_plain_graph']}x "
             f"plain graph; parity {batched['parity']}")
 
-    small = large = None
+    small = large = methods = None
     if not args.no_extra:
         log("[bench] n=1e6 and n=1e9 timings")
         small = bench_small(torch, rtcdf, inputs, args.steps)
         large = bench_scale(torch, rtcdf, inputs, args.steps)
+        log("[bench] output methods: local-CDF search vs prefix maximum")
+        methods = bench_output_methods(torch, rtcdf, inputs, args.steps)
+        log(f"[bench] output methods identical: {methods['outputs_identical']}; prefix maximum "
+            f"faster at: {methods['prefix_max_faster_at'] or 'none'}")
 
     tgt = [c for c in per_case if c["R"] <= (1 << 16)]
     rec = {
@@ -548,6 +599,7 @@ def main():
         "batched": batched,
         "learned": learned,
         "small_n": small,
+        "output_methods": methods,
         "large_n": large,
     }
     print(json.dumps(rec))

@@ -78,9 +78,17 @@ typedef enum rtcdf_status {
  *  blocks_per_tile   co-resident workgroups per compute unit working on a
  *                    range tile: 1, 2 or 4.  Each gets 160 KiB / blocks of
  *                    LDS, so T * 4 * blocks_per_tile <= 160 KiB is required.
- *  flags             0 (reserved).
+ *  flags             0, or RTCDF_FLAG_OUTPUT_PREFIX_MAX: write the output by
+ *                    the prefix-maximum method of Alg. 3 (Sec. 2.2: B = 0,
+ *                    each value stored at the first position of its output
+ *                    interval, then the running maximum of B) instead of
+ *                    the search of the local CDFs of Alg. 7.  Same output;
+ *                    it reads and writes B twice more (12 B per key in the
+ *                    output stage instead of 4) and is never the library's
+ *                    own choice.
  * A zeroed config (all fields 0) means "let the library choose" (the mode
  * set by rtcdf_set_config_mode). */
+#define RTCDF_FLAG_OUTPUT_PREFIX_MAX 1u
 typedef struct rtcdf_config {
   uint32_t tile_width;
   uint32_t items_per_thread;

@@ -76,7 +76,7 @@ bool config_valid(const rtcdf_config_t& c) {
   if (c.items_per_thread != 4 && c.items_per_thread != 8 && c.items_per_thread != 16) return false;
   if (c.blocks_per_tile != 1 && c.blocks_per_tile != 2 && c.blocks_per_tile != 4) return false;
   if ((uint64_t)c.tile_width * 4 * c.blocks_per_tile > kLdsBytes) return false;
-  if (c.flags != 0) return false;
+  if ((c.flags & ~(uint32_t)RTCDF_FLAG_OUTPUT_PREFIX_MAX) != 0) return false;
   return true;
 }
 
@@ -200,7 +200,17 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // fast-path area and the output stage sums and scans them itself.  Rows
   // spread the atomics of the histogram workgroups over more addresses; every
   // output workgroup reads rows * stride <= kFastRegionWords words.
-  p->fast = p->m == 1 && p->bits == 32 && p->passes == 1 && R <= kFastMaxRange &&
+  // Prefix-maximum output (Alg. 3) in place of Alg. 7: runs after the staged
+  // local-CDF stage, so it never takes the fast path.
+  p->pmax = (cfg.flags & RTCDF_FLAG_OUTPUT_PREFIX_MAX) != 0;
+  if (p->pmax) {
+    const uint32_t h = (uint32_t)std::min<uint64_t>(p->out_head, n);
+    p->pm_chunks = pmax_chunks(n, h);
+    const uint64_t n4 = (n - h) / 4;
+    p->pm_init_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n4 + 255) / 256,
+                                                                         (uint64_t)dev.cus * 8));
+  }
+  p->fast = p->m == 1 && p->bits == 32 && p->passes == 1 && R <= kFastMaxRange && !p->pmax &&
             env_int("RTCDF_DEV_FAST", 1) != 0;
   if (p->fast) {
     p->fast_stride = Rr;
@@ -226,6 +236,8 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   off = align256(off + ((size_t)p->nchunks + 1) * 4);
   p->off_flags = off;                       // [0]: some output chunk is sparse
   off = align256(off + 4);
+  p->off_pm = off;                          // prefix-maximum output: chunk maxima / carries
+  off = align256(off + (size_t)p->pm_chunks * 4);
   // Carry entries cover every bin of every pass (plus the partner of the last
   // bin), so even keys outside the declared range stay in bounds.
   p->carry_words = p->bits < 32 ? (size_t)p->passes * p->W + 4 : 0;
@@ -380,7 +392,7 @@ static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, ui
     if (e != hipSuccess) return hip_fail(e);
   }
   if (out) {
-    e = launch_fill(q, out, ws, s);
+    e = q.pmax ? launch_output_pmax(q, out, ws, s) : launch_fill(q, out, ws, s);
     if (e != hipSuccess) return hip_fail(e);
   }
   mark(4);

@@ -31,6 +31,10 @@ constexpr uint32_t kFastPar = 2 * kFastRegionWords;        // word read by the h
 constexpr uint32_t kFastCur = 2 * kFastRegionWords + 32;   // word read by the output stage
 constexpr uint32_t kFastAreaWords = 2 * kFastRegionWords + 64;
 
+// Prefix-maximum output method (Alg. 3): output positions per chunk, one
+// wave each.
+constexpr uint32_t kPmaxChunk = 8192;
+
 // Learned picker: sketch and MLP sizes (see include/rtcdf.h).
 constexpr int kSketchBins = 32;
 constexpr uint32_t kSketchSamples = 4096;
@@ -74,10 +78,15 @@ struct Plan {
   // itself; no reduction or local-CDF launch.
   bool fast;
   uint32_t fast_rows, fast_stride;
+  // Output by step writes and a prefix maximum (Alg. 3) instead of Alg. 7:
+  // pm_chunks chunks of kPmaxChunk positions (after the min(out_head, n)
+  // head), their maxima / carries at off_pm.
+  bool pmax;
+  uint32_t pm_chunks, pm_init_grid;
   uint32_t scan_parts;   // workgroups per tile in the local-CDF stage (fixed split)
   uint32_t scan_grid;    // workgroups of the local-CDF stage; > m: split by chunk counts
   // workspace layout
-  size_t off_partial, off_hist, off_cdf, off_rsum, off_O, off_split, off_flags, ws_bytes;
+  size_t off_partial, off_hist, off_cdf, off_rsum, off_O, off_split, off_flags, off_pm, ws_bytes;
   size_t off_carry;      // carry array inside a caller-owned workspace (rtcdf_sort_ws)
   size_t carry_words;    // 0 for 32-bit counters; the fast-path area on the fast path
 };
@@ -101,6 +110,10 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
 hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_t stream);
 hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t stream);
 hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream_t stream);
+// Prefix-maximum output (rtcdf_pmax.hip): Alg. 3 from the local CDFs and tile
+// offsets of the workspace, in four launches.
+uint32_t pmax_chunks(uint64_t n, uint32_t head);
+hipError_t launch_output_pmax(const Plan& p, int32_t* out, uint8_t* ws, hipStream_t stream);
 // Single-tile fast path: output stage from the counts the histogram left in the
 // fast-path area `area` (kFastAreaWords, whose state the launch advances).
 hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStream_t stream);

@@ -67,7 +67,9 @@ class Config(ctypes.Structure):
         return (self.tile_width, self.items_per_thread, self.blocks_per_tile)
 
     def __repr__(self):
-        return f"Config(T={self.tile_width}, items={self.items_per_thread}, bpt={self.blocks_per_tile})"
+        extra = f", flags={self.flags}" if self.flags else ""
+        return (f"Config(T={self.tile_width}, items={self.items_per_thread}, "
+                f"bpt={self.blocks_per_tile}{extra})")
 
 
 class Segment(ctypes.Structure):
@@ -127,8 +129,13 @@ def _check(st: int, what: str):
         raise RtcdfError(st, what)
 
 
-def make_config(tile_width: int, items_per_thread: int = 16, blocks_per_tile: int = 1) -> Config:
-    return Config(int(tile_width), int(items_per_thread), int(blocks_per_tile), 0)
+# rtcdf_config_t.flags: output by step writes and a prefix maximum (Alg. 3)
+FLAG_OUTPUT_PREFIX_MAX = 1
+
+
+def make_config(tile_width: int, items_per_thread: int = 16, blocks_per_tile: int = 1,
+                flags: int = 0) -> Config:
+    return Config(int(tile_width), int(items_per_thread), int(blocks_per_tile), int(flags))
 
 
 def _stream_ptr(stream):

@@ -75,7 +75,9 @@ def test_checked_mode_argument_errors(r):
 
 
 @pytest.mark.parametrize("cfg", [(100, 16, 1), (0, 16, 1), (1024, 5, 1), (1024, 16, 3),
-                                 (32768, 16, 2), (16384, 16, 4), (32896, 16, 1), (1024, 0, 1)])
+                                 (32768, 16, 2), (16384, 16, 4), (32896, 16, 1), (1024, 0, 1),
+                                 (1024, 16, 1, 2), (1024, 16, 1, 3), (1024, 16, 1, 1 << 31),
+                                 (100, 16, 1, 1)])
 def test_invalid_configs(r, cfg):
     c = r.make_config(*cfg)
     assert r.lib.rtcdf_sort_with_config(P_IN, P_OUT, 10, 0, 10, ctypes.byref(c), None) == r.INVALID_VALUE
@@ -126,3 +128,9 @@ def test_segment_layout(r):
     assert ctypes.sizeof(r.Config) == 16
     assert ctypes.sizeof(r.PlanInfo) == 56
     assert ctypes.sizeof(r.StageStats) == 40
+
+
+def test_output_flag_matches_header(r):
+    txt = open(os.path.join(ROOT, "include", "rtcdf.h")).read()
+    m = re.search(r"#define\s+RTCDF_FLAG_OUTPUT_PREFIX_MAX\s+(\d+)u", txt)
+    assert m and int(m.group(1)) == r.FLAG_OUTPUT_PREFIX_MAX
