@@ -200,6 +200,7 @@ def bench_output_methods(torch, rtcdf, inputs, steps):
     plus a prefix maximum (Alg. 3, RTCDF_FLAG_OUTPUT_PREFIX_MAX).  Uniform
     keys, n from 10^5 to 10^8, R from 2^7 to 2^22 (the paper saw Alg. 3 win
     at small n and large R), warm, HIP events; both outputs are compared."""
+    import numpy as np
     stream = torch.cuda.current_stream()
     old = rtcdf.get_config_mode()
     rtcdf.set_config_mode(rtcdf.CONFIG_DEFAULT)
@@ -211,22 +212,28 @@ def bench_output_methods(torch, rtcdf, inputs, steps):
                 a = inputs.make_device("uniform", n, 0, R, inputs.case_seed(6, 10 * i + logR))
                 b = torch.empty_like(a)
                 c = torch.empty_like(a)
-                base = rtcdf.pick_config(n, 0, R)
-                pm = rtcdf.make_config(base.tile_width, base.items_per_thread, base.blocks_per_tile,
+                lib_cfg = rtcdf.pick_config(n, 0, R)
+                search = rtcdf.make_config(lib_cfg.tile_width, lib_cfg.items_per_thread,
+                                           lib_cfg.blocks_per_tile)
+                pm = rtcdf.make_config(lib_cfg.tile_width, lib_cfg.items_per_thread, lib_cfg.blocks_per_tile,
                                        flags=rtcdf.FLAG_OUTPUT_PREFIX_MAX)
                 reps = max(steps, 20)
-                t_fill = timed_sorts(torch, rtcdf, a, b, 0, R, reps, stream, config=base)
+                t_fill = timed_sorts(torch, rtcdf, a, b, 0, R, reps, stream, config=search)
                 t_pmax = timed_sorts(torch, rtcdf, a, c, 0, R, reps, stream, config=pm)
                 same = same and bool(torch.equal(b, c))
                 if t_pmax < t_fill:
                     faster.append(f"n={n} R=2^{logR}")
                 rows.append({"n": n, "R": R, "ms_search": round(t_fill, 5), "ms_prefix_max": round(t_pmax, 5),
-                             "prefix_max_over_search": round(t_pmax / t_fill, 3)})
+                             "prefix_max_over_search": round(t_pmax / t_fill, 3),
+                             "library_choice": "prefix_max" if lib_cfg.flags else "search"})
                 del a, b, c
     finally:
         rtcdf.set_config_mode(old)
+    picked = [r["ms_prefix_max"] if r["library_choice"] == "prefix_max" else r["ms_search"] for r in rows]
+    gm = lambda v: float(np.exp(np.mean(np.log(v))))
     return {"rows": rows, "outputs_identical": same, "prefix_max_faster_at": faster,
-            "timing": "warm, HIP events, mean over repetitions, default-mode configuration for both"}
+            "library_choice_over_search_geomean": round(gm([p / r["ms_search"] for p, r in zip(picked, rows)]), 4),
+            "timing": "warm, HIP events, mean over repetitions, default-mode kernel configuration for both"}
 
 
 def bench_scale(torch, rtcdf, inputs, steps):

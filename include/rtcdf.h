@@ -83,9 +83,10 @@ typedef enum rtcdf_status {
  *                    each value stored at the first position of its output
  *                    interval, then the running maximum of B) instead of
  *                    the search of the local CDFs of Alg. 7.  Same output;
- *                    it reads and writes B twice more (12 B per key in the
- *                    output stage instead of 4) and is never the library's
- *                    own choice.
+ *                    it writes B twice and reads it once (12 B per key in
+ *                    the output stage instead of 4) but writes the steps one
+ *                    value per thread.  The library's own choice (every
+ *                    config mode) sets it when R >= 2^14 and R >= n.
  * A zeroed config (all fields 0) means "let the library choose" (the mode
  * set by rtcdf_set_config_mode). */
 #define RTCDF_FLAG_OUTPUT_PREFIX_MAX 1u
@@ -311,8 +312,9 @@ rtcdf_status_t rtcdf_mlp_pick(const int32_t* keys_in, size_t n, int64_t minVal, 
                               uint32_t* d_index, float* d_pred, hipStream_t stream);
 
 /* The configuration rtcdf_sort would use for (n, R) under the current mode,
- * written to *cfg (learned mode needs the keys for its sketch; keys_in may
- * be NULL in the other modes).  Synchronises `stream` in learned mode. */
+ * written to *cfg, flags included (learned mode needs the keys for its
+ * sketch; keys_in may be NULL in the other modes).  Synchronises `stream` in
+ * learned mode. */
 rtcdf_status_t rtcdf_pick_config(const int32_t* keys_in, size_t n, int64_t minVal,
                                  int64_t maxVal, hipStream_t stream, rtcdf_config_t* cfg);
 
@@ -356,10 +358,14 @@ typedef struct rtcdf_plan_info {
   uint32_t scan_workgroups;  /* local-CDF workgroups; 0 on the single-tile fast
                                 path (one tile, one pass of 32-bit counters, R <= 2048),
                                 where the output stage reduces and scans the counts */
-  uint32_t out_chunk;        /* output positions per chunk */
+  uint32_t out_chunk;        /* output positions per chunk (per wave with the
+                                prefix-maximum output) */
   uint32_t out_chunks;
-  uint32_t fill_workgroups;
+  uint32_t fill_workgroups;  /* output-stage workgroups */
   uint64_t workspace_bytes;
+  uint32_t output_flags;     /* RTCDF_FLAG_OUTPUT_PREFIX_MAX when the output is
+                                written by Alg. 3, else 0 */
+  uint32_t reserved;
 } rtcdf_plan_info_t;
 
 rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,

@@ -205,7 +205,8 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   p->pmax = (cfg.flags & RTCDF_FLAG_OUTPUT_PREFIX_MAX) != 0;
   if (p->pmax) {
     const uint32_t h = (uint32_t)std::min<uint64_t>(p->out_head, n);
-    p->pm_chunks = pmax_chunks(n, h);
+    p->pm_chunk = n <= kPmaxSmallN ? kPmaxChunkSmall : kPmaxChunkLarge;
+    p->pm_chunks = pmax_chunks(n, h, p->pm_chunk);
     const uint64_t n4 = (n - h) / 4;
     p->pm_init_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n4 + 255) / 256,
                                                                          (uint64_t)dev.cus * 8));
@@ -373,14 +374,15 @@ static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, ui
     }
     return RTCDF_SUCCESS;
   }
-  e = launch_reduce(q, ws, carry, s);
+  int32_t* pm_out = q.pmax ? out : nullptr;   // null on the debug path (no output)
+  e = launch_reduce(q, ws, carry, pm_out, s);
   if (e != hipSuccess) return hip_fail(e);
   mark(2);
   if (dbg_hist) {
     e = hipMemcpyAsync(dbg_hist, ws + q.off_hist, (size_t)q.R * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e);
   }
-  e = launch_tilescan(q, ws, s);
+  e = launch_tilescan(q, ws, pm_out, s);
   if (e != hipSuccess) return hip_fail(e);
   mark(3);
   if (dbg_cdf) {
@@ -700,10 +702,12 @@ rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const r
   out->hist_threads = p.hist_block;
   out->items_per_thread = p.items;
   out->scan_workgroups = p.fast ? 0 : p.scan_grid;
-  out->out_chunk = p.chunk;
-  out->out_chunks = p.nchunks;
-  out->fill_workgroups = p.fill_grid;
+  out->out_chunk = p.pmax ? p.pm_chunk : p.chunk;
+  out->out_chunks = p.pmax ? p.pm_chunks : p.nchunks;
+  out->fill_workgroups = p.pmax ? (p.pm_chunks + 3) / 4 : p.fill_grid;
   out->workspace_bytes = p.ws_bytes;
+  out->output_flags = p.pmax ? RTCDF_FLAG_OUTPUT_PREFIX_MAX : 0u;
+  out->reserved = 0;
   return RTCDF_SUCCESS;
 }
 

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -173,8 +174,24 @@ static rtcdf_status_t learned_config(const int32_t* keys, size_t n, int64_t minV
   return RTCDF_SUCCESS;
 }
 
-rtcdf_status_t pick_config(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,
-                           hipStream_t stream, rtcdf_config_t* out) {
+// Output method (the adaptive selection between Alg. 7 and Alg. 3 that the
+// paper leaves as future work in Sec. 4.1): the prefix maximum when the range
+// is at least kPmaxMinRange and at least n.  There the search path spends its
+// output stage walking many sparse values per output chunk, while the
+// prefix-maximum steps are written one value per thread by the local-CDF
+// stage; measured on MI355X over n in [10^3, 10^7] and R in [2^8, 2^24] with
+// uniform, normal and all-equal keys.  RTCDF_DEV_OUTPUT_RULE=0 keeps the
+// search everywhere (for measurement).
+constexpr uint32_t kPmaxMinRange = 1u << 14;
+
+static uint32_t output_method_flags(size_t n, uint32_t R) {
+  const char* v = std::getenv("RTCDF_DEV_OUTPUT_RULE");
+  if (v != nullptr && v[0] == '0' && v[1] == 0) return 0u;
+  return (R >= kPmaxMinRange && (uint64_t)R >= (uint64_t)n) ? RTCDF_FLAG_OUTPUT_PREFIX_MAX : 0u;
+}
+
+static rtcdf_status_t pick_kernel_config(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,
+                                         hipStream_t stream, rtcdf_config_t* out) {
   const int mode = g_mode.load();
   const uint32_t R = (uint32_t)(maxVal - minVal);
   if (mode == RTCDF_CONFIG_LEARNED) {
@@ -186,6 +203,13 @@ rtcdf_status_t pick_config(const int32_t* keys_in, size_t n, int64_t minVal, int
   if (mode != RTCDF_CONFIG_DEFAULT && tuned_config(n, R, out)) return RTCDF_SUCCESS;
   *out = default_config(n, R);
   return RTCDF_SUCCESS;
+}
+
+rtcdf_status_t pick_config(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,
+                           hipStream_t stream, rtcdf_config_t* out) {
+  rtcdf_status_t st = pick_kernel_config(keys_in, n, minVal, maxVal, stream, out);
+  if (st == RTCDF_SUCCESS) out->flags = output_method_flags(n, (uint32_t)(maxVal - minVal));
+  return st;
 }
 
 }  // namespace rtcdf

@@ -31,9 +31,12 @@ constexpr uint32_t kFastPar = 2 * kFastRegionWords;        // word read by the h
 constexpr uint32_t kFastCur = 2 * kFastRegionWords + 32;   // word read by the output stage
 constexpr uint32_t kFastAreaWords = 2 * kFastRegionWords + 64;
 
-// Prefix-maximum output method (Alg. 3): output positions per chunk, one
-// wave each.
-constexpr uint32_t kPmaxChunk = 8192;
+// Prefix-maximum output method (Alg. 3): output positions per chunk (one wave
+// each): short chunks while n <= kPmaxSmallN (more waves in flight), long ones
+// above (fewer chunk carries).
+constexpr uint32_t kPmaxChunkSmall = 2048;
+constexpr uint32_t kPmaxChunkLarge = 8192;
+constexpr uint64_t kPmaxSmallN = 1ull << 21;
 
 // Learned picker: sketch and MLP sizes (see include/rtcdf.h).
 constexpr int kSketchBins = 32;
@@ -79,10 +82,10 @@ struct Plan {
   bool fast;
   uint32_t fast_rows, fast_stride;
   // Output by step writes and a prefix maximum (Alg. 3) instead of Alg. 7:
-  // pm_chunks chunks of kPmaxChunk positions (after the min(out_head, n)
+  // pm_chunks chunks of pm_chunk positions (after the min(out_head, n)
   // head), their maxima / carries at off_pm.
   bool pmax;
-  uint32_t pm_chunks, pm_init_grid;
+  uint32_t pm_chunk, pm_chunks, pm_init_grid;
   uint32_t scan_parts;   // workgroups per tile in the local-CDF stage (fixed split)
   uint32_t scan_grid;    // workgroups of the local-CDF stage; > m: split by chunk counts
   // workspace layout
@@ -107,12 +110,17 @@ hipError_t launch_count_out_of_range(const int32_t* keys, uint64_t n, uint32_t m
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int cus, hipStream_t stream);
 hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t* carry,
                        hipStream_t stream);
-hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_t stream);
-hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t stream);
+// pm_out: the output B when the plan uses the prefix-maximum output (the
+// reduction then also writes the initial B and the local-CDF stage the steps
+// of Alg. 3), else null.
+hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, int32_t* pm_out,
+                         hipStream_t stream);
+hipError_t launch_tilescan(const Plan& p, uint8_t* ws, int32_t* pm_out, hipStream_t stream);
 hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream_t stream);
-// Prefix-maximum output (rtcdf_pmax.hip): Alg. 3 from the local CDFs and tile
-// offsets of the workspace, in four launches.
-uint32_t pmax_chunks(uint64_t n, uint32_t head);
+// Prefix-maximum output (rtcdf_pmax.hip): after the steps of Alg. 3 are in B
+// and the chunk maxima in the workspace, the prefix maximum of B in place (one
+// launch, two with more than 1024 chunks).
+uint32_t pmax_chunks(uint64_t n, uint32_t head, uint32_t chunk);
 hipError_t launch_output_pmax(const Plan& p, int32_t* out, uint8_t* ws, hipStream_t stream);
 // Single-tile fast path: output stage from the counts the histogram left in the
 // fast-path area `area` (kFastAreaWords, whose state the launch advances).

@@ -6,7 +6,9 @@
 //               counters as one partial row (coalesced, non-atomic) instead of
 //               the per-bin global atomics of Alg. 5.
 //   k_reduce    sums the partial rows of each bin -> H[R], plus per-128-bin
-//               block totals used for the tile offsets.
+//               block totals used for the tile offsets.  With the
+//               prefix-maximum output (Alg. 3) its extra workgroups write the
+//               initial B.
 //   k_tilescan  one or more workgroups per range tile: local CDF by inclusive
 //               scan (Alg. 4), tile offset O[t] (Alg. 6, as a sum of the block
 //               totals before the tile), and the value found at each output
@@ -16,6 +18,8 @@
 //               equal share of the tile's chunk boundaries.  With few tiles the
 //               workgroups are given to tiles in proportion to their chunk
 //               boundaries, which the kernel reads from the block totals.
+//               With the prefix-maximum output it writes the steps of Alg. 3
+//               instead of splitters (rtcdf_pmax.hip finishes the output).
 //   k_fill      one workgroup per output chunk: loads the inclusive cumulative
 //               counts O[t] + C_t[x] of the values that cover the chunk into LDS
 //               and writes every position p the value b_t + min{x : C_t[x] >= p'+1}
@@ -161,7 +165,32 @@ struct ReduceArgs {
   uint32_t* rsum;
   uint32_t* flags;   // cleared here for the local-CDF stage
   uint32_t R, W, G, row_words, carry_words, bits;
+  // Prefix-maximum output (Alg. 3): workgroups nred and up write the initial
+  // B[0, pm_n) = pm_fill and clear the pm_nck chunk maxima pm_M.  pm_out is
+  // null otherwise.
+  uint32_t nred;
+  int32_t* pm_out;
+  uint32_t pm_n, pm_head, pm_nck;
+  int32_t pm_fill;
+  uint32_t* pm_M;
 };
+
+// B[0, n) = fill (16-byte stores after the `head` scalars) and M[0, nck) = 0,
+// grid-stride over `workers` workgroups; `worker` is this workgroup's index.
+__device__ __forceinline__ void pmax_initial_fill(int32_t* out, uint32_t n, uint32_t head, int32_t fill,
+                                                  uint32_t* M, uint32_t nck, uint32_t worker,
+                                                  uint32_t workers) {
+  const size_t stride = (size_t)workers * blockDim.x;
+  const size_t gid = (size_t)worker * blockDim.x + threadIdx.x;
+  if (gid < head) out[gid] = fill;
+  const uint32_t n4 = (n - head) / 4;
+  v4i* body = reinterpret_cast<v4i*>(out + head);
+  const v4i f = {fill, fill, fill, fill};
+  for (size_t i = gid; i < n4; i += stride) body[i] = f;
+  const uint32_t tail = head + n4 * 4;
+  if (gid < n - tail) out[tail + gid] = fill;
+  for (size_t i = gid; i < nck; i += stride) M[i] = 0u;
+}
 
 // One workgroup per 128-bin block of one pass: the block is 128 / (32 / bits)
 // words of every partial row of the pass.  Threads are 32 row groups x NQ word
@@ -234,6 +263,11 @@ __device__ __forceinline__ void reduce_block(const ReduceArgs& a, uint32_t (*red
 __global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
   __shared__ uint32_t red[kReduceGroups][kReduceBins + 1];
   __shared__ uint32_t wsum[kReduceBlock / 64];
+  if (blockIdx.x >= a.nred) {   // prefix-maximum output: the initial B
+    pmax_initial_fill(a.pm_out, a.pm_n, a.pm_head, a.pm_fill, a.pm_M, a.pm_nck, blockIdx.x - a.nred,
+                      gridDim.x - a.nred);
+    return;
+  }
   if (a.bits == 32) reduce_block<32>(a, red, wsum);
   else if (a.bits == 16) reduce_block<16>(a, red, wsum);
   else reduce_block<8>(a, red, wsum);
@@ -252,6 +286,14 @@ struct ScanArgs {
   uint32_t R, T, out_head, chunk, nchunks, S;
   uint32_t m, grid;   // tiles; workgroups (grid > m: assigned by chunk counts)
   uint32_t* flags;    // [0] set if some chunk's window holds over chunk / 64 values
+  // Prefix-maximum output (Alg. 3; pm_out null otherwise): the first
+  // workgroup of each tile writes B[P1[d-1]] = minVal + d for every value d >= 1
+  // of the tile with keys, and the chunk maxima M (last step of each
+  // pm_chunk-position chunk); no splitters are needed.
+  int32_t* pm_out;
+  uint32_t pm_head, pm_chunk;
+  int32_t pm_min;
+  uint32_t* pm_M;
 };
 
 // First output chunk whose start position s(k) is >= P, where s(0) = 0 and
@@ -357,6 +399,20 @@ __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
   if (part == 0) {
     for (uint32_t i = tid; i < w; i += kScanBlock) a.cdf[b + i] = C[pad32(i)];
     if (tid == 0) a.O[t] = Ot;
+  }
+  if (a.pm_out != nullptr) {
+    if (part != 0) return;
+    for (uint32_t i = tid; i < w; i += kScanBlock) {
+      const uint32_t d = b + i;
+      const uint32_t e = Ot + C[pad32(i)];                       // P1[d]
+      const uint32_t s = i ? Ot + C[pad32(i - 1)] : Ot;          // P1[d - 1]
+      if (d == 0 || e <= s) continue;
+      a.pm_out[s] = a.pm_min + (int32_t)d;
+      const uint32_t c = s < a.pm_head ? 0u : (s - a.pm_head) / a.pm_chunk;
+      const uint64_t end = (uint64_t)a.pm_head + (uint64_t)(c + 1) * a.pm_chunk;
+      if (e >= end || e == a.n) a.pm_M[c] = d;                 // the last step of chunk c
+    }
+    return;
   }
   if (Nt == 0) return;
 
@@ -821,8 +877,17 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
   }
 }
 
-hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_t s) {
+hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, int32_t* pm_out, hipStream_t s) {
   ReduceArgs a;
+  a.nred = p.nred;
+  a.pm_out = pm_out;
+  a.pm_n = (uint32_t)p.n;
+  a.pm_head = (uint32_t)(p.out_head < p.n ? p.out_head : p.n);
+  a.pm_nck = p.pm_chunks;
+  a.pm_fill = (int32_t)p.min_u;
+  a.pm_M = reinterpret_cast<uint32_t*>(ws + p.off_pm);
+  if (pm_out != nullptr && (!p.pmax || p.pm_init_grid == 0 || p.n > 0xffffffffull))
+    return hipErrorInvalidValue;
   a.partial = reinterpret_cast<const uint32_t*>(ws + p.off_partial);
   a.carry = carry;
   a.hist = reinterpret_cast<uint32_t*>(ws + p.off_hist);
@@ -838,12 +903,19 @@ hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, hipStream_
   // are whole 16-byte quads of 16-byte aligned rows
   if (p.W % kReduceBins != 0 || p.row_words % 4 != 0) return hipErrorInvalidValue;
   const uint32_t threads = kReduceGroups * (kReduceBins / (32 / p.bits) / 4);
-  hipLaunchKernelGGL(k_reduce, dim3(p.nred), dim3(threads), 0, s, a);
+  const uint32_t grid = p.nred + (pm_out != nullptr ? p.pm_init_grid : 0u);
+  hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_tilescan(const Plan& p, uint8_t* ws, hipStream_t s) {
+hipError_t launch_tilescan(const Plan& p, uint8_t* ws, int32_t* pm_out, hipStream_t s) {
   ScanArgs a;
+  a.pm_out = pm_out;
+  a.pm_head = (uint32_t)(p.out_head < p.n ? p.out_head : p.n);
+  a.pm_chunk = p.pm_chunk;
+  a.pm_min = (int32_t)p.min_u;
+  a.pm_M = reinterpret_cast<uint32_t*>(ws + p.off_pm);
+  if (pm_out != nullptr && (!p.pmax || p.pm_chunk == 0)) return hipErrorInvalidValue;
   a.hist = reinterpret_cast<const uint32_t*>(ws + p.off_hist);
   a.cdf = reinterpret_cast<uint32_t*>(ws + p.off_cdf);
   a.S = p.scan_parts;

@@ -69,6 +69,16 @@ def test_distributions(r, dist, logR):
     _check(r, A, -1000, -1000 + R, _cfg(r, min(R, 8192)), pout=logR % 4)
 
 
+@pytest.mark.parametrize("n,pout", [((1 << 21) - 1, 0), (1 << 21, 3), ((1 << 21) + 1, 1), (3_000_001, 2),
+                                    (8192 * 1024 - 3, 1), (8192 * 1024 + 5, 0)])
+def test_chunk_regimes(r, n, pout):
+    """Around the switch from 2048- to 8192-position chunks (n = 2^21) and from
+    carries computed by each wave to the carry kernel (more than 1024 chunks)."""
+    R = 1 << 16
+    A = inputs.make("normal", n, 5, 5 + R, n % 1000)
+    _check(r, A, 5, 5 + R, _cfg(r, 8192), pout=pout)
+
+
 def test_in_place_and_extremes(r):
     rng = np.random.default_rng(3)
     A = rng.integers(0, 70000, size=500_001).astype(np.int32)
@@ -147,3 +157,28 @@ def test_same_output_as_interval_fill(r):
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert np.array_equal(b.cpu().numpy(), oracle.sort(A, 0, 1 << 16))
+
+
+def test_library_choice_rule(r):
+    """The library's own choice writes the output by the prefix maximum exactly
+    when R >= 2^14 and R >= n, in plan_info and pick_config alike; an explicit
+    config keeps its own output method."""
+    for n, R in ((1000, 1 << 14), (1000, (1 << 14) - 1), (16384, 1 << 14), (16385, 1 << 14),
+                 (10 ** 5, 1 << 18), (10 ** 6, 1 << 18), (10 ** 6, 1 << 22), (10 ** 8, 1 << 18),
+                 (5, 2048), (3000, 1 << 28)):
+        want = r.FLAG_OUTPUT_PREFIX_MAX if (R >= 1 << 14 and R >= n) else 0
+        info = r.plan_info(n, 0, R)
+        _say(f"rule n={n} R={R} -> {info['output_flags']}")
+        assert info["output_flags"] == want
+        assert r.pick_config(n, 0, R).flags == want
+        assert r.plan_info(n, 0, R, config=r.make_config(4096))["output_flags"] == 0
+        assert r.plan_info(n, 0, R, config=_cfg(r))["output_flags"] == r.FLAG_OUTPUT_PREFIX_MAX
+
+
+@pytest.mark.parametrize("dist", ["uniform", "normal", "all_equal", "zipf"])
+def test_library_choice_parity(r, dist):
+    """Sorts with the library's choice on both sides of the rule."""
+    for n, logR in ((3000, 18), (100_000, 20), (100_000, 16), (20_000, 14)):
+        R = 1 << logR
+        A = inputs.make(dist, n, -5000, -5000 + R, n + logR)
+        _check(r, A, -5000, -5000 + R, None, pout=n % 4)
