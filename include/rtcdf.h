@@ -365,7 +365,10 @@ typedef struct rtcdf_plan_info {
   uint64_t workspace_bytes;
   uint32_t output_flags;     /* RTCDF_FLAG_OUTPUT_PREFIX_MAX when the output is
                                 written by Alg. 3, else 0 */
-  uint32_t reserved;
+  uint32_t partition_buckets;  /* > 0: the keys are first partitioned by LDS pass
+                                  into this many buckets (one more read and write
+                                  of the keys; each pass then reads its bucket
+                                  only); 0: every pass reads the whole input */
 } rtcdf_plan_info_t;
 
 rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,

@@ -164,6 +164,22 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   p->G = G;
   p->in_per = (p->in_n4 + G - 1) / G;
 
+  // Partition by pass when the range needs kPartMinPasses or more LDS passes
+  // and n x passes is at least kPartMinWork (measured crossover;
+  // RTCDF_DEV_PARTITION = 0 / 1 forces it off / on wherever it applies).
+  {
+    const int64_t force = env_int("RTCDF_DEV_PARTITION", -1);
+    const bool fits = p->passes >= 2 && p->passes <= kPartMaxBuckets && n <= 0xffffffffull;
+    p->part = fits && (force == 1 || (force != 0 && p->passes >= kPartMinPasses &&
+                                      (uint64_t)n * p->passes >= kPartMinWork));
+    if (p->part) {
+      p->part_buckets = p->passes;
+      const uint64_t tiles = (n + kPartTileKeys - 1) / kPartTileKeys;
+      p->part_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)dev.cus * 4));
+      p->part_per = (uint32_t)((n + p->part_grid - 1) / p->part_grid);
+    }
+  }
+
   p->nred = (R + kReduceBins - 1) / kReduceBins;
 
   // Output chunks: s(0) = 0, s(k) = out_head + k * chunk.
@@ -239,6 +255,16 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   off = align256(off + 4);
   p->off_pm = off;                          // prefix-maximum output: chunk maxima / carries
   off = align256(off + (size_t)p->pm_chunks * 4);
+  // partition by pass: keys (each bucket padded to 4), counts, totals, bounds
+  const size_t P = p->part ? p->part_buckets : 0;
+  p->off_pkeys = off;
+  off = align256(off + (p->part ? ((size_t)n + 4 * P + 4) * 4 : 0));
+  p->off_pcnt = off;
+  off = align256(off + P * p->part_grid * 4);
+  p->off_ptot = off;
+  off = align256(off + P * 4);
+  p->off_pbound = off;
+  off = align256(off + (p->part ? (P + 1) * 4 : 0));
   // Carry entries cover every bin of every pass (plus the partner of the last
   // bin), so even keys outside the declared range stay in bounds.
   p->carry_words = p->bits < 32 ? (size_t)p->passes * p->W + 4 : 0;
@@ -359,7 +385,12 @@ static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, ui
     if (prof) (void)hipEventRecord(marks.ev[i], s);
   };
   mark(0);
-  hipError_t e = launch_hist(q, in, ws, carry, s);
+  hipError_t e = hipSuccess;
+  if (q.part) {
+    e = launch_partition(q, in, ws, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  e = launch_hist(q, in, ws, carry, s);
   if (e != hipSuccess) return hip_fail(e);
   mark(1);
   if (q.fast) {   // the output stage does the reduction and the scan
@@ -707,7 +738,7 @@ rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const r
   out->fill_workgroups = p.pmax ? (p.pm_chunks + 3) / 4 : p.fill_grid;
   out->workspace_bytes = p.ws_bytes;
   out->output_flags = p.pmax ? RTCDF_FLAG_OUTPUT_PREFIX_MAX : 0u;
-  out->reserved = 0;
+  out->partition_buckets = p.part ? p.part_buckets : 0u;
   return RTCDF_SUCCESS;
 }
 

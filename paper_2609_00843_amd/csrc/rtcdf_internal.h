@@ -38,6 +38,17 @@ constexpr uint32_t kPmaxChunkSmall = 2048;
 constexpr uint32_t kPmaxChunkLarge = 8192;
 constexpr uint64_t kPmaxSmallN = 1ull << 21;
 
+// Partition of the keys by LDS pass (rtcdf_part.hip), for ranges that need
+// several passes: at most kPartMaxBuckets passes; keys per partition tile.
+constexpr uint32_t kPartMaxBuckets = 8192;
+constexpr uint32_t kPartTileKeys = 4096;
+// The library partitions from kPartMinPasses passes on when n x passes is at
+// least kPartMinWork (measured on MI355X: at n = 10^8 the multi-pass
+// histogram grows ~0.05 ms a pass against a nearly constant partition cost,
+// crossing near 9 passes; smaller n cross later).
+constexpr uint32_t kPartMinPasses = 9;
+constexpr uint64_t kPartMinWork = 1ull << 26;
+
 // Learned picker: sketch and MLP sizes (see include/rtcdf.h).
 constexpr int kSketchBins = 32;
 constexpr uint32_t kSketchSamples = 4096;
@@ -86,10 +97,16 @@ struct Plan {
   // head), their maxima / carries at off_pm.
   bool pmax;
   uint32_t pm_chunk, pm_chunks, pm_init_grid;
+  // Partition by pass (part): part_grid workgroups of part_per keys sort the
+  // keys by bucket (= pass) into off_pkeys; the histogram of pass b reads
+  // bucket b, whose padded bounds are at off_pbound.
+  bool part;
+  uint32_t part_grid, part_per, part_buckets;
   uint32_t scan_parts;   // workgroups per tile in the local-CDF stage (fixed split)
   uint32_t scan_grid;    // workgroups of the local-CDF stage; > m: split by chunk counts
   // workspace layout
   size_t off_partial, off_hist, off_cdf, off_rsum, off_O, off_split, off_flags, off_pm, ws_bytes;
+  size_t off_pkeys, off_pcnt, off_ptot, off_pbound;
   size_t off_carry;      // carry array inside a caller-owned workspace (rtcdf_sort_ws)
   size_t carry_words;    // 0 for 32-bit counters; the fast-path area on the fast path
 };
@@ -108,8 +125,13 @@ hipError_t launch_clear(uint32_t* p, size_t words, hipStream_t stream);
 hipError_t launch_count_out_of_range(const int32_t* keys, uint64_t n, uint32_t min_u, uint32_t R,
                                      uint64_t* count, int cus, hipStream_t stream);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int cus, hipStream_t stream);
+// With p.part the histogram reads the partitioned keys of the workspace and
+// `keys` is not read.
 hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t* carry,
                        hipStream_t stream);
+// Partition by pass (rtcdf_part.hip): three launches, before the histogram.
+hipError_t launch_partition(const Plan& p, const int32_t* keys, uint8_t* ws, hipStream_t stream);
+size_t partition_lds_bytes(uint32_t buckets);
 // pm_out: the output B when the plan uses the prefix-maximum output (the
 // reduction then also writes the initial B and the local-CDF stage the steps
 // of Alg. 3), else null.

@@ -53,6 +53,9 @@ struct HistArgs {
   // blockIdx % merge (rows of merge_stride words) of the current region of the
   // fast-path area in `carry` instead of writing a partial row.
   uint32_t merge, merge_stride;
+  // Partition mode (non-null): `keys` is the partitioned copy and pass p reads
+  // keys[pbound[p], pbound[p + 1]) (16-byte aligned, whole vectors).
+  const uint32_t* pbound;
 };
 
 template <int ITEMS, int BITS, int BLOCK>
@@ -79,8 +82,20 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   const uint32_t base = a.min_u + pass_lo;   // key (as uint32) of bin 0 of this pass
   const uint32_t W = a.W;
 
+  // this pass's input: the whole array, or its bucket of the partitioned copy
+  const int32_t* keys = a.keys;
+  uint32_t in_n4 = a.in_n4, in_per = a.in_per, in_head = a.in_head, in_tail = a.in_tail;
+  if (a.pbound != nullptr) {
+    const uint32_t b0 = a.pbound[pass], b1 = a.pbound[pass + 1];
+    keys = a.keys + b0;
+    in_n4 = (b1 - b0) / 4;
+    in_per = (in_n4 + a.G - 1) / a.G;
+    in_head = 0;
+    in_tail = 0;
+  }
+
   constexpr int V = ITEMS / 4;
-  const v4i* body = reinterpret_cast<const v4i*>(a.keys + a.in_head);
+  const v4i* body = reinterpret_cast<const v4i*>(keys + in_head);
   const v4i outside = (v4i)(int)(base - 1u);   // lands outside every pass
   HotBin hot;                                  // narrow forms only
   uint32_t t0, step, end;
@@ -89,12 +104,12 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
     // at any moment the whole grid reads one contiguous window of the input.
     t0 = chunk * BLOCK * V + threadIdx.x;
     step = BLOCK * V * a.G;
-    end = a.in_n4;
+    end = in_n4;
   } else {
-    const uint32_t c0 = chunk * a.in_per;
+    const uint32_t c0 = chunk * in_per;
     t0 = c0 + threadIdx.x;
     step = BLOCK * V;
-    end = c0 + a.in_per < a.in_n4 ? c0 + a.in_per : a.in_n4;
+    end = c0 + in_per < in_n4 ? c0 + in_per : in_n4;
   }
   // Software pipelined: the loads of the next tile are in flight while the
   // current one is counted.  Every load is issued unconditionally from an
@@ -129,9 +144,8 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   }
   // scalar head and tail keys (at most 3 each), counted by chunk 0 / chunk G-1
   v4i e = outside;
-  if (chunk == 0 && threadIdx.x < a.in_head) e.x = a.keys[threadIdx.x];
-  if (chunk == a.G - 1 && threadIdx.x < a.in_tail)
-    e.y = a.keys[a.in_head + 4 * (size_t)a.in_n4 + threadIdx.x];
+  if (chunk == 0 && threadIdx.x < in_head) e.x = keys[threadIdx.x];
+  if (chunk == a.G - 1 && threadIdx.x < in_tail) e.y = keys[in_head + 4 * (size_t)in_n4 + threadIdx.x];
   if (threadIdx.x < 64) count4<BITS>(S, e, base, W, a.carry, pass_lo, tab, hot);
   if constexpr (BITS < 32) hot_flush(hot, tab, a.carry, pass_lo);
   __syncthreads();
@@ -870,6 +884,12 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
   a.interleave = p.hist_interleave;
   a.merge = p.fast ? p.fast_rows : 0u;
   a.merge_stride = p.fast_stride;
+  a.pbound = nullptr;
+  if (p.part) {
+    if (p.fast || p.off_pkeys % 16 != 0) return hipErrorInvalidValue;
+    a.keys = reinterpret_cast<const int32_t*>(ws + p.off_pkeys);
+    a.pbound = reinterpret_cast<const uint32_t*>(ws + p.off_pbound);
+  }
   switch (p.bits) {
     case 8: return launch_hist_block<8>(p, a, s);
     case 16: return launch_hist_block<16>(p, a, s);

@@ -473,7 +473,7 @@ class PlanInfo(ctypes.Structure):
         "tile_width", "tiles", "counter_bits", "passes", "pass_bins", "hist_workgroups",
         "hist_threads", "items_per_thread", "scan_workgroups", "out_chunk", "out_chunks",
         "fill_workgroups")] + [("workspace_bytes", ctypes.c_uint64), ("output_flags", ctypes.c_uint32),
-                                ("reserved", ctypes.c_uint32)]
+                                ("partition_buckets", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

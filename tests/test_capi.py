@@ -126,7 +126,7 @@ def test_segment_layout(r):
     assert ctypes.sizeof(r.Segment) == 32
     assert ctypes.sizeof(r.BatchBounds) == 16
     assert ctypes.sizeof(r.Config) == 16
-    assert ctypes.sizeof(r.PlanInfo) == 64   # 12 uint32, uint64 workspace_bytes, output_flags, reserved
+    assert ctypes.sizeof(r.PlanInfo) == 64   # 12 uint32, uint64 workspace_bytes, output_flags, partition_buckets
     assert ctypes.sizeof(r.StageStats) == 40
 
 
