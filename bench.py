@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 N = 100_000_000
 MIN_VAL = -1000
 LOG_R = (7, 10, 13, 16, 18)
+WIDE_LOG_R = (20, 22, 24)   # beyond the paper's ranges: the partition by pass
 DISTS = ("uniform", "normal", "all_equal")
 METRIC = "Gkeys/s + % of 8 B/key HBM roofline; batched & learned-tuned vs plain"
 
@@ -236,6 +237,40 @@ def bench_output_methods(torch, rtcdf, inputs, steps):
             "timing": "warm, HIP events, mean over repetitions, default-mode kernel configuration for both"}
 
 
+def bench_wide_ranges(torch, rtcdf, inputs, steps):
+    """n = 10^8 uniform and normal keys over R = 2^20, 2^22, 2^24 (beyond the
+    paper's ranges): the library's choice (the partition by pass from 9
+    passes on) against the histogram that reads every key once per pass
+    (RTCDF_DEV_PARTITION=0), warm, HIP events; the two outputs are compared."""
+    stream = torch.cuda.current_stream()
+    rows, same = [], True
+    n = 10 ** 8
+    reps = max(3, steps // 4)
+    try:
+        for logR in WIDE_LOG_R:
+            R = 1 << logR
+            for dist in ("uniform", "normal"):
+                a = inputs.make_device(dist, n, 0, R, inputs.case_seed(7, logR))
+                b = torch.empty_like(a)
+                c = torch.empty_like(a)
+                info = rtcdf.plan_info(n, 0, R)
+                t_lib = timed_sorts(torch, rtcdf, a, b, 0, R, reps, stream)
+                os.environ["RTCDF_DEV_PARTITION"] = "0"
+                t_multi = timed_sorts(torch, rtcdf, a, c, 0, R, reps, stream)
+                os.environ.pop("RTCDF_DEV_PARTITION")
+                same = same and bool(torch.equal(b, c))
+                rows.append({"R": R, "dist": dist, "passes": info["passes"],
+                             "partition_buckets": info["partition_buckets"], "ms": round(t_lib, 4),
+                             "gkeys_per_s": round(n / (t_lib * 1e-3) / 1e9, 1),
+                             "ms_every_pass_reads_all_keys": round(t_multi, 4),
+                             "speedup": round(t_multi / t_lib, 2)})
+                del a, b, c
+    finally:
+        os.environ.pop("RTCDF_DEV_PARTITION", None)
+    return {"workload": "n=1e8 int32 keys, minVal=0, R in {2^20, 2^22, 2^24}", "rows": rows,
+            "outputs_identical": same, "timing": "warm, HIP events, mean"}
+
+
 def bench_scale(torch, rtcdf, inputs, steps):
     """n = 10^9 keys, minVal 0, R = 2^18: uniform, all equal (87381) and normal
     (mean 2^17, sd 4096).  Element-by-element parity at this size is checked
@@ -323,12 +358,17 @@ def main():
                     help="skip the 1e6-key and 1e9-key timings")
     ap.add_argument("--profile-only", action="store_true",
                     help="only run warmup + timed steps (for rocprofv3 runs)")
+    ap.add_argument("--wide-ranges", action="store_true",
+                    help="with --profile-only: sort n = 10^8 uniform keys over R = 2^20, 2^22 and 2^24 "
+                         "(the partition by pass) instead of the range sweep")
     ap.add_argument("--output-method", choices=("search", "prefix_max"), default="search",
                     help="with --profile-only: sort with the prefix-maximum output (Alg. 3) instead "
                          "of the local-CDF search (Alg. 7)")
     args = ap.parse_args()
     if args.output_method != "search" and not args.profile_only:
         ap.error("--output-method prefix_max is a profiling mode; it needs --profile-only")
+    if args.wide_ranges and not args.profile_only:
+        ap.error("--wide-ranges is a profiling mode; it needs --profile-only")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
               f"(the sort would shard by one 4R-byte histogram all-reduce)", file=sys.stderr)
@@ -339,6 +379,8 @@ def main():
     from paper_2609_00843_amd import inputs, rtcdf
 
     cases = [(lr, d) for lr in LOG_R for d in DISTS]
+    if args.wide_ranges:
+        cases = [(lr, "uniform") for lr in WIDE_LOG_R]
     if args.cases:
         want = {(int(a), b) for a, b in (c.split(":") for c in args.cases.split(","))}
         cases = [c for c in cases if c in want]
@@ -563,7 +605,7 @@ def main():
             f"{batched['speedup_vs_plain_calls']}x plain calls, {batched['speedup_vs_plain_graph']}x "
             f"plain graph; parity {batched['parity']}")
 
-    small = large = methods = None
+    small = large = methods = wide = None
     if not args.no_extra:
         log("[bench] n=1e6 and n=1e9 timings")
         small = bench_small(torch, rtcdf, inputs, args.steps)
@@ -572,6 +614,11 @@ def main():
         methods = bench_output_methods(torch, rtcdf, inputs, args.steps)
         log(f"[bench] output methods identical: {methods['outputs_identical']}; prefix maximum "
             f"faster at: {methods['prefix_max_faster_at'] or 'none'}")
+        log("[bench] wide ranges: partition by pass")
+        wide = bench_wide_ranges(torch, rtcdf, inputs, args.steps)
+        log("[bench] wide ranges: " + ", ".join(f"2^{r['R'].bit_length() - 1} {r['dist']} {r['ms']} ms "
+                                                f"(x{r['speedup']})" for r in wide["rows"])
+            + f"; identical: {wide['outputs_identical']}")
 
     tgt = [c for c in per_case if c["R"] <= (1 << 16)]
     rec = {
@@ -607,6 +654,7 @@ def main():
         "learned": learned,
         "small_n": small,
         "output_methods": methods,
+        "wide_ranges": wide,
         "large_n": large,
     }
     print(json.dumps(rec))
