@@ -299,6 +299,7 @@ struct ScanArgs {
   uint64_t n;
   uint32_t R, T, out_head, chunk, nchunks, S;
   uint32_t m, grid;   // tiles; workgroups (grid > m: assigned by chunk counts)
+  uint32_t pre_O;     // per-tile path: O[t] was written by k_tile_offsets
   uint32_t* flags;    // [0] set if some chunk's window holds over chunk / 64 values
   // Prefix-maximum output (Alg. 3; pm_out null otherwise): the first
   // workgroup of each tile writes B[P1[d-1]] = minVal + d for every value d >= 1
@@ -309,6 +310,28 @@ struct ScanArgs {
   int32_t pm_min;
   uint32_t* pm_M;
 };
+
+// Alg. 6 for the plans whose local-CDF workgroups are not given to tiles by
+// their chunk counts (many tiles or many block totals): one workgroup forms
+// every tile total from the 128-bin block totals and writes the exclusive
+// scan O[0, m).  Each thread takes a contiguous run of tiles.
+__global__ __launch_bounds__(kScanBlock) void k_tile_offsets(const uint32_t* __restrict__ rsum, uint32_t nred,
+                                                             uint32_t nb, uint32_t m, uint32_t* __restrict__ O) {
+  __shared__ uint32_t wsum[kScanBlock / 64];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (m + kScanBlock - 1) / kScanBlock;
+  const uint32_t t0 = min(m, tid * per), t1 = min(m, t0 + per);
+  const uint32_t k1 = min(nred, t1 * nb);
+  uint32_t s = 0;
+  for (uint32_t k = t0 * nb; k < k1; ++k) s += rsum[k];
+  uint32_t total;
+  uint32_t run = block_inclusive_scan(s, wsum, &total) - s;
+  for (uint32_t t = t0; t < t1; ++t) {
+    O[t] = run;
+    const uint32_t ke = min(nred, (t + 1) * nb);
+    for (uint32_t k = t * nb; k < ke; ++k) run += rsum[k];
+  }
+}
 
 // First output chunk whose start position s(k) is >= P, where s(0) = 0 and
 // s(k) = out_head + k * chunk for k >= 1.
@@ -385,10 +408,15 @@ __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
     part = blockIdx.x % a.S;
     S = a.S;
     // Alg. 6: O[t] = number of keys below b_t = sum of the 128-bin block
-    // totals before the tile (b_t is a multiple of 128).
-    uint32_t acc = 0;
-    for (uint32_t k = tid; k < t * a.T / kReduceBins; k += kScanBlock) acc += a.rsum[k];
-    Ot = block_sum(acc, wsum);
+    // totals before the tile (b_t is a multiple of 128); with many tiles and
+    // block totals, k_tile_offsets has written it.
+    if (a.pre_O) {
+      Ot = a.O[t];
+    } else {
+      uint32_t acc = 0;
+      for (uint32_t k = tid; k < t * a.T / kReduceBins; k += kScanBlock) acc += a.rsum[k];
+      Ot = block_sum(acc, wsum);
+    }
   }
   const uint32_t b = t * a.T;
   const uint32_t w = a.R - b < a.T ? a.R - b : a.T;
@@ -951,6 +979,18 @@ hipError_t launch_tilescan(const Plan& p, uint8_t* ws, int32_t* pm_out, hipStrea
   a.out_head = p.out_head;
   a.chunk = p.chunk;
   a.nchunks = p.nchunks;
+  // The per-tile path sums the block totals before each tile in every
+  // workgroup (m x nred / 2 loads in all); above 2^28 loads one workgroup
+  // forms all offsets first.
+  a.pre_O = p.m > 1 && p.scan_grid <= p.m && (uint64_t)p.m * p.nred > (1ull << 28);
+  if (a.pre_O) {
+    // tiles of T = a multiple of 128 bins
+    if (p.T % kReduceBins != 0 || p.scan_grid != p.m * p.scan_parts) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(kScanBlock), 0, s,
+                       static_cast<const uint32_t*>(a.rsum), p.nred, p.T / kReduceBins, p.m, a.O);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+  }
   const size_t lds = ((size_t)p.T + p.T / 32 + 2 + 4 * kScanBlock) * 4;
   hipError_t e = hipFuncSetAttribute((const void*)k_tilescan,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -83,7 +83,7 @@ def test_ragged_sizes(r, forced, R):
 
 
 @pytest.mark.parametrize("dist", ["uniform", "normal", "all_equal", "zipf"])
-@pytest.mark.parametrize("R", [1 << 19, 1 << 22])
+@pytest.mark.parametrize("R", [1 << 19, 1 << 22, 1 << 24])
 def test_distributions(r, forced, dist, R):
     A = inputs.make(dist, 2_000_003, -1000, -1000 + R, inputs.case_seed(11, R % 97))
     _check(r, A, -1000, -1000 + R, pout=2)

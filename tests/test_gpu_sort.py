@@ -209,7 +209,8 @@ def test_every_config_is_identical(r, dist, logR):
 
 
 @pytest.mark.parametrize("R,T", [(4, 128), (1000, 128), (1000, 1024), (70000, 1024),
-                                 (70000, 32768), (262144, 8192), (300000, 32768)])
+                                 (70000, 32768), (262144, 8192), (300000, 32768),
+                                 ((1 << 21) + 77, 128)])   # 16385 tiles: offsets by k_tile_offsets
 def test_intermediates_match_oracle(r, R, T):
     """Tile histograms (Alg. 5), local CDFs (Alg. 4) and tile offsets (Alg. 6)."""
     rng = np.random.default_rng(R + T)
