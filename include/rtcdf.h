@@ -137,7 +137,11 @@ rtcdf_status_t rtcdf_sort_checked(const int32_t* keys_in, int32_t* keys_out, siz
 /* Bytes of device workspace rtcdf_sort_ws needs for this problem and
  * configuration (cfg NULL = library choice), written to *bytes.  The
  * requirement depends on n, R, the config and the alignment of keys_out
- * modulo 16 bytes, which is why keys_out is asked for (it is not read). */
+ * modulo 16 bytes, which is why keys_out is asked for (it is not read).
+ * Ranges that need many LDS passes (R above about 1.4 x 10^6, reported by
+ * rtcdf_plan_info as partition_buckets > 0) add a copy of the keys,
+ * 4 (n + 4 passes + 4) bytes: the keys are first grouped by pass so that each
+ * pass reads its own group only. */
 rtcdf_status_t rtcdf_workspace_bytes(size_t n, int64_t minVal, int64_t maxVal,
                                      const rtcdf_config_t* cfg, const int32_t* keys_out,
                                      size_t* bytes);
