@@ -175,7 +175,8 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
     if (p->part) {
       p->part_buckets = p->passes;
       const uint64_t tiles = (n + kPartTileKeys - 1) / kPartTileKeys;
-      p->part_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)dev.cus * 4));
+      const uint64_t per_cu = (uint64_t)std::max<int64_t>(1, env_int("RTCDF_DEV_PART_WGS_PER_CU", 4));
+      p->part_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)dev.cus * per_cu));
       p->part_per = (uint32_t)((n + p->part_grid - 1) / p->part_grid);
     }
   }

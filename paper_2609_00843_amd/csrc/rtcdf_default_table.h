@@ -26,7 +26,8 @@ static const DefaultRow kDefaultTable[] = {
     {46340u, {1024, 16, 1, 0}},   // log2 R ~ 15
     {92681u, {1024, 16, 1, 0}},   // log2 R ~ 16
     {185363u, {1024, 16, 1, 0}},   // log2 R ~ 17
-    {1u << 28, {1024, 8, 1, 0}},   // log2 R ~ 18
+    {370727u, {1024, 8, 1, 0}},   // log2 R ~ 18
+    {1u << 28, {8192, 8, 1, 0}},   // wider than the tuning rows
 };
 
 }  // namespace rtcdf

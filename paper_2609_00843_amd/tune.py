@@ -135,15 +135,24 @@ def select_static(rows):
     return table
 
 
+# Ranges wider than the tuning rows (log2 R > 18.5): measured separately on
+# MI355X over n in {10^7, 10^8}, R in {2^19 ... 2^24}, uniform and normal keys,
+# where T = 8192 with 8 keys per thread was 0.80-0.98 x the time of the last
+# tuned row's T = 1024 (the O(R) stages launch 8 x fewer tile workgroups).
+WIDE_RANGE_CONFIG = (8192, 8, 1)
+
+
 def write_default_table(table, path: str = TABLE_H, source: str = ""):
     pts, _ = grid()
     classes = sorted(table)
     lines = []
-    for j, c in enumerate(classes):
+    for c in classes:
         # class c covers R up to the geometric midpoint towards class c + 1
-        bound = "1u << 28" if j == len(classes) - 1 else f"{int(math.floor(2.0 ** (c + 0.5)))}u"
+        bound = f"{int(math.floor(2.0 ** (c + 0.5)))}u"
         T, it, b = pts[table[c]]
         lines.append(f"    {{{bound}, {{{T}, {it}, {b}, 0}}}},   // log2 R ~ {c}")
+    T, it, b = WIDE_RANGE_CONFIG
+    lines.append(f"    {{1u << 28, {{{T}, {it}, {b}, 0}}}},   // wider than the tuning rows")
     body = "\n".join(lines)
     src = f"\n// Source: {source}" if source else ""
     text = f"""// rtcdf_default_table.h -- static default configuration per range class.
