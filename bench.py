@@ -271,6 +271,43 @@ def bench_wide_ranges(torch, rtcdf, inputs, steps):
             "outputs_identical": same, "timing": "warm, HIP events, mean"}
 
 
+def bench_key_widths(torch, rtcdf, steps):
+    """n = 10^8 keys of 16 and 8 bits (rtcdf_sort_keys): the type's whole
+    range and a 2^13-value range for 16-bit keys, uniform, warm, HIP events;
+    the roofline is 2 x key bytes per key at 8 TB/s.  Each output is checked
+    to be nondecreasing with the input's value counts (bincount on the GPU)."""
+    stream = torch.cuda.current_stream()
+    n = 10 ** 8
+    rows, ok = [], True
+    g = torch.Generator(device="cuda")
+    for name, dt, kb, lo, hi in (("int16", torch.int16, 2, -32768, 32768), ("int16", torch.int16, 2, -4096, 4096),
+                                 ("uint16", torch.uint16, 2, 0, 65536), ("int8", torch.int8, 1, -128, 128),
+                                 ("uint8", torch.uint8, 1, 0, 256)):
+        g.manual_seed(hi - lo)
+        w = torch.randint(lo, hi, (n,), generator=g, device="cuda", dtype=torch.int32)
+        a = w.to(torch.int16).view(torch.uint16) if dt == torch.uint16 else w.to(dt)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            rtcdf.sort_keys(a, lo, hi, keys_out=b, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(steps, 10)
+        e0.record(stream)
+        for _ in range(reps):
+            rtcdf.sort_keys(a, lo, hi, keys_out=b, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        wide = (b.view(torch.int16).to(torch.int32) & 0xFFFF) if dt == torch.uint16 else b.to(torch.int32)
+        ok = ok and bool((wide[1:] >= wide[:-1]).all()) and bool(
+            torch.equal(torch.bincount(wide - lo, minlength=hi - lo), torch.bincount(w - lo, minlength=hi - lo)))
+        rows.append({"keys": name, "minVal": lo, "maxVal": hi, "ms": round(ms, 4),
+                     "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 1),
+                     "frac_roofline": round(2 * kb * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)})
+        del w, a, b, wide
+    return {"workload": "n=1e8 uniform 16- and 8-bit keys", "rows": rows, "checked": ok,
+            "timing": "warm, HIP events, mean"}
+
+
 def bench_scale(torch, rtcdf, inputs, steps):
     """n = 10^9 keys, minVal 0, R = 2^18: uniform, all equal (87381) and normal
     (mean 2^17, sd 4096).  Element-by-element parity at this size is checked
@@ -605,7 +642,7 @@ def main():
             f"{batched['speedup_vs_plain_calls']}x plain calls, {batched['speedup_vs_plain_graph']}x "
             f"plain graph; parity {batched['parity']}")
 
-    small = large = methods = wide = None
+    small = large = methods = wide = narrow = None
     if not args.no_extra:
         log("[bench] n=1e6 and n=1e9 timings")
         small = bench_small(torch, rtcdf, inputs, args.steps)
@@ -614,6 +651,10 @@ def main():
         methods = bench_output_methods(torch, rtcdf, inputs, args.steps)
         log(f"[bench] output methods identical: {methods['outputs_identical']}; prefix maximum "
             f"faster at: {methods['prefix_max_faster_at'] or 'none'}")
+        log("[bench] 16- and 8-bit keys")
+        narrow = bench_key_widths(torch, rtcdf, args.steps)
+        log("[bench] key widths: " + ", ".join(f"{r['keys']} [{r['minVal']},{r['maxVal']}) {r['gkeys_per_s']} Gkeys/s"
+                                               for r in narrow["rows"]) + f"; checked: {narrow['checked']}")
         log("[bench] wide ranges: partition by pass")
         wide = bench_wide_ranges(torch, rtcdf, inputs, args.steps)
         log("[bench] wide ranges: " + ", ".join(f"2^{r['R'].bit_length() - 1} {r['dist']} {r['ms']} ms "
@@ -655,6 +696,7 @@ def main():
         "small_n": small,
         "output_methods": methods,
         "wide_ranges": wide,
+        "key_widths": narrow,
         "large_n": large,
     }
     print(json.dumps(rec))

@@ -114,6 +114,28 @@ rtcdf_status_t rtcdf_sort_with_config(const int32_t* keys_in, int32_t* keys_out,
                                       int64_t minVal, int64_t maxVal,
                                       const rtcdf_config_t* cfg, hipStream_t stream);
 
+/* Keys of other widths.  The sort of 16- and 8-bit keys, signed or not: the
+ * histogram reads 16-byte vectors of 8 or 16 keys and widens them, the output
+ * stage writes the keys in their own width.  key_type is one of
+ * rtcdf_key_type_t; keys_in / keys_out are device arrays of n keys of that
+ * type, aligned to its size (they may be equal; partial overlap is
+ * RTCDF_ERROR_OVERLAP); [minVal, maxVal) must lie within the type's values.
+ * cfg as for rtcdf_sort_with_config (NULL = library choice, flags must be 0:
+ * the prefix-maximum output is offered for int32 keys only).  RTCDF_KEY_INT32
+ * is rtcdf_sort_with_config.  Asynchronous on `stream`; argument errors are
+ * returned before any GPU work.  Not in the paper (its keys are 32-bit). */
+typedef enum rtcdf_key_type {
+  RTCDF_KEY_INT32 = 0,
+  RTCDF_KEY_INT16 = 1,
+  RTCDF_KEY_UINT16 = 2,
+  RTCDF_KEY_INT8 = 3,
+  RTCDF_KEY_UINT8 = 4
+} rtcdf_key_type_t;
+
+rtcdf_status_t rtcdf_sort_keys(const void* keys_in, void* keys_out, size_t n, int key_type,
+                               int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,
+                               hipStream_t stream);
+
 /* Checked mode.  The keys lying in [minVal, maxVal) is a precondition of the
  * method (Sec. 2.1) that the sort itself does not test.  These two calls test
  * it, at the price of one more read of the keys (4 B per key):

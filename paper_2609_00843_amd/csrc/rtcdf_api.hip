@@ -98,13 +98,17 @@ static int64_t env_int(const char* name, int64_t dflt) {
 // Derives every launch parameter and the workspace layout.  `out` is only
 // inspected for its alignment.
 void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& cfg,
-               const int32_t* in, const int32_t* out, const DeviceInfo& dev, Plan* p) {
+               const void* in, const void* out, const DeviceInfo& dev, Plan* p, uint32_t kb,
+               uint32_t flip) {
   std::memset(p, 0, sizeof(*p));
   const uint32_t R = (uint32_t)(maxVal - minVal);
   p->n = n;
-  p->min_u = (uint32_t)(int32_t)minVal;
+  p->kb = kb;
+  p->flip = flip;
+  p->min_u = (uint32_t)(uint64_t)(minVal + (int64_t)flip);
   p->R = R;
-  p->items = cfg.items_per_thread;
+  // 8- and 16-bit keys: one 16-byte vector of keys per thread per step
+  p->items = kb == 4 ? cfg.items_per_thread : 4u;
   p->bpt = cfg.blocks_per_tile;
   // Tile geometry (Sec. 3): tiles never need to be wider than the range.
   const uint32_t Rr = (R + 127) & ~127u;
@@ -134,12 +138,13 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   p->hist_block = 1024 / p->bpt;
   p->hist_interleave = (uint32_t)env_int("RTCDF_DEV_HIST_INTERLEAVE", 1);
 
-  // Input body: 16-byte aligned int4 vectors between a scalar head and tail.
+  // Input body: 16-byte aligned vectors (16 / kb keys each) between a scalar
+  // head and tail.
   const uintptr_t ia = reinterpret_cast<uintptr_t>(in);
-  uint64_t head = ((16 - (ia & 15)) & 15) / 4;
+  uint64_t head = ((16 - (ia & 15)) & 15) / kb;
   if (head > n) head = n;
   p->in_head = (uint32_t)head;
-  p->in_n4 = (n - head) / 4;
+  p->in_n4 = (n - head) / (16 / kb);
   // One wave of resident workgroups over all passes; chunks per pass a multiple
   // of 8 so the XCD-aware mapping is a bijection.
   const uint32_t V = p->items / 4;
@@ -169,7 +174,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // RTCDF_DEV_PARTITION = 0 / 1 forces it off / on wherever it applies).
   {
     const int64_t force = env_int("RTCDF_DEV_PARTITION", -1);
-    const bool fits = p->passes >= 2 && p->passes <= kPartMaxBuckets && n <= 0xffffffffull;
+    const bool fits = p->passes >= 2 && p->passes <= kPartMaxBuckets && n <= 0xffffffffull && kb == 4;
     p->part = fits && (force == 1 || (force != 0 && p->passes >= kPartMinPasses &&
                                       (uint64_t)n * p->passes >= kPartMinWork));
     if (p->part) {
@@ -183,9 +188,10 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
 
   p->nred = (R + kReduceBins - 1) / kReduceBins;
 
-  // Output chunks: s(0) = 0, s(k) = out_head + k * chunk.
-  const uintptr_t oa = reinterpret_cast<uintptr_t>(out);
-  p->out_head = (uint32_t)(((16 - (oa & 15)) & 15) / 4);
+  // Output chunks: s(0) = 0, s(k) = out_head + k * chunk; the output body is
+  // written in groups of 4 keys (16, 8 or 4 bytes), aligned to their size.
+  const uintptr_t oa = reinterpret_cast<uintptr_t>(out), ga = 4 * (uintptr_t)kb;
+  p->out_head = (uint32_t)(((ga - (oa & (ga - 1))) & (ga - 1)) / kb);
   const uint32_t gran = 4 * kFillBlock;
   const uint64_t fill_per_cu = (uint64_t)env_int("RTCDF_DEV_FILL_WGS_PER_CU", 4);
   // Chunks of 2048 positions (8 KiB of output): the workgroups interleave
@@ -219,7 +225,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // output workgroup reads rows * stride <= kFastRegionWords words.
   // Prefix-maximum output (Alg. 3) in place of Alg. 7: runs after the staged
   // local-CDF stage, so it never takes the fast path.
-  p->pmax = (cfg.flags & RTCDF_FLAG_OUTPUT_PREFIX_MAX) != 0;
+  p->pmax = (cfg.flags & RTCDF_FLAG_OUTPUT_PREFIX_MAX) != 0 && kb == 4;
   if (p->pmax) {
     const uint32_t h = (uint32_t)std::min<uint64_t>(p->out_head, n);
     p->pm_chunk = n <= kPmaxSmallN ? kPmaxChunkSmall : kPmaxChunkLarge;
@@ -448,17 +454,22 @@ rtcdf_status_t resolve_config(const rtcdf_config_t* cfg, const int32_t* keys_in,
   return pick_config(keys_in, n, minVal, maxVal, stream, out);
 }
 
+// kb / flip: 8- and 16-bit keys (see make_plan); their configuration never
+// takes the prefix-maximum output, and the learned picker (whose sketch
+// reads int32 keys) is not consulted for them.
 static rtcdf_status_t sort_cached(const int32_t* in, int32_t* out, size_t n, int64_t minVal,
                                   int64_t maxVal, const rtcdf_config_t* cfg, hipStream_t s,
-                                  uint32_t* dbg_hist, uint32_t* dbg_cdf, uint32_t* dbg_O) {
+                                  uint32_t* dbg_hist, uint32_t* dbg_cdf, uint32_t* dbg_O,
+                                  uint32_t kb = 4, uint32_t flip = 0) {
   DeviceInfo dev;
   rtcdf_status_t st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;
   rtcdf_config_t c;
-  st = resolve_config(cfg, in, n, minVal, maxVal, s, &c);
+  st = resolve_config(cfg, kb == 4 ? in : nullptr, n, minVal, maxVal, s, &c);
   if (st != RTCDF_SUCCESS) return st;
+  if (kb != 4) c.flags = 0;
   Plan p;
-  make_plan(n, minVal, maxVal, c, in, out ? out : in, dev, &p);
+  make_plan(n, minVal, maxVal, c, in, out ? out : in, dev, &p, kb, flip);
   // The intermediates are only materialised by the staged path.
   if (out == nullptr) p.fast = false;
   std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -495,6 +506,34 @@ rtcdf_status_t rtcdf_sort_with_config(const int32_t* keys_in, int32_t* keys_out,
   if (st != RTCDF_SUCCESS || n == 0) return st;
   if (!config_is_zero(cfg) && !config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
   return sort_cached(keys_in, keys_out, n, minVal, maxVal, cfg, stream, nullptr, nullptr, nullptr);
+}
+
+rtcdf_status_t rtcdf_sort_keys(const void* keys_in, void* keys_out, size_t n, int key_type,
+                               int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,
+                               hipStream_t stream) {
+  uint32_t kb, flip;
+  int64_t lo, hi;   // the key type's values, [lo, hi)
+  switch (key_type) {
+    case RTCDF_KEY_INT32:
+      return rtcdf_sort_with_config(static_cast<const int32_t*>(keys_in), static_cast<int32_t*>(keys_out),
+                                    n, minVal, maxVal, cfg, stream);
+    case RTCDF_KEY_INT16: kb = 2; flip = 0x8000u; lo = -32768; hi = 32768; break;
+    case RTCDF_KEY_UINT16: kb = 2; flip = 0u; lo = 0; hi = 65536; break;
+    case RTCDF_KEY_INT8: kb = 1; flip = 0x80u; lo = -128; hi = 128; break;
+    case RTCDF_KEY_UINT8: kb = 1; flip = 0u; lo = 0; hi = 256; break;
+    default: return RTCDF_ERROR_INVALID_VALUE;
+  }
+  if (maxVal <= minVal || minVal < lo || maxVal > hi) return RTCDF_ERROR_INVALID_VALUE;
+  if ((uint64_t)n > 0xffffffffull) return RTCDF_ERROR_SIZE_TOO_LARGE;
+  if (n == 0) return RTCDF_SUCCESS;
+  if (keys_in == nullptr || keys_out == nullptr) return RTCDF_ERROR_INVALID_VALUE;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(keys_in), b = reinterpret_cast<uintptr_t>(keys_out);
+  if ((a % kb) != 0 || (b % kb) != 0) return RTCDF_ERROR_INVALID_VALUE;
+  const uintptr_t bytes = (uintptr_t)n * kb;
+  if (a != b && a < b + bytes && b < a + bytes) return RTCDF_ERROR_OVERLAP;
+  if (!config_is_zero(cfg) && (!config_valid(*cfg) || cfg->flags != 0)) return RTCDF_ERROR_INVALID_VALUE;
+  return sort_cached(static_cast<const int32_t*>(keys_in), static_cast<int32_t*>(keys_out), n, minVal, maxVal,
+                     cfg, stream, nullptr, nullptr, nullptr, kb, flip);
 }
 
 rtcdf_status_t rtcdf_count_out_of_range(const int32_t* keys, size_t n, int64_t minVal, int64_t maxVal,

@@ -63,7 +63,10 @@ constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpH
 struct Plan {
   // problem
   uint64_t n;
+  uint32_t kb;           // key bytes: 4 (int32), 2 or 1 (16- and 8-bit keys)
+  uint32_t flip;         // narrow keys: bits XORed with each key (its sign bit if signed)
   uint32_t min_u;        // (uint32)minVal; normalised value x = (uint32)key - min_u
+                         // (narrow keys: in the flipped, zero-extended domain)
   uint32_t R;            // range size
   // tile geometry (Sec. 3): m = ceil(R/T), tile t = [tT, tT + w_t)
   uint32_t T, m;
@@ -174,8 +177,11 @@ hipError_t launch_pick(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t
 rtcdf_status_t device_info(DeviceInfo* out);
 rtcdf_status_t hip_fail(hipError_t e);
 bool config_valid(const rtcdf_config_t& c);
+// kb / flip: key width in bytes and the sign-bit flip of narrow signed keys
+// (4 / 0 for int32 keys).  `in` and `out` are only inspected for alignment.
 void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& cfg,
-               const int32_t* in, const int32_t* out, const DeviceInfo& dev, Plan* p);
+               const void* in, const void* out, const DeviceInfo& dev, Plan* p, uint32_t kb = 4,
+               uint32_t flip = 0);
 
 // Configuration source (rtcdf_config.hip): the choice rtcdf_sort makes when the
 // caller gives no config, under the current config mode.

@@ -56,9 +56,51 @@ struct HistArgs {
   // Partition mode (non-null): `keys` is the partitioned copy and pass p reads
   // keys[pbound[p], pbound[p + 1]) (16-byte aligned, whole vectors).
   const uint32_t* pbound;
+  // 8- and 16-bit keys: every key's bits are XORed with `flip` (its sign bit
+  // for signed keys, 0 for unsigned) and zero-extended, which maps the key
+  // order onto the unsigned order; min_u is then in that domain.
+  uint32_t flip;
 };
 
-template <int ITEMS, int BITS, int BLOCK>
+// One 16-byte vector of keys: 4 int32 keys, or 8 / 16 narrow keys widened in
+// groups of four.  Lanes without a valid vector count `outside` (every group,
+// so that the wave-wide ballots inside count4 see every lane).
+template <int BITS, int KB>
+__device__ __forceinline__ void count_vec(uint32_t* S, v4i v, bool valid, v4i outside, uint32_t flip,
+                                          uint32_t base, uint32_t W, uint32_t* carry, uint32_t pass_lo,
+                                          uint32_t* tab, HotBin& hot) {
+  if constexpr (KB == 4) {
+    count4<BITS>(S, valid ? v : outside, base, W, carry, pass_lo, tab, hot);
+  } else if constexpr (KB == 2) {
+    const uint32_t f = flip | (flip << 16);
+    const uint32_t w[4] = {(uint32_t)v.x ^ f, (uint32_t)v.y ^ f, (uint32_t)v.z ^ f, (uint32_t)v.w ^ f};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const v4i g = {(int)(w[2 * h] & 0xffffu), (int)(w[2 * h] >> 16), (int)(w[2 * h + 1] & 0xffffu),
+                     (int)(w[2 * h + 1] >> 16)};
+      count4<BITS>(S, valid ? g : outside, base, W, carry, pass_lo, tab, hot);
+    }
+  } else {
+    const uint32_t f = flip * 0x01010101u;
+    const uint32_t w[4] = {(uint32_t)v.x ^ f, (uint32_t)v.y ^ f, (uint32_t)v.z ^ f, (uint32_t)v.w ^ f};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const v4i g = {(int)(w[h] & 0xffu), (int)((w[h] >> 8) & 0xffu), (int)((w[h] >> 16) & 0xffu),
+                     (int)(w[h] >> 24)};
+      count4<BITS>(S, valid ? g : outside, base, W, carry, pass_lo, tab, hot);
+    }
+  }
+}
+
+// Key i of a scalar head or tail, widened as in count_vec.
+template <int KB>
+__device__ __forceinline__ int32_t load_key(const int32_t* keys, size_t i, uint32_t flip) {
+  if constexpr (KB == 4) return keys[i];
+  else if constexpr (KB == 2) return (int32_t)(reinterpret_cast<const uint16_t*>(keys)[i] ^ flip);
+  else return (int32_t)(reinterpret_cast<const uint8_t*>(keys)[i] ^ flip);
+}
+
+template <int ITEMS, int BITS, int BLOCK, int KB = 4>
 __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   // The planner's LDS budget: kLdsBytes per 1024 threads (one workgroup per
   // compute unit at 1024 threads, two at 512, four at 256).  A static array
@@ -95,7 +137,8 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   }
 
   constexpr int V = ITEMS / 4;
-  const v4i* body = reinterpret_cast<const v4i*>(keys + in_head);
+  constexpr uint32_t VK = 16 / KB;   // keys per 16-byte vector
+  const v4i* body = reinterpret_cast<const v4i*>(reinterpret_cast<const uint8_t*>(keys) + (size_t)in_head * KB);
   const v4i outside = (v4i)(int)(base - 1u);   // lands outside every pass
   HotBin hot;                                  // narrow forms only
   uint32_t t0, step, end;
@@ -130,11 +173,13 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
       for (int j = 0; j < V; ++j) nxt[j] = __builtin_nontemporal_load(&body[min(t1 + j * BLOCK, last)]);
       if (tb + V * BLOCK <= end) {
 #pragma unroll
-        for (int j = 0; j < V; ++j) count4<BITS>(S, cur[j], base, W, a.carry, pass_lo, tab, hot);
+        for (int j = 0; j < V; ++j)
+          count_vec<BITS, KB>(S, cur[j], true, outside, a.flip, base, W, a.carry, pass_lo, tab, hot);
       } else {
 #pragma unroll
         for (int j = 0; j < V; ++j)
-          count4<BITS>(S, t0 + j * BLOCK < end ? cur[j] : outside, base, W, a.carry, pass_lo, tab, hot);
+          count_vec<BITS, KB>(S, cur[j], t0 + j * BLOCK < end, outside, a.flip, base, W, a.carry, pass_lo,
+                              tab, hot);
       }
 #pragma unroll
       for (int j = 0; j < V; ++j) cur[j] = nxt[j];
@@ -142,10 +187,11 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
       tb += step;
     }
   }
-  // scalar head and tail keys (at most 3 each), counted by chunk 0 / chunk G-1
+  // scalar head and tail keys (at most VK - 1 each), counted by chunk 0 / chunk G-1
   v4i e = outside;
-  if (chunk == 0 && threadIdx.x < in_head) e.x = keys[threadIdx.x];
-  if (chunk == a.G - 1 && threadIdx.x < in_tail) e.y = keys[in_head + 4 * (size_t)in_n4 + threadIdx.x];
+  if (chunk == 0 && threadIdx.x < in_head) e.x = load_key<KB>(keys, threadIdx.x, a.flip);
+  if (chunk == a.G - 1 && threadIdx.x < in_tail)
+    e.y = load_key<KB>(keys, in_head + VK * (size_t)in_n4 + threadIdx.x, a.flip);
   if (threadIdx.x < 64) count4<BITS>(S, e, base, W, a.carry, pass_lo, tab, hot);
   if constexpr (BITS < 32) hot_flush(hot, tab, a.carry, pass_lo);
   __syncthreads();
@@ -504,7 +550,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
 // --------------------------------------------------------------------- output
 
 struct FillArgs {
-  int32_t* out;
+  void* out;              // int32 keys, or 16- / 8-bit keys (kb in the plan)
   const uint32_t* cdf;    // local CDFs
   const uint32_t* O;
   const uint32_t* split;
@@ -512,7 +558,38 @@ struct FillArgs {
   uint32_t min_u, R, T, out_head, chunk, nchunks;
   uint64_t body_lo, body_hi;   // positions [body_lo, body_hi) are 16-byte aligned int4s
   const uint32_t* flags;       // [0]: some chunk is sparse (local-CDF stage)
+  uint32_t flip;               // narrow keys: stored bits = value ^ flip
 };
+
+// Four consecutive outputs (group i of the aligned body, 16 / 8 / 4 bytes)
+// and single outputs, in the key width KB.
+template <int KB>
+__device__ __forceinline__ void store_group(const FillArgs& a, uint64_t i, v4i o) {
+  if constexpr (KB == 4) {
+    v4i* body = reinterpret_cast<v4i*>(static_cast<int32_t*>(a.out) + a.body_lo);
+    __builtin_nontemporal_store(o, &body[i]);
+  } else if constexpr (KB == 2) {
+    typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+    const uint32_t f = a.flip;
+    const v2u w = {(((uint32_t)o.x ^ f) & 0xffffu) | (((uint32_t)o.y ^ f) << 16),
+                   (((uint32_t)o.z ^ f) & 0xffffu) | (((uint32_t)o.w ^ f) << 16)};
+    v2u* body = reinterpret_cast<v2u*>(static_cast<uint16_t*>(a.out) + a.body_lo);
+    __builtin_nontemporal_store(w, &body[i]);
+  } else {
+    const uint32_t f = a.flip;
+    const uint32_t w = (((uint32_t)o.x ^ f) & 0xffu) | ((((uint32_t)o.y ^ f) & 0xffu) << 8) |
+                       ((((uint32_t)o.z ^ f) & 0xffu) << 16) | (((uint32_t)o.w ^ f) << 24);
+    uint32_t* body = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(a.out) + a.body_lo);
+    __builtin_nontemporal_store(w, &body[i]);
+  }
+}
+
+template <int KB>
+__device__ __forceinline__ void store_one(const FillArgs& a, uint64_t p, int32_t v) {
+  if constexpr (KB == 4) static_cast<int32_t*>(a.out)[p] = v;
+  else if constexpr (KB == 2) static_cast<uint16_t*>(a.out)[p] = (uint16_t)((uint32_t)v ^ a.flip);
+  else static_cast<uint8_t*>(a.out)[p] = (uint8_t)((uint32_t)v ^ a.flip);
+}
 
 // Inclusive cumulative count of value v over the whole range: O[t] + C_t[x].
 __device__ __forceinline__ uint32_t cum_incl(const FillArgs& a, uint32_t v) {
@@ -539,14 +616,13 @@ __device__ __forceinline__ uint64_t chunk_start(const FillArgs& a, uint32_t k) {
 // Writes the positions [p0, p1) of one chunk whose values lie in [v0, v0 + nwin)
 // and whose inclusive cumulative counts are in win[0, nwin).  SPARSE selects
 // the form for windows of many values per step (see below).
-template <bool SPARSE>
+template <bool SPARSE, int KB>
 __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* win, uint32_t nwin,
                                            uint32_t v0, uint64_t p0, uint64_t p1, bool first,
                                            bool final, uint32_t* stage) {
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint64_t q_lo = p0 > a.body_lo ? p0 : a.body_lo;
   const uint64_t q_hi = p1 < a.body_hi ? p1 : a.body_hi;
-  v4i* body = reinterpret_cast<v4i*>(a.out + a.body_lo);
   const uint64_t i_lo = (q_lo - a.body_lo) >> 2, i_hi = q_hi > q_lo ? (q_hi - a.body_lo) >> 2 : i_lo;
   const int32_t base = (int32_t)(a.min_u + v0);
   const uint32_t last = nwin - 1;
@@ -623,23 +699,24 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
         o.w = base + (int32_t)(xw + c3);
       }
     }
-    if (i < i_hi) __builtin_nontemporal_store(o, &body[i]);
+    if (i < i_hi) store_group<KB>(a, i, o);
   }
   // scalar head (positions before the aligned body) and tail
   if (first)
     for (uint64_t p = tid; p < a.body_lo; p += kFillBlock)
-      a.out[p] = base + (int32_t)min(count_le(win, nwin, (uint32_t)p), last);
+      store_one<KB>(a, p, base + (int32_t)min(count_le(win, nwin, (uint32_t)p), last));
   if (final)
     for (uint64_t p = a.body_hi + tid; p < a.n; p += kFillBlock)
-      a.out[p] = base + (int32_t)min(count_le(win, nwin, (uint32_t)p), last);
+      store_one<KB>(a, p, base + (int32_t)min(count_le(win, nwin, (uint32_t)p), last));
 }
 
 // Chunk of positions whose window does not fit in LDS (very sparse values):
 // every position searches the cumulative counts in global memory.
+template <int KB>
 __device__ void fill_chunk_global(const FillArgs& a, uint32_t v0, uint32_t v1, uint64_t p0,
                                   uint64_t p1) {
   for (uint64_t p = p0 + threadIdx.x; p < p1; p += kFillBlock)
-    a.out[p] = (int32_t)(a.min_u + value_at_global(a, v0, v1, (uint32_t)p));
+    store_one<KB>(a, p, (int32_t)(a.min_u + value_at_global(a, v0, v1, (uint32_t)p)));
 }
 
 // Splitters of chunk k, clamped: they are always in [0, R) for keys inside
@@ -663,7 +740,7 @@ __device__ __forceinline__ void chunk_values(const FillArgs& a, uint32_t k, uint
 // 2: per chunk, the sparse form where the window holds more than one value
 // per 64 positions (a sort whose keys leave stretches of the range nearly
 // empty, such as the tails of a narrow normal distribution).
-template <int MODE>
+template <int MODE, int KB>
 __device__ __forceinline__ void fill_loop(const FillArgs& a, uint32_t (*win)[kFillWindow],
                                           uint32_t* stage) {
   const uint32_t tid = threadIdx.x, G = gridDim.x;
@@ -688,11 +765,11 @@ __device__ __forceinline__ void fill_loop(const FillArgs& a, uint32_t (*win)[kFi
     const uint64_t p0 = chunk_start(a, k);
     const uint64_t p1 = k + 1 < a.nchunks ? chunk_start(a, k + 1) : a.n;
     if (nwin > kFillWindow)
-      fill_chunk_global(a, v0, v0 + nwin - 1, p0, p1);
+      fill_chunk_global<KB>(a, v0, v0 + nwin - 1, p0, p1);
     else if (MODE == 1 || (MODE == 2 && (uint64_t)nwin * 64 > p1 - p0))
-      fill_chunk<true>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
+      fill_chunk<true, KB>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
     else
-      fill_chunk<false>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
+      fill_chunk<false, KB>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
     if (!more) break;
 
     // hand over to chunk k + G
@@ -713,14 +790,14 @@ __device__ __forceinline__ void fill_loop(const FillArgs& a, uint32_t (*win)[kFi
 // SPARSE: the sort's keys average under 64 per value, so every chunk takes the
 // sparse form.  Otherwise the dense form, unless the local-CDF stage flagged a
 // sparse chunk, in which case each chunk takes the form its window calls for.
-template <bool SPARSE>
+template <bool SPARSE, int KB = 4>
 __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
   __shared__ uint32_t win[2][kFillWindow];
   __shared__ __align__(16) uint32_t stage[kFillBlock / 64 * 256];   // per wave (sparse steps)
   if (blockIdx.x >= a.nchunks) return;
-  if (SPARSE) fill_loop<1>(a, win, stage);
-  else if (a.flags[0] == 0u) fill_loop<0>(a, win, stage);
-  else fill_loop<2>(a, win, stage);
+  if (SPARSE) fill_loop<1, KB>(a, win, stage);
+  else if (a.flags[0] == 0u) fill_loop<0, KB>(a, win, stage);
+  else fill_loop<2, KB>(a, win, stage);
 }
 
 // Output stage of the single-tile fast path (R <= kFastMaxRange, one LDS pass
@@ -747,7 +824,7 @@ __device__ __forceinline__ void count_le2(const uint32_t* C, uint32_t len, uint3
   *r1 = b;
 }
 
-template <bool SPARSE>
+template <bool SPARSE, int KB = 4>
 __global__ __launch_bounds__(kFillBlock) void k_fill_small(FillArgs a, uint32_t* area, uint32_t rows,
                                                            uint32_t stride) {
   __shared__ __align__(16) uint32_t C[kFastMaxRange];
@@ -816,9 +893,9 @@ __global__ __launch_bounds__(kFillBlock) void k_fill_small(FillArgs a, uint32_t*
       const uint32_t v0 = __builtin_amdgcn_readfirstlane(v_lo[j]);
       const uint32_t nwin = __builtin_amdgcn_readfirstlane(v_hi[j]) - v0 + 1;
       if (SPARSE || (uint64_t)nwin * 64 > p1 - p0)   // as the per-chunk mode of fill_loop
-        fill_chunk<true>(a, C + v0, nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
+        fill_chunk<true, KB>(a, C + v0, nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
       else
-        fill_chunk<false>(a, C + v0, nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
+        fill_chunk<false, KB>(a, C + v0, nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
       // Every wave waits for its stores, then the workgroup meets, once per
       // chunk.  A loop of bare stores lets the oldest workgroups on a compute
       // unit take the store path (the youngest ended ~30 us after the oldest
@@ -845,17 +922,20 @@ __global__ void k_clear(uint32_t* p, size_t words) {
     p[i] = 0u;
 }
 
-template <int ITEMS, int BITS, int BLOCK>
+template <int ITEMS, int BITS, int BLOCK, int KB = 4>
 hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
   // the counters (and the narrow forms' wrap table) fit the static LDS array
   const size_t lds = ((size_t)p.row_words + (BITS < 32 ? 2 * kWrapSlots : 0)) * 4;
   if (lds > kLdsBytes / (1024 / BLOCK)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_hist<ITEMS, BITS, BLOCK>), dim3(p.passes * p.G), dim3(BLOCK), 0, s, a);
+  hipLaunchKernelGGL((k_hist<ITEMS, BITS, BLOCK, KB>), dim3(p.passes * p.G), dim3(BLOCK), 0, s, a);
   return hipGetLastError();
 }
 
 template <int BITS, int BLOCK>
 hipError_t launch_hist_items(const Plan& p, const HistArgs& a, hipStream_t s) {
+  // 8- and 16-bit keys: one 16-byte vector (16 or 8 keys) per thread per step
+  if (p.kb == 2) return launch_hist_t<4, BITS, BLOCK, 2>(p, a, s);
+  if (p.kb == 1) return launch_hist_t<4, BITS, BLOCK, 1>(p, a, s);
   switch (p.items) {
     case 4: return launch_hist_t<4, BITS, BLOCK>(p, a, s);
     case 8: return launch_hist_t<8, BITS, BLOCK>(p, a, s);
@@ -900,7 +980,9 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
   a.in_n4 = (uint32_t)p.in_n4;     // n < 2^32: at most 2^30 vectors
   a.in_per = (uint32_t)p.in_per;
   a.in_head = p.in_head;
-  a.in_tail = (uint32_t)(p.n - p.in_head - 4 * p.in_n4);
+  if (p.kb != 4 && p.kb != 2 && p.kb != 1) return hipErrorInvalidValue;
+  a.in_tail = (uint32_t)(p.n - p.in_head - (16 / p.kb) * p.in_n4);
+  a.flip = p.flip;
   a.min_u = p.min_u;
   a.W = p.W;
   a.passes = p.passes;
@@ -914,7 +996,7 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
   a.merge_stride = p.fast_stride;
   a.pbound = nullptr;
   if (p.part) {
-    if (p.fast || p.off_pkeys % 16 != 0) return hipErrorInvalidValue;
+    if (p.fast || p.off_pkeys % 16 != 0 || p.kb != 4) return hipErrorInvalidValue;
     a.keys = reinterpret_cast<const int32_t*>(ws + p.off_pkeys);
     a.pbound = reinterpret_cast<const uint32_t*>(ws + p.off_pbound);
   }
@@ -1015,12 +1097,27 @@ hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
   a.body_hi = a.body_lo + 4 * ((p.n - a.body_lo) / 4);
   a.flags = reinterpret_cast<const uint32_t*>(ws + p.off_flags);
+  a.flip = p.flip;
   // The sparse form (look-ahead and bisection in the window) when the values
   // average fewer than 64 output positions each; the plain walk otherwise.
-  if (p.n < (uint64_t)64 * p.R)
-    hipLaunchKernelGGL(k_fill<true>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_fill<false>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a);
+  const bool sparse = p.n < (uint64_t)64 * p.R;
+  const dim3 grid(p.fill_grid), block(kFillBlock);
+  switch (p.kb) {
+    case 4:
+      if (sparse) hipLaunchKernelGGL((k_fill<true, 4>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_fill<false, 4>), grid, block, 0, s, a);
+      break;
+    case 2:
+      if (sparse) hipLaunchKernelGGL((k_fill<true, 2>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_fill<false, 2>), grid, block, 0, s, a);
+      break;
+    case 1:
+      if (sparse) hipLaunchKernelGGL((k_fill<true, 1>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_fill<false, 1>), grid, block, 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1039,12 +1136,26 @@ hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStre
   a.nchunks = p.nchunks;
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
   a.body_hi = a.body_lo + 4 * ((p.n - a.body_lo) / 4);
-  if (p.n < (uint64_t)64 * p.R)
-    hipLaunchKernelGGL(k_fill_small<true>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a, area,
-                       p.fast_rows, p.fast_stride);
-  else
-    hipLaunchKernelGGL(k_fill_small<false>, dim3(p.fill_grid), dim3(kFillBlock), 0, s, a, area,
-                       p.fast_rows, p.fast_stride);
+  a.flip = p.flip;
+  const bool sparse = p.n < (uint64_t)64 * p.R;
+  const dim3 grid(p.fill_grid), block(kFillBlock);
+  const uint32_t rows = p.fast_rows, stride = p.fast_stride;
+  switch (p.kb) {
+    case 4:
+      if (sparse) hipLaunchKernelGGL((k_fill_small<true, 4>), grid, block, 0, s, a, area, rows, stride);
+      else hipLaunchKernelGGL((k_fill_small<false, 4>), grid, block, 0, s, a, area, rows, stride);
+      break;
+    case 2:
+      if (sparse) hipLaunchKernelGGL((k_fill_small<true, 2>), grid, block, 0, s, a, area, rows, stride);
+      else hipLaunchKernelGGL((k_fill_small<false, 2>), grid, block, 0, s, a, area, rows, stride);
+      break;
+    case 1:
+      if (sparse) hipLaunchKernelGGL((k_fill_small<true, 1>), grid, block, 0, s, a, area, rows, stride);
+      else hipLaunchKernelGGL((k_fill_small<false, 1>), grid, block, 0, s, a, area, rows, stride);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

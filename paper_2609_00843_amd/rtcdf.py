@@ -115,6 +115,7 @@ _SIGS = {
     "rtcdf_stream_copy": [_vp, _vp, _sz, _vp],
     "rtcdf_count_out_of_range": [_vp, _sz, _i64, _i64, _vp, _vp],
     "rtcdf_sort_checked": [_vp, _vp, _sz, _i64, _i64, _cfgp, _vp],
+    "rtcdf_sort_keys": [_vp, _vp, _sz, ctypes.c_int, _i64, _i64, _cfgp, _vp],
 }
 for _name, _args in _SIGS.items():
     if hasattr(lib, _name):
@@ -174,6 +175,37 @@ def sort(keys_in, minVal: int, maxVal: int, keys_out=None, config: Config | None
         st = lib.rtcdf_sort_with_config(_ptr(keys_in), _ptr(keys_out), keys_in.numel(),
                                         int(minVal), int(maxVal), ctypes.byref(config), s)
     _check(st, "rtcdf_sort")
+    return keys_out
+
+
+# rtcdf_key_type_t
+KEY_INT32, KEY_INT16, KEY_UINT16, KEY_INT8, KEY_UINT8 = 0, 1, 2, 3, 4
+
+
+def _key_type(t):
+    import torch
+    types = {torch.int32: KEY_INT32, torch.int16: KEY_INT16, torch.int8: KEY_INT8, torch.uint8: KEY_UINT8}
+    if hasattr(torch, "uint16"):
+        types[torch.uint16] = KEY_UINT16
+    if t.dtype not in types or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("keys must be a contiguous CUDA tensor of int32, int16, uint16, int8 or uint8")
+    return types[t.dtype]
+
+
+def sort_keys(keys_in, minVal: int, maxVal: int, keys_out=None, config: Config | None = None,
+              stream=None):
+    """Sort int32, int16, uint16, int8 or uint8 keys in [minVal, maxVal) into
+    keys_out (same dtype; allocated if None).  Asynchronous on `stream`."""
+    import torch
+    kt = _key_type(keys_in)
+    if keys_out is None:
+        keys_out = torch.empty_like(keys_in)
+    if keys_out.dtype != keys_in.dtype or keys_out.numel() != keys_in.numel():
+        raise ValueError("keys_out must match keys_in in dtype and size")
+    _key_type(keys_out)
+    st = lib.rtcdf_sort_keys(_ptr(keys_in), _ptr(keys_out), keys_in.numel(), kt, int(minVal), int(maxVal),
+                             ctypes.byref(config) if config is not None else None, _stream_ptr(stream))
+    _check(st, "rtcdf_sort_keys")
     return keys_out
 
 

@@ -134,3 +134,30 @@ def test_output_flag_matches_header(r):
     txt = open(os.path.join(ROOT, "include", "rtcdf.h")).read()
     m = re.search(r"#define\s+RTCDF_FLAG_OUTPUT_PREFIX_MAX\s+(\d+)u", txt)
     assert m and int(m.group(1)) == r.FLAG_OUTPUT_PREFIX_MAX
+
+
+def test_sort_keys_argument_errors(r):
+    """rtcdf_sort_keys rejects bad key types, ranges outside the type, bad
+    pointers and configurations before any GPU work."""
+    L, c_in, c_out = r.lib, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
+    sk = lambda kt, lo, hi, n=10, a=c_in, b=c_out, cfg=None: L.rtcdf_sort_keys(a, b, n, kt, lo, hi, cfg, None)
+    assert sk(7, 0, 10) == r.INVALID_VALUE
+    assert sk(-1, 0, 10) == r.INVALID_VALUE
+    assert sk(r.KEY_INT16, -32769, 0) == r.INVALID_VALUE
+    assert sk(r.KEY_INT16, 0, 32769) == r.INVALID_VALUE
+    assert sk(r.KEY_UINT16, -1, 5) == r.INVALID_VALUE
+    assert sk(r.KEY_UINT16, 0, 65537) == r.INVALID_VALUE
+    assert sk(r.KEY_INT8, -129, 0) == r.INVALID_VALUE
+    assert sk(r.KEY_UINT8, 0, 257) == r.INVALID_VALUE
+    assert sk(r.KEY_UINT8, 5, 5) == r.INVALID_VALUE
+    assert sk(r.KEY_INT16, -32768, 32768, n=1 << 32) == r.SIZE_TOO_LARGE
+    assert sk(r.KEY_INT16, -32768, 32768, n=0) == r.SUCCESS                  # no-op
+    assert sk(r.KEY_INT16, 0, 10, a=None) == r.INVALID_VALUE
+    assert sk(r.KEY_INT16, 0, 10, a=ctypes.c_void_p((1 << 20) + 1)) == r.INVALID_VALUE   # odd address
+    assert sk(r.KEY_UINT8, 0, 10, b=ctypes.c_void_p((1 << 20) + 5)) == r.OVERLAP
+    assert sk(r.KEY_INT16, 0, 10, b=ctypes.c_void_p((1 << 20) - 4)) == r.OVERLAP
+    pm = r.make_config(1024, 16, 1, flags=r.FLAG_OUTPUT_PREFIX_MAX)
+    assert sk(r.KEY_INT16, 0, 10, cfg=ctypes.byref(pm)) == r.INVALID_VALUE
+    bad = r.Config(100, 16, 1, 0)
+    assert sk(r.KEY_UINT8, 0, 10, cfg=ctypes.byref(bad)) == r.INVALID_VALUE
+    assert sk(r.KEY_INT32, 0, 10, n=1 << 32) == r.SIZE_TOO_LARGE             # the int32 entry's checks

@@ -1,0 +1,120 @@
+"""GPU parity of the sort of 16- and 8-bit keys (rtcdf_sort_keys) against the
+CPU oracle, which sorts the same keys widened to int32: ragged n with every
+input/output misalignment within a 16-byte vector, full and partial ranges
+(single-tile fast path and staged path), four distributions, in place,
+several configurations, and 10^8 keys checked by the streaming verifier."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_00843_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TYPES = {"int16": (np.int16, -32768, 32768), "uint16": (np.uint16, 0, 65536),
+         "int8": (np.int8, -128, 128), "uint8": (np.uint8, 0, 256)}
+_VIEW = {np.uint16: (np.int16, "uint16")}
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def r():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_00843_amd import rtcdf
+    return rtcdf
+
+
+def _tdtype(npt):
+    return {np.int16: torch.int16, np.uint16: torch.uint16, np.int8: torch.int8, np.uint8: torch.uint8}[npt]
+
+
+def _to_dev(A, npt, pad, fill):
+    """Device buffer with A at element offset `pad`, the rest `fill`."""
+    buf = np.full(A.size + pad + 16, fill, dtype=npt)
+    buf[pad:pad + A.size] = A
+    if npt is np.uint16:
+        t = torch.from_numpy(buf.view(np.int16)).cuda().view(torch.uint16)
+    else:
+        t = torch.from_numpy(buf).cuda()
+    return t, t[pad:pad + A.size]
+
+
+def _to_host(t, npt):
+    if npt is np.uint16:
+        return t.view(torch.int16).cpu().numpy().view(np.uint16)
+    return t.cpu().numpy()
+
+
+def _check(r, A, npt, lo, hi, pin=0, pout=0, inplace=False, cfg=None):
+    _say(f"keys {npt.__name__} n={A.size} [{lo},{hi}) pin={pin} pout={pout} inplace={inplace} cfg={cfg}")
+    want = oracle.sort(A.astype(np.int32), lo, hi).astype(npt)
+    bin_, tin = _to_dev(A, npt, pin, 7)
+    if inplace:
+        r.sort_keys(tin, lo, hi, keys_out=tin, config=cfg)
+        torch.cuda.synchronize()
+        assert np.array_equal(_to_host(tin, npt), want)
+        return
+    bout, tout = _to_dev(np.zeros(A.size, dtype=npt), npt, pout, 0x5A)
+    r.sort_keys(tin, lo, hi, keys_out=tout, config=cfg)
+    torch.cuda.synchronize()
+    got = _to_host(tout, npt)
+    assert np.array_equal(got, want), f"mismatch at {np.flatnonzero(got != want)[:8]}"
+    full = _to_host(bout, npt)
+    guard = np.array(0x5A, dtype=npt)
+    assert np.all(full[:pout] == guard) and np.all(full[pout + A.size:] == guard)
+    assert np.array_equal(_to_host(tin, npt), A)
+
+
+@pytest.mark.parametrize("name", list(TYPES))
+def test_ragged_and_misaligned(r, name):
+    npt, tlo, thi = TYPES[name]
+    rng = np.random.default_rng(len(name))
+    for i, n in enumerate((1, 2, 3, 7, 15, 16, 17, 33, 1023, 4099, 65537, 300001)):
+        for lo, hi in ((tlo, thi), (tlo + 3, tlo + 3 + min(200, thi - tlo - 3)), (thi - 1, thi)):
+            A = rng.integers(lo, hi, size=n).astype(npt)
+            _check(r, A, npt, lo, hi, pin=i % 16, pout=(3 * i + 5) % 16)
+
+
+@pytest.mark.parametrize("name", list(TYPES))
+@pytest.mark.parametrize("dist", ["uniform", "normal", "all_equal", "zipf"])
+def test_distributions(r, name, dist):
+    npt, tlo, thi = TYPES[name]
+    A = (inputs.make(dist, 2_000_003, 0, thi - tlo, 17).astype(np.int64) + tlo).astype(npt)
+    _check(r, A, npt, tlo, thi, pout=1)
+
+
+@pytest.mark.parametrize("name", ["int16", "uint8"])
+def test_in_place_and_configs(r, name):
+    npt, tlo, thi = TYPES[name]
+    rng = np.random.default_rng(5)
+    A = rng.integers(tlo, thi, size=500_001).astype(npt)
+    _check(r, A, npt, tlo, thi, inplace=True)
+    for T, items, bpt in ((128, 4, 4), (1024, 8, 2), (8192, 16, 1), (32768, 4, 1)):
+        _check(r, A, npt, tlo, thi, cfg=r.make_config(T, items, bpt), pin=2, pout=3)
+
+
+@pytest.mark.parametrize("name", ["int16", "uint8"])
+def test_full_size(r, name):
+    """10^8 keys over the type's whole range, compared with the oracle's counts."""
+    npt, tlo, thi = TYPES[name]
+    n = 10 ** 8
+    rng = np.random.default_rng(9)
+    A = rng.integers(tlo, thi, size=n).astype(npt)
+    _say(f"keys full size {name}")
+    tin = torch.from_numpy(A).cuda()
+    out = r.sort_keys(tin, tlo, thi)
+    torch.cuda.synchronize()
+    cnt = oracle.counts(A.astype(np.int32), tlo, thi)
+    v = oracle.StreamingVerifier(cnt, tlo)
+    for i in range(0, n, 1 << 25):
+        v.chunk(out[i:i + (1 << 25)].cpu().numpy().astype(np.int32))
+    v.end(n)
