@@ -308,6 +308,45 @@ def bench_key_widths(torch, rtcdf, steps):
             "timing": "warm, HIP events, mean"}
 
 
+def profile_key_widths(torch, rtcdf, steps, warmup):
+    """Profiling mode: the whole-range 16- and 8-bit arrays of bench_key_widths,
+    each sorted once per step."""
+    n = 10 ** 8
+    g = torch.Generator(device="cuda")
+    arrays = []
+    for dt, lo, hi in ((torch.int16, -32768, 32768), (torch.uint16, 0, 65536), (torch.int8, -128, 128),
+                       (torch.uint8, 0, 256)):
+        g.manual_seed(hi - lo)
+        w = torch.randint(lo, hi, (n,), generator=g, device="cuda", dtype=torch.int32)
+        a = w.to(torch.int16).view(torch.uint16) if dt == torch.uint16 else w.to(dt)
+        arrays.append((a, torch.empty_like(a), lo, hi))
+        del w
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for a, b, lo, hi in arrays:
+            rtcdf.sort_keys(a, lo, hi, keys_out=b, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    log(f"[bench] key widths: {ms:.4f} ms per step of {len(arrays)} arrays")
+    # the copy reference of the counter calibration (4 x 10^8 bytes)
+    src = torch.empty(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(steps):
+        rtcdf.stream_copy(src, dst, stream=stream)
+    torch.cuda.synchronize()
+    print(json.dumps({"ms_per_step": ms, "keys_per_step": n * len(arrays)}))
+
+
 def bench_scale(torch, rtcdf, inputs, steps):
     """n = 10^9 keys, minVal 0, R = 2^18: uniform, all equal (87381) and normal
     (mean 2^17, sd 4096).  Element-by-element parity at this size is checked
@@ -398,6 +437,9 @@ def main():
     ap.add_argument("--wide-ranges", action="store_true",
                     help="with --profile-only: sort n = 10^8 uniform keys over R = 2^20, 2^22 and 2^24 "
                          "(the partition by pass) instead of the range sweep")
+    ap.add_argument("--key-widths", action="store_true",
+                    help="with --profile-only: sort n = 10^8 uniform int16, uint16, int8 and uint8 keys "
+                         "over their whole ranges instead of the range sweep")
     ap.add_argument("--output-method", choices=("search", "prefix_max"), default="search",
                     help="with --profile-only: sort with the prefix-maximum output (Alg. 3) instead "
                          "of the local-CDF search (Alg. 7)")
@@ -406,6 +448,8 @@ def main():
         ap.error("--output-method prefix_max is a profiling mode; it needs --profile-only")
     if args.wide_ranges and not args.profile_only:
         ap.error("--wide-ranges is a profiling mode; it needs --profile-only")
+    if args.key_widths and not args.profile_only:
+        ap.error("--key-widths is a profiling mode; it needs --profile-only")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
               f"(the sort would shard by one 4R-byte histogram all-reduce)", file=sys.stderr)
@@ -415,6 +459,9 @@ def main():
     import torch
     from paper_2609_00843_amd import inputs, rtcdf
 
+    if args.key_widths:
+        profile_key_widths(torch, rtcdf, args.steps, args.warmup)
+        return
     cases = [(lr, d) for lr in LOG_R for d in DISTS]
     if args.wide_ranges:
         cases = [(lr, "uniform") for lr in WIDE_LOG_R]
