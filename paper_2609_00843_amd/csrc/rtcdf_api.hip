@@ -188,10 +188,10 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
 
   p->nred = (R + kReduceBins - 1) / kReduceBins;
 
-  // Output chunks: s(0) = 0, s(k) = out_head + k * chunk; the output body is
-  // written in groups of 4 keys (16, 8 or 4 bytes), aligned to their size.
-  const uintptr_t oa = reinterpret_cast<uintptr_t>(out), ga = 4 * (uintptr_t)kb;
-  p->out_head = (uint32_t)(((ga - (oa & (ga - 1))) & (ga - 1)) / kb);
+  // Output chunks: s(0) = 0, s(k) = out_head + k * chunk; the output body
+  // starts on a 16-byte boundary (keys_out is aligned to the key size).
+  const uintptr_t oa = reinterpret_cast<uintptr_t>(out);
+  p->out_head = (uint32_t)(((16 - (oa & 15)) & 15) / kb);
   const uint32_t gran = 4 * kFillBlock;
   const uint64_t fill_per_cu = (uint64_t)env_int("RTCDF_DEV_FILL_WGS_PER_CU", 4);
   // Chunks of 2048 positions (8 KiB of output): the workgroups interleave

@@ -584,6 +584,27 @@ __device__ __forceinline__ void store_group(const FillArgs& a, uint64_t i, v4i o
   }
 }
 
+// 16 / KB consecutive narrow outputs (one 16-byte vector, index i of the
+// aligned body in units of 16 bytes): the dense form's step for 8- and
+// 16-bit keys.
+template <int KB>
+__device__ __forceinline__ void store_vec16(const FillArgs& a, uint64_t i, const int32_t* o) {
+  const uint32_t f = a.flip;
+  uint32_t w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if constexpr (KB == 2) {
+      w[q] = (((uint32_t)o[2 * q] ^ f) & 0xffffu) | (((uint32_t)o[2 * q + 1] ^ f) << 16);
+    } else {
+      w[q] = (((uint32_t)o[4 * q] ^ f) & 0xffu) | ((((uint32_t)o[4 * q + 1] ^ f) & 0xffu) << 8) |
+             ((((uint32_t)o[4 * q + 2] ^ f) & 0xffu) << 16) | (((uint32_t)o[4 * q + 3] ^ f) << 24);
+    }
+  }
+  const v4u v = {w[0], w[1], w[2], w[3]};
+  v4u* body = reinterpret_cast<v4u*>(static_cast<uint8_t*>(a.out) + a.body_lo * KB);
+  __builtin_nontemporal_store(v, &body[i]);
+}
+
 template <int KB>
 __device__ __forceinline__ void store_one(const FillArgs& a, uint64_t p, int32_t v) {
   if constexpr (KB == 4) static_cast<int32_t*>(a.out)[p] = v;
@@ -616,10 +637,63 @@ __device__ __forceinline__ uint64_t chunk_start(const FillArgs& a, uint32_t k) {
 // Writes the positions [p0, p1) of one chunk whose values lie in [v0, v0 + nwin)
 // and whose inclusive cumulative counts are in win[0, nwin).  SPARSE selects
 // the form for windows of many values per step (see below).
+// The dense form for 16- and 8-bit keys: every lane writes 16 / KB positions
+// (one 16-byte vector) per step, so a wave's step covers 512 or 1024
+// positions; the walk is fill_chunk's dense walk (below) with that step.
+template <int KB>
+__device__ __forceinline__ void fill_chunk_wide(const FillArgs& a, const uint32_t* win, uint32_t nwin,
+                                                uint32_t v0, uint64_t p0, uint64_t p1, bool first,
+                                                bool final) {
+  constexpr uint32_t PG = 16 / KB, STEP = 64 * PG;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint64_t q_lo = p0 > a.body_lo ? p0 : a.body_lo;
+  const uint64_t q_hi = p1 < a.body_hi ? p1 : a.body_hi;
+  // chunk starts and body_hi are multiples of PG positions from body_lo
+  const uint64_t i_lo = (q_lo - a.body_lo) / PG, i_hi = q_hi > q_lo ? (q_hi - a.body_lo) / PG : i_lo;
+  const int32_t base = (int32_t)(a.min_u + v0);
+  const uint32_t last = nwin - 1;
+  uint32_t xw = 0;
+  uint32_t end = win[0];
+  for (uint64_t ib = i_lo + (uint64_t)wave * 64; ib < i_hi; ib += kFillBlock) {
+    const uint32_t pw = (uint32_t)(a.body_lo + PG * ib);
+    while (xw < last && end <= pw) end = win[++xw];
+    const uint64_t i = ib + lane;
+    int32_t o[PG];
+    if (xw == last || end > pw + (STEP - 1)) {
+#pragma unroll
+      for (uint32_t j = 0; j < PG; ++j) o[j] = base + (int32_t)xw;
+    } else {
+      const uint32_t p = pw + PG * lane;
+      uint32_t c[PG];
+#pragma unroll
+      for (uint32_t j = 0; j < PG; ++j) c[j] = 0;
+      uint32_t xb = xw, e = end;
+      while (xb < last && e <= pw + (STEP - 1)) {   // boundary after value xb at position e
+#pragma unroll
+        for (uint32_t j = 0; j < PG; ++j) c[j] += e <= p + j;
+        e = win[++xb];
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < PG; ++j) o[j] = base + (int32_t)(xw + c[j]);
+    }
+    if (i < i_hi) store_vec16<KB>(a, i, o);
+  }
+  if (first)
+    for (uint64_t p = tid; p < a.body_lo; p += kFillBlock)
+      store_one<KB>(a, p, base + (int32_t)min(count_le(win, nwin, (uint32_t)p), last));
+  if (final)
+    for (uint64_t p = a.body_hi + tid; p < a.n; p += kFillBlock)
+      store_one<KB>(a, p, base + (int32_t)min(count_le(win, nwin, (uint32_t)p), last));
+}
+
 template <bool SPARSE, int KB>
 __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* win, uint32_t nwin,
                                            uint32_t v0, uint64_t p0, uint64_t p1, bool first,
                                            bool final, uint32_t* stage) {
+  if constexpr (!SPARSE && KB != 4) {
+    fill_chunk_wide<KB>(a, win, nwin, v0, p0, p1, first, final);
+    return;
+  }
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint64_t q_lo = p0 > a.body_lo ? p0 : a.body_lo;
   const uint64_t q_hi = p1 < a.body_hi ? p1 : a.body_hi;
@@ -1095,7 +1169,8 @@ hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream
   a.chunk = p.chunk;
   a.nchunks = p.nchunks;
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
-  a.body_hi = a.body_lo + 4 * ((p.n - a.body_lo) / 4);
+  // whole groups of 4 int32 keys, or of 16 / kb narrow keys (one 16-byte vector)
+  a.body_hi = a.body_lo + (16 / p.kb) * ((p.n - a.body_lo) / (16 / p.kb));
   a.flags = reinterpret_cast<const uint32_t*>(ws + p.off_flags);
   a.flip = p.flip;
   // The sparse form (look-ahead and bisection in the window) when the values
@@ -1135,7 +1210,8 @@ hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStre
   a.chunk = p.chunk;
   a.nchunks = p.nchunks;
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
-  a.body_hi = a.body_lo + 4 * ((p.n - a.body_lo) / 4);
+  // whole groups of 4 int32 keys, or of 16 / kb narrow keys (one 16-byte vector)
+  a.body_hi = a.body_lo + (16 / p.kb) * ((p.n - a.body_lo) / (16 / p.kb));
   a.flip = p.flip;
   const bool sparse = p.n < (uint64_t)64 * p.R;
   const dim3 grid(p.fill_grid), block(kFillBlock);
