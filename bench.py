@@ -569,7 +569,8 @@ def main():
     for (lr, d), a, b in zip(cases, ins, outs):
         R = 1 << lr
         info = rtcdf.plan_info(N, MIN_VAL, MIN_VAL + R, keys_in=a, keys_out=b)
-        hist_name = f"k_hist<{info['items_per_thread']}, {info['counter_bits']}, {info['hist_threads']}>"
+        # instantiation names: the last template argument is the key width (4 bytes)
+        hist_name = f"k_hist<{info['items_per_thread']}, {info['counter_bits']}, {info['hist_threads']}, 4>"
         rtcdf.profile_collect()
         rtcdf.profile_enable(True)
         for _ in range(args.steps):
@@ -581,10 +582,10 @@ def main():
         sparse = "true" if N < 64 * R else "false"   # sparse form below 64 keys per value
         if info["scan_workgroups"] == 0:
             # single-tile fast path: two launches, the output stage reduces and scans
-            stages = (("hist", hist_name), ("fill", f"k_fill_small<{sparse}>"))
+            stages = (("hist", hist_name), ("fill", f"k_fill_small<{sparse}, 4>"))
         else:
             stages = (("hist", hist_name), ("reduce", "k_reduce"), ("tilescan", "k_tilescan"),
-                      ("fill", f"k_fill<{sparse}>"))
+                      ("fill", f"k_fill<{sparse}, 4>"))
         for stg, name in stages:
             stage_tot[stg] += st[stg]
             kern_ms[name] = kern_ms.get(name, 0.0) + st[stg]
