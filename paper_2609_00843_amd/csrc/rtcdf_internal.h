@@ -41,7 +41,7 @@ constexpr uint64_t kPmaxSmallN = 1ull << 21;
 // Partition of the keys by LDS pass (rtcdf_part.hip), for ranges that need
 // several passes: at most kPartMaxBuckets passes; keys per partition tile.
 constexpr uint32_t kPartMaxBuckets = 8192;
-constexpr uint32_t kPartTileKeys = 4096;
+constexpr uint32_t kPartTileKeys = 8192;
 // The library partitions from kPartMinPasses passes on when n x passes is at
 // least kPartMinWork (measured on MI355X: at n = 10^8 the multi-pass
 // histogram grows ~0.05 ms a pass against a nearly constant partition cost,

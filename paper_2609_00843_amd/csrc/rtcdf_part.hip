@@ -34,8 +34,8 @@ namespace {
 using namespace dev;
 
 constexpr uint32_t kPartBlock = 256;
-constexpr uint32_t kPartItems = 16;                        // keys per thread per tile
-constexpr uint32_t kPartTile = kPartBlock * kPartItems;    // 4096 keys
+constexpr uint32_t kPartItems = 32;                        // keys per thread per tile
+constexpr uint32_t kPartTile = kPartBlock * kPartItems;    // 8192 keys
 static_assert(kPartTile == kPartTileKeys, "the planner sizes slices in these tiles");
 
 struct PartArgs {
