@@ -202,6 +202,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   p->chunk = (uint32_t)((want + gran - 1) / gran * gran);
   p->nchunks = 1 + ((n >= 1 && n - 1 >= p->out_head) ? (uint32_t)((n - 1 - p->out_head) / p->chunk) : 0);
   p->fill_grid = (uint32_t)std::min<uint64_t>(p->nchunks, (uint64_t)dev.cus * fill_per_cu);
+  p->fill_sparse_keys = (uint32_t)std::max<int64_t>(0, env_int("RTCDF_DEV_FILL_SPARSE_KEYS", 64));
   // Local-CDF stage: enough workgroups to spread the splitters over the chip,
   // but no more than one per 256 chunk starts.  With at most kScanBlock tiles
   // and 8 * kScanBlock block totals the kernel assigns the workgroups to tiles

@@ -90,6 +90,7 @@ struct Plan {
   uint32_t chunk;        // output positions per chunk (multiple of 4 * kFillBlock)
   uint32_t nchunks;
   uint32_t fill_grid;
+  uint32_t fill_sparse_keys;   // the sparse output form below this many keys per value
   // Single-tile fast path: the histogram accumulates into fast_rows rows of
   // fast_stride words of the fast-path area and the output stage scans them
   // itself; no reduction or local-CDF launch.

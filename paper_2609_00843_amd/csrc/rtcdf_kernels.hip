@@ -346,7 +346,8 @@ struct ScanArgs {
   uint32_t R, T, out_head, chunk, nchunks, S;
   uint32_t m, grid;   // tiles; workgroups (grid > m: assigned by chunk counts)
   uint32_t pre_O;     // per-tile path: O[t] was written by k_tile_offsets
-  uint32_t* flags;    // [0] set if some chunk's window holds over chunk / 64 values
+  uint32_t* flags;    // [0] set if some chunk's window holds over chunk / sparse_k values
+  uint32_t sparse_k;
   // Prefix-maximum output (Alg. 3; pm_out null otherwise): the first
   // workgroup of each tile writes B[P1[d-1]] = minVal + d for every value d >= 1
   // of the tile with keys, and the chunk maxima M (last step of each
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
     bool sparse = false;
     for (uint32_t j = tid; j < nbatch; j += kScanBlock) {
       a.split[kb0 + j] = stage[j];
-      if (j + 1 < nbatch) sparse |= (uint64_t)(stage[j + 1] - stage[j] + 1) * 64 > a.chunk;
+      if (j + 1 < nbatch) sparse |= (uint64_t)(stage[j + 1] - stage[j] + 1) * a.sparse_k > a.chunk;
     }
     if (__syncthreads_or(sparse) && tid == 0) a.flags[0] = 1u;
   }
@@ -559,6 +560,7 @@ struct FillArgs {
   uint64_t body_lo, body_hi;   // positions [body_lo, body_hi) are 16-byte aligned int4s
   const uint32_t* flags;       // [0]: some chunk is sparse (local-CDF stage)
   uint32_t flip;               // narrow keys: stored bits = value ^ flip
+  uint32_t sparse_k;           // a chunk takes the sparse form below this many positions per value
 };
 
 // Four consecutive outputs (group i of the aligned body, 16 / 8 / 4 bytes)
@@ -840,7 +842,7 @@ __device__ __forceinline__ void fill_loop(const FillArgs& a, uint32_t (*win)[kFi
     const uint64_t p1 = k + 1 < a.nchunks ? chunk_start(a, k + 1) : a.n;
     if (nwin > kFillWindow)
       fill_chunk_global<KB>(a, v0, v0 + nwin - 1, p0, p1);
-    else if (MODE == 1 || (MODE == 2 && (uint64_t)nwin * 64 > p1 - p0))
+    else if (MODE == 1 || (MODE == 2 && (uint64_t)nwin * a.sparse_k > p1 - p0))
       fill_chunk<true, KB>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
     else
       fill_chunk<false, KB>(a, win[buf], nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
@@ -966,7 +968,7 @@ __global__ __launch_bounds__(kFillBlock) void k_fill_small(FillArgs a, uint32_t*
       // uniform: the walk of fill_chunk is then steered by scalar registers
       const uint32_t v0 = __builtin_amdgcn_readfirstlane(v_lo[j]);
       const uint32_t nwin = __builtin_amdgcn_readfirstlane(v_hi[j]) - v0 + 1;
-      if (SPARSE || (uint64_t)nwin * 64 > p1 - p0)   // as the per-chunk mode of fill_loop
+      if (SPARSE || (uint64_t)nwin * a.sparse_k > p1 - p0)   // as the per-chunk mode of fill_loop
         fill_chunk<true, KB>(a, C + v0, nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
       else
         fill_chunk<false, KB>(a, C + v0, nwin, v0, p0, p1, k == 0, k + 1 == a.nchunks, stage);
@@ -1135,6 +1137,7 @@ hipError_t launch_tilescan(const Plan& p, uint8_t* ws, int32_t* pm_out, hipStrea
   a.out_head = p.out_head;
   a.chunk = p.chunk;
   a.nchunks = p.nchunks;
+  a.sparse_k = p.fill_sparse_keys;
   // The per-tile path sums the block totals before each tile in every
   // workgroup (m x nred / 2 loads in all); above 2^28 loads one workgroup
   // forms all offsets first.
@@ -1168,14 +1171,16 @@ hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream
   a.out_head = p.out_head;
   a.chunk = p.chunk;
   a.nchunks = p.nchunks;
+  a.sparse_k = p.fill_sparse_keys;
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
   // whole groups of 4 int32 keys, or of 16 / kb narrow keys (one 16-byte vector)
   a.body_hi = a.body_lo + (16 / p.kb) * ((p.n - a.body_lo) / (16 / p.kb));
   a.flags = reinterpret_cast<const uint32_t*>(ws + p.off_flags);
   a.flip = p.flip;
   // The sparse form (look-ahead and bisection in the window) when the values
-  // average fewer than 64 output positions each; the plain walk otherwise.
-  const bool sparse = p.n < (uint64_t)64 * p.R;
+  // average fewer than fill_sparse_keys output positions each; the plain walk
+  // otherwise.
+  const bool sparse = p.n < (uint64_t)p.fill_sparse_keys * p.R;
   const dim3 grid(p.fill_grid), block(kFillBlock);
   switch (p.kb) {
     case 4:
@@ -1209,11 +1214,12 @@ hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStre
   a.out_head = p.out_head;
   a.chunk = p.chunk;
   a.nchunks = p.nchunks;
+  a.sparse_k = p.fill_sparse_keys;
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
   // whole groups of 4 int32 keys, or of 16 / kb narrow keys (one 16-byte vector)
   a.body_hi = a.body_lo + (16 / p.kb) * ((p.n - a.body_lo) / (16 / p.kb));
   a.flip = p.flip;
-  const bool sparse = p.n < (uint64_t)64 * p.R;
+  const bool sparse = p.n < (uint64_t)p.fill_sparse_keys * p.R;
   const dim3 grid(p.fill_grid), block(kFillBlock);
   const uint32_t rows = p.fast_rows, stride = p.fast_stride;
   switch (p.kb) {
