@@ -676,38 +676,56 @@ def main():
                          f"{os.cpu_count()} host cores visible"}
         log(f"[bench] oracle {cpu['value']} Gkeys/s on 1 core; parity: {parity}")
 
+    def section(name, fn):
+        # A reported section that fails is recorded in the line; it must not
+        # cost the measured sweep its JSON line.
+        try:
+            return fn()
+        except Exception as e:
+            import traceback
+            traceback.print_exc(file=sys.stderr)
+            log(f"[bench] {name} failed: {e!r}")
+            return {"error": repr(e)}
+
     learned = None
     if not args.no_learned:
         log("[bench] learned picker vs static table on the sweep")
-        learned = bench_learned(torch, rtcdf, cases, ins, outs, max(3, args.steps // 2))
+        learned = section("learned picker",
+                          lambda: bench_learned(torch, rtcdf, cases, ins, outs, max(3, args.steps // 2)))
     batched = None
     if not args.no_batched:
         del ins, outs
         torch.cuda.empty_cache()
         log("[bench] batched workload")
-        batched = bench_batched(torch, rtcdf, inputs, args.steps, not args.no_cpu_baseline)
-        log(f"[bench] batched: {batched['gkeys_per_s']} Gkeys/s in one graph launch, "
-            f"{batched['speedup_vs_plain_calls']}x plain calls, {batched['speedup_vs_plain_graph']}x "
-            f"plain graph; parity {batched['parity']}")
+        batched = section("batched", lambda: bench_batched(torch, rtcdf, inputs, args.steps,
+                                                           not args.no_cpu_baseline))
+        if "error" not in batched:
+            log(f"[bench] batched: {batched['gkeys_per_s']} Gkeys/s in one graph launch, "
+                f"{batched['speedup_vs_plain_calls']}x plain calls, {batched['speedup_vs_plain_graph']}x "
+                f"plain graph; parity {batched['parity']}")
 
     small = large = methods = wide = narrow = None
     if not args.no_extra:
         log("[bench] n=1e6 and n=1e9 timings")
-        small = bench_small(torch, rtcdf, inputs, args.steps)
-        large = bench_scale(torch, rtcdf, inputs, args.steps)
+        small = section("n=1e6", lambda: bench_small(torch, rtcdf, inputs, args.steps))
+        large = section("n=1e9", lambda: bench_scale(torch, rtcdf, inputs, args.steps))
         log("[bench] output methods: local-CDF search vs prefix maximum")
-        methods = bench_output_methods(torch, rtcdf, inputs, args.steps)
-        log(f"[bench] output methods identical: {methods['outputs_identical']}; prefix maximum "
-            f"faster at: {methods['prefix_max_faster_at'] or 'none'}")
+        methods = section("output methods", lambda: bench_output_methods(torch, rtcdf, inputs, args.steps))
+        if "error" not in methods:
+            log(f"[bench] output methods identical: {methods['outputs_identical']}; prefix maximum "
+                f"faster at: {methods['prefix_max_faster_at'] or 'none'}")
         log("[bench] 16- and 8-bit keys")
-        narrow = bench_key_widths(torch, rtcdf, args.steps)
-        log("[bench] key widths: " + ", ".join(f"{r['keys']} [{r['minVal']},{r['maxVal']}) {r['gkeys_per_s']} Gkeys/s"
-                                               for r in narrow["rows"]) + f"; checked: {narrow['checked']}")
+        narrow = section("key widths", lambda: bench_key_widths(torch, rtcdf, args.steps))
+        if "error" not in narrow:
+            log("[bench] key widths: " + ", ".join(f"{r['keys']} [{r['minVal']},{r['maxVal']}) "
+                                                   f"{r['gkeys_per_s']} Gkeys/s" for r in narrow["rows"])
+                + f"; checked: {narrow['checked']}")
         log("[bench] wide ranges: partition by pass")
-        wide = bench_wide_ranges(torch, rtcdf, inputs, args.steps)
-        log("[bench] wide ranges: " + ", ".join(f"2^{r['R'].bit_length() - 1} {r['dist']} {r['ms']} ms "
-                                                f"(x{r['speedup']})" for r in wide["rows"])
-            + f"; identical: {wide['outputs_identical']}")
+        wide = section("wide ranges", lambda: bench_wide_ranges(torch, rtcdf, inputs, args.steps))
+        if "error" not in wide:
+            log("[bench] wide ranges: " + ", ".join(f"2^{r['R'].bit_length() - 1} {r['dist']} {r['ms']} ms "
+                                                    f"(x{r['speedup']})" for r in wide["rows"])
+                + f"; identical: {wide['outputs_identical']}")
 
     tgt = [c for c in per_case if c["R"] <= (1 << 16)]
     rec = {
