@@ -451,8 +451,8 @@ def main():
     if args.key_widths and not args.profile_only:
         ap.error("--key-widths is a profiling mode; it needs --profile-only")
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(the sort would shard by one 4R-byte histogram all-reduce)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
+              f"drives one GPU (the sort would shard by one 4R-byte histogram all-reduce)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
