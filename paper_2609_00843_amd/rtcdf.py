@@ -159,8 +159,11 @@ def _check_keys(t, what):
 def sort(keys_in, minVal: int, maxVal: int, keys_out=None, config: Config | None = None,
          stream=None):
     """Sort keys_in (int32 in [minVal, maxVal)) into keys_out (allocated if None).
-    Asynchronous on `stream` (default: torch's current stream)."""
+    Asynchronous on `stream` (default: torch's current stream).  int16, uint16,
+    int8 and uint8 tensors go to sort_keys."""
     import torch
+    if getattr(keys_in, "dtype", None) in (torch.int16, torch.int8, torch.uint8, getattr(torch, "uint16", None)):
+        return sort_keys(keys_in, minVal, maxVal, keys_out=keys_out, config=config, stream=stream)
     _check_keys(keys_in, "keys_in")
     if keys_out is None:
         keys_out = torch.empty_like(keys_in)

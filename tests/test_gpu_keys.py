@@ -118,3 +118,14 @@ def test_full_size(r, name):
     for i in range(0, n, 1 << 25):
         v.chunk(out[i:i + (1 << 25)].cpu().numpy().astype(np.int32))
     v.end(n)
+
+
+def test_sort_dispatches_by_dtype(r):
+    """rtcdf.sort takes narrow key tensors too (through rtcdf_sort_keys)."""
+    rng = np.random.default_rng(2)
+    A = rng.integers(-300, 300, size=100_003).astype(np.int16)
+    _say("sort() with int16 keys")
+    out = r.sort(torch.from_numpy(A).cuda(), -300, 300)
+    torch.cuda.synchronize()
+    assert out.dtype == torch.int16
+    assert np.array_equal(out.cpu().numpy(), oracle.sort(A.astype(np.int32), -300, 300).astype(np.int16))
