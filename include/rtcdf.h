@@ -61,7 +61,9 @@ typedef enum rtcdf_status {
   RTCDF_ERROR_WORKSPACE_TOO_SMALL = 7,
   RTCDF_ERROR_NOT_SUPPORTED = 8,    /* device is not gfx950, or feature unavailable */
   RTCDF_ERROR_NO_MODEL = 9,         /* learned mode requested but no model is loaded */
-  RTCDF_ERROR_KEY_OUT_OF_RANGE = 10 /* checked mode only: some key lies outside [minVal, maxVal) */
+  RTCDF_ERROR_KEY_OUT_OF_RANGE = 10, /* checked mode only: some key lies outside [minVal, maxVal) */
+  RTCDF_ERROR_CAPTURE_NEEDS_WORKSPACE = 11 /* rtcdf_sort under stream capture would have to
+                                             allocate its workspace (see rtcdf_sort) */
 } rtcdf_status_t;
 
 /* Largest supported range.  The workspace grows with R (about 4R + 4m bytes
@@ -101,9 +103,19 @@ typedef struct rtcdf_config {
 
 /* Sort n int32 keys from [minVal, maxVal) into keys_out (Sec. 3, Alg. 4).
  * keys_in, keys_out: device arrays of n int32 (may be equal).
- * Uses a per-device workspace cached by the library (allocated on first use
- * and grown as needed; hipMalloc may therefore run inside this call).
- * The configuration comes from the current config mode. */
+ * Uses a workspace cached by the library per (device, stream), allocated on
+ * first use and grown as needed: hipMalloc and hipFree (after waiting for
+ * `stream`) may run inside this call.
+ * The configuration comes from the current config mode.
+ * HIP graph capture: rtcdf_sort_ws and rtcdf_sort_batched are the capturable
+ * forms.  rtcdf_sort may be captured only when a sort of a problem at least as
+ * large (same stream, same plan kind) has run on `stream` before the capture
+ * began; otherwise it returns RTCDF_ERROR_CAPTURE_NEEDS_WORKSPACE without
+ * enqueuing anything.  Under capture the learned mode's pick (which reads its
+ * result back to the host) is skipped and the TUNED/DEFAULT configuration is
+ * used.  A workspace that a capture has used is never freed
+ * (rtcdf_release_workspaces keeps it; growth retires it), because the graph
+ * may be replayed at any time. */
 rtcdf_status_t rtcdf_sort(const int32_t* keys_in, int32_t* keys_out, size_t n,
                           int64_t minVal, int64_t maxVal, hipStream_t stream);
 

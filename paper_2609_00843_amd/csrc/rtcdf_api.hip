@@ -51,6 +51,22 @@ rtcdf_status_t device_info(DeviceInfo* out) {
   return RTCDF_SUCCESS;
 }
 
+static std::mutex g_attr_mu;
+static std::map<std::pair<const void*, int>, int> g_attr_done;
+
+hipError_t ensure_dynamic_lds(const void* fn, int bytes) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  auto key = std::make_pair(fn, dev);
+  auto it = g_attr_done.find(key);
+  if (it != g_attr_done.end() && it->second >= bytes) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) g_attr_done[key] = bytes;
+  return e;
+}
+
 // --------------------------------------------------------------- validation
 
 rtcdf_status_t check_problem(const int32_t* keys_in, const int32_t* keys_out, size_t n,
@@ -163,7 +179,12 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   }
   const int64_t gmul = env_int("RTCDF_DEV_HIST_GMUL", 1);
   if (gmul > 1 && gmul <= 64) G *= (uint32_t)gmul;
-  const uint64_t iters = (p->in_n4 + (uint64_t)p->hist_block * V - 1) / ((uint64_t)p->hist_block * V);
+  // The cap on G is taken from the largest body any alignment of the input
+  // can have (n / keys per vector), so that G, and with it the partial-row
+  // area of the workspace, does not depend on where keys_in starts (the
+  // workspace size is asked for without keys_in).
+  const uint64_t n4_max = n / (16 / kb);
+  const uint64_t iters = (n4_max + (uint64_t)p->hist_block * V - 1) / ((uint64_t)p->hist_block * V);
   const uint64_t gcap = std::max<uint64_t>(8, (iters + 7) / 8 * 8);
   G = (uint32_t)std::min<uint64_t>(std::max<uint32_t>(G, 8), gcap);
   p->G = G;
@@ -174,7 +195,10 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // RTCDF_DEV_PARTITION = 0 / 1 forces it off / on wherever it applies).
   {
     const int64_t force = env_int("RTCDF_DEV_PARTITION", -1);
-    const bool fits = p->passes >= 2 && p->passes <= kPartMaxBuckets && n <= 0xffffffffull && kb == 4;
+    // bucket bounds are uint32 positions in the padded copy (at most n + 3 per
+    // bucket of padding), so the padded copy must stay below 2^32 keys
+    const bool fits = p->passes >= 2 && p->passes <= kPartMaxBuckets && kb == 4 &&
+                      (uint64_t)n + 4ull * p->passes + 4 <= 0xffffffffull;
     p->part = fits && (force == 1 || (force != 0 && p->passes >= kPartMinPasses &&
                                       (uint64_t)n * p->passes >= kPartMinWork));
     if (p->part) {
@@ -304,16 +328,34 @@ struct Workspace {
   uint32_t* fast = nullptr;
   bool fast_dirty = false;
   uint64_t* check = nullptr;   // checked mode: the out-of-range count
+  // A sort captured into a HIP graph keeps raw pointers to these buffers, and
+  // the graph may be replayed at any time: once a capture has used them they
+  // are never freed (growth moves them to g_retired instead).
+  bool captured = false;
 };
 
 static std::mutex g_ws_mu;
 static std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+static std::vector<void*> g_retired;   // buffers of captured workspaces, kept until exit
 
-static rtcdf_status_t grow(Workspace& w, const Plan& p) {
+// Frees a buffer of workspace w, or keeps it alive if a capture used it.
+// `s` is the workspace's stream: its work is the only work that reads the
+// buffer, so waiting for it (not for the whole device) makes the free safe.
+static hipError_t drop_buffer(Workspace& w, void* ptr, hipStream_t s) {
+  if (ptr == nullptr) return hipSuccess;
+  if (w.captured) {
+    g_retired.push_back(ptr);
+    return hipSuccess;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  return hipFree(ptr);
+}
+
+static rtcdf_status_t grow(Workspace& w, const Plan& p, hipStream_t s) {
   if (w.ws_bytes < p.ws_bytes) {
-    hipError_t e = hipDeviceSynchronize();
+    hipError_t e = drop_buffer(w, w.ws, s);
     if (e != hipSuccess) return hip_fail(e);
-    if (w.ws) (void)hipFree(w.ws);
     w.ws = nullptr;
     w.ws_bytes = 0;
     const size_t bytes = std::max<size_t>(p.ws_bytes, (size_t)1 << 20);
@@ -336,9 +378,8 @@ static rtcdf_status_t grow(Workspace& w, const Plan& p) {
     if (e != hipSuccess) return hip_fail(e);
   }
   if (!p.fast && w.carry_words < p.carry_words) {
-    hipError_t e = hipDeviceSynchronize();
+    hipError_t e = drop_buffer(w, w.carry, s);
     if (e != hipSuccess) return hip_fail(e);
-    if (w.carry) (void)hipFree(w.carry);
     w.carry = nullptr;
     w.carry_words = 0;
     const size_t words = std::max<size_t>(p.carry_words, 1 << 16);
@@ -353,6 +394,22 @@ static rtcdf_status_t grow(Workspace& w, const Plan& p) {
     w.carry_words = words;
   }
   return RTCDF_SUCCESS;
+}
+
+// Whether work enqueued on `s` now is being captured into a graph.
+static rtcdf_status_t capturing(hipStream_t s, bool* out) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess) return hip_fail(e);
+  *out = cs != hipStreamCaptureStatusNone;
+  return RTCDF_SUCCESS;
+}
+
+// True when the cached workspace already holds everything plan p needs.
+static bool fits_cached(const Workspace& w, const Plan& p) {
+  if (w.ws_bytes < p.ws_bytes) return false;
+  if (p.fast) return w.fast != nullptr;
+  return w.carry_words >= p.carry_words;
 }
 
 // ------------------------------------------------------------- profiling
@@ -470,8 +527,15 @@ static rtcdf_status_t sort_cached(const int32_t* in, int32_t* out, size_t n, int
   DeviceInfo dev;
   rtcdf_status_t st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;
+  // Under stream capture nothing may allocate, free or wait on the host: the
+  // learned pick (which reads its result back) is skipped, and the cached
+  // workspace must already be large enough (a sort of the same or a larger
+  // problem on this stream before the capture allocates it).
+  bool cap = false;
+  st = capturing(s, &cap);
+  if (st != RTCDF_SUCCESS) return st;
   rtcdf_config_t c;
-  st = resolve_config(cfg, kb == 4 ? in : nullptr, n, minVal, maxVal, s, &c);
+  st = resolve_config(cfg, (kb == 4 && !cap) ? in : nullptr, n, minVal, maxVal, s, &c);
   if (st != RTCDF_SUCCESS) return st;
   if (kb != 4) c.flags = 0;
   Plan p;
@@ -480,7 +544,11 @@ static rtcdf_status_t sort_cached(const int32_t* in, int32_t* out, size_t n, int
   if (out == nullptr) p.fast = false;
   std::lock_guard<std::mutex> lk(g_ws_mu);
   Workspace& w = g_ws[std::make_pair(dev.device, s)];
-  st = grow(w, p);
+  if (cap) {
+    if (!fits_cached(w, p)) return RTCDF_ERROR_CAPTURE_NEEDS_WORKSPACE;
+    w.captured = true;
+  }
+  st = grow(w, p, s);
   if (st != RTCDF_SUCCESS) return st;
   if (!p.fast)
     return enqueue(p, in, out, static_cast<uint8_t*>(w.ws), w.carry, s, dbg_hist, dbg_cdf, dbg_O);
@@ -492,6 +560,39 @@ static rtcdf_status_t sort_cached(const int32_t* in, int32_t* out, size_t n, int
   st = enqueue(p, in, out, static_cast<uint8_t*>(w.ws), w.fast, s);
   if (st != RTCDF_SUCCESS) w.fast_dirty = true;
   return st;
+}
+
+// The sort in a workspace the caller provides (rtcdf_sort_ws) or the
+// library's fixed device array (rtcdf_sort_noalloc): no allocation, no host
+// synchronisation.  Arguments are checked by the caller; d_ws is 256-byte
+// aligned.  The configuration never comes from the learned pick (which reads
+// its result back to the host): the TUNED/DEFAULT choice is used.
+rtcdf_status_t sort_in_workspace(const int32_t* keys_in, int32_t* keys_out, size_t n, int64_t minVal,
+                                 int64_t maxVal, const rtcdf_config_t* cfg, void* d_ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+  DeviceInfo dev;
+  rtcdf_status_t st = device_info(&dev);
+  if (st != RTCDF_SUCCESS) return st;
+  rtcdf_config_t c;
+  if (!config_is_zero(cfg)) {
+    if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
+    c = *cfg;
+  } else {
+    st = pick_config(nullptr, n, minVal, maxVal, nullptr, &c);
+    if (st != RTCDF_SUCCESS) return st;
+  }
+  Plan p;
+  make_plan(n, minVal, maxVal, c, keys_in, keys_out, dev, &p);
+  if (ws_bytes < p.ws_bytes) return RTCDF_ERROR_WORKSPACE_TOO_SMALL;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  uint32_t* carry = reinterpret_cast<uint32_t*>(ws + p.off_carry);
+  // The carry array (or the fast path's accumulation area) must start at
+  // zero: cleared by a kernel, so no memset node enters a captured graph.
+  if (p.carry_words) {
+    hipError_t e = launch_clear(carry, p.carry_words, stream);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return enqueue(p, keys_in, keys_out, ws, carry, stream);
 }
 
 }  // namespace rtcdf
@@ -608,7 +709,9 @@ rtcdf_status_t rtcdf_workspace_bytes(size_t n, int64_t minVal, int64_t maxVal,
     if (st != RTCDF_SUCCESS) return st;
   }
   Plan p;
-  // The input alignment changes only head/tail handling, not the layout.
+  // The layout depends on n, R, the config and keys_out's alignment (output
+  // chunk starts); keys_in's alignment changes only the histogram's head and
+  // tail, never the number of its workgroups (see make_plan).
   make_plan(n, minVal, maxVal, c, probe, probe, dev, &p);
   *bytes = p.ws_bytes;
   return RTCDF_SUCCESS;
@@ -620,27 +723,7 @@ rtcdf_status_t rtcdf_sort_ws(const int32_t* keys_in, int32_t* keys_out, size_t n
   rtcdf_status_t st = check_problem(keys_in, keys_out, n, minVal, maxVal);
   if (st != RTCDF_SUCCESS || n == 0) return st;
   if (d_ws == nullptr || (reinterpret_cast<uintptr_t>(d_ws) & 255u)) return RTCDF_ERROR_INVALID_VALUE;
-  DeviceInfo dev;
-  st = device_info(&dev);
-  if (st != RTCDF_SUCCESS) return st;
-  rtcdf_config_t c;
-  if (!config_is_zero(cfg)) {
-    if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
-    c = *cfg;
-  } else {
-    st = pick_config(nullptr, n, minVal, maxVal, nullptr, &c);
-    if (st != RTCDF_SUCCESS) return st;
-  }
-  Plan p;
-  make_plan(n, minVal, maxVal, c, keys_in, keys_out, dev, &p);
-  if (ws_bytes < p.ws_bytes) return RTCDF_ERROR_WORKSPACE_TOO_SMALL;
-  uint8_t* ws = static_cast<uint8_t*>(d_ws);
-  uint32_t* carry = reinterpret_cast<uint32_t*>(ws + p.off_carry);
-  if (p.carry_words) {
-    hipError_t e = launch_clear(carry, p.carry_words, stream);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  return enqueue(p, keys_in, keys_out, ws, carry, stream);
+  return sort_in_workspace(keys_in, keys_out, n, minVal, maxVal, cfg, d_ws, ws_bytes, stream);
 }
 
 rtcdf_status_t rtcdf_debug_intermediates(const int32_t* keys_in, size_t n, int64_t minVal,
@@ -719,6 +802,8 @@ const char* rtcdf_status_string(rtcdf_status_t s) {
     case RTCDF_ERROR_NOT_SUPPORTED: return "not supported on this device";
     case RTCDF_ERROR_NO_MODEL: return "no model loaded";
     case RTCDF_ERROR_KEY_OUT_OF_RANGE: return "a key lies outside [minVal, maxVal)";
+    case RTCDF_ERROR_CAPTURE_NEEDS_WORKSPACE:
+      return "the stream is being captured and the library's workspace would have to grow";
   }
   return "unknown status";
 }
@@ -803,13 +888,18 @@ rtcdf_status_t rtcdf_stream_copy(const void* d_src, void* d_dst, size_t bytes, h
 rtcdf_status_t rtcdf_release_workspaces(void) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
   hipError_t e = hipDeviceSynchronize();
-  for (auto& kv : g_ws) {
-    if (kv.second.ws) (void)hipFree(kv.second.ws);
-    if (kv.second.carry) (void)hipFree(kv.second.carry);
-    if (kv.second.fast) (void)hipFree(kv.second.fast);
-    if (kv.second.check) (void)hipFree(kv.second.check);
+  for (auto it = g_ws.begin(); it != g_ws.end();) {
+    Workspace& w = it->second;
+    if (w.captured) {   // a captured graph may still replay with these buffers
+      ++it;
+      continue;
+    }
+    if (w.ws) (void)hipFree(w.ws);
+    if (w.carry) (void)hipFree(w.carry);
+    if (w.fast) (void)hipFree(w.fast);
+    if (w.check) (void)hipFree(w.check);
+    it = g_ws.erase(it);
   }
-  g_ws.clear();
   return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
 }
 

@@ -136,12 +136,12 @@ __device__ void fill_tile(g_i32* out, const uint32_t* C, uint32_t w, uint32_t ba
         }
       }
       v4i o;
-      if (xw == last || end > lp + 255u) {
+      if (xw == last || past_step(end, lp, 256u)) {   // end > lp unless xw == last
         o = (v4i)(int32_t)(base + xw);
       } else {
         // the look-ahead and the next end are read together
         const uint32_t far = C[pad32(min(xw + kWalk, last))], e1 = C[pad32(xw + 1)];
-        if (far <= lp + 255u) {
+        if (!past_step(far, lp, 256u)) {
           uint32_t* st = stage + wave * 256u;
           scatter_step([&](uint32_t x) { return C[pad32(x)]; }, xw, last, lp, st);
           const v4i sv = *reinterpret_cast<const v4i*>(st + 4 * lane);
@@ -152,7 +152,7 @@ __device__ void fill_tile(g_i32* out, const uint32_t* C, uint32_t w, uint32_t ba
           const uint32_t p = lp + 4 * lane;
           uint32_t c0 = end <= p, c1 = end <= p + 1, c2 = end <= p + 2, c3 = end <= p + 3;
           uint32_t xb = xw + 1, e = e1;
-          while (xb < last && e <= lp + 255u) {   // fewer than kWalk more ends
+          while (xb < last && !past_step(e, lp, 256u)) {   // fewer than kWalk more ends
             c0 += e <= p;
             c1 += e <= p + 1;
             c2 += e <= p + 2;
@@ -173,11 +173,13 @@ __device__ void fill_tile(g_i32* out, const uint32_t* C, uint32_t w, uint32_t ba
   }
   // scalar positions: before the first and after the last aligned vector
   const uint32_t s_end = q_lo < q_hi ? q_lo : P1;
-  for (uint32_t p = P0 + tid; p < s_end; p += kBBlock)
-    out[p] = (int32_t)(base + min(count_le_pad(C, w, p - P0), last));
+  // (64-bit positions, widened before the thread index is added: q_hi + tid
+  // and p + kBBlock would wrap near 2^32)
+  for (uint64_t p = (uint64_t)P0 + tid; p < s_end; p += kBBlock)
+    out[p] = (int32_t)(base + min(count_le_pad(C, w, (uint32_t)p - P0), last));
   if (q_lo < q_hi)
-    for (uint32_t p = q_hi + tid; p < P1; p += kBBlock)
-      out[p] = (int32_t)(base + min(count_le_pad(C, w, p - P0), last));
+    for (uint64_t p = (uint64_t)q_hi + tid; p < P1; p += kBBlock)
+      out[p] = (int32_t)(base + min(count_le_pad(C, w, (uint32_t)p - P0), last));
 }
 
 template <int V, bool PACKED>
@@ -313,7 +315,7 @@ hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, uint32_t* 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = (size_t)(kBLdsWords + kBStageWords) * 4;
-  e = hipFuncSetAttribute((const void*)k_batched<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  e = ensure_dynamic_lds((const void*)k_batched<4>, (int)lds);
   if (e != hipSuccess) return e;
   BatchArgs a;
   a.segs = segs;

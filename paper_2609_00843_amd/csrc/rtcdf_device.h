@@ -80,6 +80,16 @@ __device__ __forceinline__ uint32_t upper_in(const uint32_t* a, uint32_t lo, uin
   return lo;
 }
 
+// Output positions and inclusive cumulative counts are uint32 (n < 2^32), so
+// the end of a step of `span` positions starting at p, p + span, wraps when p
+// lies within span of 2^32.  Every test against a step's end is therefore made
+// relative to its start: for e >= p, e lies at or past the step's end iff
+// e - p >= span.  The callers guarantee e >= p (e is the end of a value that
+// covers or follows position p).
+__host__ __device__ __forceinline__ bool past_step(uint32_t e, uint32_t p, uint32_t span) {
+  return e - p >= span;
+}
+
 // Writes, for one wave, the value index of each of the 256 positions
 // [q, q + 256) into stage[0, 256) (this wave's LDS staging area).  E(x) is
 // the inclusive cumulative count of value x, so value x occupies positions
@@ -95,13 +105,17 @@ __device__ __forceinline__ void scatter_step(GetE E, uint32_t x0, uint32_t last,
   const uint32_t lane = lane_id();
   uint32_t xb = x0, start = q;   // start: where the run of value xb begins, clipped to q
   for (;;) {
+    // Every run starts and ends at or after q (value x0 covers q), so the
+    // bounds are kept relative to q: q + 256 may exceed 2^32 - 1.  Lanes past
+    // the last value get start = end = 0xffffffff, an empty run.
     const uint32_t x = xb + lane;
     const uint32_t e = x <= last ? E(x) : 0xffffffffu;
     const uint32_t s = lane == 0 ? start : (x <= last ? E(x - 1) : 0xffffffffu);
-    const uint32_t lo = s > q ? s : q, hi = e < q + 256u ? e : q + 256u;
-    for (uint32_t p = lo; p < hi; ++p) stage[p - q] = x;
+    const uint32_t er = e - q, sr = s - q;
+    const uint32_t lo = sr, hi = er < 256u ? er : 256u;
+    for (uint32_t r = lo; r < hi; ++r) stage[r] = x;
     const uint32_t e63 = (uint32_t)__builtin_amdgcn_readlane((int)e, 63);
-    if (xb + 63u >= last || e63 >= q + 256u) break;
+    if (xb + 63u >= last || past_step(e63, q, 256u)) break;
     start = e63;
     xb += 64u;
   }

@@ -176,6 +176,10 @@ hipError_t launch_pick(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t
 
 // Host helpers shared by the C ABI translation units (rtcdf_api.hip).
 rtcdf_status_t device_info(DeviceInfo* out);
+// Raises kernel fn's dynamic LDS limit to `bytes` on the current device, once
+// per (kernel, device): each caller passes the largest size any of its
+// launches uses, so the attribute is not set again on every launch.
+hipError_t ensure_dynamic_lds(const void* fn, int bytes);
 rtcdf_status_t hip_fail(hipError_t e);
 bool config_valid(const rtcdf_config_t& c);
 // kb / flip: key width in bytes and the sign-bit flip of narrow signed keys
@@ -183,6 +187,15 @@ bool config_valid(const rtcdf_config_t& c);
 void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& cfg,
                const void* in, const void* out, const DeviceInfo& dev, Plan* p, uint32_t kb = 4,
                uint32_t flip = 0);
+
+// Argument checks of the plain sort (n, range, pointers, overlap).
+rtcdf_status_t check_problem(const int32_t* keys_in, const int32_t* keys_out, size_t n, int64_t minVal,
+                             int64_t maxVal);
+// The sort in a device workspace of ws_bytes at d_ws (256-byte aligned),
+// after check_problem: no allocation, no host synchronisation.
+rtcdf_status_t sort_in_workspace(const int32_t* keys_in, int32_t* keys_out, size_t n, int64_t minVal,
+                                 int64_t maxVal, const rtcdf_config_t* cfg, void* d_ws, size_t ws_bytes,
+                                 hipStream_t stream);
 
 // Configuration source (rtcdf_config.hip): the choice rtcdf_sort makes when the
 // caller gives no config, under the current config mode.

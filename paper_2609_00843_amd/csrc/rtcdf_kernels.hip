@@ -661,7 +661,8 @@ __device__ __forceinline__ void fill_chunk_wide(const FillArgs& a, const uint32_
     while (xw < last && end <= pw) end = win[++xw];
     const uint64_t i = ib + lane;
     int32_t o[PG];
-    if (xw == last || end > pw + (STEP - 1)) {
+    // end > pw here unless xw == last: the step's end is tested relative to pw
+    if (xw == last || past_step(end, pw, STEP)) {
 #pragma unroll
       for (uint32_t j = 0; j < PG; ++j) o[j] = base + (int32_t)xw;
     } else {
@@ -670,7 +671,7 @@ __device__ __forceinline__ void fill_chunk_wide(const FillArgs& a, const uint32_
 #pragma unroll
       for (uint32_t j = 0; j < PG; ++j) c[j] = 0;
       uint32_t xb = xw, e = end;
-      while (xb < last && e <= pw + (STEP - 1)) {   // boundary after value xb at position e
+      while (xb < last && !past_step(e, pw, STEP)) {   // boundary after value xb at position e
 #pragma unroll
         for (uint32_t j = 0; j < PG; ++j) c[j] += e <= p + j;
         e = win[++xb];
@@ -733,13 +734,14 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
     }
     const uint64_t i = ib + lane;
     v4i o;
-    if (xw == last || end > pw + 255u) {
+    // end > pw here unless xw == last: the step's end is tested relative to pw
+    if (xw == last || past_step(end, pw, 256u)) {
       o = (v4i)(base + (int32_t)xw);
     } else if constexpr (!SPARSE) {
       const uint32_t p = pw + 4 * lane;
       uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
       uint32_t xb = xw, e = end;
-      while (xb < last && e <= pw + 255u) {   // boundary after value xb at position e
+      while (xb < last && !past_step(e, pw, 256u)) {   // boundary after value xb at position e
         c0 += e <= p;
         c1 += e <= p + 1;
         c2 += e <= p + 2;
@@ -753,7 +755,7 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
     } else {
       const uint32_t p = pw + 4 * lane;
       const uint32_t far = win[min(xw + kWalk, last)], e1 = win[xw + 1];
-      if (far <= pw + 255u) {
+      if (!past_step(far, pw, 256u)) {
         uint32_t* st = stage + (tid >> 6) * 256u;
         scatter_step([&](uint32_t x) { return win[x]; }, xw, last, pw, st);
         const v4i sv = *reinterpret_cast<const v4i*>(st + 4 * lane);
@@ -762,7 +764,7 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
         // boundary after value xw at position end, then after xw + 1 at e1, ...
         uint32_t c0 = end <= p, c1 = end <= p + 1, c2 = end <= p + 2, c3 = end <= p + 3;
         uint32_t xb = xw + 1, e = e1;
-        while (xb < last && e <= pw + 255u) {
+        while (xb < last && !past_step(e, pw, 256u)) {
           c0 += e <= p;
           c1 += e <= p + 1;
           c2 += e <= p + 2;
@@ -1151,8 +1153,10 @@ hipError_t launch_tilescan(const Plan& p, uint8_t* ws, int32_t* pm_out, hipStrea
     if (e0 != hipSuccess) return e0;
   }
   const size_t lds = ((size_t)p.T + p.T / 32 + 2 + 4 * kScanBlock) * 4;
-  hipError_t e = hipFuncSetAttribute((const void*)k_tilescan,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // the attribute is raised once, to the size of the widest tile (T = 32768)
+  constexpr size_t kMaxLds = ((size_t)32768 + 32768 / 32 + 2 + 4 * kScanBlock) * 4;
+  if (lds > kMaxLds) return hipErrorInvalidValue;
+  hipError_t e = ensure_dynamic_lds((const void*)k_tilescan, (int)kMaxLds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tilescan, dim3(p.scan_grid), dim3(kScanBlock), lds, s, a);
   return hipGetLastError();

@@ -233,7 +233,8 @@ hipError_t launch_partition(const Plan& p, const int32_t* keys, uint8_t* ws, hip
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = partition_lds_bytes(a.P);
-  e = hipFuncSetAttribute((const void*)k_part_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // raised once, to the size for the most buckets
+  e = ensure_dynamic_lds((const void*)k_part_scatter, (int)partition_lds_bytes(kPartMaxBuckets));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_part_scatter, dim3(a.G), dim3(kPartBlock), lds, s, a);
   return hipGetLastError();

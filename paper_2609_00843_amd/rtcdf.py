@@ -39,10 +39,11 @@ STATUS = {
     8: "RTCDF_ERROR_NOT_SUPPORTED",
     9: "RTCDF_ERROR_NO_MODEL",
     10: "RTCDF_ERROR_KEY_OUT_OF_RANGE",
+    11: "RTCDF_ERROR_CAPTURE_NEEDS_WORKSPACE",
 }
 SUCCESS, INVALID_VALUE, SIZE_TOO_LARGE, RANGE_TOO_LARGE, OVERLAP = 0, 1, 2, 3, 4
 OUT_OF_MEMORY, HIP_ERROR, WORKSPACE_TOO_SMALL, NOT_SUPPORTED, NO_MODEL = 5, 6, 7, 8, 9
-KEY_OUT_OF_RANGE = 10
+KEY_OUT_OF_RANGE, CAPTURE_NEEDS_WORKSPACE = 10, 11
 MAX_RANGE = 1 << 28
 BATCH_MAX_RANGE = 1 << 16
 CONFIG_DEFAULT, CONFIG_TUNED, CONFIG_LEARNED = 0, 1, 2

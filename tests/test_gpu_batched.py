@@ -116,6 +116,18 @@ def test_batch_workload_sample(r):
     _check(arrays, specs, pairs, dout, offs)
 
 
+def test_batch_workload_full(r):
+    """All 4096 arrays of the batch workload (about 5.9 x 10^8 keys), the
+    batch the benchmark times, each compared with the oracle's sort, with
+    guard words between the outputs."""
+    segs = inputs.batched_segments(4096)
+    specs = [(s["n"], s["minVal"], s["maxVal"] - s["minVal"], s["dist"]) for s in segs]
+    _say(f"full workload: {len(specs)} segments, {sum(s[0] for s in specs)} keys")
+    arrays, pairs, din, dout, offs = _build(specs, 5)
+    _run(r, pairs)
+    _check(arrays, specs, pairs, dout, offs)
+
+
 def test_skipped_descriptors(r):
     """range 0 or above the bounds, and NULL pointers, are skipped."""
     import ctypes

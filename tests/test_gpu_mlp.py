@@ -1,8 +1,18 @@
 """GPU parity of the learned picker's kernels against the float64 reference
 (oracle/mlp_ref.py): sketch, forward, gradient, Adam, training determinism and
-the masked argmin pick.  FP32 against float64: relative tolerance 1e-4 on
-outputs and gradients (sums of at most 2000 x 64 products, fp32 unit
-roundoff 6e-8), exact bin counts."""
+the masked argmin pick.  Exact bin counts.
+
+Tolerance of the FP32 kernels against float64.  The reference runs on the
+same fp32-rounded parameters and inputs the kernels receive, so the only
+difference is FP32 rounding inside the kernels.  Every output or gradient
+element is a composition of sums; to first order in the unit roundoff
+u = 2^-24, rounding changes element e by at most K u A_e, where A_e is the
+same element computed with every factor replaced by its absolute value (and
+ReLU masks kept) and K is the total length of the sums on its dependency
+chain (forward 34 + 64 + 64, backward 54 + 64, the batch sum B).  The test
+allows |got - want| <= 1e-4 |want| + 2 K u A_e: relative tolerance 1e-4 where
+no cancellation occurs, and the derived bound (with a factor 2 of slack) where
+it does."""
 import sys
 
 import numpy as np
@@ -80,19 +90,56 @@ def test_sketch(r, dist, n, R):
     assert np.array_equal(np.rint(got[2:] * S), np.rint(want[2:] * S))   # identical bin counts
 
 
+U32 = 2.0 ** -24
+
+
+def _f32(a):
+    """The float64 value of a's float32 rounding (what the kernels receive)."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _magnitudes(p, X, T, Mk):
+    """Absolute-value forms of the forward output and of every gradient
+    element (ReLU masks of the true forward pass kept): the A_e of the
+    module docstring."""
+    A = {k: np.abs(v) for k, v in p.items()}
+    Y, (_, Z1, _, Z2, _) = M.forward(p, X)
+    H1a = (np.abs(X) @ A["W1"].T + A["b1"]) * (Z1 > 0)
+    H2a = (H1a @ A["W2"].T + A["b2"]) * (Z2 > 0)
+    Ya = H2a @ A["W3"].T + A["b3"]
+    dYa = 2.0 * Mk * (np.abs(Y - T) + Ya) / Mk.sum()
+    g = {"W3": dYa.T @ H2a, "b3": dYa.sum(axis=0)}
+    dZ2a = (dYa @ A["W3"]) * (Z2 > 0)
+    g["W2"], g["b2"] = dZ2a.T @ H1a, dZ2a.sum(axis=0)
+    dZ1a = (dZ2a @ A["W2"]) * (Z1 > 0)
+    g["W1"], g["b1"] = dZ1a.T @ np.abs(X), dZ1a.sum(axis=0)
+    return Ya, _flat(g)
+
+
 def test_forward_and_gradient(r):
-    p = _init(1)
-    X, T, Mk = _batch(2, 300)
+    p = {k: _f32(v) for k, v in _init(1).items()}
+    X, T, Mk = (_f32(a) for a in _batch(2, 300))
+    B = X.shape[0]
     P = _dev(_flat(p))
     _say("forward")
     Y = r.mlp_forward(P, _dev(X)).cpu().numpy()
     Yr, cache = M.forward(p, X)
-    assert np.allclose(Y, Yr, rtol=1e-4, atol=1e-4 * np.abs(Yr).max())
+    Ya, Ga = _magnitudes(p, X, T, Mk)
+    k_fwd = 34 + 64 + 64
+    assert np.all(np.abs(Y - Yr) <= 1e-4 * np.abs(Yr) + 2 * k_fwd * U32 * Ya)
     _say("gradient")
     G, L = r.mlp_gradient(P, _dev(X), _dev(T), _dev(Mk))
     gr = _flat(M.backward(p, cache, Yr, T, Mk))
-    g = G.cpu().numpy()
-    assert np.allclose(g, gr, rtol=1e-3, atol=1e-4 * np.abs(gr).max())
+    g = G.cpu().numpy().astype(np.float64)
+    k_bwd = k_fwd + 54 + 64 + B
+    bound = 1e-4 * np.abs(gr) + 2 * k_bwd * U32 * Ga
+    worst = int(np.argmax(np.abs(g - gr) - bound))
+    assert np.all(np.abs(g - gr) <= bound), (worst, g[worst], gr[worst], bound[worst])
+    # Batch sums of 300 terms of both signs cancel (A_e is ~10^3 |g_e| at the
+    # median), which is what the K u A_e term covers; the stated relative
+    # tolerance alone holds for all but a few elements (a CPU emulation of
+    # sequential FP32 sums gives 99.9 %).
+    assert np.mean(np.abs(g - gr) <= 1e-4 * np.abs(gr)) >= 0.99
     assert float(L.cpu()[0]) == pytest.approx(M.loss(Yr, T, Mk), rel=1e-4)
 
 

@@ -358,6 +358,69 @@ def test_fast_path_graph_replay(r):
             r.sort(tin, 0, R, keys_out=out1, stream=s)
         s.synchronize()
         assert np.array_equal(out1.cpu().numpy(), want)
+    # Releasing the library's workspaces keeps the ones a capture used: the
+    # graph still replays correctly afterwards, and a larger sort on the same
+    # stream (which grows the workspace) retires the captured buffers instead
+    # of freeing them.
+    r.release_workspaces()
+    big = torch.from_numpy(inputs.uniform(3_000_000, 0, 1 << 16, 58)).cuda()
+    with torch.cuda.stream(s):
+        r.sort(big, 0, 1 << 16, stream=s)
+    s.synchronize()
+    A = inputs.make("normal", n, 0, R, 59)
+    tin.copy_(torch.from_numpy(A))
+    out1.fill_(-1)
+    torch.cuda.synchronize()
+    _say("fast path graph: replay after release and growth")
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(out1.cpu().numpy(), oracle.sort(A, 0, R))
+
+
+def test_capture_without_workspace_is_refused(r):
+    """rtcdf_sort on a stream whose library workspace does not exist yet
+    cannot allocate under capture: it returns CAPTURE_NEEDS_WORKSPACE and
+    enqueues nothing."""
+    n, R = 100_000, 5000
+    tin = torch.from_numpy(inputs.uniform(n, 0, R, 60)).cuda()
+    out = torch.empty_like(tin)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    _say("capture without a workspace")
+    with pytest.raises(r.RtcdfError) as ei:
+        with torch.cuda.graph(g, stream=s):
+            r.sort(tin, 0, R, keys_out=out, stream=s)
+    assert ei.value.status == r.CAPTURE_NEEDS_WORKSPACE
+    # the stream works normally afterwards
+    with torch.cuda.stream(s):
+        r.sort(tin, 0, R, keys_out=out, stream=s)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.sort(tin.cpu().numpy(), 0, R))
+
+
+@pytest.mark.parametrize("n", [65536 * 1 + 4, 65536 * 2 + 1, 65536 * 3 + 3, 65536 * 8 + 2, 262_147])
+def test_caller_workspace_alignments(r, n):
+    """rtcdf_workspace_bytes is asked with keys_out only; the workspace it
+    reports suffices whatever the alignment of keys_in (the histogram's
+    workgroup count does not depend on it), including n where the input body
+    crosses a multiple of the histogram's keys per workgroup round."""
+    R = 1000
+    A = inputs.uniform(n, -3, -3 + R, n)
+    want = oracle.sort(A, -3, -3 + R)
+    for oi in range(4):
+        for oo in range(4):
+            if oi == oo:
+                continue
+            bi = torch.empty(n + 4, dtype=torch.int32, device="cuda")
+            bo = torch.empty(n + 4, dtype=torch.int32, device="cuda")
+            tin, out = bi[oi:oi + n], bo[oo:oo + n]
+            tin.copy_(torch.from_numpy(A))
+            nb = r.workspace_bytes(n, -3, -3 + R, keys_out=out)
+            ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            _say(f"sort_ws alignment n={n} in+{oi} out+{oo} bytes={nb}")
+            r.sort_ws(tin, out, -3, -3 + R, ws)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want)
 
 
 def test_checked_mode(r):
