@@ -190,6 +190,26 @@ rtcdf_status_t rtcdf_sort_ws(const int32_t* keys_in, int32_t* keys_out, size_t n
                              int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,
                              void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sort of
+ * rtcdf_sort_ws with its workspace in a fixed device array of the library,
+ * RTCDF_NOALLOC_MAX_WORKSPACE bytes, that each GPU the library runs on holds
+ * from the first call on it until the process ends.  Arguments, output and
+ * configuration as for rtcdf_sort_ws (cfg NULL = library choice; the learned
+ * pick is not consulted).  No hipMalloc, hipFree or other allocation, no host
+ * synchronisation.  A problem whose workspace (rtcdf_workspace_bytes) exceeds
+ * the array returns RTCDF_ERROR_WORKSPACE_TOO_SMALL before any GPU work (for
+ * example n = 10^8 fits up to R = 2^20; ranges that partition the keys by pass
+ * need a copy of the keys and fit only for small n).  Every call on one GPU
+ * uses that GPU's one array, which keeps the previous call's contents (the
+ * sort needs no initialised workspace): calls that may overlap in time on one
+ * GPU (unordered streams, or several host threads) race and must be
+ * serialised by the caller, e.g. by issuing them on one stream. */
+#define RTCDF_NOALLOC_MAX_WORKSPACE (64u << 20)
+rtcdf_status_t rtcdf_sort_noalloc(const int32_t* keys_in, int32_t* keys_out, size_t n,
+                                  int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,
+                                  hipStream_t stream);
+
 /* Test hook for the intermediate arrays of Alg. 4-6 for tile width
  * cfg->tile_width: d_hist[R] receives the tile histograms (Alg. 5), d_cdf[R]
  * the local CDFs (in-place inclusive scan per tile), d_offsets[m] the tile

@@ -100,6 +100,7 @@ _SIGS = {
     "rtcdf_sort_with_config": [_vp, _vp, _sz, _i64, _i64, _cfgp, _vp],
     "rtcdf_workspace_bytes": [_sz, _i64, _i64, _cfgp, _vp, ctypes.POINTER(ctypes.c_size_t)],
     "rtcdf_sort_ws": [_vp, _vp, _sz, _i64, _i64, _cfgp, _vp, _sz, _vp],
+    "rtcdf_sort_noalloc": [_vp, _vp, _sz, _i64, _i64, _cfgp, _vp],
     "rtcdf_debug_intermediates": [_vp, _sz, _i64, _i64, _cfgp, _u32p, _u32p, _u32p, _vp],
     "rtcdf_batched_workspace_bytes": [ctypes.c_uint32, ctypes.POINTER(BatchBounds),
                                       ctypes.POINTER(ctypes.c_size_t)],
@@ -265,6 +266,21 @@ def sort_ws(keys_in, keys_out, minVal: int, maxVal: int, workspace, config: Conf
                            _ptr(workspace), workspace.numel() * workspace.element_size(),
                            _stream_ptr(stream))
     _check(st, "rtcdf_sort_ws")
+    return keys_out
+
+
+NOALLOC_MAX_WORKSPACE = 64 << 20
+
+
+def sort_noalloc(keys_in, keys_out, minVal: int, maxVal: int, config: Config | None = None,
+                 stream=None):
+    """Sort with the library's fixed device workspace (no allocation); calls
+    on one GPU must not overlap in time."""
+    _check_keys(keys_in, "keys_in")
+    _check_keys(keys_out, "keys_out")
+    st = lib.rtcdf_sort_noalloc(_ptr(keys_in), _ptr(keys_out), keys_in.numel(), int(minVal), int(maxVal),
+                                ctypes.byref(config) if config is not None else None, _stream_ptr(stream))
+    _check(st, "rtcdf_sort_noalloc")
     return keys_out
 
 
