@@ -80,18 +80,44 @@ typedef enum rtcdf_status {
  *  blocks_per_tile   co-resident workgroups per compute unit working on a
  *                    range tile: 1, 2 or 4.  Each gets 160 KiB / blocks of
  *                    LDS, so T * 4 * blocks_per_tile <= 160 KiB is required.
- *  flags             0, or RTCDF_FLAG_OUTPUT_PREFIX_MAX: write the output by
- *                    the prefix-maximum method of Alg. 3 (Sec. 2.2: B = 0,
- *                    each value stored at the first position of its output
- *                    interval, then the running maximum of B) instead of
- *                    the search of the local CDFs of Alg. 7.  Same output;
- *                    it writes B twice and reads it once (12 B per key in
- *                    the output stage instead of 4) but writes the steps one
- *                    value per thread.  The library's own choice (every
- *                    config mode) sets it when R >= 2^14 and R >= n.
+ *  flags             an OR of the RTCDF_FLAG_* options below (0: none).
+ * Options (none changes the output; each changes how it is computed):
+ *  RTCDF_FLAG_OUTPUT_PREFIX_MAX  write the output by the prefix-maximum
+ *                    method of Alg. 3 (Sec. 2.2: B = 0, each value stored at
+ *                    the first position of its output interval, then the
+ *                    running maximum of B) instead of the search of the local
+ *                    CDFs of Alg. 7.  It writes B twice and reads it once
+ *                    (12 B per key in the output stage instead of 4) but
+ *                    writes the steps one value per thread.  The library's
+ *                    own choice (every config mode) sets it when R >= 2^14
+ *                    and R >= n.
+ *  RTCDF_FLAG_COUNTERS_16 / RTCDF_FLAG_COUNTERS_32  the width of the
+ *                    histogram's LDS counters (Alg. 5): two 16-bit counters
+ *                    per 32-bit word, or one 32-bit counter, instead of the
+ *                    library's choice (32 bits where that needs no more LDS
+ *                    passes than four 8-bit counters per word, else 8 bits).
+ *                    Narrower counters fit more bins per pass but wrap
+ *                    (repaired exactly); heavily repeated keys wrap 8-bit
+ *                    counters every 256 hits.
+ *  RTCDF_FLAG_WAVE_DEDUPE  before its LDS atomics a wave matches one
+ *                    candidate value (its hot value, else its first lane's
+ *                    key) against all its keys with ballots and adds the
+ *                    copies of a frequent value once: skewed keys no longer
+ *                    serialise on one LDS address.
+ *  RTCDF_FLAG_CHUNK_4096  4096 output positions per output chunk instead
+ *                    of 2048 (fewer chunk boundaries; sparse windows of more
+ *                    than 4096 values take the slower global search).
  * A zeroed config (all fields 0) means "let the library choose" (the mode
- * set by rtcdf_set_config_mode). */
-#define RTCDF_FLAG_OUTPUT_PREFIX_MAX 1u
+ * set by rtcdf_set_config_mode).  A config with tile_width, items_per_thread
+ * and blocks_per_tile 0 and some flags means the static default table's
+ * (tile_width, items_per_thread, blocks_per_tile) for the problem with those
+ * flags (the extra points of the tuning grid are such configs). */
+#define RTCDF_FLAG_OUTPUT_PREFIX_MAX 0x01u
+#define RTCDF_FLAG_COUNTERS_16 0x04u
+#define RTCDF_FLAG_COUNTERS_32 0x08u
+#define RTCDF_FLAG_COUNTERS_MASK 0x0cu
+#define RTCDF_FLAG_WAVE_DEDUPE 0x10u
+#define RTCDF_FLAG_CHUNK_4096 0x20u
 typedef struct rtcdf_config {
   uint32_t tile_width;
   uint32_t items_per_thread;
@@ -271,26 +297,32 @@ rtcdf_status_t rtcdf_sort_batched(const rtcdf_segment_t* d_segments, uint32_t nu
 typedef enum rtcdf_config_mode {
   RTCDF_CONFIG_DEFAULT = 0,   /* static per-R table (selected by the geometric-mean method of Sec. 4.1) */
   RTCDF_CONFIG_TUNED = 1,     /* nearest entry of a loaded tuning database, else DEFAULT */
-  RTCDF_CONFIG_LEARNED = 2    /* the loaded MLP picker, else TUNED/DEFAULT */
+  RTCDF_CONFIG_LEARNED = 2    /* the loaded MLP picker (see rtcdf_load_model), else TUNED/DEFAULT */
 } rtcdf_config_mode_t;
 
 rtcdf_status_t rtcdf_set_config_mode(int mode);
 int rtcdf_get_config_mode(void);
 
-/* The tuning grid: tile width T in {2^10 .. 2^15} x items per thread in
- * {4, 8, 16} x blocks per tile in {1, 2, 4}; index i = 9 * log2(T / 1024) +
- * 3 * log2(items / 4) + log2(blocks).  Points with T * 4 * blocks > 160 KiB
- * are invalid (45 of the 54 are valid).  configs / valid: host arrays of
- * RTCDF_GRID_SIZE entries, either may be NULL. */
-#define RTCDF_GRID_SIZE 54
+/* The tuning grid, RTCDF_GRID_SIZE points.  Points 0-53: tile width T in
+ * {2^10 .. 2^15} x items per thread in {4, 8, 16} x blocks per tile in
+ * {1, 2, 4}, flags 0; index i = 9 * log2(T / 1024) + 3 * log2(items / 4) +
+ * log2(blocks).  Points with T * 4 * blocks > 160 KiB are invalid (45 of the
+ * 54).  Points 54-60, the option points: (0, 0, 0, flags), i.e. the static
+ * table's (T, items, blocks) for the problem with the flags
+ * PREFIX_MAX, COUNTERS_16, COUNTERS_16 | WAVE_DEDUPE, WAVE_DEDUPE,
+ * CHUNK_4096, COUNTERS_16 | CHUNK_4096, COUNTERS_32 (52 valid points in all).
+ * configs / valid: host arrays of RTCDF_GRID_SIZE entries, either may be
+ * NULL. */
+#define RTCDF_GRID_SIZE 61
 rtcdf_status_t rtcdf_config_grid(rtcdf_config_t* configs, uint8_t* valid);
 
 /* Exhaustive autotuner: times every valid grid configuration of the plain
  * sort of keys_in into keys_out (device arrays, as rtcdf_sort_with_config)
  * with HIP events on `stream`: `warmup` untimed sorts, then the median of
  * `reps` timed sorts.  times_ms: host array of RTCDF_GRID_SIZE (invalid
- * points get -1); *best (may be NULL) receives the fastest configuration.
- * Synchronises the stream. */
+ * points get -1); *best (may be NULL) receives the fastest configuration
+ * (an option point as its (0, 0, 0, flags) form).  keys_out holds the sorted
+ * keys afterwards.  Synchronises the stream. */
 rtcdf_status_t rtcdf_autotune(const int32_t* keys_in, int32_t* keys_out, size_t n, int64_t minVal,
                               int64_t maxVal, uint32_t warmup, uint32_t reps, float* times_ms,
                               rtcdf_config_t* best, hipStream_t stream);
@@ -301,19 +333,52 @@ rtcdf_status_t rtcdf_autotune(const int32_t* keys_in, int32_t* keys_out, size_t 
 rtcdf_status_t rtcdf_load_tuned_table(const char* path);
 
 /* LEARNED mode model: a file written by paper_2609_00843_amd/learn.py
- * ("RTCDFMLP", version 1 or 2, sizes, training ranges of log2 n and log2 R,
- * version 2 only: the decision margin and the trusted feature range zmax,
- * feature mean and sd, the RTCDF_MLP_PARAMS weights, the valid-configuration
- * mask).  The network predicts a centred log run time per grid configuration;
- * its choice is used only when it predicts at least `margin` (natural-log
- * units) less than for the configuration TUNED/DEFAULT would give, else that
- * one is kept (version 1: margin 0).  Arrays outside the training ranges of
- * log2 n and log2 R (by more than half an octave), or whose sketch features
- * lie more than zmax standard deviations from the training mean in some
- * feature (zmax 0: no such limit), fall back to TUNED, then DEFAULT.
- * rtcdf_unload_model forgets it. */
+ * ("RTCDFMLP", version 3, sizes, training ranges of log2 n and log2 R, the
+ * decision margin and the trusted feature range zmax, feature mean and sd,
+ * the RTCDF_MLP_PARAMS weights, the valid-configuration mask; files whose
+ * output count is not RTCDF_GRID_SIZE are refused).  The network predicts a
+ * centred log run time per grid point from the keys' sketch.  In LEARNED
+ * mode, a sort given no configuration (and rtcdf_pick_config with keys):
+ *  - uses the network's fastest point where it predicts at least `margin`
+ *    (natural-log units) less than for the configuration TUNED/DEFAULT would
+ *    give, else keeps that one;
+ *  - where the network is not trusted -- n or R outside its training ranges
+ *    by more than half an octave, or a sketch more than zmax standard
+ *    deviations from the training mean in some feature (zmax 0: no limit) --
+ *    times the whole grid on the keys (rtcdf_autotune, into a scratch buffer
+ *    it allocates) and uses the fastest point; that result is kept for the
+ *    shape class (n and R to half an octave, the sketch's largest bin fraction
+ *    and its position), so later arrays of the class are not timed again
+ *    (rtcdf_set_learned_fallback(0) keeps TUNED/DEFAULT there instead);
+ *  - keeps every decision for (device, keys_in, n, minVal, maxVal) until the
+ *    model changes or rtcdf_clear_pick_cache, so a buffer sorted again costs
+ *    no pick (outputs are identical whatever is chosen; only speed differs).
+ * A sort never waits for the network: its first call for a buffer enqueues
+ * the pick (one small kernel whose result lands in pinned host memory) on
+ * `stream` ahead of the sort and sorts with the TUNED/DEFAULT choice; a later
+ * call uses the decision once that kernel has finished.  The exhaustive
+ * fallback, when it runs, times the grid inside the call that decides.
+ * rtcdf_pick_config waits for the pick and decides at once.  Under stream
+ * capture the pick is skipped.  rtcdf_unload_model forgets the model. */
 rtcdf_status_t rtcdf_load_model(const char* path);
 rtcdf_status_t rtcdf_unload_model(void);
+rtcdf_status_t rtcdf_set_learned_fallback(int on);
+rtcdf_status_t rtcdf_clear_pick_cache(void);
+
+/* How the last configuration choice on this thread was made (by a sort given
+ * no configuration, or rtcdf_pick_config), and its grid index (-1 if the
+ * configuration is not a grid point). */
+typedef enum rtcdf_pick_source {
+  RTCDF_PICK_STATIC = 0,               /* TUNED/DEFAULT, the network not consulted */
+  RTCDF_PICK_NETWORK = 1,              /* the network's point */
+  RTCDF_PICK_NETWORK_KEPT_STATIC = 2,  /* the network predicted less than the margin of gain */
+  RTCDF_PICK_AUTOTUNED = 3,            /* exhaustive timing (network not trusted) */
+  RTCDF_PICK_CACHED = 4,               /* an earlier decision for the same buffer and problem */
+  RTCDF_PICK_PENDING = 5               /* the static choice: the network's pick for this buffer
+                                          is still running (a sort never waits for it) */
+} rtcdf_pick_source_t;
+int rtcdf_last_pick_source(void);
+int rtcdf_last_pick_index(void);
 
 /* ---- Learned picker kernels (the network is trained by these) ---------- */
 
@@ -325,14 +390,15 @@ rtcdf_status_t rtcdf_unload_model(void);
 #define RTCDF_SKETCH_SAMPLES 4096
 #define RTCDF_MLP_INPUTS 34
 #define RTCDF_MLP_HIDDEN 64
-#define RTCDF_MLP_OUTPUTS 54
-#define RTCDF_MLP_PARAMS 9910
+#define RTCDF_MLP_OUTPUTS 61
+#define RTCDF_MLP_PARAMS 10365
 rtcdf_status_t rtcdf_sketch(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,
                             float* d_features, hipStream_t stream);
 
-/* FP32 MLP y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 (34 -> 64 -> 64 -> 54).
+/* FP32 MLP y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 (34 -> 64 -> 64 -> 61, one
+ * output per grid point).
  * d_params: device float[RTCDF_MLP_PARAMS] laid out W1[64][34] b1 W2[64][64]
- * b2 W3[54][64] b3.  d_X: batch x 34 (row-major), d_Y: batch x 54. */
+ * b2 W3[61][64] b3.  d_X: batch x 34 (row-major), d_Y: batch x 61. */
 rtcdf_status_t rtcdf_mlp_forward(const float* d_params, const float* d_X, uint32_t batch, float* d_Y,
                                  hipStream_t stream);
 
@@ -340,7 +406,7 @@ rtcdf_status_t rtcdf_mlp_forward(const float* d_params, const float* d_X, uint32
 rtcdf_status_t rtcdf_mlp_workspace_bytes(uint32_t batch, size_t* bytes);
 
 /* Gradient of the masked mean squared error sum(M (Y - T)^2) / sum(M) over
- * the batch (d_T, d_M: batch x 54; M is 0/1) into d_grad[RTCDF_MLP_PARAMS];
+ * the batch (d_T, d_M: batch x 61; M is 0/1) into d_grad[RTCDF_MLP_PARAMS];
  * the loss into d_loss[0] if not NULL.  Deterministic (fixed-order sums).
  * Reads back the mask total (synchronises the stream). */
 rtcdf_status_t rtcdf_mlp_gradient(const float* d_params, const float* d_X, const float* d_T,
@@ -362,9 +428,10 @@ rtcdf_status_t rtcdf_mlp_train(float* d_params, float* d_m, float* d_v, uint32_t
                                hipStream_t stream);
 
 /* Sketch -> standardised features ((f - mean) / sd, d_norm = mean[34] then
- * sd[34]) -> MLP -> index of the smallest prediction among d_valid[54] != 0
- * (lowest index on ties) into d_index[0]; predictions into d_pred[54] if not
- * NULL.  One small launch, no host synchronisation. */
+ * sd[34]) -> MLP -> index of the smallest prediction among d_valid[61] != 0
+ * (lowest index on ties) into d_index[0]; predictions into d_pred[61] if not
+ * NULL.  d_params must be 16-byte aligned.  One small launch, no host
+ * synchronisation. */
 rtcdf_status_t rtcdf_mlp_pick(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,
                               const float* d_params, const float* d_norm, const uint8_t* d_valid,
                               uint32_t* d_index, float* d_pred, hipStream_t stream);
@@ -427,6 +494,8 @@ typedef struct rtcdf_plan_info {
                                   into this many buckets (one more read and write
                                   of the keys; each pass then reads its bucket
                                   only); 0: every pass reads the whole input */
+  uint32_t hist_dedupe;        /* 1: the histogram aggregates a wave's duplicates
+                                  (RTCDF_FLAG_WAVE_DEDUPE) */
 } rtcdf_plan_info_t;
 
 rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,

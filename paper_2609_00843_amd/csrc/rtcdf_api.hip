@@ -87,18 +87,49 @@ rtcdf_status_t check_problem(const int32_t* keys_in, const int32_t* keys_out, si
   return RTCDF_SUCCESS;
 }
 
+static bool flags_valid(uint32_t f) {
+  constexpr uint32_t known = RTCDF_FLAG_OUTPUT_PREFIX_MAX | RTCDF_FLAG_COUNTERS_MASK | RTCDF_FLAG_WAVE_DEDUPE |
+                             RTCDF_FLAG_CHUNK_4096;
+  if ((f & ~known) != 0) return false;
+  if ((f & RTCDF_FLAG_COUNTERS_MASK) == RTCDF_FLAG_COUNTERS_MASK) return false;   // both widths
+  return true;
+}
+
+// (T, items, blocks) all zero: the static table's for the problem (see
+// complete_config); the flags alone are then the configuration.
+static bool config_is_partial(const rtcdf_config_t& c) {
+  return c.tile_width == 0 && c.items_per_thread == 0 && c.blocks_per_tile == 0 && c.flags != 0;
+}
+
 bool config_valid(const rtcdf_config_t& c) {
+  if (!flags_valid(c.flags)) return false;
+  if (config_is_partial(c)) return true;
   if (c.tile_width < 128 || c.tile_width > 32768 || (c.tile_width % 128) != 0) return false;
   if (c.items_per_thread != 4 && c.items_per_thread != 8 && c.items_per_thread != 16) return false;
   if (c.blocks_per_tile != 1 && c.blocks_per_tile != 2 && c.blocks_per_tile != 4) return false;
   if ((uint64_t)c.tile_width * 4 * c.blocks_per_tile > kLdsBytes) return false;
-  if ((c.flags & ~(uint32_t)RTCDF_FLAG_OUTPUT_PREFIX_MAX) != 0) return false;
   return true;
 }
 
 static bool config_is_zero(const rtcdf_config_t* c) {
   return c == nullptr ||
          (c->tile_width == 0 && c->items_per_thread == 0 && c->blocks_per_tile == 0 && c->flags == 0);
+}
+
+// The full configuration of a plain sort: the library's choice for a null or
+// zeroed cfg (keys_in may be null: no learned pick then), the static table's
+// (T, items, blocks) with cfg's flags for a partial cfg, else cfg itself.
+rtcdf_status_t complete_config(const rtcdf_config_t* cfg, const int32_t* keys_in, size_t n, int64_t minVal,
+                               int64_t maxVal, hipStream_t stream, rtcdf_config_t* out) {
+  if (config_is_zero(cfg)) return pick_config(keys_in, n, minVal, maxVal, stream, out);
+  if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
+  if (config_is_partial(*cfg)) {
+    *out = static_config_for(n, (uint32_t)(maxVal - minVal));
+    out->flags = cfg->flags;
+    return RTCDF_SUCCESS;
+  }
+  *out = *cfg;
+  return RTCDF_SUCCESS;
 }
 
 // ----------------------------------------------------------------- planning
@@ -145,6 +176,10 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // two 16-bit ones at equal passes: half the partial-row traffic, wraps of hot
   // bins gathered in LDS).  16-bit counters stay selectable for measurement.
   p->bits = passes32 <= passes8 ? 32 : 8;
+  const uint32_t cw = cfg.flags & RTCDF_FLAG_COUNTERS_MASK;
+  if (cw == RTCDF_FLAG_COUNTERS_16) p->bits = 16;
+  else if (cw == RTCDF_FLAG_COUNTERS_32) p->bits = 32;
+  p->dedupe = (cfg.flags & RTCDF_FLAG_WAVE_DEDUPE) != 0 && kb == 4;
   const int force_bits = env_int("RTCDF_DEV_COUNTER_BITS", 0);
   if (force_bits == 8 || force_bits == 16 || force_bits == 32) p->bits = (uint32_t)force_bits;
   const uint32_t k = p->bits == 8 ? k8 : (p->bits == 16 ? k16 : k32);
@@ -226,6 +261,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // per-chunk work over as many bytes (measured 21-26 % faster at n = 10^8);
   // from 4 keys per value on, so that a chunk's values fit the LDS window.
   if (kb != 4 && n >= 4ull * R) want = 8192;
+  if (kb == 4 && (cfg.flags & RTCDF_FLAG_CHUNK_4096)) want = 4096;
   const int64_t force_chunk = env_int("RTCDF_DEV_FILL_CHUNK", 0);
   if (force_chunk > 0) want = (uint64_t)force_chunk;
   p->chunk = (uint32_t)((want + gran - 1) / gran * gran);
@@ -506,17 +542,6 @@ static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, ui
   return RTCDF_SUCCESS;
 }
 
-rtcdf_status_t resolve_config(const rtcdf_config_t* cfg, const int32_t* keys_in, size_t n,
-                              int64_t minVal, int64_t maxVal, hipStream_t stream,
-                              rtcdf_config_t* out) {
-  if (!config_is_zero(cfg)) {
-    if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
-    *out = *cfg;
-    return RTCDF_SUCCESS;
-  }
-  return pick_config(keys_in, n, minVal, maxVal, stream, out);
-}
-
 // kb / flip: 8- and 16-bit keys (see make_plan); their configuration never
 // takes the prefix-maximum output, and the learned picker (whose sketch
 // reads int32 keys) is not consulted for them.
@@ -535,7 +560,7 @@ static rtcdf_status_t sort_cached(const int32_t* in, int32_t* out, size_t n, int
   st = capturing(s, &cap);
   if (st != RTCDF_SUCCESS) return st;
   rtcdf_config_t c;
-  st = resolve_config(cfg, (kb == 4 && !cap) ? in : nullptr, n, minVal, maxVal, s, &c);
+  st = complete_config(cfg, (kb == 4 && !cap) ? in : nullptr, n, minVal, maxVal, s, &c);
   if (st != RTCDF_SUCCESS) return st;
   if (kb != 4) c.flags = 0;
   Plan p;
@@ -574,13 +599,8 @@ rtcdf_status_t sort_in_workspace(const int32_t* keys_in, int32_t* keys_out, size
   rtcdf_status_t st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;
   rtcdf_config_t c;
-  if (!config_is_zero(cfg)) {
-    if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
-    c = *cfg;
-  } else {
-    st = pick_config(nullptr, n, minVal, maxVal, nullptr, &c);
-    if (st != RTCDF_SUCCESS) return st;
-  }
+  st = complete_config(cfg, nullptr, n, minVal, maxVal, nullptr, &c);
+  if (st != RTCDF_SUCCESS) return st;
   Plan p;
   make_plan(n, minVal, maxVal, c, keys_in, keys_out, dev, &p);
   if (ws_bytes < p.ws_bytes) return RTCDF_ERROR_WORKSPACE_TOO_SMALL;
@@ -701,13 +721,8 @@ rtcdf_status_t rtcdf_workspace_bytes(size_t n, int64_t minVal, int64_t maxVal,
   st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;
   rtcdf_config_t c;
-  if (!config_is_zero(cfg)) {
-    if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
-    c = *cfg;
-  } else {
-    st = pick_config(nullptr, n, minVal, maxVal, nullptr, &c);
-    if (st != RTCDF_SUCCESS) return st;
-  }
+  st = complete_config(cfg, nullptr, n, minVal, maxVal, nullptr, &c);
+  if (st != RTCDF_SUCCESS) return st;
   Plan p;
   // The layout depends on n, R, the config and keys_out's alignment (output
   // chunk starts); keys_in's alignment changes only the histogram's head and
@@ -836,6 +851,8 @@ rtcdf_status_t rtcdf_profile_collect(rtcdf_stage_stats_t* out) {
 
 int rtcdf_version(void) { return 100; }
 
+static_assert(sizeof(rtcdf_plan_info_t) == 72, "rtcdf_plan_info_t layout (the Python binding mirrors it)");
+
 rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t* cfg,
                                const int32_t* keys_in, const int32_t* keys_out, rtcdf_plan_info_t* out) {
   if (out == nullptr || n == 0) return RTCDF_ERROR_INVALID_VALUE;
@@ -846,13 +863,8 @@ rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const r
   st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;
   rtcdf_config_t c;
-  if (!config_is_zero(cfg)) {
-    if (!config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
-    c = *cfg;
-  } else {
-    st = pick_config(nullptr, n, minVal, maxVal, nullptr, &c);
-    if (st != RTCDF_SUCCESS) return st;
-  }
+  st = complete_config(cfg, nullptr, n, minVal, maxVal, nullptr, &c);
+  if (st != RTCDF_SUCCESS) return st;
   Plan p;
   make_plan(n, minVal, maxVal, c, keys_in ? keys_in : probe, keys_out ? keys_out : probe, dev, &p);
   out->tile_width = p.T;
@@ -870,6 +882,7 @@ rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const r
   out->workspace_bytes = p.ws_bytes;
   out->output_flags = p.pmax ? RTCDF_FLAG_OUTPUT_PREFIX_MAX : 0u;
   out->partition_buckets = p.part ? p.part_buckets : 0u;
+  out->hist_dedupe = p.dedupe ? 1u : 0u;
   return RTCDF_SUCCESS;
 }
 

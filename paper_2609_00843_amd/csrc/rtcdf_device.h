@@ -231,6 +231,27 @@ __device__ __forceinline__ void hot_flush(HotBin& hot, uint32_t* tab, uint32_t* 
   hot.cnt = 0;
 }
 
+// Flush of the hot-bin register in every counter width: into the wrap table
+// for the narrow forms, straight into the LDS counter for 32-bit counters
+// (which cannot wrap).
+template <int BITS, bool PAD>
+__device__ __forceinline__ void hot_flush_any(HotBin& hot, uint32_t* S, uint32_t* tab, uint32_t* carry,
+                                              uint32_t pass_lo) {
+  if constexpr (BITS < 32) {
+    hot_flush(hot, tab, carry, pass_lo);
+  } else {
+    if (hot.cnt && lane_id() == (uint32_t)(__ffsll((unsigned long long)__ballot(1)) - 1))
+      atomicAdd(&S[PAD ? pad32(hot.bin) : hot.bin], hot.cnt);
+    hot.cnt = 0;
+  }
+}
+
+// Wave-level aggregation (RTCDF_FLAG_WAVE_DEDUPE): a candidate value with at
+// least this many copies among a wave's 4 x 64 keys is counted once.  (Up to
+// four candidates per vector were measured slower on every workload: the
+// extra ballots cost more than the LDS conflicts they remove.)
+constexpr uint32_t kDedupeMin = 8;
+
 // Four 8-bit counters per LDS word (bin x in byte x & 3 of word x >> 2).  An
 // add of c << 8s changes the bytes above s through carries; every byte whose
 // represented change differs from its true change (c for byte s, 0 above) is
@@ -267,11 +288,18 @@ __device__ __forceinline__ uint32_t shl1(uint32_t s) {
   return r;
 }
 
-template <int BITS, bool PAD = false>
+// DEDUPE (RTCDF_FLAG_WAVE_DEDUPE; the hot-bin register must then be flushed
+// with hot_flush_any after the last count): when the wave's keys are not all
+// one value, a candidate value -- the wave's hot bin, else the first lane's
+// first key -- is matched against the wave's 4 x 64 keys with four ballots;
+// if it has kDedupeMin or more copies they are added to the hot-bin register
+// at once and skip their LDS atomics (a frequent value would otherwise put
+// many lanes of one atomic on one LDS word, and wrap 8-bit counters).
+template <int BITS, bool PAD = false, bool DEDUPE = false>
 __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32_t W,
                                        uint32_t* carry, uint32_t pass_lo, uint32_t* tab, HotBin& hot) {
-  const uint32_t x0 = (uint32_t)k.x - base, x1 = (uint32_t)k.y - base;
-  const uint32_t x2 = (uint32_t)k.z - base, x3 = (uint32_t)k.w - base;
+  uint32_t x0 = (uint32_t)k.x - base, x1 = (uint32_t)k.y - base;
+  uint32_t x2 = (uint32_t)k.z - base, x3 = (uint32_t)k.w - base;
   const uint32_t lead = (uint32_t)__builtin_amdgcn_readfirstlane((int)x0);
   const uint64_t active = __ballot(1);
   // the other three keys are compared only when every first key matches
@@ -295,6 +323,31 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
       }
     }
     return;
+  }
+  if constexpr (DEDUPE) {
+    uint32_t cand = hot.bin != kWrapEmpty ? hot.bin : lead;
+    uint32_t c = (uint32_t)(__popcll(__ballot(x0 == cand)) + __popcll(__ballot(x1 == cand)) +
+                            __popcll(__ballot(x2 == cand)) + __popcll(__ballot(x3 == cand)));
+    if (c < kDedupeMin && cand != lead) {
+      cand = lead;
+      c = (uint32_t)(__popcll(__ballot(x0 == cand)) + __popcll(__ballot(x1 == cand)) +
+                     __popcll(__ballot(x2 == cand)) + __popcll(__ballot(x3 == cand)));
+    }
+    if (c >= kDedupeMin) {
+      if (cand < W) {
+        if (cand != hot.bin) {
+          hot_flush_any<BITS, PAD>(hot, S, tab, carry, pass_lo);
+          hot.bin = cand;
+        }
+        hot.cnt += c;
+      }
+      // the copies are counted (or lie outside this pass): none takes an atomic
+      constexpr uint32_t kNone = 0xffffffffu;
+      x0 = x0 == cand ? kNone : x0;
+      x1 = x1 == cand ? kNone : x1;
+      x2 = x2 == cand ? kNone : x2;
+      x3 = x3 == cand ? kNone : x3;
+    }
   }
   if constexpr (BITS == 16 || BITS == 8) {
     // Bin x is the field at bit (x & (32 / BITS - 1)) * BITS of word x >> LOG.

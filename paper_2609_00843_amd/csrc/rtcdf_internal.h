@@ -54,7 +54,7 @@ constexpr int kSketchBins = 32;
 constexpr uint32_t kSketchSamples = 4096;
 constexpr int kMlpIn = 2 + kSketchBins;      // log2 n, log2 R, bin fractions
 constexpr int kMlpHidden = 64;
-constexpr int kMlpOut = 54;                  // the configuration grid
+constexpr int kMlpOut = RTCDF_GRID_SIZE;     // the configuration grid
 constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
                            kMlpOut * kMlpHidden + kMlpOut;
 
@@ -74,6 +74,7 @@ struct Plan {
   uint32_t items, bpt;
   // histogram passes
   uint32_t bits;         // LDS counter width: 32, 16 (two per word) or 8 (four per word)
+  bool dedupe;           // wave-level aggregation of a frequent value before the LDS atomics
   uint32_t W;            // bins per LDS pass (multiple of 128, or R rounded up when one pass)
   uint32_t passes;       // ceil(R / W)
   uint32_t G;            // workgroups (input chunks) per pass, multiple of 8
@@ -168,11 +169,17 @@ hipError_t launch_mlp_grad(const float* P, const float* X, const float* T, const
 size_t mlp_grad_scratch_floats(uint32_t B);
 hipError_t launch_adam(float* P, const float* G, float* Mo, float* Vo, float lr, float b1, float b2,
                        float eps, uint32_t t, hipStream_t s);
-// out_pred (54 predictions) and out_zmax (the largest |normalised feature|)
-// may be null.
+// out_pred (kMlpOut predictions), out_zmax (the largest |normalised
+// feature|) and out_feat (the kMlpIn raw sketch features) may be null.  With
+// acc (kPickAccWords device words, zero, returned to zero by the kernel) the
+// sampling is spread over kPickGroups workgroups; without it one workgroup
+// samples (the same features and outputs either way).
+constexpr uint32_t kPickGroups = 16;
+constexpr uint32_t kPickAccWords = kSketchBins + 1;
 hipError_t launch_pick(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R, uint32_t samples,
                        const float* P, const float* norm, const uint8_t* valid, uint32_t* out_index,
-                       float* out_pred, float* out_zmax, hipStream_t s);
+                       float* out_pred, float* out_zmax, float* out_feat, hipStream_t s,
+                       uint32_t* acc = nullptr);
 
 // Host helpers shared by the C ABI translation units (rtcdf_api.hip).
 rtcdf_status_t device_info(DeviceInfo* out);
@@ -197,9 +204,20 @@ rtcdf_status_t sort_in_workspace(const int32_t* keys_in, int32_t* keys_out, size
                                  int64_t maxVal, const rtcdf_config_t* cfg, void* d_ws, size_t ws_bytes,
                                  hipStream_t stream);
 
+// The full configuration of a plain sort from the caller's cfg (null or
+// zeroed: the library's choice for the config mode, with the learned pick only
+// when keys_in is given; partial: the static table's knobs with cfg's flags).
+rtcdf_status_t complete_config(const rtcdf_config_t* cfg, const int32_t* keys_in, size_t n, int64_t minVal,
+                               int64_t maxVal, hipStream_t stream, rtcdf_config_t* out);
+// The static default table's configuration for (n, R) (flags 0).
+rtcdf_config_t static_config_for(size_t n, uint32_t R);
+
 // Configuration source (rtcdf_config.hip): the choice rtcdf_sort makes when the
 // caller gives no config, under the current config mode.
+// With keys_in in LEARNED mode, wait false never waits for the network's pick
+// (the first sort of a buffer enqueues it and gets the static choice), wait
+// true waits for it.
 rtcdf_status_t pick_config(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,
-                           hipStream_t stream, rtcdf_config_t* out);
+                           hipStream_t stream, rtcdf_config_t* out, bool wait = false);
 
 }  // namespace rtcdf

@@ -65,12 +65,12 @@ struct HistArgs {
 // One 16-byte vector of keys: 4 int32 keys, or 8 / 16 narrow keys widened in
 // groups of four.  Lanes without a valid vector count `outside` (every group,
 // so that the wave-wide ballots inside count4 see every lane).
-template <int BITS, int KB>
+template <int BITS, int KB, bool DEDUPE = false>
 __device__ __forceinline__ void count_vec(uint32_t* S, v4i v, bool valid, v4i outside, uint32_t flip,
                                           uint32_t base, uint32_t W, uint32_t* carry, uint32_t pass_lo,
                                           uint32_t* tab, HotBin& hot) {
   if constexpr (KB == 4) {
-    count4<BITS>(S, valid ? v : outside, base, W, carry, pass_lo, tab, hot);
+    count4<BITS, false, DEDUPE>(S, valid ? v : outside, base, W, carry, pass_lo, tab, hot);
   } else if constexpr (KB == 2) {
     const uint32_t f = flip | (flip << 16);
     const uint32_t w[4] = {(uint32_t)v.x ^ f, (uint32_t)v.y ^ f, (uint32_t)v.z ^ f, (uint32_t)v.w ^ f};
@@ -100,7 +100,10 @@ __device__ __forceinline__ int32_t load_key(const int32_t* keys, size_t i, uint3
   else return (int32_t)(reinterpret_cast<const uint8_t*>(keys)[i] ^ flip);
 }
 
-template <int ITEMS, int BITS, int BLOCK, int KB = 4>
+// DEDUPE: wave-level aggregation of frequent values (RTCDF_FLAG_WAVE_DEDUPE,
+// int32 keys only), a separate instantiation so that the default counting
+// loop carries none of its instructions.
+template <int ITEMS, int BITS, int BLOCK, int KB = 4, bool DEDUPE = false>
 __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   // The planner's LDS budget: kLdsBytes per 1024 threads (one workgroup per
   // compute unit at 1024 threads, two at 512, four at 256).  A static array
@@ -174,12 +177,12 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
       if (tb + V * BLOCK <= end) {
 #pragma unroll
         for (int j = 0; j < V; ++j)
-          count_vec<BITS, KB>(S, cur[j], true, outside, a.flip, base, W, a.carry, pass_lo, tab, hot);
+          count_vec<BITS, KB, DEDUPE>(S, cur[j], true, outside, a.flip, base, W, a.carry, pass_lo, tab, hot);
       } else {
 #pragma unroll
         for (int j = 0; j < V; ++j)
-          count_vec<BITS, KB>(S, cur[j], t0 + j * BLOCK < end, outside, a.flip, base, W, a.carry, pass_lo,
-                              tab, hot);
+          count_vec<BITS, KB, DEDUPE>(S, cur[j], t0 + j * BLOCK < end, outside, a.flip, base, W, a.carry,
+                                      pass_lo, tab, hot);
       }
 #pragma unroll
       for (int j = 0; j < V; ++j) cur[j] = nxt[j];
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   if (chunk == a.G - 1 && threadIdx.x < in_tail)
     e.y = load_key<KB>(keys, in_head + VK * (size_t)in_n4 + threadIdx.x, a.flip);
   if (threadIdx.x < 64) count4<BITS>(S, e, base, W, a.carry, pass_lo, tab, hot);
-  if constexpr (BITS < 32) hot_flush(hot, tab, a.carry, pass_lo);
+  if constexpr (BITS < 32 || DEDUPE) hot_flush_any<BITS, false>(hot, S, tab, a.carry, pass_lo);
   __syncthreads();
   if constexpr (BITS < 32) wrap_flush(tab, a.carry, pass_lo, threadIdx.x);
 
@@ -1000,12 +1003,12 @@ __global__ void k_clear(uint32_t* p, size_t words) {
     p[i] = 0u;
 }
 
-template <int ITEMS, int BITS, int BLOCK, int KB = 4>
+template <int ITEMS, int BITS, int BLOCK, int KB = 4, bool DEDUPE = false>
 hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
   // the counters (and the narrow forms' wrap table) fit the static LDS array
   const size_t lds = ((size_t)p.row_words + (BITS < 32 ? 2 * kWrapSlots : 0)) * 4;
   if (lds > kLdsBytes / (1024 / BLOCK)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_hist<ITEMS, BITS, BLOCK, KB>), dim3(p.passes * p.G), dim3(BLOCK), 0, s, a);
+  hipLaunchKernelGGL((k_hist<ITEMS, BITS, BLOCK, KB, DEDUPE>), dim3(p.passes * p.G), dim3(BLOCK), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1014,6 +1017,13 @@ hipError_t launch_hist_items(const Plan& p, const HistArgs& a, hipStream_t s) {
   // 8- and 16-bit keys: one 16-byte vector (16 or 8 keys) per thread per step
   if (p.kb == 2) return launch_hist_t<4, BITS, BLOCK, 2>(p, a, s);
   if (p.kb == 1) return launch_hist_t<4, BITS, BLOCK, 1>(p, a, s);
+  if (p.dedupe) {
+    switch (p.items) {
+      case 4: return launch_hist_t<4, BITS, BLOCK, 4, true>(p, a, s);
+      case 8: return launch_hist_t<8, BITS, BLOCK, 4, true>(p, a, s);
+      default: return launch_hist_t<16, BITS, BLOCK, 4, true>(p, a, s);
+    }
+  }
   switch (p.items) {
     case 4: return launch_hist_t<4, BITS, BLOCK>(p, a, s);
     case 8: return launch_hist_t<8, BITS, BLOCK>(p, a, s);

@@ -21,6 +21,8 @@ constexpr int D0 = kMlpIn, H = kMlpHidden, D3 = kMlpOut;
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + H * D0, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H;
 constexpr int OFF_W3 = OFF_B2 + H, OFF_B3 = OFF_W3 + D3 * H, NPARAM = OFF_B3 + D3;
 static_assert(NPARAM == kMlpParams, "parameter layout");
+static_assert(D3 <= 64 && H == 64, "one 64-thread workgroup computes every unit of a layer");
+static_assert(NPARAM * 4 + 1024 < 65536, "the pick kernel stages every weight in LDS");
 
 // ---------------------------------------------------------------- sketch
 
@@ -34,11 +36,24 @@ __device__ void sketch_block(const int32_t* keys, uint64_t n, int64_t minVal, ui
   if (tid < kSketchBins) bins[tid] = 0;
   __syncthreads();
   const uint64_t S = n < samples ? n : samples;
-  for (uint64_t i = tid; i < S; i += blockDim.x) {
-    const uint64_t pos = (i * n) / S;
-    const int64_t key = keys[pos];
-    const uint64_t b = ((uint64_t)(key - minVal) * kSketchBins) / R;
-    atomicAdd(&bins[b < kSketchBins ? b : kSketchBins - 1], 1u);
+  // The sample loads of a thread are issued together (kBatch in flight), then
+  // binned: a scattered load costs a memory latency, not a bandwidth.
+  constexpr uint32_t kBatch = 16;
+  for (uint64_t i0 = 0; i0 < S; i0 += (uint64_t)kBatch * blockDim.x) {
+    int32_t key[kBatch];
+#pragma unroll
+    for (uint32_t k = 0; k < kBatch; ++k) {
+      const uint64_t i = i0 + (uint64_t)k * blockDim.x + tid;
+      key[k] = i < S ? keys[(i * n) / S] : 0;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kBatch; ++k) {
+      const uint64_t i = i0 + (uint64_t)k * blockDim.x + tid;
+      if (i < S) {
+        const uint64_t b = ((uint64_t)((int64_t)key[k] - minVal) * kSketchBins) / R;
+        atomicAdd(&bins[b < kSketchBins ? b : kSketchBins - 1], 1u);
+      }
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -60,7 +75,7 @@ __global__ __launch_bounds__(256) void k_sketch(const int32_t* keys, uint64_t n,
 // ---------------------------------------------------------------- forward
 
 // One workgroup of 64 threads per sample; thread j computes hidden unit j (and
-// output unit j when j < 54).  Stores Z1, Z2 (pre-activations) and Y.
+// output unit j when j < D3 <= 64).  Stores Z1, Z2 (pre-activations) and Y.
 __device__ void mlp_forward_sample(const float* P, const float* x, float* z1, float* z2, float* y,
                                    float* h /* LDS, 2 * 64 */) {
   const int j = threadIdx.x;
@@ -201,17 +216,34 @@ __global__ void k_sum_loss(const float* lossterm, uint32_t B, float inv_count, f
 
 // ---------------------------------------------------------------- pick
 
-// Sketch -> standardised features -> MLP -> argmin over the valid
-// configurations (lowest index on ties).  One workgroup of 256 threads.
-__global__ __launch_bounds__(256) void k_pick(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R,
-                                              uint32_t samples, const float* P, const float* norm,
-                                              const uint8_t* valid, uint32_t* out_index, float* out_pred,
-                                              float* out_zmax) {
-  __shared__ uint32_t bins[kSketchBins];
-  __shared__ float f[D0];
-  __shared__ float h[2 * H];
-  __shared__ float y[D3];
-  sketch_block(keys, n, minVal, R, samples, f, bins);
+// The network and the masked argmin for one array, by one workgroup of 256
+// threads, from the raw features f (LDS, D0 floats; standardised in place).
+// The weights are first staged into LDS (Ps) with coalesced loads; each unit's
+// dot product is split over 4 threads and combined with lane shuffles.
+__device__ void pick_block(const float* P, const float* norm, const uint8_t* valid, float* f, float* Ps,
+                           float* h, float* y, uint32_t* out_index, float* out_pred, float* out_zmax,
+                           float* out_feat) {
+  {
+    // every load of the staging is issued before the first store (16-byte
+    // vectors; P and Ps are 16-byte aligned), then the scalar tail
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    constexpr int kV = NPARAM / 4, kPer = (kV + 255) / 256;
+    const v4f* P4 = reinterpret_cast<const v4f*>(P);
+    v4f r[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = (int)threadIdx.x + k * 256;
+      r[k] = P4[i < kV ? i : kV - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = (int)threadIdx.x + k * 256;
+      if (i < kV) reinterpret_cast<v4f*>(Ps)[i] = r[k];
+    }
+    for (int i = 4 * kV + (int)threadIdx.x; i < NPARAM; i += 256) Ps[i] = P[i];
+  }
+  if (out_feat && threadIdx.x < D0) out_feat[threadIdx.x] = f[threadIdx.x];
+  __syncthreads();
   if (threadIdx.x < D0) f[threadIdx.x] = (f[threadIdx.x] - norm[threadIdx.x]) / norm[D0 + threadIdx.x];
   __syncthreads();
   if (out_zmax && threadIdx.x == 0) {   // distance from the training features, in sd units
@@ -219,33 +251,114 @@ __global__ __launch_bounds__(256) void k_pick(const int32_t* keys, uint64_t n, i
     for (int i = 0; i < D0; ++i) z = fmaxf(z, fabsf(f[i]));
     out_zmax[0] = z;
   }
-  // All 256 threads take part in the barriers; the first 64 compute.
-  const int j = threadIdx.x;
-  if (j < H) {
-    float a = P[OFF_B1 + j];
-    for (int i = 0; i < D0; ++i) a = fmaf(P[OFF_W1 + j * D0 + i], f[i], a);
-    h[j] = fmaxf(a, 0.f);
-  }
+  // unit j of a layer: threads 4j .. 4j + 3, thread q sums the inputs i = q mod 4
+  const int j = threadIdx.x >> 2, q = threadIdx.x & 3;
+  float a = 0.f;
+  for (int i = q; i < D0; i += 4) a = fmaf(Ps[OFF_W1 + j * D0 + i], f[i], a);
+  a += __shfl_xor(a, 1, 64);
+  a += __shfl_xor(a, 2, 64);
+  if (q == 0) h[j] = fmaxf(a + Ps[OFF_B1 + j], 0.f);
   __syncthreads();
-  if (j < H) {
-    float b = P[OFF_B2 + j];
-    for (int i = 0; i < H; ++i) b = fmaf(P[OFF_W2 + j * H + i], h[i], b);
-    h[H + j] = fmaxf(b, 0.f);
-  }
+  float b = 0.f;
+  for (int i = q; i < H; i += 4) b = fmaf(Ps[OFF_W2 + j * H + i], h[i], b);
+  b += __shfl_xor(b, 1, 64);
+  b += __shfl_xor(b, 2, 64);
+  if (q == 0) h[H + j] = fmaxf(b + Ps[OFF_B2 + j], 0.f);
   __syncthreads();
-  if (j < D3) {
-    float c = P[OFF_B3 + j];
-    for (int i = 0; i < H; ++i) c = fmaf(P[OFF_W3 + j * H + i], h[H + i], c);
+  float c = 0.f;
+  if (j < D3)
+    for (int i = q; i < H; i += 4) c = fmaf(Ps[OFF_W3 + j * H + i], h[H + i], c);
+  c += __shfl_xor(c, 1, 64);
+  c += __shfl_xor(c, 2, 64);
+  if (j < D3 && q == 0) {
+    c += Ps[OFF_B3 + j];
     y[j] = c;
     if (out_pred) out_pred[j] = c;
   }
   __syncthreads();
-  if (j == 0) {
+  if (threadIdx.x == 0) {
     int best = -1;
     for (int k = 0; k < D3; ++k)
       if (valid[k] && (best < 0 || y[k] < y[best])) best = k;
     out_index[0] = (uint32_t)best;
   }
+}
+
+// Sketch -> standardised features -> MLP -> argmin over the valid
+// configurations (lowest index on ties).  One workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_pick(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R,
+                                              uint32_t samples, const float* P, const float* norm,
+                                              const uint8_t* valid, uint32_t* out_index, float* out_pred,
+                                              float* out_zmax, float* out_feat) {
+  __shared__ __align__(16) float Ps[NPARAM];
+  __shared__ uint32_t bins[kSketchBins];
+  __shared__ float f[D0];
+  __shared__ float h[2 * H];
+  __shared__ float y[D3];
+  sketch_block(keys, n, minVal, R, samples, f, bins);
+  pick_block(P, norm, valid, f, Ps, h, y, out_index, out_pred, out_zmax, out_feat);
+}
+
+// The same pick with the sampling spread over gridDim.x workgroups (the
+// sample loads are scattered over the whole array, and one compute unit keeps
+// only so many misses in flight).  Each workgroup bins its share of the S
+// samples (sample i at position floor(i n / S), as in sketch_block) and adds
+// its bin counts to acc[0, 32); the last workgroup to finish (counter
+// acc[32]) reads them, returns acc to zero for the next pick and runs the
+// network.  acc must be zero on entry.
+__global__ __launch_bounds__(256) void k_pick_spread(const int32_t* keys, uint64_t n, int64_t minVal,
+                                                     uint64_t R, uint32_t samples, const float* P,
+                                                     const float* norm, const uint8_t* valid,
+                                                     uint32_t* acc, uint32_t* out_index, float* out_pred,
+                                                     float* out_zmax, float* out_feat) {
+  __shared__ __align__(16) float Ps[NPARAM];
+  __shared__ uint32_t bins[kSketchBins];
+  __shared__ float f[D0];
+  __shared__ float h[2 * H];
+  __shared__ float y[D3];
+  __shared__ uint32_t last;
+  const uint32_t tid = threadIdx.x, G = gridDim.x, w = blockIdx.x;
+  if (tid < kSketchBins) bins[tid] = 0;
+  __syncthreads();
+  const uint64_t S = n < samples ? n : samples;
+  const uint64_t i0 = S * w / G, i1 = S * (w + 1) / G;
+  constexpr uint32_t kBatch = 4;
+  for (uint64_t b0 = i0; b0 < i1; b0 += (uint64_t)kBatch * 256) {
+    int32_t key[kBatch];
+#pragma unroll
+    for (uint32_t k = 0; k < kBatch; ++k) {
+      const uint64_t i = b0 + (uint64_t)k * 256 + tid;
+      key[k] = i < i1 ? keys[(i * n) / S] : 0;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kBatch; ++k) {
+      const uint64_t i = b0 + (uint64_t)k * 256 + tid;
+      if (i < i1) {
+        const uint64_t b = ((uint64_t)((int64_t)key[k] - minVal) * kSketchBins) / R;
+        atomicAdd(&bins[b < kSketchBins ? b : kSketchBins - 1], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < kSketchBins && bins[tid]) atomicAdd(&acc[tid], bins[tid]);
+  __threadfence();   // this workgroup's counts are visible before it is counted as done
+  __syncthreads();
+  if (tid == 0) last = atomicAdd(&acc[kSketchBins], 1u) == G - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (tid < kSketchBins) {
+    const uint32_t c = __hip_atomic_load(&acc[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    f[2 + tid] = S ? (float)c / (float)S : 0.f;
+    acc[tid] = 0u;
+  }
+  if (tid == 0) {
+    acc[kSketchBins] = 0u;
+    f[0] = n ? log2f((float)n) : 0.f;
+    f[1] = log2f((float)R);
+  }
+  __syncthreads();
+  pick_block(P, norm, valid, f, Ps, h, y, out_index, out_pred, out_zmax, out_feat);
 }
 
 }  // namespace
@@ -264,7 +377,7 @@ hipError_t launch_mlp_forward(const float* P, const float* X, uint32_t B, float*
 }
 
 // Gradient of the masked MSE at P over the batch (X, T, M) into G; loss into
-// *loss_dev.  scratch: 2 * B * 64 + 2 * B * 64 + B * 54 + B * 54 + B floats.
+// *loss_dev.  scratch: 4 * B * H + 2 * B * D3 + B floats.
 hipError_t launch_mlp_grad(const float* P, const float* X, const float* T, const float* M, uint32_t B,
                            float inv_count, float* G, float* loss_dev, float* scratch, hipStream_t s) {
   if (B == 0) return hipSuccess;
@@ -297,9 +410,14 @@ hipError_t launch_adam(float* P, const float* G, float* Mo, float* Vo, float lr,
 
 hipError_t launch_pick(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R, uint32_t samples,
                        const float* P, const float* norm, const uint8_t* valid, uint32_t* out_index,
-                       float* out_pred, float* out_zmax, hipStream_t s) {
+                       float* out_pred, float* out_zmax, float* out_feat, hipStream_t s, uint32_t* acc) {
+  if (acc != nullptr) {
+    hipLaunchKernelGGL(k_pick_spread, dim3(kPickGroups), dim3(256), 0, s, keys, n, minVal, R, samples, P, norm,
+                       valid, acc, out_index, out_pred, out_zmax, out_feat);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_pick, dim3(1), dim3(256), 0, s, keys, n, minVal, R, samples, P, norm, valid,
-                     out_index, out_pred, out_zmax);
+                     out_index, out_pred, out_zmax, out_feat);
   return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@ squared error).
 
     python -m paper_2609_00843_amd.learn train --db TRAIN.jsonl --out MODEL.bin
     python -m paper_2609_00843_amd.learn evaluate --db TEST.jsonl --model MODEL.bin
+    python -m paper_2609_00843_amd.learn heldout --model MODEL.bin --out EVAL.json
 
 A checkpoint (.npz next to the model: weights, Adam moments, step, feature
 normalisation, loss history) lets training resume.
@@ -37,14 +38,17 @@ import numpy as np
 
 from . import tune
 
-SIZES = (34, 64, 64, 54)
+NOUT = len(tune.grid()[0])          # one network output per grid point
+SIZES = (34, 64, 64, NOUT)
+NPARAMS = sum(SIZES[i + 1] * SIZES[i] + SIZES[i + 1] for i in range(3))
+MODEL_VERSION = 3
 
 
 def dataset(rows):
     _, valid = tune.grid()
     X = np.array([r["features"] for r in rows], dtype=np.float64)
-    T = np.zeros((len(rows), 54))
-    M = np.zeros((len(rows), 54))
+    T = np.zeros((len(rows), NOUT))
+    M = np.zeros((len(rows), NOUT))
     for i, r in enumerate(rows):
         t = np.array(r["times_ms"], dtype=np.float64)
         ok = np.array(valid) & (t > 0)
@@ -82,11 +86,12 @@ def zmax_of(X, mu, sd) -> float:
 
 
 def save_model(path: str, params, mu, sd, ranges, margin: float = 0.0, zmax: float = 0.0):
-    """Model file version 2 (version 1 has no margin and zmax fields)."""
+    """Model file version 3 (the grid with option points; version 1 had no
+    margin and zmax fields, versions 1 and 2 the 54-point grid)."""
     _, valid = tune.grid()
     with open(path, "wb") as f:
         f.write(b"RTCDFMLP")
-        f.write(struct.pack("<5I", 2, 34, 64, 54, 9910))
+        f.write(struct.pack("<5I", MODEL_VERSION, 34, 64, NOUT, NPARAMS))
         f.write(struct.pack("<4f", *ranges))
         f.write(struct.pack("<2f", margin, zmax))
         f.write(np.asarray(mu, dtype=np.float32).tobytes())
@@ -139,38 +144,40 @@ def predict(params, mu, sd, X):
 
 
 def load_model_file(path: str):
-    """(params, mean, sd, ranges, margin, zmax) of a model file of version 1 or 2."""
+    """(params, mean, sd, ranges, margin, zmax) of a model file of version 1,
+    2 or 3 (its parameter count is read from the header)."""
     with open(path, "rb") as f:
         raw = f.read()
     assert raw[:8] == b"RTCDFMLP"
-    version = struct.unpack("<I", raw[8:12])[0]
-    assert version in (1, 2)
+    version, _, _, _, nparams = struct.unpack("<5I", raw[8:28])
+    assert version in (1, 2, 3)
     o = 8 + 20
     ranges = struct.unpack("<4f", raw[o:o + 16])
     o += 16
     margin = zmax = 0.0
-    if version == 2:
+    if version >= 2:
         margin, zmax = struct.unpack("<2f", raw[o:o + 8])
         o += 8
     mu = np.frombuffer(raw, dtype=np.float32, count=34, offset=o).astype(np.float64)
     o += 136
     sd = np.frombuffer(raw, dtype=np.float32, count=34, offset=o).astype(np.float64)
     o += 136
-    params = np.frombuffer(raw, dtype=np.float32, count=9910, offset=o).copy()
+    params = np.frombuffer(raw, dtype=np.float32, count=nparams, offset=o).copy()
     return params, mu, sd, ranges, margin, zmax
 
 
 def static_indices(rows):
-    """Grid index of the static table's configuration for every row (the
-    library's DEFAULT pick, host logic only)."""
+    """Grid index of the static choice for every row (the library's DEFAULT
+    pick: the static table and the output-method rule; host logic only)."""
     from . import rtcdf
-    pts, _ = tune.grid()
-    idx_of = {p: i for i, p in enumerate(pts)}
     old = rtcdf.get_config_mode()
     rtcdf.set_config_mode(rtcdf.CONFIG_DEFAULT)
     try:
-        return [idx_of[rtcdf.pick_config(r["n"], r["minVal"], r["minVal"] + r["R"]).as_tuple()]
-                for r in rows]
+        out = []
+        for r in rows:
+            rtcdf.pick_config(r["n"], r["minVal"], r["minVal"] + r["R"])
+            out.append(rtcdf.last_pick()[0])
+        return out
     finally:
         rtcdf.set_config_mode(old)
 
@@ -181,7 +188,7 @@ def decide(y, ok, static: int, margin: float, trusted: bool = True) -> int:
     static choice."""
     if not trusted:
         return static
-    pick = min((y[j], j) for j in range(54) if ok[j])[1]
+    pick = min((y[j], j) for j in range(len(y)) if ok[j])[1]
     if ok[static] and y[static] - y[pick] < margin:
         return static
     return pick
@@ -252,6 +259,121 @@ def evaluate(rows, model_path: str):
     return res, per
 
 
+def time_config(torch, rtcdf, a, b, lo, hi, cfg, warmup=10, reps=30, runs=3):
+    """Median over `runs` runs of the median of `reps` sorts, each bracketed by
+    HIP events on the stream, after `warmup` untimed sorts (the paper's
+    protocol: the median of 3 run-medians of 30 after 10 warm-ups)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        rtcdf.sort(a, lo, hi, keys_out=b, config=cfg, stream=stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    meds = []
+    for _ in range(runs):
+        for e0, e1 in ev:
+            e0.record(stream)
+            rtcdf.sort(a, lo, hi, keys_out=b, config=cfg, stream=stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        meds.append(float(np.median([e0.elapsed_time(e1) for e0, e1 in ev])))
+    return float(np.median(meds))
+
+
+PICK_NAMES = {0: "static", 1: "network", 2: "network_kept_static", 3: "autotuned", 4: "cached", 5: "pending"}
+
+
+def evaluate_retimed(specs, model_path: str, warmup: int = 10, reps: int = 30, runs: int = 3,
+                     tune_reps: int = 5, log=print):
+    """Held-out evaluation with every time measured in this run, on the GPU.
+    Per array (generated on the device from its spec):
+      1. exhaustive autotuning of the whole grid (the judge of regret);
+      2. the library's LEARNED decision from a cold decision cache (its pick
+         time measured, including any exhaustive fallback), and the time of
+         the same call once the decision is cached;
+      3. the static choice (DEFAULT mode), the learned choice and the
+         exhaustive best re-timed by time_config (median of run-medians).
+    Gain = t(static) / t(learned) (steady state: the decision made once); the
+    gains with one cold pick per K sorts are reported beside it."""
+    import time
+    import torch
+    from . import inputs, rtcdf
+    pts, valid = tune.grid()
+    rtcdf.load_model(model_path)
+    old = rtcdf.get_config_mode()
+    per = []
+    try:
+        for k, s in enumerate(specs):
+            n, lo = s["n"], s["minVal"]
+            hi = lo + s["R"]
+            a = inputs.make_device(s["dist"], n, lo, hi, s["seed"], sd_div=s["sd_div"])
+            b = torch.empty_like(a)
+            torch.cuda.synchronize()
+            rtcdf.set_config_mode(rtcdf.CONFIG_DEFAULT)
+            cfg_s = rtcdf.pick_config(n, lo, hi)
+            i_s = rtcdf.last_pick()[0]
+            times, _ = rtcdf.autotune(a, lo, hi, keys_out=b, warmup=2, reps=tune_reps)
+            i_b = min((t, j) for j, t in enumerate(times) if valid[j] and t > 0)[1]
+            rtcdf.set_config_mode(rtcdf.CONFIG_LEARNED)
+            rtcdf.clear_pick_cache()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cfg_l = rtcdf.pick_config(n, lo, hi, keys_in=a)
+            pick_ms = (time.perf_counter() - t0) * 1e3
+            i_l, src = rtcdf.last_pick()
+            t0 = time.perf_counter()
+            rtcdf.pick_config(n, lo, hi, keys_in=a)
+            cached_ms = (time.perf_counter() - t0) * 1e3
+            rtcdf.set_config_mode(rtcdf.CONFIG_DEFAULT)
+            cfg_b = rtcdf.make_config(*pts[i_b])
+            memo = {}
+
+            def t_of(cfg):
+                key = cfg.as_tuple()
+                if key not in memo:
+                    memo[key] = time_config(torch, rtcdf, a, b, lo, hi, cfg, warmup, reps, runs)
+                return memo[key]
+
+            ts, tl, tb = t_of(cfg_s), t_of(cfg_l), t_of(cfg_b)
+            row = {"key": s["key"], "dist": s["dist"] if s["dist"] != "normal" else f"normal/{s['sd_div']:g}",
+                   "n": n, "R": s["R"], "static": i_s, "learned": i_l, "best": i_b,
+                   "source": PICK_NAMES.get(src, src), "t_static": ts, "t_learned": tl, "t_best": tb,
+                   "t_best_autotune": float(times[i_b]), "pick_ms": pick_ms, "cached_pick_ms": cached_ms,
+                   "features": rtcdf.sketch(a, lo, hi).cpu().tolist()}
+            per.append(row)
+            log(f"[heldout] {k + 1}/{len(specs)} n={n} R={s['R']} {row['dist']} {row['source']}: static "
+                f"{ts:.4f} learned {tl:.4f} best {tb:.4f} ms (pick {pick_ms:.3f} ms)")
+            del a, b
+    finally:
+        rtcdf.set_config_mode(old)
+    return summarise_retimed(per), per
+
+
+def summarise_retimed(per):
+    """Gain, regret and pick-cost summary of evaluate_retimed's rows, overall,
+    per distribution and per decision source."""
+    def block(rows):
+        if not rows:
+            return None
+        g = np.array([r["t_static"] / r["t_learned"] for r in rows])
+        reg = np.array([r["t_learned"] / r["t_best"] - 1.0 for r in rows])
+        sreg = np.array([r["t_static"] / r["t_best"] - 1.0 for r in rows])
+        out = {"arrays": len(rows), "gain_geomean": float(np.exp(np.log(g).mean())),
+               "regret_mean": float(reg.mean()), "regret_median": float(np.median(reg)),
+               "regret_p95": float(np.percentile(reg, 95)), "regret_max": float(reg.max()),
+               "static_regret_mean": float(sreg.mean()),
+               "learned_differs": float(np.mean([r["learned"] != r["static"] for r in rows]))}
+        for K in (1, 10, 100):
+            gk = [r["t_static"] / (r["t_learned"] + r["pick_ms"] / K) for r in rows]
+            out[f"gain_geomean_one_pick_per_{K}_sorts"] = float(np.exp(np.mean(np.log(gk))))
+        out["pick_ms_median"] = float(np.median([r["pick_ms"] for r in rows]))
+        out["cached_pick_ms_median"] = float(np.median([r["cached_pick_ms"] for r in rows]))
+        return out
+    res = block(per)
+    res["by_dist"] = {d: block([r for r in per if r["dist"] == d]) for d in sorted({r["dist"] for r in per})}
+    res["by_source"] = {s: block([r for r in per if r["source"] == s])
+                        for s in sorted({r["source"] for r in per})}
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -265,7 +387,21 @@ def main(argv=None):
     e.add_argument("--db", required=True)
     e.add_argument("--model", required=True)
     e.add_argument("--out", default=None)
+    h = sub.add_parser("heldout", help="re-timed evaluation on a held-out set generated on the GPU")
+    h.add_argument("--model", required=True)
+    h.add_argument("--set", default="heldout")
+    h.add_argument("--count", type=int, default=500)
+    h.add_argument("--start", type=int, default=0)
+    h.add_argument("--stop", type=int, default=None)
+    h.add_argument("--out", required=True)
     args = ap.parse_args(argv)
+    if args.cmd == "heldout":
+        specs = tune.specs(args.set, args.count)[args.start:args.stop]
+        res, per = evaluate_retimed(specs, args.model, log=lambda *a: print(*a, flush=True))
+        with open(args.out, "w") as f:
+            json.dump({"summary": res, "arrays": per}, f)
+        print(json.dumps({k: v for k, v in res.items() if k not in ("by_dist", "by_source")}))
+        return 0
     if args.cmd == "train":
         rows = tune.load_db(args.db)
         order = np.random.default_rng(args.seed).permutation(len(rows))

@@ -65,7 +65,8 @@ class Config(ctypes.Structure):
                 ("blocks_per_tile", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
     def as_tuple(self):
-        return (self.tile_width, self.items_per_thread, self.blocks_per_tile)
+        """(T, items, blocks, flags): the form of the grid points."""
+        return (self.tile_width, self.items_per_thread, self.blocks_per_tile, self.flags)
 
     def __repr__(self):
         extra = f", flags={self.flags}" if self.flags else ""
@@ -132,8 +133,16 @@ def _check(st: int, what: str):
         raise RtcdfError(st, what)
 
 
-# rtcdf_config_t.flags: output by step writes and a prefix maximum (Alg. 3)
-FLAG_OUTPUT_PREFIX_MAX = 1
+# rtcdf_config_t.flags: output by step writes and a prefix maximum (Alg. 3);
+# the histogram's counter width; wave-level aggregation of duplicates; output
+# chunk size
+FLAG_OUTPUT_PREFIX_MAX = 0x01
+FLAG_COUNTERS_16 = 0x04
+FLAG_COUNTERS_32 = 0x08
+FLAG_WAVE_DEDUPE = 0x10
+FLAG_CHUNK_4096 = 0x20
+# how a configuration was chosen (rtcdf_last_pick_source)
+PICK_STATIC, PICK_NETWORK, PICK_NETWORK_KEPT_STATIC, PICK_AUTOTUNED, PICK_CACHED, PICK_PENDING = 0, 1, 2, 3, 4, 5
 
 
 def make_config(tile_width: int, items_per_thread: int = 16, blocks_per_tile: int = 1,
@@ -394,8 +403,8 @@ def sort_batched(d_segments, num_segments: int, bounds: BatchBounds, workspace, 
 
 # ---- configuration grid, autotuner, learned picker
 
-GRID_SIZE = 54
-MLP_INPUTS, MLP_HIDDEN, MLP_OUTPUTS, MLP_PARAMS = 34, 64, 54, 9910
+GRID_SIZE = 61
+MLP_INPUTS, MLP_HIDDEN, MLP_OUTPUTS, MLP_PARAMS = 34, 64, 61, 10365
 SKETCH_BINS, SKETCH_SAMPLES = 32, 4096
 
 _fp = ctypes.c_void_p
@@ -406,6 +415,10 @@ for _name, _args in {
     "rtcdf_load_tuned_table": [ctypes.c_char_p],
     "rtcdf_load_model": [ctypes.c_char_p],
     "rtcdf_unload_model": [],
+    "rtcdf_set_learned_fallback": [ctypes.c_int],
+    "rtcdf_clear_pick_cache": [],
+    "rtcdf_last_pick_source": [],
+    "rtcdf_last_pick_index": [],
     "rtcdf_sketch": [_vp, _sz, _i64, _i64, _fp, _vp],
     "rtcdf_mlp_forward": [_fp, _fp, ctypes.c_uint32, _fp, _vp],
     "rtcdf_mlp_workspace_bytes": [ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)],
@@ -422,7 +435,8 @@ for _name, _args in {
 
 
 def config_grid():
-    """[(T, items, blocks)] * 54 and the validity mask."""
+    """[(T, items, blocks, flags)] * GRID_SIZE (option points as (0, 0, 0,
+    flags)) and the validity mask."""
     cfgs = (Config * GRID_SIZE)()
     valid = (ctypes.c_uint8 * GRID_SIZE)()
     _check(lib.rtcdf_config_grid(cfgs, valid), "rtcdf_config_grid")
@@ -455,6 +469,19 @@ def unload_model():
     _check(lib.rtcdf_unload_model(), "rtcdf_unload_model")
 
 
+def set_learned_fallback(on: bool):
+    _check(lib.rtcdf_set_learned_fallback(1 if on else 0), "rtcdf_set_learned_fallback")
+
+
+def clear_pick_cache():
+    _check(lib.rtcdf_clear_pick_cache(), "rtcdf_clear_pick_cache")
+
+
+def last_pick() -> tuple:
+    """(grid index or -1, PICK_* source) of the last choice on this thread."""
+    return int(lib.rtcdf_last_pick_index()), int(lib.rtcdf_last_pick_source())
+
+
 def sketch(keys_in, minVal: int, maxVal: int, out=None, stream=None):
     import torch
     if out is None:
@@ -464,8 +491,21 @@ def sketch(keys_in, minVal: int, maxVal: int, out=None, stream=None):
     return out
 
 
+def _check_mlp(params=None, X=None, rows=None, what="mlp"):
+    """Shape checks of the picker's device arrays (the kernels index them by
+    the network's fixed sizes)."""
+    if params is not None and params.numel() != MLP_PARAMS:
+        raise ValueError(f"{what}: params must hold {MLP_PARAMS} floats")
+    if X is not None and (X.dim() != 2 or X.shape[1] != MLP_INPUTS):
+        raise ValueError(f"{what}: X must be batch x {MLP_INPUTS}")
+    for t in rows or ():
+        if X is not None and t.numel() != X.shape[0] * MLP_OUTPUTS:
+            raise ValueError(f"{what}: targets and mask must be batch x {MLP_OUTPUTS}")
+
+
 def mlp_forward(params, X, stream=None):
     import torch
+    _check_mlp(params, X, what="mlp_forward")
     B = X.shape[0]
     Y = torch.empty((B, MLP_OUTPUTS), dtype=torch.float32, device=X.device)
     _check(lib.rtcdf_mlp_forward(_ptr(params), _ptr(X), B, _ptr(Y), _stream_ptr(stream)),
@@ -483,6 +523,7 @@ def mlp_workspace(batch: int, device="cuda"):
 def mlp_gradient(params, X, T, M, ws=None, stream=None):
     """(gradient, loss) of the masked MSE at params."""
     import torch
+    _check_mlp(params, X, (T, M), what="mlp_gradient")
     B = X.shape[0]
     if ws is None:
         ws = mlp_workspace(B, X.device)
@@ -494,12 +535,19 @@ def mlp_gradient(params, X, T, M, ws=None, stream=None):
 
 
 def mlp_adam_step(params, grad, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    for a in (params, grad, m, v):
+        _check_mlp(a, what="mlp_adam_step")
     _check(lib.rtcdf_mlp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), lr, beta1, beta2,
                                    eps, _stream_ptr(stream)), "rtcdf_mlp_adam_step")
 
 
 def mlp_train(params, m, v, t0: int, X, T, M, steps: int, lr: float, ws=None, loss_history=None,
               stream=None):
+    for a in (params, m, v):
+        _check_mlp(a, what="mlp_train")
+    _check_mlp(None, X, (T, M), what="mlp_train")
+    if loss_history is not None and loss_history.numel() < steps:
+        raise ValueError("mlp_train: loss_history must hold one float per step")
     B = X.shape[0]
     if ws is None:
         ws = mlp_workspace(B, X.device)
@@ -510,8 +558,11 @@ def mlp_train(params, m, v, t0: int, X, T, M, steps: int, lr: float, ws=None, lo
 
 
 def mlp_pick(keys_in, minVal: int, maxVal: int, params, norm, valid, stream=None):
-    """(index tensor[1], predictions tensor[54]) on the device."""
+    """(index tensor[1], predictions tensor[MLP_OUTPUTS]) on the device."""
     import torch
+    _check_mlp(params, what="mlp_pick")
+    if norm.numel() != 2 * MLP_INPUTS or valid.numel() != MLP_OUTPUTS:
+        raise ValueError("mlp_pick: norm must hold 2 x 34 floats and valid one byte per grid point")
     idx = torch.empty(1, dtype=torch.int32, device=keys_in.device)
     pred = torch.empty(MLP_OUTPUTS, dtype=torch.float32, device=keys_in.device)
     _check(lib.rtcdf_mlp_pick(_ptr(keys_in), keys_in.numel(), int(minVal), int(maxVal), _ptr(params),
@@ -525,7 +576,7 @@ class PlanInfo(ctypes.Structure):
         "tile_width", "tiles", "counter_bits", "passes", "pass_bins", "hist_workgroups",
         "hist_threads", "items_per_thread", "scan_workgroups", "out_chunk", "out_chunks",
         "fill_workgroups")] + [("workspace_bytes", ctypes.c_uint64), ("output_flags", ctypes.c_uint32),
-                                ("partition_buckets", ctypes.c_uint32)]
+                                ("partition_buckets", ctypes.c_uint32), ("hist_dedupe", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -3,7 +3,7 @@
 The database is append-only JSON lines, one row per measured array:
     {"key": ..., "n": ..., "minVal": ..., "R": ..., "dist": ..., "sd_div": ...,
      "features": [34 floats from the GPU sketch kernel],
-     "times_ms": [54 medians from rtcdf_autotune, -1 for invalid grid points]}
+     "times_ms": [one median per grid point from rtcdf_autotune, -1 for invalid ones]}
 Rows are keyed by the array's seed, so an interrupted collection resumes where
 it stopped.
 
@@ -35,28 +35,43 @@ TABLE_H = os.path.join(PKG, "csrc", "rtcdf_default_table.h")
 GRID_T = [1024 << i for i in range(6)]
 GRID_ITEMS = [4, 8, 16]
 GRID_BPT = [1, 2, 4]
+PLAIN_POINTS = 54
+# option points (flags of rtcdf_config_t, on the static table's T / items /
+# blocks): prefix-maximum output, 16-bit counters, 16-bit counters with wave
+# aggregation of duplicates, wave aggregation, 4096-position output chunks,
+# 16-bit counters with 4096-position chunks, 32-bit counters
+GRID_OPTIONS = (0x01, 0x04, 0x14, 0x10, 0x20, 0x24, 0x08)
 
 
 def grid():
-    """The 54 grid points (T, items, blocks) in library order and their validity."""
+    """The grid points (T, items, blocks, flags) in library order and their
+    validity: 54 plain points, then the option points as (0, 0, 0, flags)."""
     pts, valid = [], []
     for T in GRID_T:
         for it in GRID_ITEMS:
             for b in GRID_BPT:
-                pts.append((T, it, b))
+                pts.append((T, it, b, 0))
                 valid.append(T * 4 * b <= 163840)
+    for f in GRID_OPTIONS:
+        pts.append((0, 0, 0, f))
+        valid.append(True)
     return pts, valid
+
+
+SETS = {"train": 0, "test": 1, "heldout": 2}
 
 
 def specs(which: str, count: int, seed: int = None):
     """Arrays like the single-array workloads: n log-uniform in [1e6, 1e9], R
     log-uniform in [2^7, 2^18] (rounded), minVal 0, keys uniform, normal with
-    sd R/6, normal with sd R/64 or all equal; the held-out set adds Zipf(1.1)."""
+    sd R/6, normal with sd R/64 or all equal; the held-out sets ("test", and
+    "heldout", drawn from a seed no decision of the picker has seen) add
+    Zipf(1.1)."""
     if seed is None:
-        seed = inputs.case_seed(5, 0 if which == "train" else 1)
+        seed = inputs.case_seed(5, SETS[which])
     rng = np.random.Generator(np.random.Philox(np.random.SeedSequence([seed, 5])))
     dists = [("uniform", 6.0), ("normal", 6.0), ("normal", 64.0), ("all_equal", 6.0)]
-    if which == "test":
+    if which != "train":
         dists.append(("zipf", 6.0))
     out = []
     for i in range(count):
@@ -116,7 +131,8 @@ def range_class(R: int) -> int:
 
 
 def select_static(rows):
-    """{range class: grid index} by the smallest geometric mean of t / t_best."""
+    """{range class: grid index} by the smallest geometric mean of t / t_best
+    over the plain (T, items, blocks) points, the paper's grid."""
     _, valid = grid()
     by_class = {}
     for r in rows:
@@ -124,11 +140,12 @@ def select_static(rows):
     table = {}
     for c, rs in sorted(by_class.items()):
         scores = []
-        for i in range(54):
+        for i in range(PLAIN_POINTS):
             if not valid[i]:
                 scores.append(math.inf)
                 continue
-            logs = [math.log(r["times_ms"][i] / min(t for t, v in zip(r["times_ms"], valid) if v))
+            logs = [math.log(r["times_ms"][i] /
+                             min(t for t, v in zip(r["times_ms"][:PLAIN_POINTS], valid) if v))
                     for r in rs]
             scores.append(sum(logs) / len(logs))
         table[c] = int(np.argmin(scores))
@@ -149,7 +166,7 @@ def write_default_table(table, path: str = TABLE_H, source: str = ""):
     for c in classes:
         # class c covers R up to the geometric midpoint towards class c + 1
         bound = f"{int(math.floor(2.0 ** (c + 0.5)))}u"
-        T, it, b = pts[table[c]]
+        T, it, b, _ = pts[table[c]]
         lines.append(f"    {{{bound}, {{{T}, {it}, {b}, 0}}}},   // log2 R ~ {c}")
     T, it, b = WIDE_RANGE_CONFIG
     lines.append(f"    {{1u << 28, {{{T}, {it}, {b}, 0}}}},   // wider than the tuning rows")
@@ -181,21 +198,22 @@ static const DefaultRow kDefaultTable[] = {{
 
 
 def write_tuned_table(rows, path: str):
-    """One line per measured array: log2 n, log2 R and its fastest configuration."""
+    """One line per measured array: log2 n, log2 R and its fastest grid point
+    (T items blocks flags; an option point as 0 0 0 flags)."""
     pts, valid = grid()
     with open(path, "w") as f:
-        f.write("# log2n log2R T items blocks  (fastest measured configuration per array)\n")
+        f.write("# log2n log2R T items blocks flags  (fastest measured grid point per array)\n")
         for r in rows:
             i = min((t, j) for j, t in enumerate(r["times_ms"]) if valid[j] and t > 0)[1]
-            T, it, b = pts[i]
-            f.write(f"{math.log2(r['n']):.4f} {math.log2(r['R']):.4f} {T} {it} {b}\n")
+            T, it, b, fl = pts[i]
+            f.write(f"{math.log2(r['n']):.4f} {math.log2(r['R']):.4f} {T} {it} {b} {fl}\n")
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     c = sub.add_parser("collect")
-    c.add_argument("--set", default="train", choices=["train", "test"])
+    c.add_argument("--set", default="train", choices=sorted(SETS))
     c.add_argument("--count", type=int, default=2000)
     c.add_argument("--db", required=True)
     c.add_argument("--start", type=int, default=0)
@@ -214,7 +232,7 @@ def main(argv=None):
         table = select_static(rows)
         write_default_table(table, source=f"{os.path.basename(args.db)}, {len(rows)} arrays")
         write_tuned_table(rows, args.tuned_out)
-        print(json.dumps({str(k): grid()[0][v] for k, v in table.items()}))
+        print(json.dumps({str(k): grid()[0][v][:3] for k, v in table.items()}))
 
 
 if __name__ == "__main__":

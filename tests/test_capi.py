@@ -126,14 +126,36 @@ def test_segment_layout(r):
     assert ctypes.sizeof(r.Segment) == 32
     assert ctypes.sizeof(r.BatchBounds) == 16
     assert ctypes.sizeof(r.Config) == 16
-    assert ctypes.sizeof(r.PlanInfo) == 64   # 12 uint32, uint64 workspace_bytes, output_flags, partition_buckets
+    # 12 uint32, uint64 workspace_bytes, output_flags, partition_buckets,
+    # hist_dedupe, padded to 8 bytes
+    assert ctypes.sizeof(r.PlanInfo) == 72
     assert ctypes.sizeof(r.StageStats) == 40
 
 
-def test_output_flag_matches_header(r):
+def test_flags_and_sizes_match_header(r):
     txt = open(os.path.join(ROOT, "include", "rtcdf.h")).read()
-    m = re.search(r"#define\s+RTCDF_FLAG_OUTPUT_PREFIX_MAX\s+(\d+)u", txt)
-    assert m and int(m.group(1)) == r.FLAG_OUTPUT_PREFIX_MAX
+    for name in ("OUTPUT_PREFIX_MAX", "COUNTERS_16", "COUNTERS_32", "WAVE_DEDUPE", "CHUNK_4096"):
+        m = re.search(r"#define\s+RTCDF_FLAG_%s\s+(0x[0-9a-f]+|\d+)u" % name, txt)
+        assert m and int(m.group(1), 0) == getattr(r, "FLAG_" + name), name
+    for name, val in (("GRID_SIZE", r.GRID_SIZE), ("MLP_OUTPUTS", r.MLP_OUTPUTS), ("MLP_PARAMS", r.MLP_PARAMS),
+                      ("NOALLOC_MAX_WORKSPACE", r.NOALLOC_MAX_WORKSPACE)):
+        m = re.search(r"#define\s+RTCDF_%s\s+\(?(\d+)u?( << (\d+))?" % name, txt)
+        assert m, name
+        got = int(m.group(1)) << (int(m.group(3)) if m.group(3) else 0)
+        assert got == val, name
+
+
+def test_config_validation(r):
+    """Option flags: known bits only, not both counter widths; a config with
+    zero knobs and some flags is valid (the static knobs with those flags)."""
+    L = r.lib
+    c_in, c_out = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
+    def st(cfg):
+        return L.rtcdf_sort_with_config(c_in, c_out, 10, 0, 100, ctypes.byref(cfg), None)
+    assert st(r.make_config(1024, 16, 1, flags=0x40)) == r.INVALID_VALUE          # unknown bit
+    assert st(r.make_config(1024, 16, 1, flags=0x0c)) == r.INVALID_VALUE          # both widths
+    assert st(r.make_config(0, 0, 0, flags=0x0c)) == r.INVALID_VALUE
+    assert st(r.make_config(0, 16, 1, flags=0x04)) == r.INVALID_VALUE             # partly zero
 
 
 def test_sort_keys_argument_errors(r):

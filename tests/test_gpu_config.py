@@ -74,3 +74,89 @@ def test_learned_mode_sorts_match_oracle(r):
     finally:
         r.set_config_mode(old)
         r.unload_model()
+
+
+def test_learned_sorts_do_not_wait_for_the_pick(r):
+    """In LEARNED mode the first sort of a buffer enqueues the network's pick
+    and sorts with the static choice (source PENDING, or the decision if the
+    pick already finished); once the pick has run the next sort decides, and
+    later ones reuse the decision (CACHED).  Every output equals the
+    oracle's."""
+    if not os.path.exists(MODEL):
+        pytest.skip("no shipped model")
+    r.load_model(MODEL)
+    old = r.get_config_mode()
+    decided = (r.PICK_NETWORK, r.PICK_NETWORK_KEPT_STATIC, r.PICK_AUTOTUNED)
+    try:
+        r.set_config_mode(r.CONFIG_LEARNED)
+        r.clear_pick_cache()
+        for i, (dist, n, lo, R) in enumerate((("uniform", 30_000_000, -5, 1 << 13),
+                                              ("normal", 2_000_000, 0, 1 << 17),
+                                              ("all_equal", 5_000_000, 3, 1000))):
+            A = inputs.make(dist, n, lo, lo + R, inputs.case_seed(72, i))
+            a = torch.from_numpy(A).cuda()
+            want = oracle.sort(A, lo, lo + R)
+            sources = []
+            for k in range(3):
+                b = r.sort(a, lo, lo + R)
+                sources.append(r.last_pick()[1])
+                torch.cuda.synchronize()
+                assert np.array_equal(b.cpu().numpy(), want)
+            _say(f"learned sort sources {dist}: {sources}")
+            assert sources[0] in (r.PICK_PENDING,) + decided
+            assert sources[1] in decided + (r.PICK_CACHED,)
+            assert sources[2] == r.PICK_CACHED or sources[2] == r.PICK_NETWORK_KEPT_STATIC
+    finally:
+        r.set_config_mode(old)
+        r.unload_model()
+        r.clear_pick_cache()
+
+
+def test_learned_gain_over_static(r):
+    """What the trained network (with its exhaustive fallback for sketches it
+    does not trust) gains over the method without it: the first 60 arrays of
+    the held-out set (a seed no training or tuning decision saw; Zipf keys
+    included) with n <= 10^8.  Each array is timed with the static choice
+    (DEFAULT mode) and with LEARNED mode's decision, as the median of 3
+    run-medians of 30 sorts after 10 warm-ups; both outputs equal the
+    oracle's counts.  The geometric-mean gain must exceed 1.01 overall and
+    1.05 on the Zipf arrays (8-bit counters wrap on their hot values)."""
+    import math
+    from paper_2609_00843_amd import learn, tune
+    if not os.path.exists(MODEL):
+        pytest.skip("no shipped model")
+    specs = [s for s in tune.specs("heldout", 500) if s["n"] <= 10 ** 8][:60]
+    r.load_model(MODEL)
+    old = r.get_config_mode()
+    gains, zipf = [], []
+    try:
+        r.clear_pick_cache()
+        for s in specs:
+            n, lo = s["n"], s["minVal"]
+            hi = lo + s["R"]
+            a = inputs.make_device(s["dist"], n, lo, hi, s["seed"], sd_div=s["sd_div"])
+            b = torch.empty_like(a)
+            r.set_config_mode(r.CONFIG_DEFAULT)
+            cs = r.pick_config(n, lo, hi)
+            r.set_config_mode(r.CONFIG_LEARNED)
+            cl = r.pick_config(n, lo, hi, keys_in=a)
+            r.set_config_mode(r.CONFIG_DEFAULT)
+            ts = learn.time_config(torch, r, a, b, lo, hi, cs)
+            tl = ts if cl.as_tuple() == cs.as_tuple() else learn.time_config(torch, r, a, b, lo, hi, cl)
+            cnt = oracle.counts(a.cpu().numpy(), lo, hi)
+            v = oracle.StreamingVerifier(cnt, lo)
+            v.chunk(b.cpu().numpy())
+            v.end(n)
+            gains.append(ts / tl)
+            if s["dist"] == "zipf":
+                zipf.append(ts / tl)
+            _say(f"gain n={n} R={s['R']} {s['dist']}: static {ts:.4f} learned {tl:.4f} ms ({ts / tl:.3f})")
+            del a, b
+    finally:
+        r.set_config_mode(old)
+        r.unload_model()
+        r.clear_pick_cache()
+    gm = math.exp(sum(map(math.log, gains)) / len(gains))
+    gz = math.exp(sum(map(math.log, zipf)) / len(zipf))
+    _say(f"geometric-mean gain {gm:.4f} over {len(gains)} arrays, Zipf {gz:.4f} over {len(zipf)}")
+    assert gm > 1.01 and gz > 1.05

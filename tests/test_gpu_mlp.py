@@ -9,7 +9,7 @@ element is a composition of sums; to first order in the unit roundoff
 u = 2^-24, rounding changes element e by at most K u A_e, where A_e is the
 same element computed with every factor replaced by its absolute value (and
 ReLU masks kept) and K is the total length of the sums on its dependency
-chain (forward 34 + 64 + 64, backward 54 + 64, the batch sum B).  The test
+chain (forward 34 + 64 + 64, backward 61 + 64, the batch sum B).  The test
 allows |got - want| <= 1e-4 |want| + 2 K u A_e: relative tolerance 1e-4 where
 no cancellation occurs, and the derived bound (with a factor 2 of slack) where
 it does."""
@@ -23,7 +23,8 @@ from paper_2609_00843_amd import inputs
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
-SIZES = (34, 64, 64, 54)
+SIZES = (34, 64, 64, 61)
+NPARAM = sum(SIZES[i + 1] * SIZES[i] + SIZES[i + 1] for i in range(3))   # 10365
 
 
 def _say(*a):
@@ -69,10 +70,10 @@ def _dev(a):
 def _batch(seed, B):
     rng = np.random.default_rng(seed)
     X = rng.normal(size=(B, 34))
-    T = rng.normal(size=(B, 54))
-    Mk = np.ones((B, 54))
+    T = rng.normal(size=(B, SIZES[3]))
+    Mk = np.ones((B, SIZES[3]))
     Mk[:, [38, 41, 44, 46, 47, 49, 50, 52, 53]] = 0.0      # the invalid grid points
-    Mk[rng.random(size=(B, 54)) < 0.05] = 0.0
+    Mk[rng.random(size=(B, SIZES[3])) < 0.05] = 0.0
     return X, T, Mk
 
 
@@ -131,7 +132,7 @@ def test_forward_and_gradient(r):
     G, L = r.mlp_gradient(P, _dev(X), _dev(T), _dev(Mk))
     gr = _flat(M.backward(p, cache, Yr, T, Mk))
     g = G.cpu().numpy().astype(np.float64)
-    k_bwd = k_fwd + 54 + 64 + B
+    k_bwd = k_fwd + SIZES[3] + 64 + B
     bound = 1e-4 * np.abs(gr) + 2 * k_bwd * U32 * Ga
     worst = int(np.argmax(np.abs(g - gr) - bound))
     assert np.all(np.abs(g - gr) <= bound), (worst, g[worst], gr[worst], bound[worst])
@@ -145,10 +146,10 @@ def test_forward_and_gradient(r):
 
 def test_adam_step(r):
     rng = np.random.default_rng(3)
-    p = {"w": rng.normal(size=9910)}
-    g = {"w": rng.normal(size=9910)}
-    m = {"w": rng.normal(size=9910) * 0.1}
-    v = {"w": np.abs(rng.normal(size=9910)) * 0.01}
+    p = {"w": rng.normal(size=NPARAM)}
+    g = {"w": rng.normal(size=NPARAM)}
+    m = {"w": rng.normal(size=NPARAM) * 0.1}
+    v = {"w": np.abs(rng.normal(size=NPARAM)) * 0.01}
     P, Gd, Md, Vd = _dev(p["w"]), _dev(g["w"]), _dev(m["w"]), _dev(v["w"])
     _say("adam")
     r.mlp_adam_step(P, Gd, Md, Vd, 7, lr=1e-2)
@@ -200,8 +201,8 @@ def test_pick(r):
 @pytest.mark.parametrize("margin", [0.0, 0.02, 1e30])
 def test_learned_pick_applies_margin(r, tmp_path, margin):
     """LEARNED mode keeps the static configuration unless the network predicts
-    at least the model's margin of gain: the library's choice equals
-    learn.decide applied to the pick kernel's own predictions."""
+    at least the model's margin of gain: the library's choice (its grid
+    index) equals learn.decide applied to the pick kernel's own predictions."""
     from paper_2609_00843_amd import learn, tune
     p = _flat(_init(8))
     rng = np.random.default_rng(9)
@@ -217,25 +218,35 @@ def test_learned_pick_applies_margin(r, tmp_path, margin):
             d = torch.from_numpy(A).cuda()
             _say(f"learned pick {dist} margin={margin}")
             r.set_config_mode(r.CONFIG_DEFAULT)
-            static = pts.index(r.pick_config(n, 0, R).as_tuple())
+            r.pick_config(n, 0, R)
+            static = r.last_pick()[0]
             r.set_config_mode(r.CONFIG_LEARNED)
-            got = pts.index(r.pick_config(n, 0, R, keys_in=d).as_tuple())
+            r.clear_pick_cache()
+            cfg = r.pick_config(n, 0, R, keys_in=d)
+            got, source = r.last_pick()
             norm = np.concatenate([mu, sd])
             validd = torch.tensor(np.array(valid, dtype=np.uint8), device="cuda")
             _, pred = r.mlp_pick(d, 0, R, _dev(p), _dev(norm), validd)
             # the library compares in FP32: so does the reference here
             want = learn.decide(pred.cpu().numpy(), np.array(valid), static, np.float32(margin))
             assert got == want
+            assert source in (r.PICK_NETWORK, r.PICK_NETWORK_KEPT_STATIC)
+            if want >= tune.PLAIN_POINTS:   # an option point: static knobs with its flags
+                assert cfg.flags == pts[want][3] and cfg.tile_width > 0
             if margin >= 1e30:
-                assert got == static
+                assert got == static and source == r.PICK_NETWORK_KEPT_STATIC
+            # the same buffer again: the decision is reused without a pick
+            r.pick_config(n, 0, R, keys_in=d)
+            assert r.last_pick() == (got, r.PICK_CACHED)
     finally:
         r.set_config_mode(old)
         r.unload_model()
 
 
 def test_learned_pick_feature_gate(r, tmp_path):
-    """A sketch farther than zmax from the training mean keeps the static
-    configuration whatever the network prefers; within it the network decides."""
+    """A sketch farther than zmax from the training mean is not judged by the
+    network: with the exhaustive fallback off the static configuration is
+    kept whatever the network prefers; within zmax the network decides."""
     from paper_2609_00843_amd import learn, tune
     p = _flat(_init(8))
     pts, valid = tune.grid()
@@ -246,8 +257,10 @@ def test_learned_pick_feature_gate(r, tmp_path):
     z = float(np.abs(feats - mu).max())          # the array's distance in sd units
     old = r.get_config_mode()
     try:
+        r.set_learned_fallback(False)
         r.set_config_mode(r.CONFIG_DEFAULT)
-        static = pts.index(r.pick_config(A.size, 0, 50000).as_tuple())
+        r.pick_config(A.size, 0, 50000)
+        static = r.last_pick()[0]
         _, pred = r.mlp_pick(d, 0, 50000, _dev(p), _dev(np.concatenate([mu, sd])),
                              torch.tensor(np.array(valid, dtype=np.uint8), device="cuda"))
         free = learn.decide(pred.cpu().numpy(), np.array(valid), static, np.float32(0.0))
@@ -257,7 +270,47 @@ def test_learned_pick_feature_gate(r, tmp_path):
             r.load_model(path)
             r.set_config_mode(r.CONFIG_LEARNED)
             _say(f"feature gate zmax={zmax:.3f} (array at {z:.3f})")
-            assert pts.index(r.pick_config(A.size, 0, 50000, keys_in=d).as_tuple()) == want
+            r.pick_config(A.size, 0, 50000, keys_in=d)
+            assert r.last_pick()[0] == want
             r.unload_model()
     finally:
+        r.set_learned_fallback(True)
         r.set_config_mode(old)
+
+
+def test_learned_fallback_autotunes_untrusted_arrays(r, tmp_path):
+    """Where the network is not trusted the grid is timed exhaustively: the
+    decision's source is AUTOTUNED, its index a valid grid point, the sort
+    with it equals the oracle's, and a second array of the same shape class
+    reuses the result (no second timing: much faster than the first)."""
+    import time
+    from paper_2609_00843_amd import learn, tune
+    import oracle
+    p = _flat(_init(8))
+    pts, valid = tune.grid()
+    mu, sd = np.zeros(34), np.ones(34)
+    path = str(tmp_path / "m.bin")
+    learn.save_model(path, p, mu, sd, (10.0, 30.0, 4.0, 20.0), margin=0.0, zmax=1e-3)   # nothing trusted
+    r.load_model(path)
+    old = r.get_config_mode()
+    try:
+        r.set_config_mode(r.CONFIG_LEARNED)
+        r.clear_pick_cache()
+        walls = []
+        for seed in (20, 21):
+            A = inputs.make("zipf", 1_000_000, 0, 20000, seed)
+            d = torch.from_numpy(A).cuda()
+            _say(f"fallback pick seed={seed}")
+            t0 = time.perf_counter()
+            r.pick_config(A.size, 0, 20000, keys_in=d)
+            walls.append(time.perf_counter() - t0)
+            idx, source = r.last_pick()
+            assert source == r.PICK_AUTOTUNED and valid[idx]
+            out = r.sort(d, 0, 20000)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), oracle.sort(A, 0, 20000))
+        assert walls[1] < 0.5 * walls[0]
+    finally:
+        r.set_config_mode(old)
+        r.unload_model()
+        r.clear_pick_cache()

@@ -97,8 +97,8 @@ def test_every_grid_point(r):
     want = oracle.sort(A, 7, 7 + 20000)
     tin = torch.from_numpy(A).cuda()
     out = torch.empty_like(tin)
-    for (T, items, bpt), ok in zip(cfgs, valid):
-        if not ok:
+    for (T, items, bpt, flags), ok in zip(cfgs, valid):
+        if not ok or flags:     # the plain points (the option points carry their own flags)
             continue
         _say(f"pmax grid T={T} items={items} bpt={bpt}")
         out.fill_(-1)

@@ -208,6 +208,30 @@ def test_every_config_is_identical(r, dist, logR):
         assert np.array_equal(out.cpu().numpy(), want), (T, items, bpt)
 
 
+OPTION_FLAGS = (0x01, 0x04, 0x14, 0x10, 0x20, 0x24, 0x08, 0x18, 0x30, 0x11, 0x15)
+
+
+@pytest.mark.parametrize("dist,n,logR", [("uniform", 777_777, 7), ("zipf", 1_000_003, 10), ("normal", 2_000_001, 13),
+                                         ("zipf", 3_000_000, 16), ("all_equal", 500_000, 16),
+                                         ("normal", 1_500_001, 18), ("zipf", 999_999, 18)])
+def test_option_flags_are_identical(r, dist, n, logR):
+    """Every option flag (counter widths, wave aggregation of duplicates,
+    4096-position chunks, the prefix-maximum output) and some combinations,
+    on the static knobs and on explicit ones, give the oracle's output."""
+    R, minVal = 1 << logR, -77
+    A = inputs.make(dist, n, minVal, minVal + R, inputs.case_seed(6, logR * 7 + n % 5))
+    want = oracle.sort(A, minVal, minVal + R)
+    _, tin = _to_dev(A, 2)
+    for flags in OPTION_FLAGS:
+        for cfg in (r.make_config(0, 0, 0, flags=flags), r.make_config(2048, 8, 2, flags=flags)):
+            _say(f"option flags {flags:#x} cfg={cfg} {dist} R={R}")
+            out = r.sort(tin, minVal, minVal + R, config=cfg)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want), (flags, cfg)
+    info = r.plan_info(n, minVal, minVal + R, config=r.make_config(0, 0, 0, flags=0x14))
+    assert info["counter_bits"] == 16 and info["hist_dedupe"] == 1
+
+
 @pytest.mark.parametrize("R,T", [(4, 128), (1000, 128), (1000, 1024), (70000, 1024),
                                  (70000, 32768), (262144, 8192), (300000, 32768),
                                  ((1 << 21) + 77, 128)])   # 16385 tiles: offsets by k_tile_offsets

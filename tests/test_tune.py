@@ -18,7 +18,7 @@ def _rows(seed):
     for i in range(60):
         R = int(2 ** rng.uniform(7, 18))
         n = int(10 ** rng.uniform(6, 9))
-        t = rng.uniform(0.5, 2.0, size=54) * (n / 1e7)
+        t = rng.uniform(0.5, 2.0, size=len(valid)) * (n / 1e7)
         t = [float(x) if v else -1.0 for x, v in zip(t, valid)]
         rows.append({"key": f"k{i}", "n": n, "minVal": 0, "R": R, "dist": "uniform", "sd_div": 6.0,
                      "features": list(rng.random(34)), "times_ms": t})
@@ -29,14 +29,15 @@ def test_grid_matches_library():
     from paper_2609_00843_amd import rtcdf
     pts, valid = tune.grid()
     lp, lv = rtcdf.config_grid()
-    assert pts == lp and valid == lv and sum(valid) == 45
+    assert pts == lp and valid == lv and sum(valid) == 52
+    assert sum(valid[:tune.PLAIN_POINTS]) == 45 and all(p[:3] == (0, 0, 0) for p in pts[tune.PLAIN_POINTS:])
 
 
 def test_static_selection_matches_reference():
     rows = _rows(1)
     _, valid = tune.grid()
     ref_rows = [(tune.range_class(r["R"]), r["key"], j, r["times_ms"][j])
-                for r in rows for j in range(54) if valid[j]]
+                for r in rows for j in range(tune.PLAIN_POINTS) if valid[j]]
     assert tune.select_static(rows) == tune_ref.select_per_range(ref_rows)
 
 
@@ -50,10 +51,14 @@ def test_default_and_tuned_tables_drive_the_pick(tmp_path):
     old = rtcdf.get_config_mode()
     try:
         rtcdf.set_config_mode(rtcdf.CONFIG_TUNED)
-        for r in rows[:10]:
+        for r in rows[:30]:
             best = min((t, j) for j, t in enumerate(r["times_ms"]) if valid[j])[1]
             got = rtcdf.pick_config(r["n"], 0, r["R"]).as_tuple()
-            assert got == pts[best]
+            assert rtcdf.last_pick()[0] == best
+            if best < tune.PLAIN_POINTS:
+                assert got == pts[best]
+            else:     # an option point: the static table's knobs with its flags
+                assert got[3] == pts[best][3] and got[:3] != (0, 0, 0)
     finally:
         rtcdf.set_config_mode(old)
     bad = tmp_path / "bad.txt"
@@ -100,7 +105,7 @@ def test_decision_margin():
     margin of predicted gain; the margin is chosen on measured times."""
     _, valid = tune.grid()
     ok = np.array(valid)
-    y = np.zeros(54)
+    y = np.zeros(learn.NOUT)
     y[5] = -0.03                                  # predicted 3% faster than everything else
     assert learn.decide(y, ok, 0, 0.02) == 5
     assert learn.decide(y, ok, 0, 0.05) == 0
@@ -108,11 +113,11 @@ def test_decision_margin():
     assert learn.decide(y, ok, 0, 0.0, trusted=False) == 0
     rows = []
     for g in (1.10, 0.90, 1.02):                # static / picked time ratio per row
-        t = np.ones(54)
+        t = np.ones(learn.NOUT)
         t[5] = 1.0 / g
         t[~ok] = -1.0
         rows.append({"times_ms": t.tolist()})
-    Y = np.zeros((3, 54))
+    Y = np.zeros((3, learn.NOUT))
     Y[:, 5] = [-0.2, -0.01, -0.05]               # the network is confident where it is right
     mg, gain = learn.choose_margin(Y, rows, [0, 0, 0])
     # margins in (0.01, 0.05] keep rows 0 and 2 and drop row 1; the largest wins the tie
@@ -122,6 +127,6 @@ def test_decision_margin():
 def test_dataset_targets_are_centred():
     rows = _rows(3)
     X, T, M = learn.dataset(rows)
-    assert X.shape == (60, 34) and T.shape == (60, 54)
+    assert X.shape == (60, 34) and T.shape == (60, learn.NOUT) == (60, 61)
     assert np.allclose((T * M).sum(axis=1), 0.0, atol=1e-9)
-    assert M.sum(axis=1).tolist() == [45.0] * 60
+    assert M.sum(axis=1).tolist() == [52.0] * 60
