@@ -144,6 +144,48 @@ def bench_batched(torch, rtcdf, inputs, steps, check):
             "speedup_vs_plain_graph": round(t_plain_graph / t_batched, 2), "parity": parity}
 
 
+def profile_batched(torch, rtcdf, inputs, steps, warmup):
+    """Profiling mode: the 4096-array batched workload, `warmup` then `steps`
+    graph replays (one launch of the ordering kernel and one of k_batched
+    each), then the copy reference of the counter calibration."""
+    segs = inputs.batched_segments(4096)
+    total = sum(s["n"] for s in segs)
+    dev = torch.device("cuda:0")
+    din = torch.empty(total, dtype=torch.int32, device=dev)
+    dout = torch.empty(total, dtype=torch.int32, device=dev)
+    pairs, o = [], 0
+    for s in segs:
+        n = s["n"]
+        din[o:o + n] = inputs.make_device(s["dist"], n, s["minVal"], s["maxVal"], s["seed"], device=dev)
+        pairs.append((din[o:o + n], dout[o:o + n], s["minVal"], s["maxVal"]))
+        o += n
+    d, bounds, k = rtcdf.make_segments(pairs)
+    ws = torch.empty(rtcdf.batched_workspace_bytes(k, bounds), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    rtcdf.sort_batched(d, k, bounds, ws, stream=stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rtcdf.sort_batched(d, k, bounds, ws, stream=torch.cuda.current_stream())
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    log(f"[bench] batched: {ms:.4f} ms per replay, {total / (ms * 1e-3) / 1e9:.1f} Gkeys/s")
+    src = torch.empty(N, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(steps):
+        rtcdf.stream_copy(src, dst, stream=stream)
+    torch.cuda.synchronize()
+    print(json.dumps({"ms_per_step": ms, "keys_per_step": total}))
+
+
 def timed_sorts(torch, rtcdf, a, b, lo, hi, reps, stream, config=None):
     for _ in range(3):
         rtcdf.sort(a, lo, hi, keys_out=b, stream=stream, config=config)
@@ -507,6 +549,9 @@ def main():
     ap.add_argument("--key-widths", action="store_true",
                     help="with --profile-only: sort n = 10^8 uniform int16, uint16, int8 and uint8 keys "
                          "over their whole ranges instead of the range sweep")
+    ap.add_argument("--batched", action="store_true",
+                    help="with --profile-only: replay the 4096-array batched workload's graph instead of "
+                         "the range sweep")
     ap.add_argument("--output-method", choices=("search", "prefix_max"), default="search",
                     help="with --profile-only: sort with the prefix-maximum output (Alg. 3) instead "
                          "of the local-CDF search (Alg. 7)")
@@ -528,6 +573,11 @@ def main():
 
     if args.key_widths:
         profile_key_widths(torch, rtcdf, args.steps, args.warmup)
+        return
+    if args.batched:
+        if not args.profile_only:
+            ap.error("--batched is a profiling mode; it needs --profile-only")
+        profile_batched(torch, rtcdf, inputs, args.steps, args.warmup)
         return
     cases = [(lr, d) for lr in LOG_R for d in DISTS]
     if args.wide_ranges:

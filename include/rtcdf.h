@@ -251,7 +251,10 @@ rtcdf_status_t rtcdf_debug_intermediates(const int32_t* keys_in, size_t n, int64
 /* One independent array of a batch (device-resident, 32 bytes): n int32 keys
  * at keys_in from [minVal, minVal + range), sorted into keys_out.  keys_out
  * may equal keys_in (in place) but must not overlap any other segment's
- * output.  1 <= range <= RTCDF_BATCH_MAX_RANGE.  config is reserved (0).
+ * output.  1 <= range <= RTCDF_BATCH_MAX_RANGE.  config: the segment's
+ * keys per thread per load step of its histogram (the items_per_thread knob
+ * of rtcdf_config_t): 4, 8 or 16; 0 (or any other value) means 16.  It
+ * changes the speed of the segment's sort, never its output.
  * A descriptor with n = 0, range = 0, range > RTCDF_BATCH_MAX_RANGE (or above
  * the bounds' max_range) or a NULL pointer is skipped and its output left
  * untouched. */
@@ -281,9 +284,10 @@ rtcdf_status_t rtcdf_batched_workspace_bytes(uint32_t num_segments,
                                              const rtcdf_batch_bounds_t* bounds, size_t* bytes);
 
 /* Sort every segment of d_segments[num_segments] (a device array) in one
- * persistent launch (Alg. 4 of the paper per segment, each segment handled by
- * one workgroup, largest segments first), preceded by a one-workgroup
- * ordering kernel.  Each segment's output equals rtcdf_sort of that segment.
+ * persistent launch (Alg. 4 of the paper per range tile of 32768 values: a
+ * segment is one or two work items, each handled by one workgroup in LDS,
+ * largest first), preceded by a one-workgroup ordering kernel.  Each
+ * segment's output equals rtcdf_sort of that segment.
  * d_ws: caller-owned device workspace of ws_bytes bytes (>=
  * rtcdf_batched_workspace_bytes), 256-byte aligned, no initialisation
  * needed, not shared with a concurrent call.  No allocation and no host

@@ -755,8 +755,8 @@ rtcdf_status_t rtcdf_debug_intermediates(const int32_t* keys_in, size_t n, int64
 // ---- batched
 
 struct BatchLayout {
-  size_t off_counters, off_order, off_scratch, bytes;
-  uint32_t grid, scratch_words;
+  size_t off_counters, off_order, bytes;
+  uint32_t grid;
 };
 
 static rtcdf_status_t batch_layout(uint32_t nseg, const rtcdf_batch_bounds_t* bounds, BatchLayout* L) {
@@ -765,12 +765,13 @@ static rtcdf_status_t batch_layout(uint32_t nseg, const rtcdf_batch_bounds_t* bo
   DeviceInfo dev;
   rtcdf_status_t st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;
-  L->grid = (uint32_t)std::max(1, std::min<int>(dev.cus, (int)std::max<uint32_t>(nseg, 1)));
-  L->scratch_words = (uint32_t)batched_scratch_words(bounds->max_range);
+  // one persistent workgroup per compute unit, or one per work item (a
+  // segment is one or two items)
+  const uint64_t items = (uint64_t)std::max<uint32_t>(nseg, 1) * (bounds->max_range > 32768 ? 2 : 1);
+  L->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dev.cus, items));
   L->off_counters = 0;
   L->off_order = 256;
-  L->off_scratch = align256(L->off_order + (size_t)nseg * 4);
-  L->bytes = align256(L->off_scratch + (size_t)L->grid * L->scratch_words * 4);
+  L->bytes = align256(L->off_order + batched_order_words(nseg) * 4);
   return RTCDF_SUCCESS;
 }
 
@@ -798,9 +799,7 @@ rtcdf_status_t rtcdf_sort_batched(const rtcdf_segment_t* d_segments, uint32_t nu
   if (ws_bytes < L.bytes) return RTCDF_ERROR_WORKSPACE_TOO_SMALL;
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
   hipError_t e = launch_batched(d_segments, num_segments, reinterpret_cast<uint32_t*>(ws + L.off_order),
-                                reinterpret_cast<uint32_t*>(ws + L.off_counters),
-                                reinterpret_cast<uint32_t*>(ws + L.off_scratch), L.scratch_words, L.grid,
-                                stream);
+                                reinterpret_cast<uint32_t*>(ws + L.off_counters), L.grid, stream);
   return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
 }
 

@@ -1,21 +1,25 @@
 // rtcdf_batched.hip -- batched RT-CDF: thousands of independent arrays with
 // uneven n and R sorted by one persistent launch.
 //
-// Each workgroup (1024 threads, 1 per compute unit, 135 KiB of LDS) takes whole
-// arrays ("segments") from a device work queue and runs every step of Alg. 4
-// of the paper for it without touching another workgroup:
-//   Alg. 5  histogram of the segment's keys in LDS (32-bit counters for
-//           R <= 2^15; two 16-bit counters per word above, with the exact
-//           wrap repair of the plain path into a per-workgroup global array);
-//   Alg. 4  local CDF of each range tile (width 2^15) by a blocked LDS scan;
-//   Alg. 6  tile offsets as the running total of the tile populations;
-//   Alg. 7  every output position gets b_t + min{x : C_t[x] >= p' + 1}; each
-//           wave writes 256 consecutive positions per step and carries the
-//           current value and its end from step to step.
-// A one-workgroup ordering kernel runs first: it buckets the segments by
-// log2(n + R) so that the queue hands out the largest segments first (longest
-// processing time first), and it resets the queue counter, so the pair of
-// launches can be captured in a HIP graph and replayed.
+// The work items are range tiles of the arrays ("segments"): a segment with
+// R <= 32768 is one item, a wider one (R <= 2^16) two, one per half of its
+// range.  Each workgroup (1024 threads, 1 per compute unit, 135 KiB of LDS)
+// takes items from a device work queue and runs every step of Alg. 4 of the
+// paper for it without touching another workgroup:
+//   Alg. 5  histogram of the keys that fall in the item's tile, in LDS (32-bit
+//           counters; keys outside the tile are not counted);
+//   Alg. 4  local CDF of the tile by a blocked LDS scan;
+//   Alg. 6  the tile's offset: 0 for the first tile; n minus the tile's own
+//           population for the last one (no key lies above it), so the two
+//           items of a segment never wait for each other;
+//   Alg. 7  every output position of the tile gets b_t + min{x : C_t[x] >=
+//           p' + 1}; each wave writes 256 consecutive positions per step and
+//           carries the current value and its end from step to step.
+// A one-workgroup ordering kernel runs first: it lists the items bucketed by
+// log2(n + R) so that the queue hands out the largest first (longest
+// processing time first; the two items of a segment side by side), and it
+// resets the queue, so the pair of launches can be captured in a HIP graph
+// and replayed.
 #include <hip/hip_runtime.h>
 
 #include "rtcdf_device.h"
@@ -38,15 +42,24 @@ constexpr uint32_t kBTile = 32768;                   // values per local CDF til
 constexpr uint32_t kBLdsWords = 33792;               // pad32(kBTile): LDS words of one padded tile
 constexpr uint32_t kBStageWords = kBBlock / 64 * 256;  // per-wave output staging (sparse steps)
 constexpr uint32_t kBBuckets = 34;
+static_assert(RTCDF_BATCH_MAX_RANGE <= 2 * kBTile, "a segment is at most two tiles");
 
 struct BatchArgs {
   const rtcdf_segment_t* segs;
   uint32_t nseg;
-  const uint32_t* order;
-  uint32_t* counters;      // [0] next queue slot
-  uint32_t* scratch;       // per workgroup: scratch_words (16-bit counter repair / counts)
-  uint32_t scratch_words;
+  const uint32_t* order;   // work items: 2 x segment index + tile
+  uint32_t* counters;      // [0] next queue slot, [1] number of items
 };
+
+// Whether a descriptor is sorted at all (others are skipped, output untouched).
+__device__ __forceinline__ bool seg_valid(const rtcdf_segment_t& d) {
+  return d.n != 0 && d.range != 0 && d.range <= RTCDF_BATCH_MAX_RANGE && d.keys_in != nullptr &&
+         d.keys_out != nullptr;
+}
+
+__device__ __forceinline__ uint32_t seg_tiles(const rtcdf_segment_t& d) {
+  return seg_valid(d) ? (d.range > kBTile ? 2u : 1u) : 0u;
+}
 
 __device__ __forceinline__ uint32_t seg_bucket(const rtcdf_segment_t& d) {
   const uint64_t size = (uint64_t)d.n + d.range + 1;
@@ -59,7 +72,10 @@ __global__ __launch_bounds__(1024) void k_batch_order(const rtcdf_segment_t* seg
   __shared__ uint32_t hist[kBBuckets];
   if (threadIdx.x < kBBuckets) hist[threadIdx.x] = 0;
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nseg; i += blockDim.x) atomicAdd(&hist[seg_bucket(segs[i])], 1u);
+  for (uint32_t i = threadIdx.x; i < nseg; i += blockDim.x) {
+    const uint32_t t = seg_tiles(segs[i]);
+    if (t) atomicAdd(&hist[seg_bucket(segs[i])], t);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t run = 0;
@@ -68,11 +84,16 @@ __global__ __launch_bounds__(1024) void k_batch_order(const rtcdf_segment_t* seg
       hist[b] = run;
       run += c;
     }
-    counters[0] = 0;   // the queue starts empty at every launch
+    counters[0] = 0;     // the queue starts empty at every launch
+    counters[1] = run;   // items
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nseg; i += blockDim.x)
-    order[atomicAdd(&hist[seg_bucket(segs[i])], 1u)] = i;
+  for (uint32_t i = threadIdx.x; i < nseg; i += blockDim.x) {
+    const uint32_t t = seg_tiles(segs[i]);
+    if (t == 0) continue;
+    const uint32_t at = atomicAdd(&hist[seg_bucket(segs[i])], t);
+    for (uint32_t k = 0; k < t; ++k) order[at + k] = 2 * i + k;
+  }
 }
 
 // In-place inclusive scan of the padded LDS array C[0..w); returns the total.
@@ -182,17 +203,19 @@ __device__ void fill_tile(g_i32* out, const uint32_t* C, uint32_t w, uint32_t ba
       out[p] = (int32_t)(base + min(count_le_pad(C, w, (uint32_t)p - P0), last));
 }
 
-template <int V, bool PACKED>
-__device__ void count_segment(const g_i32* in, uint32_t n, uint32_t min_u, uint32_t R, uint32_t* S,
-                              uint32_t* carry) {
+// Counts the keys of `in` whose value lies in the tile [base, base + w)
+// (normalised to x = key - base; others are not counted) into the padded
+// 32-bit LDS counters S.
+template <int V>
+__device__ void count_tile(const g_i32* in, uint32_t n, uint32_t base, uint32_t w, uint32_t* S) {
   const uint32_t tid = threadIdx.x;
   const uintptr_t ia = (uintptr_t)in;
   uint32_t head = (uint32_t)(((16 - (ia & 15)) & 15) / 4);
   if (head > n) head = n;
   const uint32_t n4 = (n - head) / 4, tail = n - head - 4 * n4;
   const g_v4i* body = (const g_v4i*)(in + head);
-  const v4i outside = (v4i)(int)(min_u - 1u);   // normalises to 0xffffffff: never counted
-  HotBin hot;                                    // unused by the 32- and 16-bit forms
+  const v4i outside = (v4i)(int)(base - 1u);   // normalises to 0xffffffff: never counted
+  HotBin hot;                                   // unused by the 32-bit form
   // Pipelined as in the plain histogram: unconditional loads from indices
   // clamped into [0, n4), `outside` for lanes past the end of the last tile.
   if (n4 > 0) {
@@ -207,13 +230,11 @@ __device__ void count_segment(const g_i32* in, uint32_t n, uint32_t min_u, uint3
       for (int j = 0; j < V; ++j) nxt[j] = __builtin_nontemporal_load(&body[min(t1 + j * kBBlock, last)]);
       if (tb + kBBlock * V <= n4) {
 #pragma unroll
-        for (int j = 0; j < V; ++j)
-          count4<PACKED ? 16 : 32, !PACKED>(S, cur[j], min_u, R, carry, 0u, nullptr, hot);
+        for (int j = 0; j < V; ++j) count4<32, true>(S, cur[j], base, w, nullptr, 0u, nullptr, hot);
       } else {
 #pragma unroll
         for (int j = 0; j < V; ++j)
-          count4<PACKED ? 16 : 32, !PACKED>(S, t0 + j * kBBlock < n4 ? cur[j] : outside, min_u, R, carry,
-                                            0u, nullptr, hot);
+          count4<32, true>(S, t0 + j * kBBlock < n4 ? cur[j] : outside, base, w, nullptr, 0u, nullptr, hot);
       }
 #pragma unroll
       for (int j = 0; j < V; ++j) cur[j] = nxt[j];
@@ -223,108 +244,82 @@ __device__ void count_segment(const g_i32* in, uint32_t n, uint32_t min_u, uint3
     v4i e = outside;
     if (tid < head) e.x = in[tid];
     if (tid < tail) e.y = in[head + 4 * n4 + tid];
-    count4<PACKED ? 16 : 32, !PACKED>(S, e, min_u, R, carry, 0u, nullptr, hot);
+    count4<32, true>(S, e, base, w, nullptr, 0u, nullptr, hot);
   }
 }
 
-template <int V>
-__device__ void sort_segment(const rtcdf_segment_t& d, uint32_t* S, uint32_t* wsum, uint32_t* cnt,
-                             uint32_t scratch_words) {
+// Keys per thread per load step of the count phase, from the descriptor's
+// config (4, 8 or 16; anything else is the default, 16).
+__device__ __forceinline__ uint32_t seg_vectors(uint32_t config) {
+  return config == 4 ? 1u : (config == 8 ? 2u : 4u);
+}
+
+// Work item `tile` of segment d: the tile's histogram, local CDF and output
+// interval (see the file comment).
+__device__ void sort_item(const rtcdf_segment_t& d, uint32_t tile, uint32_t* S, uint32_t* wsum) {
   const uint32_t tid = threadIdx.x;
   const uint32_t n = d.n, R = d.range;
-  // Descriptors that break the documented limits are skipped (output untouched).
-  if (n == 0 || R == 0 || R > RTCDF_BATCH_MAX_RANGE || d.keys_in == nullptr || d.keys_out == nullptr)
-    return;
   const g_i32* in = (const g_i32*)d.keys_in;
   g_i32* out = (g_i32*)d.keys_out;
-  if (R > kBTile && scratch_words < R + 2) return;
-  const uint32_t min_u = (uint32_t)d.minVal;
+  const uint32_t lo = tile * kBTile;
+  const uint32_t w = R - lo < kBTile ? R - lo : kBTile;
+  const uint32_t base = (uint32_t)d.minVal + lo;
   const uintptr_t oa = (uintptr_t)out;
   uint32_t body_lo = (uint32_t)(((16 - (oa & 15)) & 15) / 4);
   if (body_lo > n) body_lo = n;
-
-  if (R <= kBTile) {
-    // One tile: 32-bit counters in the padded layout, scanned in place.
-    const uint32_t words = pad32(R - 1) + 1;
-    for (uint32_t i = tid; i < words; i += kBBlock) S[i] = 0u;
-    __syncthreads();
-    count_segment<V, false>(in, n, min_u, R, S, nullptr);
-    __syncthreads();
-    const uint32_t total = scan_tile(S, R, wsum);
-    fill_tile(out, S, R, min_u, 0u, total, body_lo, S + kBLdsWords);
-    __syncthreads();   // LDS is reused by the next segment
-    return;
+  const uint32_t words = pad32(w - 1) + 1;
+  for (uint32_t i = tid; i < words; i += kBBlock) S[i] = 0u;
+  __syncthreads();
+  switch (seg_vectors(d.config)) {
+    case 1: count_tile<1>(in, n, base, w, S); break;
+    case 2: count_tile<2>(in, n, base, w, S); break;
+    default: count_tile<4>(in, n, base, w, S); break;
   }
-
-  // Two tiles: 16-bit counters, repaired and merged into the workgroup's
-  // global count array, then each tile's counts are scanned in LDS.  The count
-  // array belongs to this workgroup alone, so workgroup-scope ordering is
-  // enough between its phases (every store and atomic has reached L2 before
-  // the barrier; the reads below bypass L1).  A device-scope fence here would
-  // write back the whole L2 of the XCD, once per segment.
-  for (uint32_t i = tid; i < (R + 1) / 2; i += kBBlock) S[i] = 0u;
-  for (uint32_t i = tid; i < R + 2; i += kBBlock) cnt[i] = 0u;
-  __threadfence_block();
   __syncthreads();
-  count_segment<V, true>(in, n, min_u, R, S, cnt);
-  __threadfence_block();
-  __syncthreads();
-  for (uint32_t x = tid; x < R; x += kBBlock) atomicAdd(&cnt[x], (S[x >> 1] >> ((x & 1u) << 4)) & 0xffffu);
-  __threadfence_block();
-  __syncthreads();
-  uint32_t O = 0;
-  for (uint32_t b = 0; b < R; b += kBTile) {
-    const uint32_t w = R - b < kBTile ? R - b : kBTile;
-    for (uint32_t i = tid; i < w; i += kBBlock)
-      S[pad32(i)] = __hip_atomic_load(&cnt[b + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const uint32_t Nt = scan_tile(S, w, wsum);
-    if (Nt) fill_tile(out, S, w, min_u + b, O, O + Nt, body_lo, S + kBLdsWords);
-    O += Nt;
-    __syncthreads();
-  }
+  const uint32_t Nt = scan_tile(S, w, wsum);
+  // Alg. 6: the first tile starts at 0, the last one ends at n (no key lies
+  // above it); Nt <= n, so the interval stays inside the output even if the
+  // keys broke the range precondition.
+  const uint32_t P0 = tile == 0 ? 0u : n - Nt;
+  if (Nt) fill_tile(out, S, w, base, P0, P0 + Nt, body_lo, S + kBLdsWords);
+  __syncthreads();   // LDS is reused by the next item
 }
 
-template <int V>
 __global__ __launch_bounds__(kBBlock) void k_batched(BatchArgs a) {
   extern __shared__ uint32_t S[];
   __shared__ uint32_t wsum[kBBlock / 64];
   __shared__ uint32_t s_q;
-  uint32_t* cnt = a.scratch + (size_t)blockIdx.x * a.scratch_words;
+  const uint32_t items = a.counters[1];
   for (;;) {
     if (threadIdx.x == 0) s_q = atomicAdd(&a.counters[0], 1u);
     __syncthreads();
     const uint32_t q = s_q;
     __syncthreads();
-    if (q >= a.nseg) break;
-    const rtcdf_segment_t d = a.segs[a.order[q]];
-    sort_segment<V>(d, S, wsum, cnt, a.scratch_words);
+    if (q >= items) break;
+    const uint32_t it = a.order[q];
+    const rtcdf_segment_t d = a.segs[it >> 1];
+    if (seg_valid(d)) sort_item(d, it & 1u, S, wsum);
   }
 }
 
 }  // namespace
 
-size_t batched_scratch_words(uint32_t max_range) {
-  return max_range > kBTile ? (size_t)max_range + 2 : 0;
-}
+size_t batched_order_words(uint32_t nseg) { return 2ull * nseg; }
 
-hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, uint32_t* order,
-                          uint32_t* counters, uint32_t* scratch, uint32_t scratch_words, uint32_t grid,
-                          hipStream_t s) {
+hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, uint32_t* order, uint32_t* counters,
+                          uint32_t grid, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, segs, nseg, order, counters);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = (size_t)(kBLdsWords + kBStageWords) * 4;
-  e = ensure_dynamic_lds((const void*)k_batched<4>, (int)lds);
+  e = ensure_dynamic_lds((const void*)k_batched, (int)lds);
   if (e != hipSuccess) return e;
   BatchArgs a;
   a.segs = segs;
   a.nseg = nseg;
   a.order = order;
   a.counters = counters;
-  a.scratch = scratch;
-  a.scratch_words = scratch_words;
-  hipLaunchKernelGGL(k_batched<4>, dim3(grid), dim3(kBBlock), lds, s, a);
+  hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBBlock), lds, s, a);
   return hipGetLastError();
 }
 

@@ -153,11 +153,11 @@ hipError_t launch_output_pmax(const Plan& p, int32_t* out, uint8_t* ws, hipStrea
 // fast-path area `area` (kFastAreaWords, whose state the launch advances).
 hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStream_t stream);
 
-// Batched sort (rtcdf_batched.hip).
-size_t batched_scratch_words(uint32_t max_range);
-hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, uint32_t* order,
-                          uint32_t* counters, uint32_t* scratch, uint32_t scratch_words, uint32_t grid,
-                          hipStream_t stream);
+// Batched sort (rtcdf_batched.hip): the work-item list holds
+// batched_order_words(nseg) words; counters 2 words.
+size_t batched_order_words(uint32_t nseg);
+hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, uint32_t* order, uint32_t* counters,
+                          uint32_t grid, hipStream_t stream);
 
 // Learned picker (rtcdf_mlp.hip).
 hipError_t launch_sketch(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R, uint32_t samples,

@@ -363,13 +363,21 @@ def stream_copy(src, dst, stream=None):
 
 # ---- batched sort
 
-def make_segments(pairs, device="cuda"):
+def make_segments(pairs, device="cuda", configs=None):
     """Device descriptor array and host bounds for rtcdf_sort_batched.
 
     pairs: iterable of (keys_in, keys_out, minVal, maxVal) with int32 CUDA
-    tensors.  Returns (descriptors as a uint8 CUDA tensor, BatchBounds, count)."""
+    tensors.  configs: None (every segment's config 0), a list with one
+    config word per segment (keys per thread per load step: 4, 8 or 16), or
+    "auto": the items_per_thread of the configuration the current config mode
+    chooses for each segment's (n, range).  Returns (descriptors as a uint8
+    CUDA tensor, BatchBounds, count)."""
     import torch
     pairs = list(pairs)
+    if isinstance(configs, str) and configs == "auto":
+        configs = [pick_config(max(a.numel(), 1), lo, hi).items_per_thread for a, _, lo, hi in pairs]
+    elif configs is not None and len(configs) != len(pairs):
+        raise ValueError("one config per segment")
     arr = (Segment * max(len(pairs), 1))()
     total, max_n, max_r = 0, 0, 0
     for i, (a, b, lo, hi) in enumerate(pairs):
@@ -377,7 +385,8 @@ def make_segments(pairs, device="cuda"):
         if R < 1 or R > BATCH_MAX_RANGE or lo < -(2 ** 31) or hi > 2 ** 31:
             raise ValueError(f"segment {i}: range [{lo}, {hi}) not supported by the batched sort")
         n = a.numel()
-        arr[i] = Segment(a.data_ptr() if n else 0, b.data_ptr() if n else 0, n, int(lo), R, 0)
+        arr[i] = Segment(a.data_ptr() if n else 0, b.data_ptr() if n else 0, n, int(lo), R,
+                         int(configs[i]) if configs is not None else 0)
         total += n
         max_n = max(max_n, n)
         max_r = max(max_r, R)

@@ -71,8 +71,8 @@ def _check(arrays, specs, pairs, dout, offs_out):
     assert np.all(full[mask] == GUARD), "memory outside the outputs was written"
 
 
-def _run(r, pairs):
-    d, bounds, k = r.make_segments(pairs)
+def _run(r, pairs, configs=None):
+    d, bounds, k = r.make_segments(pairs, configs=configs)
     ws = torch.empty(r.batched_workspace_bytes(k, bounds), dtype=torch.uint8, device="cuda")
     ws.fill_(0xCD)
     r.sort_batched(d, k, bounds, ws)
@@ -126,6 +126,22 @@ def test_batch_workload_full(r):
     arrays, pairs, din, dout, offs = _build(specs, 5)
     _run(r, pairs)
     _check(arrays, specs, pairs, dout, offs)
+
+
+def test_segment_configs(r):
+    """Per-segment configs (keys per thread per load step 4, 8, 16, the
+    default 0, and an unknown value, which means the default) and the
+    library's choice ("auto") give the oracle's output, one- and two-tile
+    segments alike."""
+    segs = inputs.batched_segments(300, seed=91)
+    specs = [(s["n"], s["minVal"], s["maxVal"] - s["minVal"], s["dist"]) for s in segs]
+    specs += [(500_000, -9, 65536, "uniform"), (400_001, 5, 40000, "normal"), (300_000, 0, 60000, "all_equal")]
+    arrays, pairs, din, dout, offs = _build(specs, 6)
+    for configs in ([(4, 8, 16, 0, 7)[i % 5] for i in range(len(specs))], "auto"):
+        _say(f"segment configs {configs if isinstance(configs, str) else 'mixed'}")
+        dout.fill_(GUARD)
+        _run(r, pairs, configs)
+        _check(arrays, specs, pairs, dout, offs)
 
 
 def test_skipped_descriptors(r):
