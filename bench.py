@@ -430,8 +430,8 @@ def bench_learned(torch, rtcdf, cases, ins, outs, steps):
                  timing, the LEARNED decision, static / learned / best each
                  the median of 3 run-medians of 30) on the first 40 arrays of
                  the held-out set with n <= 10^8.
-    The full 500-array held-out evaluation is reported as stored
-    (held_out_full_stored: learn.py heldout, its own run)."""
+    Only what this run measures is reported; the full 500-array held-out
+    evaluation is `learn.py heldout`, a run of its own."""
     import math
     from paper_2609_00843_amd import inputs, learn, tune
     model = os.path.join(ROOT, "paper_2609_00843_amd", "data", "model.bin")
@@ -520,13 +520,6 @@ def bench_learned(torch, rtcdf, cases, ins, outs, steps):
     finally:
         rtcdf.set_config_mode(old)
         rtcdf.clear_pick_cache()
-    ev = os.path.join(ROOT, "paper_2609_00843_amd", "data", "learned_eval.json")
-    if os.path.exists(ev):
-        full = json.load(open(ev)).get("summary", {})
-        res["held_out_full_stored"] = {"note": "stored result of `learn.py heldout` (500 arrays), not measured "
-                                               "by this run",
-                                       **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in full.items()
-                                          if k not in ("by_dist", "by_source")}}
     return res
 
 
