@@ -755,8 +755,9 @@ rtcdf_status_t rtcdf_debug_intermediates(const int32_t* keys_in, size_t n, int64
 // ---- batched
 
 struct BatchLayout {
-  size_t off_counters, off_order, bytes;
+  size_t off_counters, off_order, off_slots, bytes;
   uint32_t grid;
+  BatchPlan plan;
 };
 
 static rtcdf_status_t batch_layout(uint32_t nseg, const rtcdf_batch_bounds_t* bounds, BatchLayout* L) {
@@ -765,13 +766,13 @@ static rtcdf_status_t batch_layout(uint32_t nseg, const rtcdf_batch_bounds_t* bo
   DeviceInfo dev;
   rtcdf_status_t st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;
-  // one persistent workgroup per compute unit, or one per work item (a
-  // segment is one or two items)
-  const uint64_t items = (uint64_t)std::max<uint32_t>(nseg, 1) * (bounds->max_range > 32768 ? 2 : 1);
-  L->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dev.cus, items));
+  L->plan = batched_plan(nseg, bounds->total_keys, dev.cus);
+  // one persistent workgroup per compute unit, or one per work item
+  L->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dev.cus, L->plan.items_max));
   L->off_counters = 0;
   L->off_order = 256;
-  L->bytes = align256(L->off_order + batched_order_words(nseg) * 4);
+  L->off_slots = align256(L->off_order + L->plan.order_words * 4);
+  L->bytes = align256(L->off_slots + L->plan.slot_words * 4);
   return RTCDF_SUCCESS;
 }
 
@@ -798,8 +799,9 @@ rtcdf_status_t rtcdf_sort_batched(const rtcdf_segment_t* d_segments, uint32_t nu
   if (st != RTCDF_SUCCESS) return st;
   if (ws_bytes < L.bytes) return RTCDF_ERROR_WORKSPACE_TOO_SMALL;
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
-  hipError_t e = launch_batched(d_segments, num_segments, reinterpret_cast<uint32_t*>(ws + L.off_order),
-                                reinterpret_cast<uint32_t*>(ws + L.off_counters), L.grid, stream);
+  hipError_t e = launch_batched(d_segments, num_segments, L.plan, reinterpret_cast<uint32_t*>(ws + L.off_order),
+                                reinterpret_cast<uint32_t*>(ws + L.off_counters),
+                                reinterpret_cast<uint32_t*>(ws + L.off_slots), L.grid, stream);
   return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
 }
 

@@ -153,11 +153,20 @@ hipError_t launch_output_pmax(const Plan& p, int32_t* out, uint8_t* ws, hipStrea
 // fast-path area `area` (kFastAreaWords, whose state the launch advances).
 hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStream_t stream);
 
-// Batched sort (rtcdf_batched.hip): the work-item list holds
-// batched_order_words(nseg) words; counters 2 words.
-size_t batched_order_words(uint32_t nseg);
-hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, uint32_t* order, uint32_t* counters,
-                          uint32_t grid, hipStream_t stream);
+// Batched sort (rtcdf_batched.hip).  batched_plan sizes the workspace from
+// the host-side bounds: order_words words of work-item list, slot_words words
+// of chunked-tile state (counters: 3 words).
+struct BatchPlan {
+  uint32_t K;            // keys (and output positions) per chunk of a chunked segment
+  uint32_t max_slots;    // chunked tiles the workspace holds
+  uint32_t max_chunks;   // count items (and fill items) it holds
+  uint64_t items_max;    // work items it holds
+  uint64_t order_words;
+  uint64_t slot_words;
+};
+BatchPlan batched_plan(uint32_t nseg, uint64_t total_keys, uint32_t cus);
+hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, const BatchPlan& plan, uint32_t* order,
+                          uint32_t* counters, uint32_t* slots, uint32_t grid, hipStream_t stream);
 
 // Learned picker (rtcdf_mlp.hip).
 hipError_t launch_sketch(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R, uint32_t samples,

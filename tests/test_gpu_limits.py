@@ -108,8 +108,8 @@ def test_uint8_near_2pow32(r):
 
 
 def test_batched_segment_near_2pow32(r):
-    """One batch segment of 2^32 - 1 keys (two range tiles, 16-bit counters)
-    beside a small one."""
+    """One batch segment of 2^32 - 1 keys (two range tiles, each split into
+    512 chunks over the workgroups) beside a small one."""
     n, lo, R = N32, -77, 40000
     tail = [(lo + R - 30, 2), (lo + R - 29, 1), (lo + R - 1, 80)]
     _say(f"batched segment n={n} R={R}")
@@ -123,6 +123,7 @@ def test_batched_segment_near_2pow32(r):
     r.sort_batched(d, k, bounds, ws)
     torch.cuda.synchronize()
     del a
+    assert int(ws[8:12].cpu().view(torch.int32).item()) == 0   # no timed-out wait
     assert np.array_equal(small_out.cpu().numpy(), oracle.sort(small.cpu().numpy(), 3, 103))
     _verify(b, cnt, lo, n)
 
