@@ -91,14 +91,18 @@ typedef enum rtcdf_status {
  *                    writes the steps one value per thread.  The library's
  *                    own choice (every config mode) sets it when R >= 2^14
  *                    and R >= n.
- *  RTCDF_FLAG_COUNTERS_16 / RTCDF_FLAG_COUNTERS_32  the width of the
- *                    histogram's LDS counters (Alg. 5): two 16-bit counters
- *                    per 32-bit word, or one 32-bit counter, instead of the
- *                    library's choice (32 bits where that needs no more LDS
- *                    passes than four 8-bit counters per word, else 8 bits).
- *                    Narrower counters fit more bins per pass but wrap
+ *  RTCDF_FLAG_COUNTERS_16 / RTCDF_FLAG_COUNTERS_32 / RTCDF_FLAG_COUNTERS_4
+ *                    the width of the histogram's LDS counters (Alg. 5): two
+ *                    16-bit counters per 32-bit word, one 32-bit counter, or
+ *                    eight 4-bit counters, instead of the library's choice
+ *                    (32 bits where that needs no more LDS passes than four
+ *                    8-bit counters per word, else 8 bits).  At most one of
+ *                    the three.  Narrower counters fit more bins per pass
+ *                    (4-bit: 2^18 bins in one pass over the keys) but wrap
  *                    (repaired exactly); heavily repeated keys wrap 8-bit
- *                    counters every 256 hits.
+ *                    counters every 256 hits and 4-bit ones every 16, so
+ *                    4-bit counters pay only for spread-out keys.  Int32 keys
+ *                    only (ignored by rtcdf_sort_keys for narrower keys).
  *  RTCDF_FLAG_WAVE_DEDUPE  before its LDS atomics a wave matches one
  *                    candidate value (its hot value, else its first lane's
  *                    key) against all its keys with ballots and adds the
@@ -115,7 +119,8 @@ typedef enum rtcdf_status {
 #define RTCDF_FLAG_OUTPUT_PREFIX_MAX 0x01u
 #define RTCDF_FLAG_COUNTERS_16 0x04u
 #define RTCDF_FLAG_COUNTERS_32 0x08u
-#define RTCDF_FLAG_COUNTERS_MASK 0x0cu
+#define RTCDF_FLAG_COUNTERS_4 0x40u
+#define RTCDF_FLAG_COUNTERS_MASK 0x4cu
 #define RTCDF_FLAG_WAVE_DEDUPE 0x10u
 #define RTCDF_FLAG_CHUNK_4096 0x20u
 typedef struct rtcdf_config {
@@ -311,13 +316,14 @@ int rtcdf_get_config_mode(void);
  * {2^10 .. 2^15} x items per thread in {4, 8, 16} x blocks per tile in
  * {1, 2, 4}, flags 0; index i = 9 * log2(T / 1024) + 3 * log2(items / 4) +
  * log2(blocks).  Points with T * 4 * blocks > 160 KiB are invalid (45 of the
- * 54).  Points 54-60, the option points: (0, 0, 0, flags), i.e. the static
+ * 54).  Points 54-61, the option points: (0, 0, 0, flags), i.e. the static
  * table's (T, items, blocks) for the problem with the flags
  * PREFIX_MAX, COUNTERS_16, COUNTERS_16 | WAVE_DEDUPE, WAVE_DEDUPE,
- * CHUNK_4096, COUNTERS_16 | CHUNK_4096, COUNTERS_32 (52 valid points in all).
+ * CHUNK_4096, COUNTERS_16 | CHUNK_4096, COUNTERS_32, COUNTERS_4 (53 valid
+ * points in all).
  * configs / valid: host arrays of RTCDF_GRID_SIZE entries, either may be
  * NULL. */
-#define RTCDF_GRID_SIZE 61
+#define RTCDF_GRID_SIZE 62
 rtcdf_status_t rtcdf_config_grid(rtcdf_config_t* configs, uint8_t* valid);
 
 /* Exhaustive autotuner: times every valid grid configuration of the plain
@@ -394,15 +400,15 @@ int rtcdf_last_pick_index(void);
 #define RTCDF_SKETCH_SAMPLES 4096
 #define RTCDF_MLP_INPUTS 34
 #define RTCDF_MLP_HIDDEN 64
-#define RTCDF_MLP_OUTPUTS 61
-#define RTCDF_MLP_PARAMS 10365
+#define RTCDF_MLP_OUTPUTS 62
+#define RTCDF_MLP_PARAMS 10430
 rtcdf_status_t rtcdf_sketch(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,
                             float* d_features, hipStream_t stream);
 
-/* FP32 MLP y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 (34 -> 64 -> 64 -> 61, one
+/* FP32 MLP y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 (34 -> 64 -> 64 -> 62, one
  * output per grid point).
  * d_params: device float[RTCDF_MLP_PARAMS] laid out W1[64][34] b1 W2[64][64]
- * b2 W3[61][64] b3.  d_X: batch x 34 (row-major), d_Y: batch x 61. */
+ * b2 W3[62][64] b3.  d_X: batch x 34 (row-major), d_Y: batch x 62. */
 rtcdf_status_t rtcdf_mlp_forward(const float* d_params, const float* d_X, uint32_t batch, float* d_Y,
                                  hipStream_t stream);
 
@@ -410,7 +416,7 @@ rtcdf_status_t rtcdf_mlp_forward(const float* d_params, const float* d_X, uint32
 rtcdf_status_t rtcdf_mlp_workspace_bytes(uint32_t batch, size_t* bytes);
 
 /* Gradient of the masked mean squared error sum(M (Y - T)^2) / sum(M) over
- * the batch (d_T, d_M: batch x 61; M is 0/1) into d_grad[RTCDF_MLP_PARAMS];
+ * the batch (d_T, d_M: batch x 62; M is 0/1) into d_grad[RTCDF_MLP_PARAMS];
  * the loss into d_loss[0] if not NULL.  Deterministic (fixed-order sums).
  * Reads back the mask total (synchronises the stream). */
 rtcdf_status_t rtcdf_mlp_gradient(const float* d_params, const float* d_X, const float* d_T,
@@ -432,8 +438,8 @@ rtcdf_status_t rtcdf_mlp_train(float* d_params, float* d_m, float* d_v, uint32_t
                                hipStream_t stream);
 
 /* Sketch -> standardised features ((f - mean) / sd, d_norm = mean[34] then
- * sd[34]) -> MLP -> index of the smallest prediction among d_valid[61] != 0
- * (lowest index on ties) into d_index[0]; predictions into d_pred[61] if not
+ * sd[34]) -> MLP -> index of the smallest prediction among d_valid[62] != 0
+ * (lowest index on ties) into d_index[0]; predictions into d_pred[62] if not
  * NULL.  d_params must be 16-byte aligned.  One small launch, no host
  * synchronisation. */
 rtcdf_status_t rtcdf_mlp_pick(const int32_t* keys_in, size_t n, int64_t minVal, int64_t maxVal,

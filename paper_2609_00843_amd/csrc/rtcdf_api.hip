@@ -91,7 +91,8 @@ static bool flags_valid(uint32_t f) {
   constexpr uint32_t known = RTCDF_FLAG_OUTPUT_PREFIX_MAX | RTCDF_FLAG_COUNTERS_MASK | RTCDF_FLAG_WAVE_DEDUPE |
                              RTCDF_FLAG_CHUNK_4096;
   if ((f & ~known) != 0) return false;
-  if ((f & RTCDF_FLAG_COUNTERS_MASK) == RTCDF_FLAG_COUNTERS_MASK) return false;   // both widths
+  const uint32_t cw = f & RTCDF_FLAG_COUNTERS_MASK;
+  if ((cw & (cw - 1)) != 0) return false;   // more than one width
   return true;
 }
 
@@ -169,6 +170,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   const uint32_t k32 = std::max<uint32_t>(1, lds / (4 * p->T));
   const uint32_t k16 = std::max<uint32_t>(1, (lds - 512) / (2 * p->T));   // 512 B wrap table
   const uint32_t k8 = std::max<uint32_t>(1, (lds - 512) / p->T);
+  const uint32_t k4 = std::max<uint32_t>(1, 2 * (lds - 512) / p->T);
   const uint32_t passes32 = (p->m + k32 - 1) / k32;
   const uint32_t passes8 = (p->m + k8 - 1) / k8;
   // 32-bit counters where they need no more passes (no wraps, no returning
@@ -179,10 +181,12 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   const uint32_t cw = cfg.flags & RTCDF_FLAG_COUNTERS_MASK;
   if (cw == RTCDF_FLAG_COUNTERS_16) p->bits = 16;
   else if (cw == RTCDF_FLAG_COUNTERS_32) p->bits = 32;
+  else if (cw == RTCDF_FLAG_COUNTERS_4 && kb == 4) p->bits = 4;
   p->dedupe = (cfg.flags & RTCDF_FLAG_WAVE_DEDUPE) != 0 && kb == 4;
   const int force_bits = env_int("RTCDF_DEV_COUNTER_BITS", 0);
-  if (force_bits == 8 || force_bits == 16 || force_bits == 32) p->bits = (uint32_t)force_bits;
-  const uint32_t k = p->bits == 8 ? k8 : (p->bits == 16 ? k16 : k32);
+  if (force_bits == 8 || force_bits == 16 || force_bits == 32 || (force_bits == 4 && kb == 4))
+    p->bits = (uint32_t)force_bits;
+  const uint32_t k = p->bits == 4 ? k4 : (p->bits == 8 ? k8 : (p->bits == 16 ? k16 : k32));
   p->passes = (p->m + k - 1) / k;
   p->W = p->passes == 1 ? std::min<uint32_t>(Rr, k * p->T) : k * p->T;
   p->row_words = p->W / (32 / p->bits);
@@ -208,6 +212,13 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
     // partial rows: their traffic (written once, read once) is capped at 1/32
     // of the 8 bytes per key.
     const uint64_t want = (n + 10ull * R - 1) / (10ull * R);
+    const uint64_t cap = n / (32ull * p->passes * p->row_words);
+    const uint64_t g = std::min<uint64_t>(want, cap);
+    if (g > G) G = (uint32_t)std::min<uint64_t>((g + 7) / 8 * 8, 1u << 16);
+  } else if (p->bits == 4) {
+    // The same bound for nibble counters (a wrap every 16 hits): at most R
+    // keys per workgroup, about one per bin for uniform keys.
+    const uint64_t want = (n + (uint64_t)R - 1) / R;
     const uint64_t cap = n / (32ull * p->passes * p->row_words);
     const uint64_t g = std::min<uint64_t>(want, cap);
     if (g > G) G = (uint32_t)std::min<uint64_t>((g + 7) / 8 * 8, 1u << 16);

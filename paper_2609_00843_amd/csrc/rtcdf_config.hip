@@ -39,6 +39,7 @@ constexpr uint32_t kGridOptions[RTCDF_GRID_SIZE - kPlainPoints] = {
     RTCDF_FLAG_CHUNK_4096,
     RTCDF_FLAG_COUNTERS_16 | RTCDF_FLAG_CHUNK_4096,
     RTCDF_FLAG_COUNTERS_32,
+    RTCDF_FLAG_COUNTERS_4,
 };
 static_assert(RTCDF_GRID_SIZE == kMlpOut, "one network output per grid point");
 
@@ -530,12 +531,12 @@ rtcdf_status_t rtcdf_load_tuned_table(const char* path) {
   return RTCDF_SUCCESS;
 }
 
-// Model file: "RTCDFMLP" | u32 version (1, 2 or 3) | u32 inputs, hidden,
+// Model file: "RTCDFMLP" | u32 version (1 to 4) | u32 inputs, hidden,
 // outputs, params | f32 log2n_lo, log2n_hi, log2r_lo, log2r_hi | versions 2
-// and 3: f32 margin, f32 zmax | f32 mean[inputs] | f32 sd[inputs] |
+// and up: f32 margin, f32 zmax | f32 mean[inputs] | f32 sd[inputs] |
 // f32 params[params] | u8 valid[outputs].  The outputs must match this
-// library's grid (version 3: RTCDF_GRID_SIZE points with the option points;
-// files of the 54-point grid are refused).
+// library's grid (version 4: RTCDF_GRID_SIZE points, the option points with
+// 4-bit counters; files of other grids are refused).
 rtcdf_status_t rtcdf_load_model(const char* path) {
   if (path == nullptr) return RTCDF_ERROR_INVALID_VALUE;
   FILE* f = std::fopen(path, "rb");
@@ -546,7 +547,7 @@ rtcdf_status_t rtcdf_load_model(const char* path) {
   float ranges[4];
   float gate[2] = {0.f, 0.f};   // margin, zmax
   bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "RTCDFMLP", 8) == 0 &&
-            std::fread(hdr, 4, 5, f) == 5 && hdr[0] >= 1 && hdr[0] <= 3 && hdr[1] == (uint32_t)kMlpIn &&
+            std::fread(hdr, 4, 5, f) == 5 && hdr[0] >= 1 && hdr[0] <= 4 && hdr[1] == (uint32_t)kMlpIn &&
             hdr[2] == (uint32_t)kMlpHidden && hdr[3] == (uint32_t)kMlpOut && hdr[4] == (uint32_t)kMlpParams &&
             std::fread(ranges, 4, 4, f) == 4 && (hdr[0] == 1 || std::fread(gate, 4, 2, f) == 2);
   ok = ok && std::isfinite(gate[0]) && gate[0] >= 0.f && std::isfinite(gate[1]) && gate[1] >= 0.f;

@@ -252,24 +252,27 @@ __device__ __forceinline__ void hot_flush_any(HotBin& hot, uint32_t* S, uint32_t
 // extra ballots cost more than the LDS conflicts they remove.)
 constexpr uint32_t kDedupeMin = 8;
 
-// Four 8-bit counters per LDS word (bin x in byte x & 3 of word x >> 2).  An
-// add of c << 8s changes the bytes above s through carries; every byte whose
-// represented change differs from its true change (c for byte s, 0 above) is
-// repaired, modulo 2^32, through the wrap table.  Rare for spread-out keys.
-__device__ __forceinline__ void fix_u8(uint32_t old, uint32_t x, uint32_t c, uint32_t* tab,
-                                       uint32_t* carry, uint32_t pass_lo) {
-  const uint32_t s = x & 3u, s8 = s << 3;
-  const uint32_t nw = old + (c << s8);
-  const uint32_t base = x & ~3u;
-  for (uint32_t j = s; j < 4; ++j) {
-    const int32_t rep = (int32_t)((nw >> (8 * j)) & 0xffu) - (int32_t)((old >> (8 * j)) & 0xffu);
+// 32 / BITS packed counters per LDS word (8-bit: bin x in byte x & 3 of word
+// x >> 2; 4-bit: nibble x & 7 of word x >> 3).  An add of c << (BITS s)
+// changes the fields above s through carries; every field whose represented
+// change differs from its true change (c for field s, 0 above) is repaired,
+// modulo 2^32, through the wrap table.  Rare for spread-out keys.
+template <int BITS>
+__device__ __forceinline__ void fix_packed(uint32_t old, uint32_t x, uint32_t c, uint32_t* tab,
+                                           uint32_t* carry, uint32_t pass_lo) {
+  constexpr uint32_t F = 32 / BITS, M = (1u << BITS) - 1u;
+  const uint32_t s = x & (F - 1u);
+  const uint32_t nw = old + (c << (BITS * s));
+  const uint32_t base = x & ~(F - 1u);
+  for (uint32_t j = s; j < F; ++j) {
+    const int32_t rep = (int32_t)((nw >> (BITS * j)) & M) - (int32_t)((old >> (BITS * j)) & M);
     const int32_t tru = j == s ? (int32_t)c : 0;
     if (rep != tru) wrap_add(tab, base + j, (uint32_t)(tru - rep), carry, pass_lo);
   }
 }
 
 // Counts the four keys of one vector per lane with BITS-bit LDS counters (32,
-// 16 or 8).  If every active lane of the wave holds four copies of one value
+// 16, 8 or 4).  If every active lane of the wave holds four copies of one value
 // (all-equal or heavily skewed keys), a single lane adds them with one LDS
 // atomic instead of 4 x 64 atomics on the same address (8-bit form: into the
 // wave's hot-bin register in the narrow forms).  Otherwise
@@ -277,8 +280,8 @@ __device__ __forceinline__ void fix_u8(uint32_t old, uint32_t x, uint32_t c, uin
 // off.  In the narrow forms the four returning atomics are issued back to
 // back and a counter that just wrapped is repaired after a single wave-wide
 // test.  PAD selects the padded 32-bit layout (bin x at x + x / 32).  `tab`
-// and `hot` (the wrap table and the hot-bin register) are used by the 8- and
-// 16-bit forms; the 16-bit form may run without a table (tab == nullptr).
+// and `hot` (the wrap table and the hot-bin register) are used by the 4-, 8-
+// and 16-bit forms; the 16-bit form may run without a table (tab == nullptr).
 // 1 << (s mod 32): the hardware shift reads only the low five bits of the
 // amount, so no mask is needed (the compiler emits one when it can prove the
 // amount's low bits are zero, as for x << 3).
@@ -349,12 +352,12 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
       x3 = x3 == cand ? kNone : x3;
     }
   }
-  if constexpr (BITS == 16 || BITS == 8) {
+  if constexpr (BITS == 16 || BITS == 8 || BITS == 4) {
     // Bin x is the field at bit (x & (32 / BITS - 1)) * BITS of word x >> LOG.
     // That offset is (x << SH) & 31, and the hardware shifts and bit-field
     // extracts read only the low 5 bits of an offset, so the masks fold away.
-    constexpr uint32_t LOG = BITS == 16 ? 1 : 2, SH = BITS == 16 ? 4 : 3;
-    constexpr uint32_t FULL = BITS == 16 ? 0xffffu : 0xffu;
+    constexpr uint32_t LOG = BITS == 16 ? 1 : (BITS == 8 ? 2 : 3), SH = BITS == 16 ? 4 : (BITS == 8 ? 3 : 2);
+    constexpr uint32_t FULL = (1u << BITS) - 1u;
     const uint32_t s0 = x0 << SH, s1 = x1 << SH, s2 = x2 << SH, s3 = x3 << SH;
     uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
     if (x0 < W) o0 = atomicAdd(&S[x0 >> LOG], shl1(s0));
@@ -373,10 +376,10 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
         if (w2) fix_u16(o2, x2, 1u, carry, pass_lo);
         if (w3) fix_u16(o3, x3, 1u, carry, pass_lo);
       } else {
-        if (w0) fix_u8(o0, x0, 1u, tab, carry, pass_lo);
-        if (w1) fix_u8(o1, x1, 1u, tab, carry, pass_lo);
-        if (w2) fix_u8(o2, x2, 1u, tab, carry, pass_lo);
-        if (w3) fix_u8(o3, x3, 1u, tab, carry, pass_lo);
+        if (w0) fix_packed<BITS>(o0, x0, 1u, tab, carry, pass_lo);
+        if (w1) fix_packed<BITS>(o1, x1, 1u, tab, carry, pass_lo);
+        if (w2) fix_packed<BITS>(o2, x2, 1u, tab, carry, pass_lo);
+        if (w3) fix_packed<BITS>(o3, x3, 1u, tab, carry, pass_lo);
       }
     }
   } else {

@@ -257,7 +257,8 @@ __device__ __forceinline__ void pmax_initial_fill(int32_t* out, uint32_t n, uint
 
 // One workgroup per 128-bin block of one pass: the block is 128 / (32 / bits)
 // words of every partial row of the pass.  Threads are 32 row groups x NQ word
-// quads (NQ = 32, 16, 8 for 32-, 16-, 8-bit counters: 1024, 512, 256 threads);
+// quads (NQ = 32, 16, 8, 4 for 32-, 16-, 8-, 4-bit counters: 1024, 512, 256,
+// 128 threads);
 // each thread adds the 16-byte quad of every 32nd row, four loads in flight,
 // and splits the words into their counters.  The row groups are summed in LDS;
 // every bin adds (and re-zeroes) its carry entry (narrow counters), and the
@@ -285,11 +286,14 @@ __device__ __forceinline__ void reduce_block(const ReduceArgs& a, uint32_t (*red
       } else if constexpr (BITS == 16) {
         acc[2 * j] += ws[j] & 0xffffu;
         acc[2 * j + 1] += ws[j] >> 16;
-      } else {
+      } else if constexpr (BITS == 8) {
         acc[4 * j] += ws[j] & 0xffu;
         acc[4 * j + 1] += (ws[j] >> 8) & 0xffu;
         acc[4 * j + 2] += (ws[j] >> 16) & 0xffu;
         acc[4 * j + 3] += ws[j] >> 24;
+      } else {
+#pragma unroll
+        for (uint32_t f = 0; f < 8; ++f) acc[8 * j + f] += (ws[j] >> (4 * f)) & 0xfu;
       }
     }
   };
@@ -333,7 +337,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
   }
   if (a.bits == 32) reduce_block<32>(a, red, wsum);
   else if (a.bits == 16) reduce_block<16>(a, red, wsum);
-  else reduce_block<8>(a, red, wsum);
+  else if (a.bits == 8) reduce_block<8>(a, red, wsum);
+  else reduce_block<4>(a, red, wsum);
   if (blockIdx.x == 0 && threadIdx.x == 0) a.flags[0] = 0u;
 }
 
@@ -1015,8 +1020,13 @@ hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
 template <int BITS, int BLOCK>
 hipError_t launch_hist_items(const Plan& p, const HistArgs& a, hipStream_t s) {
   // 8- and 16-bit keys: one 16-byte vector (16 or 8 keys) per thread per step
-  if (p.kb == 2) return launch_hist_t<4, BITS, BLOCK, 2>(p, a, s);
-  if (p.kb == 1) return launch_hist_t<4, BITS, BLOCK, 1>(p, a, s);
+  // (4-bit counters serve int32 keys only)
+  if constexpr (BITS == 4) {
+    if (p.kb != 4) return hipErrorInvalidValue;
+  } else {
+    if (p.kb == 2) return launch_hist_t<4, BITS, BLOCK, 2>(p, a, s);
+    if (p.kb == 1) return launch_hist_t<4, BITS, BLOCK, 1>(p, a, s);
+  }
   if (p.dedupe) {
     switch (p.items) {
       case 4: return launch_hist_t<4, BITS, BLOCK, 4, true>(p, a, s);
@@ -1089,6 +1099,7 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
     a.pbound = reinterpret_cast<const uint32_t*>(ws + p.off_pbound);
   }
   switch (p.bits) {
+    case 4: return launch_hist_block<4>(p, a, s);
     case 8: return launch_hist_block<8>(p, a, s);
     case 16: return launch_hist_block<16>(p, a, s);
     default: return launch_hist_block<32>(p, a, s);

@@ -41,7 +41,7 @@ from . import tune
 NOUT = len(tune.grid()[0])          # one network output per grid point
 SIZES = (34, 64, 64, NOUT)
 NPARAMS = sum(SIZES[i + 1] * SIZES[i] + SIZES[i + 1] for i in range(3))
-MODEL_VERSION = 3
+MODEL_VERSION = 4
 
 
 def dataset(rows):
@@ -86,8 +86,9 @@ def zmax_of(X, mu, sd) -> float:
 
 
 def save_model(path: str, params, mu, sd, ranges, margin: float = 0.0, zmax: float = 0.0):
-    """Model file version 3 (the grid with option points; version 1 had no
-    margin and zmax fields, versions 1 and 2 the 54-point grid)."""
+    """Model file version 4 (the grid with the 4-bit counter option point;
+    version 1 had no margin and zmax fields, versions 1 and 2 the 54-point
+    grid, version 3 the 61-point grid)."""
     _, valid = tune.grid()
     with open(path, "wb") as f:
         f.write(b"RTCDFMLP")
@@ -150,7 +151,7 @@ def load_model_file(path: str):
         raw = f.read()
     assert raw[:8] == b"RTCDFMLP"
     version, _, _, _, nparams = struct.unpack("<5I", raw[8:28])
-    assert version in (1, 2, 3)
+    assert version in (1, 2, 3, 4)
     o = 8 + 20
     ranges = struct.unpack("<4f", raw[o:o + 16])
     o += 16

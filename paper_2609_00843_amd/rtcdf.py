@@ -139,6 +139,7 @@ def _check(st: int, what: str):
 FLAG_OUTPUT_PREFIX_MAX = 0x01
 FLAG_COUNTERS_16 = 0x04
 FLAG_COUNTERS_32 = 0x08
+FLAG_COUNTERS_4 = 0x40
 FLAG_WAVE_DEDUPE = 0x10
 FLAG_CHUNK_4096 = 0x20
 # how a configuration was chosen (rtcdf_last_pick_source)
@@ -412,8 +413,8 @@ def sort_batched(d_segments, num_segments: int, bounds: BatchBounds, workspace, 
 
 # ---- configuration grid, autotuner, learned picker
 
-GRID_SIZE = 61
-MLP_INPUTS, MLP_HIDDEN, MLP_OUTPUTS, MLP_PARAMS = 34, 64, 61, 10365
+GRID_SIZE = 62
+MLP_INPUTS, MLP_HIDDEN, MLP_OUTPUTS, MLP_PARAMS = 34, 64, 62, 10430
 SKETCH_BINS, SKETCH_SAMPLES = 32, 4096
 
 _fp = ctypes.c_void_p

@@ -39,8 +39,8 @@ PLAIN_POINTS = 54
 # option points (flags of rtcdf_config_t, on the static table's T / items /
 # blocks): prefix-maximum output, 16-bit counters, 16-bit counters with wave
 # aggregation of duplicates, wave aggregation, 4096-position output chunks,
-# 16-bit counters with 4096-position chunks, 32-bit counters
-GRID_OPTIONS = (0x01, 0x04, 0x14, 0x10, 0x20, 0x24, 0x08)
+# 16-bit counters with 4096-position chunks, 32-bit counters, 4-bit counters
+GRID_OPTIONS = (0x01, 0x04, 0x14, 0x10, 0x20, 0x24, 0x08, 0x40)
 
 
 def grid():
@@ -124,6 +124,46 @@ def collect(db: str, which: str, count: int, warmup: int = 2, reps: int = 5, sta
             print(f"[tune] {k + 1}/{len(todo)} n={s['n']} R={s['R']} {s['dist']}/{s['sd_div']:g} "
                   f"best={best.as_tuple()} {min(t for t in times if t > 0):.4f} ms", flush=True)
             del a, b
+
+
+def extend(db: str, out: str, warmup: int = 2, reps: int = 5, start: int = 0, stop: int = None):
+    """Rows of `db` measured on a smaller grid get the times of the grid points
+    added since (appended to times_ms, same protocol as rtcdf_autotune: the
+    median of `reps` sorts, each between HIP events, after `warmup` untimed
+    ones).  Rows [start, stop) are written to `out`, one per line as they are
+    measured; rows already complete are copied."""
+    import torch
+    from . import rtcdf
+    pts, valid = grid()
+    rows = load_db(db)[start:stop]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    with open(out, "w") as f:
+        for k, s in enumerate(rows):
+            have = len(s["times_ms"])
+            if have < len(pts):
+                a = inputs.make_device(s["dist"], s["n"], s["minVal"], s["minVal"] + s["R"], s["seed"],
+                                       device=dev, sd_div=s["sd_div"])
+                b = torch.empty_like(a)
+                for j in range(have, len(pts)):
+                    if not valid[j]:
+                        s["times_ms"].append(-1.0)
+                        continue
+                    cfg = rtcdf.make_config(*pts[j])
+                    for _ in range(warmup):
+                        rtcdf.sort(a, s["minVal"], s["minVal"] + s["R"], keys_out=b, config=cfg, stream=stream)
+                    for e0, e1 in ev:
+                        e0.record(stream)
+                        rtcdf.sort(a, s["minVal"], s["minVal"] + s["R"], keys_out=b, config=cfg, stream=stream)
+                        e1.record(stream)
+                    torch.cuda.synchronize()
+                    s["times_ms"].append(float(np.median([e0.elapsed_time(e1) for e0, e1 in ev])))
+                del a, b
+                print(f"[extend] {k + 1}/{len(rows)} n={s['n']} R={s['R']} {s['dist']}/{s['sd_div']:g} "
+                      f"+{len(pts) - have} points: {s['times_ms'][have:]}", flush=True)
+            f.write(json.dumps(s) + "\n")
+            f.flush()
 
 
 def range_class(R: int) -> int:
@@ -220,6 +260,12 @@ def main(argv=None):
     c.add_argument("--stop", type=int, default=None)
     c.add_argument("--budget-s", type=float, default=None)
     c.add_argument("--reps", type=int, default=5)
+    e = sub.add_parser("extend")
+    e.add_argument("--db", required=True)
+    e.add_argument("--out", required=True)
+    e.add_argument("--start", type=int, default=0)
+    e.add_argument("--stop", type=int, default=None)
+    e.add_argument("--reps", type=int, default=5)
     t = sub.add_parser("table")
     t.add_argument("--db", required=True)
     t.add_argument("--tuned-out", default=os.path.join(DATA, "tuned_table.txt"))
@@ -227,6 +273,8 @@ def main(argv=None):
     if args.cmd == "collect":
         collect(args.db, args.set, args.count, reps=args.reps, start=args.start, stop=args.stop,
                 budget_s=args.budget_s)
+    elif args.cmd == "extend":
+        extend(args.db, args.out, reps=args.reps, start=args.start, stop=args.stop)
     else:
         rows = load_db(args.db)
         table = select_static(rows)

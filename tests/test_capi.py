@@ -134,7 +134,7 @@ def test_segment_layout(r):
 
 def test_flags_and_sizes_match_header(r):
     txt = open(os.path.join(ROOT, "include", "rtcdf.h")).read()
-    for name in ("OUTPUT_PREFIX_MAX", "COUNTERS_16", "COUNTERS_32", "WAVE_DEDUPE", "CHUNK_4096"):
+    for name in ("OUTPUT_PREFIX_MAX", "COUNTERS_16", "COUNTERS_32", "COUNTERS_4", "WAVE_DEDUPE", "CHUNK_4096"):
         m = re.search(r"#define\s+RTCDF_FLAG_%s\s+(0x[0-9a-f]+|\d+)u" % name, txt)
         assert m and int(m.group(1), 0) == getattr(r, "FLAG_" + name), name
     for name, val in (("GRID_SIZE", r.GRID_SIZE), ("MLP_OUTPUTS", r.MLP_OUTPUTS), ("MLP_PARAMS", r.MLP_PARAMS),
@@ -146,15 +146,17 @@ def test_flags_and_sizes_match_header(r):
 
 
 def test_config_validation(r):
-    """Option flags: known bits only, not both counter widths; a config with
-    zero knobs and some flags is valid (the static knobs with those flags)."""
+    """Option flags: known bits only, at most one counter width; a config
+    with zero knobs and some flags is valid (the static knobs with those
+    flags)."""
     L = r.lib
     c_in, c_out = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
     def st(cfg):
         return L.rtcdf_sort_with_config(c_in, c_out, 10, 0, 100, ctypes.byref(cfg), None)
-    assert st(r.make_config(1024, 16, 1, flags=0x40)) == r.INVALID_VALUE          # unknown bit
-    assert st(r.make_config(1024, 16, 1, flags=0x0c)) == r.INVALID_VALUE          # both widths
-    assert st(r.make_config(0, 0, 0, flags=0x0c)) == r.INVALID_VALUE
+    assert st(r.make_config(1024, 16, 1, flags=0x80)) == r.INVALID_VALUE          # unknown bit
+    for two in (0x0c, 0x44, 0x48, 0x4c):                                          # two widths
+        assert st(r.make_config(1024, 16, 1, flags=two)) == r.INVALID_VALUE
+        assert st(r.make_config(0, 0, 0, flags=two)) == r.INVALID_VALUE
     assert st(r.make_config(0, 16, 1, flags=0x04)) == r.INVALID_VALUE             # partly zero
 
 

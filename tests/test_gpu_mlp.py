@@ -9,7 +9,7 @@ element is a composition of sums; to first order in the unit roundoff
 u = 2^-24, rounding changes element e by at most K u A_e, where A_e is the
 same element computed with every factor replaced by its absolute value (and
 ReLU masks kept) and K is the total length of the sums on its dependency
-chain (forward 34 + 64 + 64, backward 61 + 64, the batch sum B).  The test
+chain (forward 34 + 64 + 64, backward 62 + 64, the batch sum B).  The test
 allows |got - want| <= 1e-4 |want| + 2 K u A_e: relative tolerance 1e-4 where
 no cancellation occurs, and the derived bound (with a factor 2 of slack) where
 it does."""
@@ -23,8 +23,8 @@ from paper_2609_00843_amd import inputs
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
-SIZES = (34, 64, 64, 61)
-NPARAM = sum(SIZES[i + 1] * SIZES[i] + SIZES[i + 1] for i in range(3))   # 10365
+SIZES = (34, 64, 64, 62)
+NPARAM = sum(SIZES[i + 1] * SIZES[i] + SIZES[i + 1] for i in range(3))   # 10430
 
 
 def _say(*a):

@@ -158,7 +158,24 @@ def test_few_distinct_values_wide_range(r, k):
     _run(r, A, 0, R)
 
 
-@pytest.mark.parametrize("bits", [8, 16, 32])
+@pytest.mark.parametrize("R", [1 << 16, (1 << 18) + 5, 1 << 20])
+def test_nibble_counter_overflow(r, R):
+    """4-bit counters (RTCDF_FLAG_COUNTERS_4): more equal keys per workgroup
+    than a nibble holds (15), in every nibble of one LDS word, across words
+    and in the last bin; and few distinct values spread over the range."""
+    n = 6_000_001
+    rng = np.random.default_rng(R + 4)
+    cfg = r.make_config(0, 0, 0, flags=r.FLAG_COUNTERS_4)
+    assert r.plan_info(n, -77, -77 + R, config=cfg)["counter_bits"] == 4
+    picks = ([0], [0, 1], [7], [R - 1], [2, 3, R - 1], list(range(8)), [5, 8, 9, 15, 16])
+    for pick in list(picks) + [list(rng.choice(R, size=300, replace=False))]:
+        vals = np.asarray(pick, dtype=np.int64)
+        A = (vals[rng.integers(0, vals.size, size=n)] - 77).astype(np.int32)
+        _say(f"nibble overflow R={R} values={len(pick)}")
+        _run(r, A, -77, -77 + R, cfg=cfg)
+
+
+@pytest.mark.parametrize("bits", [4, 8, 16, 32])
 @pytest.mark.parametrize("dist,R", [("zipf", 1000), ("normal", 65537), ("uniform", 1 << 18),
                                     ("all_equal", 1 << 17)])
 def test_forced_counter_width(r, monkeypatch, bits, dist, R):
@@ -208,7 +225,7 @@ def test_every_config_is_identical(r, dist, logR):
         assert np.array_equal(out.cpu().numpy(), want), (T, items, bpt)
 
 
-OPTION_FLAGS = (0x01, 0x04, 0x14, 0x10, 0x20, 0x24, 0x08, 0x18, 0x30, 0x11, 0x15)
+OPTION_FLAGS = (0x01, 0x04, 0x14, 0x10, 0x20, 0x24, 0x08, 0x18, 0x30, 0x11, 0x15, 0x40, 0x50, 0x60, 0x41)
 
 
 @pytest.mark.parametrize("dist,n,logR", [("uniform", 777_777, 7), ("zipf", 1_000_003, 10), ("normal", 2_000_001, 13),
@@ -230,6 +247,8 @@ def test_option_flags_are_identical(r, dist, n, logR):
             assert np.array_equal(out.cpu().numpy(), want), (flags, cfg)
     info = r.plan_info(n, minVal, minVal + R, config=r.make_config(0, 0, 0, flags=0x14))
     assert info["counter_bits"] == 16 and info["hist_dedupe"] == 1
+    info = r.plan_info(n, minVal, minVal + R, config=r.make_config(0, 0, 0, flags=0x40))
+    assert info["counter_bits"] == 4
 
 
 @pytest.mark.parametrize("R,T", [(4, 128), (1000, 128), (1000, 1024), (70000, 1024),

@@ -29,7 +29,7 @@ def test_grid_matches_library():
     from paper_2609_00843_amd import rtcdf
     pts, valid = tune.grid()
     lp, lv = rtcdf.config_grid()
-    assert pts == lp and valid == lv and sum(valid) == 52
+    assert pts == lp and valid == lv and sum(valid) == 53
     assert sum(valid[:tune.PLAIN_POINTS]) == 45 and all(p[:3] == (0, 0, 0) for p in pts[tune.PLAIN_POINTS:])
 
 
@@ -127,6 +127,6 @@ def test_decision_margin():
 def test_dataset_targets_are_centred():
     rows = _rows(3)
     X, T, M = learn.dataset(rows)
-    assert X.shape == (60, 34) and T.shape == (60, learn.NOUT) == (60, 61)
+    assert X.shape == (60, 34) and T.shape == (60, learn.NOUT) == (60, 62)
     assert np.allclose((T * M).sum(axis=1), 0.0, atol=1e-9)
-    assert M.sum(axis=1).tolist() == [52.0] * 60
+    assert M.sum(axis=1).tolist() == [53.0] * 60
