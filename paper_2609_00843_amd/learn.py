@@ -395,7 +395,20 @@ def main(argv=None):
     h.add_argument("--start", type=int, default=0)
     h.add_argument("--stop", type=int, default=None)
     h.add_argument("--out", required=True)
+    m = sub.add_parser("merge", help="one summary over several heldout result files")
+    m.add_argument("parts", nargs="+")
+    m.add_argument("--out", required=True)
     args = ap.parse_args(argv)
+    if args.cmd == "merge":
+        per = []
+        for path in args.parts:
+            with open(path) as f:
+                per.extend(json.load(f)["arrays"])
+        res = summarise_retimed(per)
+        with open(args.out, "w") as f:
+            json.dump({"summary": res, "arrays": per}, f)
+        print(json.dumps({k: v for k, v in res.items() if k not in ("by_dist", "by_source")}))
+        return 0
     if args.cmd == "heldout":
         specs = tune.specs(args.set, args.count)[args.start:args.stop]
         res, per = evaluate_retimed(specs, args.model, log=lambda *a: print(*a, flush=True))
