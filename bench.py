@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 N = 100_000_000
 MIN_VAL = -1000
 LOG_R = (7, 10, 13, 16, 18)
+PICK_NAMES = {0: "static", 1: "network", 2: "network_kept_static", 3: "autotuned", 4: "cached", 5: "pending"}
 WIDE_LOG_R = (20, 22, 24)   # beyond the paper's ranges: the partition by pass
 DISTS = ("uniform", "normal", "all_equal")
 METRIC = "Gkeys/s + % of 8 B/key HBM roofline; batched & learned-tuned vs plain"
@@ -283,7 +284,10 @@ def bench_wide_ranges(torch, rtcdf, inputs, steps):
     """n = 10^8 uniform and normal keys over R = 2^20, 2^22, 2^24 (beyond the
     paper's ranges): the library's choice (the partition by pass from 9
     passes on) against the histogram that reads every key once per pass
-    (RTCDF_DEV_PARTITION=0), warm, HIP events; the two outputs are compared."""
+    (RTCDF_DEV_PARTITION=0), and the LEARNED mode (these ranges lie outside
+    the network's trusted range, so its decision is the exhaustive autotune
+    of the grid, made once and cached; timed after it), warm, HIP events;
+    the outputs are compared."""
     stream = torch.cuda.current_stream()
     rows, same = [], True
     n = 10 ** 8
@@ -301,11 +305,31 @@ def bench_wide_ranges(torch, rtcdf, inputs, steps):
                 t_multi = timed_sorts(torch, rtcdf, a, c, 0, R, reps, stream)
                 os.environ.pop("RTCDF_DEV_PARTITION")
                 same = same and bool(torch.equal(b, c))
-                rows.append({"R": R, "dist": dist, "passes": info["passes"],
-                             "partition_buckets": info["partition_buckets"], "ms": round(t_lib, 4),
-                             "gkeys_per_s": round(n / (t_lib * 1e-3) / 1e9, 1),
-                             "ms_every_pass_reads_all_keys": round(t_multi, 4),
-                             "speedup": round(t_multi / t_lib, 2)})
+                row = {"R": R, "dist": dist, "passes": info["passes"],
+                       "partition_buckets": info["partition_buckets"], "ms": round(t_lib, 4),
+                       "gkeys_per_s": round(n / (t_lib * 1e-3) / 1e9, 1),
+                       "ms_every_pass_reads_all_keys": round(t_multi, 4),
+                       "speedup": round(t_multi / t_lib, 2)}
+                model = os.path.join(ROOT, "paper_2609_00843_amd", "data", "model.bin")
+                if os.path.exists(model):
+                    old = rtcdf.get_config_mode()
+                    try:
+                        rtcdf.load_model(model)
+                        rtcdf.set_config_mode(rtcdf.CONFIG_LEARNED)
+                        rtcdf.clear_pick_cache()
+                        rtcdf.pick_config(n, 0, R, keys_in=a)      # the decision, made once
+                        point, src = rtcdf.last_pick()
+                        c.fill_(0)
+                        t_l = timed_sorts(torch, rtcdf, a, c, 0, R, reps, stream)
+                        same = same and bool(torch.equal(b, c))
+                        row.update({"ms_learned": round(t_l, 4), "learned_point": int(point),
+                                    "learned_flags": rtcdf.config_grid()[0][point][3],
+                                    "learned_source": PICK_NAMES.get(src, src),
+                                    "gain_learned": round(t_lib / t_l, 3)})
+                    finally:
+                        rtcdf.set_config_mode(old)
+                        rtcdf.clear_pick_cache()
+                rows.append(row)
                 del a, b, c
     finally:
         os.environ.pop("RTCDF_DEV_PARTITION", None)
@@ -348,6 +372,70 @@ def bench_key_widths(torch, rtcdf, steps):
         del w, a, b, wide
     return {"workload": "n=1e8 uniform 16- and 8-bit keys", "rows": rows, "checked": ok,
             "timing": "warm, HIP events, mean"}
+
+
+def profile_large_n(torch, rtcdf, inputs, steps, warmup, flags=0):
+    """Profiling mode: the n = 10^9, R = 2^18 arrays of the scale section
+    (uniform, all equal, normal sd R/64), `warmup` then `steps` sorts each,
+    one array resident at a time (4 GB in + 4 GB out)."""
+    dev = torch.device("cuda:0")
+    n, R = 1_000_000_000, 1 << 18
+    b = torch.empty(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    cfg = rtcdf.make_config(0, 0, 0, flags=flags) if flags else None
+    res = {}
+    for dist, sd_div in (("uniform", 6.0), ("all_equal", 6.0), ("normal", 64.0)):
+        a = inputs.make_device(dist, n, 0, R, inputs.case_seed(3, int(sd_div)), sd_div=sd_div, device=dev)
+        for _ in range(warmup):
+            rtcdf.sort(a, 0, R, keys_out=b, stream=stream, config=cfg)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            rtcdf.sort(a, 0, R, keys_out=b, stream=stream, config=cfg)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[dist] = e0.elapsed_time(e1) / steps
+        log(f"[bench] n=1e9 R=2^18 {dist}: {res[dist]:.3f} ms per sort")
+        del a
+    print(json.dumps({"ms_per_sort": res}))
+
+
+def profile_picker(torch, rtcdf, inputs, steps, warmup):
+    """Profiling mode: the learned picker's kernels.  Per step, for each of
+    four arrays (n = 10^8; R = 2^10, 2^16, 2^18; uniform and normal sd R/6)
+    with the shipped model in LEARNED mode: the decision cache is cleared and
+    rtcdf_pick_config decides (sketch + network pick, k_pick_spread); then
+    one call of rtcdf_mlp_train (forward, gradient and Adam kernels) runs
+    `steps` training steps on a 2000 x 34 batch of synthetic features."""
+    model = os.path.join(ROOT, "paper_2609_00843_amd", "data", "model.bin")
+    dev = torch.device("cuda:0")
+    n = 10 ** 8
+    arrays = [(inputs.make_device(d, n, 0, 1 << lr, inputs.case_seed(8, lr), device=dev), 1 << lr)
+              for lr, d in ((10, "uniform"), (16, "normal"), (18, "uniform"), (18, "normal"))]
+    rtcdf.load_model(model)
+    old = rtcdf.get_config_mode()
+    rtcdf.set_config_mode(rtcdf.CONFIG_LEARNED)
+    try:
+        for k in range(warmup + steps):
+            for a, R in arrays:
+                rtcdf.clear_pick_cache()
+                rtcdf.pick_config(n, 0, R, keys_in=a)
+        torch.cuda.synchronize()
+    finally:
+        rtcdf.set_config_mode(old)
+        rtcdf.clear_pick_cache()
+    g = torch.Generator(device=dev)
+    g.manual_seed(2609)
+    B = 2000
+    X = torch.randn((B, rtcdf.MLP_INPUTS), generator=g, device=dev)
+    T = torch.randn((B, rtcdf.MLP_OUTPUTS), generator=g, device=dev) * 0.1
+    M = torch.ones((B, rtcdf.MLP_OUTPUTS), device=dev)
+    P = torch.randn(rtcdf.MLP_PARAMS, generator=g, device=dev) * 0.05
+    m, v = torch.zeros_like(P), torch.zeros_like(P)
+    rtcdf.mlp_train(P, m, v, 0, X, T, M, steps, 1e-3, ws=rtcdf.mlp_workspace(B, dev))
+    torch.cuda.synchronize()
+    print(json.dumps({"picks": (warmup + steps) * len(arrays), "train_steps": steps}))
 
 
 def profile_key_widths(torch, rtcdf, steps, warmup):
@@ -545,6 +633,14 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="with --profile-only: replay the 4096-array batched workload's graph instead of "
                          "the range sweep")
+    ap.add_argument("--large-n", action="store_true",
+                    help="with --profile-only: sort the n = 10^9, R = 2^18 arrays (uniform, all equal, "
+                         "normal sd R/64) instead of the range sweep")
+    ap.add_argument("--picker", action="store_true",
+                    help="with --profile-only: run the learned picker's decision and training kernels")
+    ap.add_argument("--flags", type=lambda x: int(x, 0), default=0,
+                    help="with --profile-only: sort with the static knobs and these option flags "
+                         "(e.g. 0x40: 4-bit counters) instead of the library's choice")
     ap.add_argument("--output-method", choices=("search", "prefix_max"), default="search",
                     help="with --profile-only: sort with the prefix-maximum output (Alg. 3) instead "
                          "of the local-CDF search (Alg. 7)")
@@ -555,6 +651,8 @@ def main():
         ap.error("--wide-ranges is a profiling mode; it needs --profile-only")
     if args.key_widths and not args.profile_only:
         ap.error("--key-widths is a profiling mode; it needs --profile-only")
+    if (args.large_n or args.picker or args.flags) and not args.profile_only:
+        ap.error("--large-n, --picker and --flags are profiling modes; they need --profile-only")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
               f"drives one GPU (the sort would shard by one 4R-byte histogram all-reduce)", file=sys.stderr)
@@ -566,6 +664,12 @@ def main():
 
     if args.key_widths:
         profile_key_widths(torch, rtcdf, args.steps, args.warmup)
+        return
+    if args.large_n:
+        profile_large_n(torch, rtcdf, inputs, args.steps, args.warmup, args.flags)
+        return
+    if args.picker:
+        profile_picker(torch, rtcdf, inputs, args.steps, args.warmup)
         return
     if args.batched:
         if not args.profile_only:
@@ -590,6 +694,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     cfgs = [None] * len(cases)
+    if args.flags:
+        cfgs = [rtcdf.make_config(0, 0, 0, flags=args.flags)] * len(cases)
     if args.output_method == "prefix_max":
         for i, (lr, _) in enumerate(cases):
             c = rtcdf.pick_config(N, MIN_VAL, MIN_VAL + (1 << lr))
