@@ -109,13 +109,11 @@ __global__ __launch_bounds__(1024) void k_batch_order(BatchArgs a) {
   const uint32_t tid = threadIdx.x;
   if (tid < kBBuckets) hist[tid] = 0;
   __syncthreads();
-  // every thread takes a contiguous run of segments, so slots and chunk
-  // items follow segment order
-  const uint32_t per = (a.nseg + 1023u) / 1024u;
-  const uint32_t i0 = min(tid * per, a.nseg), i1 = min(i0 + per, a.nseg);
+  // thread t takes segments t, t + 1024, ... (coalesced descriptor reads);
+  // slots and chunk items are numbered in (thread, segment) order
   uint32_t slots = 0;
   uint64_t chunks = 0;
-  for (uint32_t i = i0; i < i1; ++i) {
+  for (uint32_t i = tid; i < a.nseg; i += 1024u) {
     const rtcdf_segment_t d = a.segs[i];
     const uint32_t t = seg_tiles(d), c = seg_chunks(d, a.K);
     if (t != 0 && c != 0) {
@@ -130,7 +128,7 @@ __global__ __launch_bounds__(1024) void k_batch_order(BatchArgs a) {
   // beyond the workspace's capacity (bounds that understate the batch) no
   // segment is chunked
   const bool chunked = tot_slots <= a.max_slots && tot_chunks <= a.max_chunks;
-  for (uint32_t i = i0; i < i1; ++i) {
+  for (uint32_t i = tid; i < a.nseg; i += 1024u) {
     const rtcdf_segment_t d = a.segs[i];
     const uint32_t t = seg_tiles(d);
     if (t != 0 && !(chunked && seg_chunks(d, a.K) != 0)) atomicAdd(&hist[seg_bucket(d)], t);
@@ -151,7 +149,7 @@ __global__ __launch_bounds__(1024) void k_batch_order(BatchArgs a) {
   __syncthreads();
   uint2* order = (uint2*)a.order;
   uint32_t slot = slot0, chunk = chunk0;
-  for (uint32_t i = i0; i < i1; ++i) {
+  for (uint32_t i = tid; i < a.nseg; i += 1024u) {
     const rtcdf_segment_t d = a.segs[i];
     const uint32_t t = seg_tiles(d);
     if (t == 0) continue;

@@ -256,19 +256,19 @@ __device__ __forceinline__ void pmax_initial_fill(int32_t* out, uint32_t n, uint
 }
 
 // One workgroup per 128-bin block of one pass: the block is 128 / (32 / bits)
-// words of every partial row of the pass.  Threads are 32 row groups x NQ word
-// quads (NQ = 32, 16, 8, 4 for 32-, 16-, 8-, 4-bit counters: 1024, 512, 256,
-// 128 threads);
+// words of every partial row of the pass.  Threads are RG row groups x NQ word
+// quads (NQ = 32, 16, 8, 4 for 32-, 16-, 8-, 4-bit counters; RG = 32, or 64
+// for 4-bit counters: 1024, 512, 256, 256 threads);
 // each thread adds the 16-byte quad of every 32nd row, four loads in flight,
 // and splits the words into their counters.  The row groups are summed in LDS;
 // every bin adds (and re-zeroes) its carry entry (narrow counters), and the
 // workgroup writes H and the block total.
-constexpr uint32_t kReduceGroups = 32;
+__host__ __device__ constexpr uint32_t reduce_groups(uint32_t bits) { return bits == 4 ? 64u : 32u; }
 
 template <int BITS>
 __device__ __forceinline__ void reduce_block(const ReduceArgs& a, uint32_t (*red)[kReduceBins + 1],
                                              uint32_t* wsum) {
-  constexpr uint32_t per = 32 / BITS, NQ = kReduceBins / per / 4;
+  constexpr uint32_t per = 32 / BITS, NQ = kReduceBins / per / 4, RG = reduce_groups(BITS);
   const uint32_t tid = threadIdx.x, q = tid % NQ, rg = tid / NQ;
   const uint32_t r0 = blockIdx.x * kReduceBins;   // first bin (passes hold W bins, W % 128 == 0)
   const uint32_t pass = r0 / a.W, w0 = (r0 - pass * a.W) / per;
@@ -298,7 +298,7 @@ __device__ __forceinline__ void reduce_block(const ReduceArgs& a, uint32_t (*red
     }
   };
   uint32_t g = rg;
-  const uint32_t G = a.G, NG = kReduceGroups;
+  const uint32_t G = a.G, NG = RG;
   for (; g + 3 * NG < G; g += 4 * NG) {
     const v4u x0 = src[(size_t)g * rs4], x1 = src[(size_t)(g + NG) * rs4];
     const v4u x2 = src[(size_t)(g + 2 * NG) * rs4], x3 = src[(size_t)(g + 3 * NG) * rs4];
@@ -314,7 +314,7 @@ __device__ __forceinline__ void reduce_block(const ReduceArgs& a, uint32_t (*red
   __syncthreads();
   uint32_t tot = 0;
   if (tid < kReduceBins) {
-    for (uint32_t r = 0; r < kReduceGroups; ++r) tot += red[r][tid];
+    for (uint32_t r = 0; r < RG; ++r) tot += red[r][tid];
     const uint32_t bin = r0 + tid;
     if (BITS < 32 && bin < a.carry_words) {
       tot += a.carry[bin];
@@ -328,7 +328,10 @@ __device__ __forceinline__ void reduce_block(const ReduceArgs& a, uint32_t (*red
 }
 
 __global__ __launch_bounds__(kReduceBlock) void k_reduce(ReduceArgs a) {
-  __shared__ uint32_t red[kReduceGroups][kReduceBins + 1];
+  // the row-group sums: reduce_groups(bits) rows of kReduceBins + 1 words
+  // (dynamic, so that the narrow widths keep the occupancy of a 16 KiB block)
+  extern __shared__ uint32_t red_lds[];
+  auto red = reinterpret_cast<uint32_t (*)[kReduceBins + 1]>(red_lds);
   __shared__ uint32_t wsum[kReduceBlock / 64];
   if (blockIdx.x >= a.nred) {   // prefix-maximum output: the initial B
     pmax_initial_fill(a.pm_out, a.pm_n, a.pm_head, a.pm_fill, a.pm_M, a.pm_nck, blockIdx.x - a.nred,
@@ -1131,9 +1134,10 @@ hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, int32_t* p
   // 128-bin blocks never straddle passes (W % 128 == 0), and a block's words
   // are whole 16-byte quads of 16-byte aligned rows
   if (p.W % kReduceBins != 0 || p.row_words % 4 != 0) return hipErrorInvalidValue;
-  const uint32_t threads = kReduceGroups * (kReduceBins / (32 / p.bits) / 4);
+  const uint32_t threads = reduce_groups(p.bits) * (kReduceBins / (32 / p.bits) / 4);
   const uint32_t grid = p.nred + (pm_out != nullptr ? p.pm_init_grid : 0u);
-  hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(threads), 0, s, a);
+  const size_t lds = (size_t)reduce_groups(p.bits) * (kReduceBins + 1) * 4;
+  hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
