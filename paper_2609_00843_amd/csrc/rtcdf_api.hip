@@ -168,9 +168,11 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // passes over the input.
   const uint32_t lds = kLdsBytes / p->bpt;
   const uint32_t k32 = std::max<uint32_t>(1, lds / (4 * p->T));
-  const uint32_t k16 = std::max<uint32_t>(1, (lds - 512) / (2 * p->T));   // 512 B wrap table
-  const uint32_t k8 = std::max<uint32_t>(1, (lds - 512) / p->T);
-  const uint32_t k4 = std::max<uint32_t>(1, 2 * (lds - 512) / p->T);
+  // narrow counters leave room for a wrap table of at least 64 slots and its
+  // mask word (516 B)
+  const uint32_t k16 = std::max<uint32_t>(1, (lds - 516) / (2 * p->T));
+  const uint32_t k8 = std::max<uint32_t>(1, (lds - 516) / p->T);
+  const uint32_t k4 = std::max<uint32_t>(1, 2 * (lds - 516) / p->T);
   const uint32_t passes32 = (p->m + k32 - 1) / k32;
   const uint32_t passes8 = (p->m + k8 - 1) / k8;
   // 32-bit counters where they need no more passes (no wraps, no returning
@@ -188,8 +190,18 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
     p->bits = (uint32_t)force_bits;
   const uint32_t k = p->bits == 4 ? k4 : (p->bits == 8 ? k8 : (p->bits == 16 ? k16 : k32));
   p->passes = (p->m + k - 1) / k;
-  p->W = p->passes == 1 ? std::min<uint32_t>(Rr, k * p->T) : k * p->T;
+  // Passes of equal width (whole tiles): no more passes than k tiles a pass
+  // needs, and the LDS the counters leave goes to the wrap table.
+  p->W = p->passes == 1 ? std::min<uint32_t>(Rr, k * p->T) : (p->m + p->passes - 1) / p->passes * p->T;
   p->row_words = p->W / (32 / p->bits);
+  // The wrap table takes the LDS the counters leave, up to kWrapSlotsMax slots:
+  // a pass with few bins (R = 2^16 in one pass of 8-bit counters) gives every
+  // warm bin of skewed keys a slot of its own.
+  p->wrap_slots = kWrapSlots;
+  if (p->bits < 32) {
+    const uint32_t free_words = lds / 4 > p->row_words + 1 ? lds / 4 - p->row_words - 1 : 0;
+    while (p->wrap_slots < kWrapSlotsMax && 4 * p->wrap_slots <= free_words) p->wrap_slots *= 2;
+  }
   p->hist_block = 1024 / p->bpt;
   p->hist_interleave = (uint32_t)env_int("RTCDF_DEV_HIST_INTERLEAVE", 1);
 

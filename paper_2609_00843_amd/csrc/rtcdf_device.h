@@ -184,33 +184,36 @@ __device__ __forceinline__ void add_u16(uint32_t* S, uint32_t x, uint32_t c, uin
   fix_u16(old, x, c, carry, pass_lo);
 }
 
-// Wrap table of the 8-bit form: kWrapSlots (bin, amount) pairs in LDS that
-// collect the repairs of one workgroup, so that a heavily hit bin costs one
-// global atomic per workgroup at the end instead of one per wrap.  Slot
-// bin % kWrapSlots belongs to the first bin that claims it; a repair whose slot
-// is held by another bin goes straight to the global carry array.
-constexpr uint32_t kWrapSlots = 64;
+// Wrap table of the narrow forms: S (bin, amount) pairs in LDS that collect
+// the repairs of one workgroup, so that a heavily hit bin costs one global
+// atomic per workgroup at the end instead of one per wrap.  S is a power of
+// two from kWrapSlots up to kWrapSlotsMax, as many as the LDS left over by the
+// counters holds; tab[-1] holds S - 1.  Slot bin % S belongs to the first bin
+// that claims it; a repair whose slot is held by another bin goes straight to
+// the global carry array.
 constexpr uint32_t kWrapEmpty = 0xffffffffu;
 
 __device__ __forceinline__ void wrap_add(uint32_t* tab, uint32_t bin, uint32_t d, uint32_t* carry,
                                          uint32_t pass_lo) {
-  uint32_t* slot = tab + (bin & (kWrapSlots - 1));
+  const uint32_t mask = tab[-1];
+  uint32_t* slot = tab + (bin & mask);
   const uint32_t prev = atomicCAS(slot, kWrapEmpty, bin);
   // Workgroup scope for the LDS add, device scope for the global one: the
   // compiler then keeps them apart instead of merging them into one flat
   // atomic, whose counters would stop it from pipelining the input loads.
   if (prev == kWrapEmpty || prev == bin)
-    __hip_atomic_fetch_add(slot + kWrapSlots, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(slot + mask + 1u, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   else
     __hip_atomic_fetch_add(&carry[pass_lo + bin], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Moves the table's amounts to the global carry array (one thread per slot,
-// after the workgroup's last count).
+// Moves the table's amounts to the global carry array (the workgroup's
+// threads stride over the slots, after its last count).
 __device__ __forceinline__ void wrap_flush(const uint32_t* tab, uint32_t* carry, uint32_t pass_lo,
                                            uint32_t t) {
-  if (t < kWrapSlots) {
-    const uint32_t bin = tab[t], d = tab[t + kWrapSlots];
+  const uint32_t slots = tab[-1] + 1u;
+  for (; t < slots; t += blockDim.x) {
+    const uint32_t bin = tab[t], d = tab[t + slots];
     if (bin != kWrapEmpty && d != 0u) atomicAdd(&carry[pass_lo + bin], d);
   }
 }

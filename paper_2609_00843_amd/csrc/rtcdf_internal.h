@@ -16,6 +16,8 @@ constexpr uint32_t kFillWindow = 4096;      // cumulative counts held in LDS by 
 constexpr uint32_t kFillBlock = 256;        // threads per output workgroup
 constexpr uint32_t kScanBlock = 1024;       // threads per local-CDF workgroup
 constexpr uint32_t kReduceBlock = 1024;     // threads per reduction workgroup
+constexpr uint32_t kWrapSlots = 64;         // least slots of the narrow histogram's LDS wrap table
+constexpr uint32_t kWrapSlotsMax = 4096;    // most slots (the LDS left by the counters permitting)
 
 // Single-tile fast path (one tile, one pass of 32-bit counters, R <= 2048).
 // Its accumulation area holds two regions of kFastRegionWords and two parity
@@ -79,6 +81,7 @@ struct Plan {
   uint32_t passes;       // ceil(R / W)
   uint32_t G;            // workgroups (input chunks) per pass, multiple of 8
   uint32_t row_words;    // 32-bit words per partial row (W * bits / 32)
+  uint32_t wrap_slots;   // narrow counters: slots of the histogram's LDS wrap table
   uint32_t hist_block;   // threads per histogram workgroup
   uint32_t hist_interleave;  // 1: tiles dealt round-robin to chunks; 0: contiguous chunks
   uint32_t in_head;      // keys before the 16-byte aligned input body

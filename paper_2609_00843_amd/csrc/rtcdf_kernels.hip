@@ -46,6 +46,7 @@ struct HistArgs {
   uint32_t in_n4, in_per;   // n < 2^32 keys: vector indices fit 32 bits
   uint32_t in_head, in_tail;
   uint32_t min_u, W, passes, G, row_words, R;
+  uint32_t wrap_slots;   // narrow forms: slots of the LDS wrap table (a power of two)
   uint32_t interleave;
   uint32_t* partial;
   uint32_t* carry;
@@ -115,11 +116,13 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   const uint32_t wg = blockIdx.x, xcd = wg & 7u, slot = wg >> 3;
   const uint32_t pass = slot % a.passes;
   const uint32_t chunk = (slot / a.passes) * 8u + xcd;
-  // LDS: the counters, then (narrow forms) the wrap table's bins and amounts.
-  uint32_t* tab = S + a.row_words;
+  // LDS: the counters, then (narrow forms) the wrap table: its slot mask, its
+  // bins and its amounts.
+  uint32_t* tab = S + a.row_words + 1;
   for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) S[i] = 0u;
   if constexpr (BITS < 32) {
-    if (threadIdx.x < 2 * kWrapSlots) tab[threadIdx.x] = threadIdx.x < kWrapSlots ? kWrapEmpty : 0u;
+    if (threadIdx.x == 0) tab[-1] = a.wrap_slots - 1u;
+    for (uint32_t i = threadIdx.x; i < 2 * a.wrap_slots; i += BLOCK) tab[i] = i < a.wrap_slots ? kWrapEmpty : 0u;
   }
   __syncthreads();
 
@@ -1014,7 +1017,7 @@ __global__ void k_clear(uint32_t* p, size_t words) {
 template <int ITEMS, int BITS, int BLOCK, int KB = 4, bool DEDUPE = false>
 hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
   // the counters (and the narrow forms' wrap table) fit the static LDS array
-  const size_t lds = ((size_t)p.row_words + (BITS < 32 ? 2 * kWrapSlots : 0)) * 4;
+  const size_t lds = ((size_t)p.row_words + (BITS < 32 ? 1 + 2 * (size_t)p.wrap_slots : 0)) * 4;
   if (lds > kLdsBytes / (1024 / BLOCK)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_hist<ITEMS, BITS, BLOCK, KB, DEDUPE>), dim3(p.passes * p.G), dim3(BLOCK), 0, s, a);
   return hipGetLastError();
@@ -1089,6 +1092,7 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
   a.passes = p.passes;
   a.G = p.G;
   a.row_words = p.row_words;
+  a.wrap_slots = p.wrap_slots;
   a.R = p.R;
   a.partial = reinterpret_cast<uint32_t*>(ws + p.off_partial);
   a.carry = carry;

@@ -103,9 +103,9 @@ def test_learned_sorts_do_not_wait_for_the_pick(r):
                 torch.cuda.synchronize()
                 assert np.array_equal(b.cpu().numpy(), want)
             _say(f"learned sort sources {dist}: {sources}")
-            assert sources[0] in (r.PICK_PENDING,) + decided
-            assert sources[1] in decided + (r.PICK_CACHED,)
-            assert sources[2] == r.PICK_CACHED or sources[2] == r.PICK_NETWORK_KEPT_STATIC
+            assert sources[0] in (r.PICK_PENDING,) + decided, (dist, sources)
+            assert sources[1] in decided + (r.PICK_CACHED,), (dist, sources)
+            assert sources[2] == r.PICK_CACHED or sources[2] == r.PICK_NETWORK_KEPT_STATIC, (dist, sources)
     finally:
         r.set_config_mode(old)
         r.unload_model()
