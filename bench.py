@@ -780,8 +780,9 @@ def main():
     for (lr, d), a, b in zip(cases, ins, outs):
         R = 1 << lr
         info = rtcdf.plan_info(N, MIN_VAL, MIN_VAL + R, keys_in=a, keys_out=b)
-        # instantiation names: the last template argument is the key width (4 bytes)
-        hist_name = f"k_hist<{info['items_per_thread']}, {info['counter_bits']}, {info['hist_threads']}, 4>"
+        # instantiation names: the key width (4 bytes), then the wave-aggregation switch
+        hist_name = (f"k_hist<{info['items_per_thread']}, {info['counter_bits']}, {info['hist_threads']}, 4, "
+                     f"{'true' if info['hist_dedupe'] else 'false'}>")
         rtcdf.profile_collect()
         rtcdf.profile_enable(True)
         for _ in range(args.steps):
