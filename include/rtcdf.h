@@ -159,10 +159,15 @@ rtcdf_status_t rtcdf_sort_with_config(const int32_t* keys_in, int32_t* keys_out,
 
 /* Keys of other widths.  The sort of 16- and 8-bit keys, signed or not: the
  * histogram reads 16-byte vectors of 8 or 16 keys and widens them, the output
- * stage writes the keys in their own width.  key_type is one of
- * rtcdf_key_type_t; keys_in / keys_out are device arrays of n keys of that
- * type, aligned to its size (they may be equal; partial overlap is
- * RTCDF_ERROR_OVERLAP); [minVal, maxVal) must lie within the type's values.
+ * stage writes the keys in their own width.  int64 keys: any window
+ * [minVal, maxVal) of int64 values with R = maxVal - minVal <=
+ * RTCDF_MAX_RANGE (maxVal <= INT64_MAX, so INT64_MAX itself is not a
+ * sortable key); every key is normalised to key - minVal in 64-bit
+ * arithmetic, counts stay 32-bit (n < 2^32), and the output stage writes
+ * minVal + value as 8-byte keys.  key_type is one of rtcdf_key_type_t;
+ * keys_in / keys_out are device arrays of n keys of that type, aligned to its
+ * size (they may be equal; partial overlap is RTCDF_ERROR_OVERLAP);
+ * [minVal, maxVal) must lie within the type's values.
  * cfg as for rtcdf_sort_with_config (NULL = library choice, flags must be 0:
  * the prefix-maximum output is offered for int32 keys only).  RTCDF_KEY_INT32
  * is rtcdf_sort_with_config.  Asynchronous on `stream`; argument errors are
@@ -172,7 +177,8 @@ typedef enum rtcdf_key_type {
   RTCDF_KEY_INT16 = 1,
   RTCDF_KEY_UINT16 = 2,
   RTCDF_KEY_INT8 = 3,
-  RTCDF_KEY_UINT8 = 4
+  RTCDF_KEY_UINT8 = 4,
+  RTCDF_KEY_INT64 = 5
 } rtcdf_key_type_t;
 
 rtcdf_status_t rtcdf_sort_keys(const void* keys_in, void* keys_out, size_t n, int key_type,

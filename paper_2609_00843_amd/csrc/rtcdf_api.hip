@@ -153,10 +153,12 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   p->n = n;
   p->kb = kb;
   p->flip = flip;
-  p->min_u = (uint32_t)(uint64_t)(minVal + (int64_t)flip);
+  p->min_u = kb == 8 ? 0u : (uint32_t)(uint64_t)(minVal + (int64_t)flip);
+  p->min64 = minVal;
   p->R = R;
-  // 8- and 16-bit keys: one 16-byte vector of keys per thread per step
-  p->items = kb == 4 ? cfg.items_per_thread : 4u;
+  // 8- and 16-bit keys: one 16-byte vector of keys per thread per step;
+  // int64 keys: two (four keys)
+  p->items = kb == 4 ? cfg.items_per_thread : (kb == 8 ? 8u : 4u);
   p->bpt = cfg.blocks_per_tile;
   // Tile geometry (Sec. 3): tiles never need to be wider than the range.
   const uint32_t Rr = (R + 127) & ~127u;
@@ -283,7 +285,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // 8192-position chunks (16 or 8 KiB) keep every wave busy and repay the
   // per-chunk work over as many bytes (measured 21-26 % faster at n = 10^8);
   // from 4 keys per value on, so that a chunk's values fit the LDS window.
-  if (kb != 4 && n >= 4ull * R) want = 8192;
+  if (kb < 4 && n >= 4ull * R) want = 8192;
   if (kb == 4 && (cfg.flags & RTCDF_FLAG_CHUNK_4096)) want = 4096;
   const int64_t force_chunk = env_int("RTCDF_DEV_FILL_CHUNK", 0);
   if (force_chunk > 0) want = (uint64_t)force_chunk;
@@ -671,9 +673,11 @@ rtcdf_status_t rtcdf_sort_keys(const void* keys_in, void* keys_out, size_t n, in
     case RTCDF_KEY_UINT16: kb = 2; flip = 0u; lo = 0; hi = 65536; break;
     case RTCDF_KEY_INT8: kb = 1; flip = 0x80u; lo = -128; hi = 128; break;
     case RTCDF_KEY_UINT8: kb = 1; flip = 0u; lo = 0; hi = 256; break;
+    case RTCDF_KEY_INT64: kb = 8; flip = 0u; lo = INT64_MIN; hi = INT64_MAX; break;
     default: return RTCDF_ERROR_INVALID_VALUE;
   }
   if (maxVal <= minVal || minVal < lo || maxVal > hi) return RTCDF_ERROR_INVALID_VALUE;
+  if ((uint64_t)maxVal - (uint64_t)minVal > RTCDF_MAX_RANGE) return RTCDF_ERROR_RANGE_TOO_LARGE;
   if ((uint64_t)n > 0xffffffffull) return RTCDF_ERROR_SIZE_TOO_LARGE;
   if (n == 0) return RTCDF_SUCCESS;
   if (keys_in == nullptr || keys_out == nullptr) return RTCDF_ERROR_INVALID_VALUE;

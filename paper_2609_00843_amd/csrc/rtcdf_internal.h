@@ -65,10 +65,12 @@ constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpH
 struct Plan {
   // problem
   uint64_t n;
-  uint32_t kb;           // key bytes: 4 (int32), 2 or 1 (16- and 8-bit keys)
+  uint32_t kb;           // key bytes: 4 (int32), 2 or 1 (16- and 8-bit keys), 8 (int64)
   uint32_t flip;         // narrow keys: bits XORed with each key (its sign bit if signed)
   uint32_t min_u;        // (uint32)minVal; normalised value x = (uint32)key - min_u
-                         // (narrow keys: in the flipped, zero-extended domain)
+                         // (narrow keys: in the flipped, zero-extended domain; int64
+                         // keys: 0, the kernels normalising with min64)
+  int64_t min64;         // minVal (int64 keys: x = key - min64, exact in 64 bits)
   uint32_t R;            // range size
   // tile geometry (Sec. 3): m = ceil(R/T), tile t = [tT, tT + w_t)
   uint32_t T, m;

@@ -46,6 +46,7 @@ struct HistArgs {
   uint32_t in_n4, in_per;   // n < 2^32 keys: vector indices fit 32 bits
   uint32_t in_head, in_tail;
   uint32_t min_u, W, passes, G, row_words, R;
+  int64_t min64;         // int64 keys: normalised value x = key - min64 (min_u is 0)
   uint32_t wrap_slots;   // narrow forms: slots of the LDS wrap table (a power of two)
   uint32_t interleave;
   uint32_t* partial;
@@ -63,14 +64,27 @@ struct HistArgs {
   uint32_t flip;
 };
 
-// One 16-byte vector of keys: 4 int32 keys, or 8 / 16 narrow keys widened in
-// groups of four.  Lanes without a valid vector count `outside` (every group,
-// so that the wave-wide ballots inside count4 see every lane).
+// The normalised value of an int64 key: key - min64, exact in 64 bits, or
+// 0xffffffff (counted nowhere) if that is not below R.
+__device__ __forceinline__ uint32_t norm64(uint32_t lo, uint32_t hi, int64_t min64, uint32_t R) {
+  const uint64_t x = (((uint64_t)hi << 32) | lo) - (uint64_t)min64;
+  return x < R ? (uint32_t)x : 0xffffffffu;
+}
+
+// One 16-byte vector of keys: 4 int32 keys, 8 / 16 narrow keys widened in
+// groups of four, or 2 int64 keys normalised (with min_u 0, so base is the
+// pass's first bin) and padded with two keys outside every pass.  Lanes
+// without a valid vector count `outside` (every group, so that the wave-wide
+// ballots inside count4 see every lane).
 template <int BITS, int KB, bool DEDUPE = false>
 __device__ __forceinline__ void count_vec(uint32_t* S, v4i v, bool valid, v4i outside, uint32_t flip,
                                           uint32_t base, uint32_t W, uint32_t* carry, uint32_t pass_lo,
-                                          uint32_t* tab, HotBin& hot) {
-  if constexpr (KB == 4) {
+                                          uint32_t* tab, HotBin& hot, int64_t min64 = 0, uint32_t R = 0) {
+  if constexpr (KB == 8) {
+    const v4i g = {(int)norm64((uint32_t)v.x, (uint32_t)v.y, min64, R),
+                   (int)norm64((uint32_t)v.z, (uint32_t)v.w, min64, R), outside.x, outside.x};
+    count4<BITS>(S, valid ? g : outside, base, W, carry, pass_lo, tab, hot);
+  } else if constexpr (KB == 4) {
     count4<BITS, false, DEDUPE>(S, valid ? v : outside, base, W, carry, pass_lo, tab, hot);
   } else if constexpr (KB == 2) {
     const uint32_t f = flip | (flip << 16);
@@ -93,10 +107,15 @@ __device__ __forceinline__ void count_vec(uint32_t* S, v4i v, bool valid, v4i ou
   }
 }
 
-// Key i of a scalar head or tail, widened as in count_vec.
+// Key i of a scalar head or tail, widened (or, for int64 keys, normalised) as
+// in count_vec.
 template <int KB>
-__device__ __forceinline__ int32_t load_key(const int32_t* keys, size_t i, uint32_t flip) {
-  if constexpr (KB == 4) return keys[i];
+__device__ __forceinline__ int32_t load_key(const int32_t* keys, size_t i, uint32_t flip, int64_t min64 = 0,
+                                            uint32_t R = 0) {
+  if constexpr (KB == 8) {
+    const uint64_t k = reinterpret_cast<const uint64_t*>(keys)[i];
+    return (int32_t)norm64((uint32_t)k, (uint32_t)(k >> 32), min64, R);
+  } else if constexpr (KB == 4) return keys[i];
   else if constexpr (KB == 2) return (int32_t)(reinterpret_cast<const uint16_t*>(keys)[i] ^ flip);
   else return (int32_t)(reinterpret_cast<const uint8_t*>(keys)[i] ^ flip);
 }
@@ -180,12 +199,13 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
       if (tb + V * BLOCK <= end) {
 #pragma unroll
         for (int j = 0; j < V; ++j)
-          count_vec<BITS, KB, DEDUPE>(S, cur[j], true, outside, a.flip, base, W, a.carry, pass_lo, tab, hot);
+          count_vec<BITS, KB, DEDUPE>(S, cur[j], true, outside, a.flip, base, W, a.carry, pass_lo, tab, hot,
+                                      a.min64, a.R);
       } else {
 #pragma unroll
         for (int j = 0; j < V; ++j)
           count_vec<BITS, KB, DEDUPE>(S, cur[j], t0 + j * BLOCK < end, outside, a.flip, base, W, a.carry,
-                                      pass_lo, tab, hot);
+                                      pass_lo, tab, hot, a.min64, a.R);
       }
 #pragma unroll
       for (int j = 0; j < V; ++j) cur[j] = nxt[j];
@@ -195,9 +215,9 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   }
   // scalar head and tail keys (at most VK - 1 each), counted by chunk 0 / chunk G-1
   v4i e = outside;
-  if (chunk == 0 && threadIdx.x < in_head) e.x = load_key<KB>(keys, threadIdx.x, a.flip);
+  if (chunk == 0 && threadIdx.x < in_head) e.x = load_key<KB>(keys, threadIdx.x, a.flip, a.min64, a.R);
   if (chunk == a.G - 1 && threadIdx.x < in_tail)
-    e.y = load_key<KB>(keys, in_head + VK * (size_t)in_n4 + threadIdx.x, a.flip);
+    e.y = load_key<KB>(keys, in_head + VK * (size_t)in_n4 + threadIdx.x, a.flip, a.min64, a.R);
   if (threadIdx.x < 64) count4<BITS>(S, e, base, W, a.carry, pass_lo, tab, hot);
   if constexpr (BITS < 32 || DEDUPE) hot_flush_any<BITS, false>(hot, S, tab, a.carry, pass_lo);
   __syncthreads();
@@ -571,17 +591,27 @@ struct FillArgs {
   const uint32_t* split;
   uint64_t n;
   uint32_t min_u, R, T, out_head, chunk, nchunks;
+  int64_t min64;               // int64 keys: stored key = min64 + value (min_u is 0)
   uint64_t body_lo, body_hi;   // positions [body_lo, body_hi) are 16-byte aligned int4s
   const uint32_t* flags;       // [0]: some chunk is sparse (local-CDF stage)
   uint32_t flip;               // narrow keys: stored bits = value ^ flip
   uint32_t sparse_k;           // a chunk takes the sparse form below this many positions per value
 };
 
-// Four consecutive outputs (group i of the aligned body, 16 / 8 / 4 bytes)
-// and single outputs, in the key width KB.
+// Four consecutive outputs (group i of the aligned body, 32 / 16 / 8 / 4
+// bytes) and single outputs, in the key width KB.  An int64 output is min64
+// plus the value, exact in 64 bits.
 template <int KB>
 __device__ __forceinline__ void store_group(const FillArgs& a, uint64_t i, v4i o) {
-  if constexpr (KB == 4) {
+  if constexpr (KB == 8) {
+    const uint64_t m = (uint64_t)a.min64;
+    const uint64_t k0 = m + (uint32_t)o.x, k1 = m + (uint32_t)o.y, k2 = m + (uint32_t)o.z, k3 = m + (uint32_t)o.w;
+    const v4i lo = {(int)(uint32_t)k0, (int)(uint32_t)(k0 >> 32), (int)(uint32_t)k1, (int)(uint32_t)(k1 >> 32)};
+    const v4i hi = {(int)(uint32_t)k2, (int)(uint32_t)(k2 >> 32), (int)(uint32_t)k3, (int)(uint32_t)(k3 >> 32)};
+    v4i* body = reinterpret_cast<v4i*>(static_cast<int64_t*>(a.out) + a.body_lo);
+    __builtin_nontemporal_store(lo, &body[2 * i]);
+    __builtin_nontemporal_store(hi, &body[2 * i + 1]);
+  } else if constexpr (KB == 4) {
     v4i* body = reinterpret_cast<v4i*>(static_cast<int32_t*>(a.out) + a.body_lo);
     __builtin_nontemporal_store(o, &body[i]);
   } else if constexpr (KB == 2) {
@@ -623,7 +653,8 @@ __device__ __forceinline__ void store_vec16(const FillArgs& a, uint64_t i, const
 
 template <int KB>
 __device__ __forceinline__ void store_one(const FillArgs& a, uint64_t p, int32_t v) {
-  if constexpr (KB == 4) static_cast<int32_t*>(a.out)[p] = v;
+  if constexpr (KB == 8) static_cast<int64_t*>(a.out)[p] = (int64_t)((uint64_t)a.min64 + (uint32_t)v);
+  else if constexpr (KB == 4) static_cast<int32_t*>(a.out)[p] = v;
   else if constexpr (KB == 2) static_cast<uint16_t*>(a.out)[p] = (uint16_t)((uint32_t)v ^ a.flip);
   else static_cast<uint8_t*>(a.out)[p] = (uint8_t)((uint32_t)v ^ a.flip);
 }
@@ -707,7 +738,7 @@ template <bool SPARSE, int KB>
 __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* win, uint32_t nwin,
                                            uint32_t v0, uint64_t p0, uint64_t p1, bool first,
                                            bool final, uint32_t* stage) {
-  if constexpr (!SPARSE && KB != 4) {
+  if constexpr (!SPARSE && KB < 4) {
     fill_chunk_wide<KB>(a, win, nwin, v0, p0, p1, first, final);
     return;
   }
@@ -1027,11 +1058,13 @@ template <int BITS, int BLOCK>
 hipError_t launch_hist_items(const Plan& p, const HistArgs& a, hipStream_t s) {
   // 8- and 16-bit keys: one 16-byte vector (16 or 8 keys) per thread per step
   // (4-bit counters serve int32 keys only)
+  // (int64 keys: two 16-byte vectors, four keys, per thread per step)
   if constexpr (BITS == 4) {
     if (p.kb != 4) return hipErrorInvalidValue;
   } else {
     if (p.kb == 2) return launch_hist_t<4, BITS, BLOCK, 2>(p, a, s);
     if (p.kb == 1) return launch_hist_t<4, BITS, BLOCK, 1>(p, a, s);
+    if (p.kb == 8) return launch_hist_t<8, BITS, BLOCK, 8>(p, a, s);
   }
   if (p.dedupe) {
     switch (p.items) {
@@ -1084,8 +1117,9 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
   a.in_n4 = (uint32_t)p.in_n4;     // n < 2^32: at most 2^30 vectors
   a.in_per = (uint32_t)p.in_per;
   a.in_head = p.in_head;
-  if (p.kb != 4 && p.kb != 2 && p.kb != 1) return hipErrorInvalidValue;
+  if (p.kb != 4 && p.kb != 2 && p.kb != 1 && p.kb != 8) return hipErrorInvalidValue;
   a.in_tail = (uint32_t)(p.n - p.in_head - (16 / p.kb) * p.in_n4);
+  a.min64 = p.min64;
   a.flip = p.flip;
   a.min_u = p.min_u;
   a.W = p.W;
@@ -1206,8 +1240,11 @@ hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream
   a.nchunks = p.nchunks;
   a.sparse_k = p.fill_sparse_keys;
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
-  // whole groups of 4 int32 keys, or of 16 / kb narrow keys (one 16-byte vector)
-  a.body_hi = a.body_lo + (16 / p.kb) * ((p.n - a.body_lo) / (16 / p.kb));
+  // whole groups of 4 int32 or int64 keys, or of 16 / kb narrow keys (one
+  // 16-byte vector)
+  const uint32_t group = p.kb >= 4 ? 4u : 16u / p.kb;
+  a.body_hi = a.body_lo + group * ((p.n - a.body_lo) / group);
+  a.min64 = p.min64;
   a.flags = reinterpret_cast<const uint32_t*>(ws + p.off_flags);
   a.flip = p.flip;
   // The sparse form (look-ahead and bisection in the window) when the values
@@ -1227,6 +1264,10 @@ hipError_t launch_fill(const Plan& p, int32_t* out, const uint8_t* ws, hipStream
     case 1:
       if (sparse) hipLaunchKernelGGL((k_fill<true, 1>), grid, block, 0, s, a);
       else hipLaunchKernelGGL((k_fill<false, 1>), grid, block, 0, s, a);
+      break;
+    case 8:
+      if (sparse) hipLaunchKernelGGL((k_fill<true, 8>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_fill<false, 8>), grid, block, 0, s, a);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1249,8 +1290,11 @@ hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStre
   a.nchunks = p.nchunks;
   a.sparse_k = p.fill_sparse_keys;
   a.body_lo = p.out_head < p.n ? p.out_head : p.n;
-  // whole groups of 4 int32 keys, or of 16 / kb narrow keys (one 16-byte vector)
-  a.body_hi = a.body_lo + (16 / p.kb) * ((p.n - a.body_lo) / (16 / p.kb));
+  // whole groups of 4 int32 or int64 keys, or of 16 / kb narrow keys (one
+  // 16-byte vector)
+  const uint32_t group = p.kb >= 4 ? 4u : 16u / p.kb;
+  a.body_hi = a.body_lo + group * ((p.n - a.body_lo) / group);
+  a.min64 = p.min64;
   a.flip = p.flip;
   const bool sparse = p.n < (uint64_t)p.fill_sparse_keys * p.R;
   const dim3 grid(p.fill_grid), block(kFillBlock);
@@ -1267,6 +1311,10 @@ hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStre
     case 1:
       if (sparse) hipLaunchKernelGGL((k_fill_small<true, 1>), grid, block, 0, s, a, area, rows, stride);
       else hipLaunchKernelGGL((k_fill_small<false, 1>), grid, block, 0, s, a, area, rows, stride);
+      break;
+    case 8:
+      if (sparse) hipLaunchKernelGGL((k_fill_small<true, 8>), grid, block, 0, s, a, area, rows, stride);
+      else hipLaunchKernelGGL((k_fill_small<false, 8>), grid, block, 0, s, a, area, rows, stride);
       break;
     default:
       return hipErrorInvalidValue;

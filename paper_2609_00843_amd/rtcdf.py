@@ -171,10 +171,11 @@ def _check_keys(t, what):
 def sort(keys_in, minVal: int, maxVal: int, keys_out=None, config: Config | None = None,
          stream=None):
     """Sort keys_in (int32 in [minVal, maxVal)) into keys_out (allocated if None).
-    Asynchronous on `stream` (default: torch's current stream).  int16, uint16,
-    int8 and uint8 tensors go to sort_keys."""
+    Asynchronous on `stream` (default: torch's current stream).  int64, int16,
+    uint16, int8 and uint8 tensors go to sort_keys."""
     import torch
-    if getattr(keys_in, "dtype", None) in (torch.int16, torch.int8, torch.uint8, getattr(torch, "uint16", None)):
+    if getattr(keys_in, "dtype", None) in (torch.int64, torch.int16, torch.int8, torch.uint8,
+                                           getattr(torch, "uint16", None)):
         return sort_keys(keys_in, minVal, maxVal, keys_out=keys_out, config=config, stream=stream)
     _check_keys(keys_in, "keys_in")
     if keys_out is None:
@@ -194,23 +195,24 @@ def sort(keys_in, minVal: int, maxVal: int, keys_out=None, config: Config | None
 
 
 # rtcdf_key_type_t
-KEY_INT32, KEY_INT16, KEY_UINT16, KEY_INT8, KEY_UINT8 = 0, 1, 2, 3, 4
+KEY_INT32, KEY_INT16, KEY_UINT16, KEY_INT8, KEY_UINT8, KEY_INT64 = 0, 1, 2, 3, 4, 5
 
 
 def _key_type(t):
     import torch
-    types = {torch.int32: KEY_INT32, torch.int16: KEY_INT16, torch.int8: KEY_INT8, torch.uint8: KEY_UINT8}
+    types = {torch.int32: KEY_INT32, torch.int16: KEY_INT16, torch.int8: KEY_INT8, torch.uint8: KEY_UINT8,
+             torch.int64: KEY_INT64}
     if hasattr(torch, "uint16"):
         types[torch.uint16] = KEY_UINT16
     if t.dtype not in types or not t.is_cuda or not t.is_contiguous():
-        raise TypeError("keys must be a contiguous CUDA tensor of int32, int16, uint16, int8 or uint8")
+        raise TypeError("keys must be a contiguous CUDA tensor of int32, int64, int16, uint16, int8 or uint8")
     return types[t.dtype]
 
 
 def sort_keys(keys_in, minVal: int, maxVal: int, keys_out=None, config: Config | None = None,
               stream=None):
-    """Sort int32, int16, uint16, int8 or uint8 keys in [minVal, maxVal) into
-    keys_out (same dtype; allocated if None).  Asynchronous on `stream`."""
+    """Sort int32, int64, int16, uint16, int8 or uint8 keys in [minVal, maxVal)
+    into keys_out (same dtype; allocated if None).  Asynchronous on `stream`."""
     import torch
     kt = _key_type(keys_in)
     if keys_out is None:

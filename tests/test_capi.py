@@ -185,3 +185,12 @@ def test_sort_keys_argument_errors(r):
     bad = r.Config(100, 16, 1, 0)
     assert sk(r.KEY_UINT8, 0, 10, cfg=ctypes.byref(bad)) == r.INVALID_VALUE
     assert sk(r.KEY_INT32, 0, 10, n=1 << 32) == r.SIZE_TOO_LARGE             # the int32 entry's checks
+    # int64 keys: any window of at most RTCDF_MAX_RANGE values below INT64_MAX
+    i64min, i64max = -(1 << 63), (1 << 63) - 1
+    assert sk(r.KEY_INT64, i64min, i64min + (1 << 28) + 1) == r.RANGE_TOO_LARGE
+    assert sk(r.KEY_INT64, i64min, i64max) == r.RANGE_TOO_LARGE
+    assert sk(r.KEY_INT64, 5, 5) == r.INVALID_VALUE
+    assert sk(r.KEY_INT64, 0, 10, n=1 << 32) == r.SIZE_TOO_LARGE
+    assert sk(r.KEY_INT64, 0, 10, a=ctypes.c_void_p((1 << 20) + 4)) == r.INVALID_VALUE   # 8-byte alignment
+    assert sk(r.KEY_INT64, 0, 10, b=ctypes.c_void_p((1 << 20) + 72)) == r.OVERLAP        # 80 bytes from 2^20
+    assert sk(r.KEY_INT64, 0, 10, cfg=ctypes.byref(pm)) == r.INVALID_VALUE

@@ -129,3 +129,91 @@ def test_sort_dispatches_by_dtype(r):
     torch.cuda.synchronize()
     assert out.dtype == torch.int16
     assert np.array_equal(out.cpu().numpy(), oracle.sort(A.astype(np.int32), -300, 300).astype(np.int16))
+
+
+# ---- int64 keys (rtcdf_sort_keys, RTCDF_KEY_INT64) ----------------------------
+
+I64MIN, I64MAX = -(1 << 63), (1 << 63) - 1
+
+
+def _want64(A, lo, hi):
+    """The oracle's sort of the normalised values key - lo (Sec. 2.1: minVal is
+    notation; the counting sort is the same on [0, R)), shifted back; checked
+    against numpy's sort as a second, independent reference."""
+    R = hi - lo
+    x = (A.astype(object) - lo).astype(np.int64) if lo < -(1 << 62) else (A - np.int64(lo))
+    want = oracle.sort(x.astype(np.int32), 0, R).astype(np.int64)
+    want = (want.astype(object) + lo).astype(np.int64) if lo < -(1 << 62) else want + np.int64(lo)
+    assert np.array_equal(want, np.sort(A))
+    return want
+
+
+def _check64(r, A, lo, hi, pin=0, pout=0, inplace=False, cfg=None):
+    _say(f"int64 keys n={A.size} [{lo},{hi}) pin={pin} pout={pout} inplace={inplace} cfg={cfg}")
+    want = _want64(A, lo, hi)
+    buf = np.full(A.size + pin + 4, 7, dtype=np.int64)
+    buf[pin:pin + A.size] = A
+    tb = torch.from_numpy(buf).cuda()
+    tin = tb[pin:pin + A.size]
+    if inplace:
+        r.sort_keys(tin, lo, hi, keys_out=tin, config=cfg)
+        torch.cuda.synchronize()
+        assert np.array_equal(tin.cpu().numpy(), want)
+        return
+    bout = torch.full((A.size + pout + 4,), 0x5A5A5A5A5A5A5A5A, dtype=torch.int64, device="cuda")
+    tout = bout[pout:pout + A.size]
+    r.sort_keys(tin, lo, hi, keys_out=tout, config=cfg)
+    torch.cuda.synchronize()
+    got = tout.cpu().numpy()
+    assert np.array_equal(got, want), f"mismatch at {np.flatnonzero(got != want)[:8]}"
+    full = bout.cpu().numpy()
+    assert np.all(full[:pout] == 0x5A5A5A5A5A5A5A5A) and np.all(full[pout + A.size:] == 0x5A5A5A5A5A5A5A5A)
+    assert np.array_equal(tin.cpu().numpy(), A)
+
+
+@pytest.mark.parametrize("lo,R", [(0, 1), (-5, 7), (10 ** 12, 128), (-(10 ** 15), 2048), (3, 2049),
+                                  (I64MIN, 65536), (I64MAX - (1 << 18), 1 << 18), (-(1 << 40), 1 << 20)])
+def test_int64_ragged_and_misaligned(r, lo, R):
+    """Ragged n with both 8-byte alignments of input and output inside a
+    16-byte vector, windows anywhere in the int64 values (both extremes), the
+    single-tile fast path (R <= 2048) and the staged path."""
+    rng = np.random.default_rng(R)
+    for i, n in enumerate((1, 2, 3, 4, 5, 7, 9, 1023, 4099, 65537, 300001)):
+        x = rng.integers(0, R, size=n)
+        A = np.array([lo + int(v) for v in x], dtype=np.int64) if lo < -(1 << 62) else x.astype(np.int64) + np.int64(lo)
+        _check64(r, A, lo, lo + R, pin=i % 2, pout=(i // 2) % 2)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "normal", "all_equal", "zipf"])
+@pytest.mark.parametrize("R", [1 << 10, 1 << 16, 1 << 18])
+def test_int64_distributions(r, dist, R):
+    lo = 7 * 10 ** 14
+    A = inputs.make(dist, 2_000_003, 0, R, 23).astype(np.int64) + np.int64(lo)
+    _check64(r, A, lo, lo + R, pout=1)
+
+
+def test_int64_in_place_and_configs(r):
+    rng = np.random.default_rng(6)
+    lo = -(10 ** 13)
+    A = rng.integers(0, 1 << 17, size=700_001).astype(np.int64) + np.int64(lo)
+    _check64(r, A, lo, lo + (1 << 17), inplace=True)
+    for T, items, bpt in ((128, 4, 4), (1024, 8, 2), (8192, 16, 1), (32768, 4, 1)):
+        _check64(r, A, lo, lo + (1 << 17), cfg=r.make_config(T, items, bpt), pin=1, pout=0)
+
+
+def test_int64_full_size(r):
+    """5 x 10^7 int64 keys over 2^18 values, compared with the oracle's counts
+    by the streaming verifier."""
+    n, lo, R = 50_000_000, 123_456_789_012, 1 << 18
+    rng = np.random.default_rng(10)
+    x = rng.integers(0, R, size=n).astype(np.int32)
+    _say("int64 keys full size")
+    tin = torch.from_numpy(x.astype(np.int64) + np.int64(lo)).cuda()
+    out = r.sort(tin, lo, lo + R)
+    torch.cuda.synchronize()
+    assert out.dtype == torch.int64
+    cnt = oracle.counts(x, 0, R)
+    v = oracle.StreamingVerifier(cnt, 0)
+    for i in range(0, n, 1 << 24):
+        v.chunk((out[i:i + (1 << 24)] - lo).to(torch.int32).cpu().numpy())
+    v.end(n)
