@@ -339,19 +339,25 @@ def bench_wide_ranges(torch, rtcdf, inputs, steps):
 
 def bench_key_widths(torch, rtcdf, steps):
     """n = 10^8 keys of 16 and 8 bits (rtcdf_sort_keys): the type's whole
-    range and a 2^13-value range for 16-bit keys, uniform, warm, HIP events;
-    the roofline is 2 x key bytes per key at 8 TB/s.  Each output is checked
-    to be nondecreasing with the input's value counts (bincount on the GPU)."""
+    range and a 2^13-value range for 16-bit keys, uniform; and int64 keys over
+    2^16 and 2^18 values at minVal 10^12; warm, HIP events; the roofline is
+    2 x key bytes per key at 8 TB/s.  Each output is checked to be
+    nondecreasing with the input's value counts (bincount on the GPU)."""
     stream = torch.cuda.current_stream()
     n = 10 ** 8
     rows, ok = [], True
     g = torch.Generator(device="cuda")
     for name, dt, kb, lo, hi in (("int16", torch.int16, 2, -32768, 32768), ("int16", torch.int16, 2, -4096, 4096),
                                  ("uint16", torch.uint16, 2, 0, 65536), ("int8", torch.int8, 1, -128, 128),
-                                 ("uint8", torch.uint8, 1, 0, 256)):
-        g.manual_seed(hi - lo)
-        w = torch.randint(lo, hi, (n,), generator=g, device="cuda", dtype=torch.int32)
-        a = w.to(torch.int16).view(torch.uint16) if dt == torch.uint16 else w.to(dt)
+                                 ("uint8", torch.uint8, 1, 0, 256), ("int64", torch.int64, 8, 10 ** 12, 10 ** 12 + 65536),
+                                 ("int64", torch.int64, 8, 10 ** 12, 10 ** 12 + 262144)):
+        g.manual_seed((hi - lo) & 0xffffffff)
+        off = lo if dt == torch.int64 else 0
+        w = torch.randint(lo - off, hi - off, (n,), generator=g, device="cuda", dtype=torch.int32)
+        if dt == torch.int64:
+            a = w.to(torch.int64) + off
+        else:
+            a = w.to(torch.int16).view(torch.uint16) if dt == torch.uint16 else w.to(dt)
         b = torch.empty_like(a)
         for _ in range(3):
             rtcdf.sort_keys(a, lo, hi, keys_out=b, stream=stream)
@@ -363,14 +369,18 @@ def bench_key_widths(torch, rtcdf, steps):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        wide = (b.view(torch.int16).to(torch.int32) & 0xFFFF) if dt == torch.uint16 else b.to(torch.int32)
+        if dt == torch.int64:
+            wide = (b - off).to(torch.int32)
+        else:
+            wide = (b.view(torch.int16).to(torch.int32) & 0xFFFF) if dt == torch.uint16 else b.to(torch.int32)
         ok = ok and bool((wide[1:] >= wide[:-1]).all()) and bool(
-            torch.equal(torch.bincount(wide - lo, minlength=hi - lo), torch.bincount(w - lo, minlength=hi - lo)))
+            torch.equal(torch.bincount(wide - (lo - off), minlength=hi - lo),
+                        torch.bincount(w - (lo - off), minlength=hi - lo)))
         rows.append({"keys": name, "minVal": lo, "maxVal": hi, "ms": round(ms, 4),
                      "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 1),
                      "frac_roofline": round(2 * kb * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)})
         del w, a, b, wide
-    return {"workload": "n=1e8 uniform 16- and 8-bit keys", "rows": rows, "checked": ok,
+    return {"workload": "n=1e8 uniform 16-, 8- and 64-bit keys", "rows": rows, "checked": ok,
             "timing": "warm, HIP events, mean"}
 
 
@@ -439,8 +449,8 @@ def profile_picker(torch, rtcdf, inputs, steps, warmup):
 
 
 def profile_key_widths(torch, rtcdf, steps, warmup):
-    """Profiling mode: the whole-range 16- and 8-bit arrays of bench_key_widths,
-    each sorted once per step."""
+    """Profiling mode: the whole-range 16- and 8-bit arrays of bench_key_widths
+    and its int64 array over 2^18 values, each sorted once per step."""
     n = 10 ** 8
     g = torch.Generator(device="cuda")
     arrays = []
@@ -451,6 +461,11 @@ def profile_key_widths(torch, rtcdf, steps, warmup):
         a = w.to(torch.int16).view(torch.uint16) if dt == torch.uint16 else w.to(dt)
         arrays.append((a, torch.empty_like(a), lo, hi))
         del w
+    g.manual_seed(262144)
+    w = torch.randint(0, 262144, (n,), generator=g, device="cuda", dtype=torch.int32)
+    arrays.append((w.to(torch.int64) + 10 ** 12, torch.empty(n, dtype=torch.int64, device="cuda"), 10 ** 12,
+                   10 ** 12 + 262144))
+    del w
     stream = torch.cuda.current_stream()
 
     def step():
@@ -926,7 +941,7 @@ def main():
         if "error" not in methods:
             log(f"[bench] output methods identical: {methods['outputs_identical']}; prefix maximum "
                 f"faster at: {methods['prefix_max_faster_at'] or 'none'}")
-        log("[bench] 16- and 8-bit keys")
+        log("[bench] 16-, 8- and 64-bit keys")
         narrow = section("key widths", lambda: bench_key_widths(torch, rtcdf, args.steps))
         if "error" not in narrow:
             log("[bench] key widths: " + ", ".join(f"{r['keys']} [{r['minVal']},{r['maxVal']}) "

@@ -598,20 +598,12 @@ struct FillArgs {
   uint32_t sparse_k;           // a chunk takes the sparse form below this many positions per value
 };
 
-// Four consecutive outputs (group i of the aligned body, 32 / 16 / 8 / 4
-// bytes) and single outputs, in the key width KB.  An int64 output is min64
-// plus the value, exact in 64 bits.
+// Four consecutive outputs (group i of the aligned body, 16 / 8 / 4 bytes)
+// and single outputs, in the key width KB.  An int64 output is min64 plus the
+// value, exact in 64 bits.
 template <int KB>
 __device__ __forceinline__ void store_group(const FillArgs& a, uint64_t i, v4i o) {
-  if constexpr (KB == 8) {
-    const uint64_t m = (uint64_t)a.min64;
-    const uint64_t k0 = m + (uint32_t)o.x, k1 = m + (uint32_t)o.y, k2 = m + (uint32_t)o.z, k3 = m + (uint32_t)o.w;
-    const v4i lo = {(int)(uint32_t)k0, (int)(uint32_t)(k0 >> 32), (int)(uint32_t)k1, (int)(uint32_t)(k1 >> 32)};
-    const v4i hi = {(int)(uint32_t)k2, (int)(uint32_t)(k2 >> 32), (int)(uint32_t)k3, (int)(uint32_t)(k3 >> 32)};
-    v4i* body = reinterpret_cast<v4i*>(static_cast<int64_t*>(a.out) + a.body_lo);
-    __builtin_nontemporal_store(lo, &body[2 * i]);
-    __builtin_nontemporal_store(hi, &body[2 * i + 1]);
-  } else if constexpr (KB == 4) {
+  if constexpr (KB == 4) {
     v4i* body = reinterpret_cast<v4i*>(static_cast<int32_t*>(a.out) + a.body_lo);
     __builtin_nontemporal_store(o, &body[i]);
   } else if constexpr (KB == 2) {
@@ -649,6 +641,27 @@ __device__ __forceinline__ void store_vec16(const FillArgs& a, uint64_t i, const
   const v4u v = {w[0], w[1], w[2], w[3]};
   v4u* body = reinterpret_cast<v4u*>(static_cast<uint8_t*>(a.out) + a.body_lo * KB);
   __builtin_nontemporal_store(v, &body[i]);
+}
+
+// The int64 outputs of one wave's 256-position step (groups [ib, ib + 64) of
+// the aligned body, those below i_hi): lane l holds positions 2l, 2l + 1,
+// 128 + 2l and 129 + 2l of the step (fill_chunk's pair layout), so each of
+// its two 16-byte stores is one lane's share of a contiguous 1 KB wave store
+// and every line is written whole by one instruction.
+__device__ __forceinline__ void store_pairs64(const FillArgs& a, uint64_t ib, uint32_t lane, uint64_t i_hi,
+                                              v4i o) {
+  const uint64_t m = (uint64_t)a.min64;
+  v4i* body = reinterpret_cast<v4i*>(static_cast<int64_t*>(a.out) + a.body_lo) + 2 * ib;
+  if (ib + (lane >> 1) < i_hi) {
+    const uint64_t k0 = m + (uint32_t)o.x, k1 = m + (uint32_t)o.y;
+    const v4i w = {(int)(uint32_t)k0, (int)(uint32_t)(k0 >> 32), (int)(uint32_t)k1, (int)(uint32_t)(k1 >> 32)};
+    __builtin_nontemporal_store(w, &body[lane]);
+  }
+  if (ib + 32 + (lane >> 1) < i_hi) {
+    const uint64_t k2 = m + (uint32_t)o.z, k3 = m + (uint32_t)o.w;
+    const v4i w = {(int)(uint32_t)k2, (int)(uint32_t)(k2 >> 32), (int)(uint32_t)k3, (int)(uint32_t)(k3 >> 32)};
+    __builtin_nontemporal_store(w, &body[64 + lane]);
+  }
 }
 
 template <int KB>
@@ -754,11 +767,14 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
   // grow), so a step whose 256 positions hold one value touches no memory but
   // the store.  Otherwise the value boundaries inside the step are visited in
   // order (one broadcast LDS read each) and every lane counts the boundaries
-  // at or below each of its four positions.  In the SPARSE form, where more
+  // at or below each of its four positions: pa, pa + 1, pb, pb + 1 from the
+  // step's start, four consecutive ones (one 16-byte store), or for int64
+  // keys two pairs 128 apart (store_pairs64).  In the SPARSE form, where more
   // than kWalk values end before the step or inside it (most of them empty),
   // one look-ahead read shows it: the wave then bisects for its position or
   // scatters the step's values over an LDS stage (scatter_step).
   constexpr uint32_t kWalk = 8;
+  const uint32_t pa = KB == 8 ? 2 * lane : 4 * lane, pb = KB == 8 ? 128 + 2 * lane : 4 * lane + 2;
   uint32_t xw = 0;
   uint32_t end = win[0];
   for (uint64_t ib = i_lo + (uint64_t)wave * 64; ib < i_hi; ib += kFillBlock) {
@@ -783,14 +799,14 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
     if (xw == last || past_step(end, pw, 256u)) {
       o = (v4i)(base + (int32_t)xw);
     } else if constexpr (!SPARSE) {
-      const uint32_t p = pw + 4 * lane;
+      const uint32_t p = pw + pa, q = pw + pb;
       uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
       uint32_t xb = xw, e = end;
       while (xb < last && !past_step(e, pw, 256u)) {   // boundary after value xb at position e
         c0 += e <= p;
         c1 += e <= p + 1;
-        c2 += e <= p + 2;
-        c3 += e <= p + 3;
+        c2 += e <= q;
+        c3 += e <= q + 1;
         e = win[++xb];
       }
       o.x = base + (int32_t)(xw + c0);
@@ -798,22 +814,28 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
       o.z = base + (int32_t)(xw + c2);
       o.w = base + (int32_t)(xw + c3);
     } else {
-      const uint32_t p = pw + 4 * lane;
+      const uint32_t p = pw + pa, q = pw + pb;
       const uint32_t far = win[min(xw + kWalk, last)], e1 = win[xw + 1];
       if (!past_step(far, pw, 256u)) {
         uint32_t* st = stage + (tid >> 6) * 256u;
         scatter_step([&](uint32_t x) { return win[x]; }, xw, last, pw, st);
-        const v4i sv = *reinterpret_cast<const v4i*>(st + 4 * lane);
-        o = (v4i)base + sv;
+        if constexpr (KB == 8) {
+          typedef int v2i_t __attribute__((ext_vector_type(2)));
+          const v2i_t sa = *reinterpret_cast<const v2i_t*>(st + pa), sb = *reinterpret_cast<const v2i_t*>(st + pb);
+          o = (v4i)base + (v4i){sa.x, sa.y, sb.x, sb.y};
+        } else {
+          const v4i sv = *reinterpret_cast<const v4i*>(st + 4 * lane);
+          o = (v4i)base + sv;
+        }
       } else {
         // boundary after value xw at position end, then after xw + 1 at e1, ...
-        uint32_t c0 = end <= p, c1 = end <= p + 1, c2 = end <= p + 2, c3 = end <= p + 3;
+        uint32_t c0 = end <= p, c1 = end <= p + 1, c2 = end <= q, c3 = end <= q + 1;
         uint32_t xb = xw + 1, e = e1;
         while (xb < last && !past_step(e, pw, 256u)) {
           c0 += e <= p;
           c1 += e <= p + 1;
-          c2 += e <= p + 2;
-          c3 += e <= p + 3;
+          c2 += e <= q;
+          c3 += e <= q + 1;
           e = win[++xb];
         }
         o.x = base + (int32_t)(xw + c0);
@@ -822,7 +844,8 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, const uint32_t* wi
         o.w = base + (int32_t)(xw + c3);
       }
     }
-    if (i < i_hi) store_group<KB>(a, i, o);
+    if constexpr (KB == 8) store_pairs64(a, ib, lane, i_hi, o);
+    else if (i < i_hi) store_group<KB>(a, i, o);
   }
   // scalar head (positions before the aligned body) and tail
   if (first)
