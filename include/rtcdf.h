@@ -32,7 +32,18 @@
  *  - keys_out may equal keys_in (in place): the output stage never reads the
  *    input.  Partial overlap is rejected.
  *  - Keys need only 4-byte alignment; the kernels peel unaligned heads/tails.
- *  - n < 2^32 (counts are 32-bit, Sec. 3.2 workspace analysis).
+ *  - n <= 2^40.  Below 2^32 every count and output position of the sort is
+ *    32-bit, as in the paper's kernels (Sec. 3.2 workspace analysis).  From
+ *    n = 2^32 on (not in the paper) the sorts of rtcdf_sort,
+ *    rtcdf_sort_with_config, rtcdf_sort_keys, rtcdf_sort_checked and
+ *    rtcdf_sort_ws keep the per-value counts in 64 bits: the input is counted
+ *    in pieces of 2^31 keys, and the output is written in windows of 2^31
+ *    positions by the same local-CDF and output stages, each window from the
+ *    counts of its own positions.  The configuration is then the caller's or
+ *    the static choice for a 2^31-key piece (no learned pick, no
+ *    prefix-maximum output), and the workspace adds 8 bytes per value of the
+ *    range.  rtcdf_plan_info and rtcdf_debug_intermediates describe one plain
+ *    plan and take n < 2^32 only.
  *  - Functions are thread-safe with respect to different devices; concurrent
  *    calls on one device that use the library's internal workspace are
  *    serialised internally by a mutex but their GPU work is only ordered if
@@ -53,7 +64,7 @@ extern "C" {
 typedef enum rtcdf_status {
   RTCDF_SUCCESS = 0,
   RTCDF_ERROR_INVALID_VALUE = 1,    /* NULL with n > 0, maxVal <= minVal, range outside int32, bad config */
-  RTCDF_ERROR_SIZE_TOO_LARGE = 2,   /* n >= 2^32 */
+  RTCDF_ERROR_SIZE_TOO_LARGE = 2,   /* n > 2^40; n >= 2^32 for the plan-info / intermediates calls */
   RTCDF_ERROR_RANGE_TOO_LARGE = 3,  /* R > RTCDF_MAX_RANGE */
   RTCDF_ERROR_OVERLAP = 4,          /* keys_in and keys_out overlap without being equal */
   RTCDF_ERROR_OUT_OF_MEMORY = 5,    /* device workspace allocation failed */
@@ -163,7 +174,7 @@ rtcdf_status_t rtcdf_sort_with_config(const int32_t* keys_in, int32_t* keys_out,
  * [minVal, maxVal) of int64 values with R = maxVal - minVal <=
  * RTCDF_MAX_RANGE (maxVal <= INT64_MAX, so INT64_MAX itself is not a
  * sortable key); every key is normalised to key - minVal in 64-bit
- * arithmetic, counts stay 32-bit (n < 2^32), and the output stage writes
+ * arithmetic (counts as for int32 keys, 64-bit from n = 2^32), and the output stage writes
  * minVal + value as 8-byte keys.  key_type is one of rtcdf_key_type_t;
  * keys_in / keys_out are device arrays of n keys of that type, aligned to its
  * size (they may be equal; partial overlap is RTCDF_ERROR_OVERLAP);

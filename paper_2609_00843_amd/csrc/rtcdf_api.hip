@@ -74,7 +74,7 @@ rtcdf_status_t check_problem(const int32_t* keys_in, const int32_t* keys_out, si
   if (maxVal <= minVal) return RTCDF_ERROR_INVALID_VALUE;
   if (minVal < (int64_t)INT32_MIN || maxVal > (int64_t)INT32_MAX + 1) return RTCDF_ERROR_INVALID_VALUE;
   if ((uint64_t)(maxVal - minVal) > (uint64_t)RTCDF_MAX_RANGE) return RTCDF_ERROR_RANGE_TOO_LARGE;
-  if ((uint64_t)n > 0xffffffffull) return RTCDF_ERROR_SIZE_TOO_LARGE;
+  if ((uint64_t)n > kWideMaxN) return RTCDF_ERROR_SIZE_TOO_LARGE;
   if (n == 0) return RTCDF_SUCCESS;
   if (keys_in == nullptr || keys_out == nullptr) return RTCDF_ERROR_INVALID_VALUE;
   if ((reinterpret_cast<uintptr_t>(keys_in) & 3u) || (reinterpret_cast<uintptr_t>(keys_out) & 3u))
@@ -147,7 +147,7 @@ static int64_t env_int(const char* name, int64_t dflt) {
 // inspected for its alignment.
 void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& cfg,
                const void* in, const void* out, const DeviceInfo& dev, Plan* p, uint32_t kb,
-               uint32_t flip) {
+               uint32_t flip, PlanRole role) {
   std::memset(p, 0, sizeof(*p));
   const uint32_t R = (uint32_t)(maxVal - minVal);
   p->n = n;
@@ -259,8 +259,8 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
     // bucket of padding), so the padded copy must stay below 2^32 keys
     const bool fits = p->passes >= 2 && p->passes <= kPartMaxBuckets && kb == 4 &&
                       (uint64_t)n + 4ull * p->passes + 4 <= 0xffffffffull;
-    p->part = fits && (force == 1 || (force != 0 && p->passes >= kPartMinPasses &&
-                                      (uint64_t)n * p->passes >= kPartMinWork));
+    p->part = fits && role != PlanRole::kWindow &&
+              (force == 1 || (force != 0 && p->passes >= kPartMinPasses && (uint64_t)n * p->passes >= kPartMinWork));
     if (p->part) {
       p->part_buckets = p->passes;
       const uint64_t tiles = (n + kPartTileKeys - 1) / kPartTileKeys;
@@ -316,7 +316,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   // output workgroup reads rows * stride <= kFastRegionWords words.
   // Prefix-maximum output (Alg. 3) in place of Alg. 7: runs after the staged
   // local-CDF stage, so it never takes the fast path.
-  p->pmax = (cfg.flags & RTCDF_FLAG_OUTPUT_PREFIX_MAX) != 0 && kb == 4;
+  p->pmax = (cfg.flags & RTCDF_FLAG_OUTPUT_PREFIX_MAX) != 0 && kb == 4 && role == PlanRole::kSort;
   if (p->pmax) {
     const uint32_t h = (uint32_t)std::min<uint64_t>(p->out_head, n);
     p->pm_chunk = n <= kPmaxSmallN ? kPmaxChunkSmall : kPmaxChunkLarge;
@@ -326,7 +326,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
                                                                          (uint64_t)dev.cus * 8));
   }
   p->fast = p->m == 1 && p->bits == 32 && p->passes == 1 && R <= kFastMaxRange && !p->pmax &&
-            env_int("RTCDF_DEV_FAST", 1) != 0;
+            role == PlanRole::kSort && env_int("RTCDF_DEV_FAST", 1) != 0;
   if (p->fast) {
     p->fast_stride = Rr;
     const int64_t force_rows = env_int("RTCDF_DEV_FAST_ROWS", 0);
@@ -567,6 +567,35 @@ static rtcdf_status_t enqueue(const Plan& p, const int32_t* in, int32_t* out, ui
   return RTCDF_SUCCESS;
 }
 
+// A sort of n >= 2^32 keys in the library's workspace (see rtcdf_wide.hip).
+// The configuration is the caller's, or the static choice for a piece of
+// kWidePiece keys (the learned pick is not consulted); the prefix-maximum
+// output is never taken.
+static rtcdf_status_t sort_wide_cached(const int32_t* in, int32_t* out, size_t n, int64_t minVal,
+                                       int64_t maxVal, const rtcdf_config_t* cfg, hipStream_t s, bool cap,
+                                       const DeviceInfo& dev, uint32_t kb, uint32_t flip) {
+  rtcdf_config_t c;
+  rtcdf_status_t st = complete_config(cfg, nullptr, kWidePiece, minVal, maxVal, s, &c);
+  if (st != RTCDF_SUCCESS) return st;
+  if (kb != 4) c.flags = 0;
+  WidePlan wp;
+  make_wide_plan(n, minVal, maxVal, c, in, out, dev, &wp, kb, flip);
+  Plan need;   // what the cached workspace must hold
+  std::memset(&need, 0, sizeof(need));
+  need.ws_bytes = wp.ws_bytes;
+  need.carry_words = wp.carry_words;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  Workspace& w = g_ws[std::make_pair(dev.device, s)];
+  if (cap) {
+    if (!fits_cached(w, need)) return RTCDF_ERROR_CAPTURE_NEEDS_WORKSPACE;
+    w.captured = true;
+  }
+  st = grow(w, need, s);
+  if (st != RTCDF_SUCCESS) return st;
+  const hipError_t e = enqueue_wide(wp, in, out, static_cast<uint8_t*>(w.ws), w.carry, s);
+  return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
+}
+
 // kb / flip: 8- and 16-bit keys (see make_plan); their configuration never
 // takes the prefix-maximum output, and the learned picker (whose sketch
 // reads int32 keys) is not consulted for them.
@@ -584,6 +613,10 @@ static rtcdf_status_t sort_cached(const int32_t* in, int32_t* out, size_t n, int
   bool cap = false;
   st = capturing(s, &cap);
   if (st != RTCDF_SUCCESS) return st;
+  if (n > 0xffffffffull) {
+    if (out == nullptr) return RTCDF_ERROR_SIZE_TOO_LARGE;   // intermediates: n < 2^32 only
+    return sort_wide_cached(in, out, n, minVal, maxVal, cfg, s, cap, dev, kb, flip);
+  }
   rtcdf_config_t c;
   st = complete_config(cfg, (kb == 4 && !cap) ? in : nullptr, n, minVal, maxVal, s, &c);
   if (st != RTCDF_SUCCESS) return st;
@@ -624,6 +657,18 @@ rtcdf_status_t sort_in_workspace(const int32_t* keys_in, int32_t* keys_out, size
   rtcdf_status_t st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;
   rtcdf_config_t c;
+  if (n > 0xffffffffull) {   // n >= 2^32: counts in 64 bits (rtcdf_wide.hip)
+    st = complete_config(cfg, nullptr, kWidePiece, minVal, maxVal, nullptr, &c);
+    if (st != RTCDF_SUCCESS) return st;
+    WidePlan wp;
+    make_wide_plan(n, minVal, maxVal, c, keys_in, keys_out, dev, &wp);
+    if (ws_bytes < wp.ws_bytes) return RTCDF_ERROR_WORKSPACE_TOO_SMALL;
+    uint8_t* ws = static_cast<uint8_t*>(d_ws);
+    uint32_t* carry = reinterpret_cast<uint32_t*>(ws + wp.off_carry);
+    hipError_t e = wp.carry_words ? launch_clear(carry, wp.carry_words, stream) : hipSuccess;
+    if (e == hipSuccess) e = enqueue_wide(wp, keys_in, keys_out, ws, carry, stream);
+    return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
+  }
   st = complete_config(cfg, nullptr, n, minVal, maxVal, nullptr, &c);
   if (st != RTCDF_SUCCESS) return st;
   Plan p;
@@ -678,7 +723,7 @@ rtcdf_status_t rtcdf_sort_keys(const void* keys_in, void* keys_out, size_t n, in
   }
   if (maxVal <= minVal || minVal < lo || maxVal > hi) return RTCDF_ERROR_INVALID_VALUE;
   if ((uint64_t)maxVal - (uint64_t)minVal > RTCDF_MAX_RANGE) return RTCDF_ERROR_RANGE_TOO_LARGE;
-  if ((uint64_t)n > 0xffffffffull) return RTCDF_ERROR_SIZE_TOO_LARGE;
+  if ((uint64_t)n > kWideMaxN) return RTCDF_ERROR_SIZE_TOO_LARGE;
   if (n == 0) return RTCDF_SUCCESS;
   if (keys_in == nullptr || keys_out == nullptr) return RTCDF_ERROR_INVALID_VALUE;
   const uintptr_t a = reinterpret_cast<uintptr_t>(keys_in), b = reinterpret_cast<uintptr_t>(keys_out);
@@ -748,8 +793,15 @@ rtcdf_status_t rtcdf_workspace_bytes(size_t n, int64_t minVal, int64_t maxVal,
   st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;
   rtcdf_config_t c;
-  st = complete_config(cfg, nullptr, n, minVal, maxVal, nullptr, &c);
+  const bool wide = n > 0xffffffffull;
+  st = complete_config(cfg, nullptr, wide ? kWidePiece : n, minVal, maxVal, nullptr, &c);
   if (st != RTCDF_SUCCESS) return st;
+  if (wide) {
+    WidePlan wp;
+    make_wide_plan(n, minVal, maxVal, c, probe, probe, dev, &wp);
+    *bytes = wp.ws_bytes;
+    return RTCDF_SUCCESS;
+  }
   Plan p;
   // The layout depends on n, R, the config and keys_out's alignment (output
   // chunk starts); keys_in's alignment changes only the histogram's head and
@@ -775,6 +827,7 @@ rtcdf_status_t rtcdf_debug_intermediates(const int32_t* keys_in, size_t n, int64
   rtcdf_status_t st = check_problem(keys_in, keys_in, n, minVal, maxVal);
   if (st != RTCDF_SUCCESS) return st;
   if (n == 0) return RTCDF_ERROR_INVALID_VALUE;
+  if (n > 0xffffffffull) return RTCDF_ERROR_SIZE_TOO_LARGE;
   if (config_is_zero(cfg) || !config_valid(*cfg)) return RTCDF_ERROR_INVALID_VALUE;
   return sort_cached(keys_in, nullptr, n, minVal, maxVal, cfg, stream, d_hist, d_cdf, d_offsets);
 }
@@ -836,7 +889,7 @@ const char* rtcdf_status_string(rtcdf_status_t s) {
   switch (s) {
     case RTCDF_SUCCESS: return "success";
     case RTCDF_ERROR_INVALID_VALUE: return "invalid value";
-    case RTCDF_ERROR_SIZE_TOO_LARGE: return "n too large (n must be < 2^32)";
+    case RTCDF_ERROR_SIZE_TOO_LARGE: return "n too large (sorts: n <= 2^40; plan and intermediates: n < 2^32)";
     case RTCDF_ERROR_RANGE_TOO_LARGE: return "range too large";
     case RTCDF_ERROR_OVERLAP: return "input and output overlap partially";
     case RTCDF_ERROR_OUT_OF_MEMORY: return "out of device memory";
@@ -887,6 +940,7 @@ rtcdf_status_t rtcdf_plan_info(size_t n, int64_t minVal, int64_t maxVal, const r
   const int32_t* probe = reinterpret_cast<const int32_t*>((uintptr_t)256);
   rtcdf_status_t st = check_problem(probe, probe, n, minVal, maxVal);
   if (st != RTCDF_SUCCESS) return st;
+  if (n > 0xffffffffull) return RTCDF_ERROR_SIZE_TOO_LARGE;   // one plan describes n < 2^32 only
   DeviceInfo dev;
   st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;

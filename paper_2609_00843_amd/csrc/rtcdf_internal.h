@@ -203,11 +203,43 @@ rtcdf_status_t device_info(DeviceInfo* out);
 hipError_t ensure_dynamic_lds(const void* fn, int bytes);
 rtcdf_status_t hip_fail(hipError_t e);
 bool config_valid(const rtcdf_config_t& c);
+// What a plan is for: a whole sort; the histogram and reduction of one piece
+// of a sort of n >= 2^32 keys (no single-tile fast path, no prefix-maximum
+// output: the reduction must leave H); or one output window of such a sort
+// (the local-CDF and output stages only: neither of those, and no partition
+// by pass, whose key copy the window never uses).
+enum class PlanRole { kSort, kPiece, kWindow };
+
 // kb / flip: key width in bytes and the sign-bit flip of narrow signed keys
 // (4 / 0 for int32 keys).  `in` and `out` are only inspected for alignment.
 void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& cfg,
                const void* in, const void* out, const DeviceInfo& dev, Plan* p, uint32_t kb = 4,
-               uint32_t flip = 0);
+               uint32_t flip = 0, PlanRole role = PlanRole::kSort);
+
+// Sorts of n >= 2^32 keys (rtcdf_wide.hip): the input is counted in pieces
+// of kWidePiece keys into 64-bit per-value counts, and the output written in
+// windows of kWidePiece positions, each by the plain local-CDF and output
+// stages.  Sorts of up to kWideMaxN keys are accepted.
+constexpr uint64_t kWidePiece = 1ull << 31;
+constexpr uint64_t kWideMaxN = 1ull << 40;
+struct WidePlan {
+  uint64_t n;
+  uint32_t kb, R;
+  int cus;
+  uint64_t piece;         // keys per piece = positions per window
+  uint64_t pieces;        // pieces = windows = ceil(n / piece)
+  Plan hist_full, hist_last;   // histogram + reduction of a whole piece / of the last one
+  Plan win_full, win_last;     // local-CDF + output stages of a whole window / of the last one
+  // workspace: the plain plans' regions (shared, used one stage at a time),
+  // then the 64-bit counts H64[R] and the block prefixes of their scan
+  size_t off_h64, off_pre, off_carry, carry_words, ws_bytes;
+};
+void make_wide_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& cfg, const void* in,
+                    const void* out, const DeviceInfo& dev, WidePlan* w, uint32_t kb = 4, uint32_t flip = 0);
+// `carry` points at a zeroed array of w.carry_words (narrow counters), which
+// the reductions return to zero.
+hipError_t enqueue_wide(const WidePlan& w, const void* in, void* out, uint8_t* ws, uint32_t* carry,
+                        hipStream_t s);
 
 // Argument checks of the plain sort (n, range, pointers, overlap).
 rtcdf_status_t check_problem(const int32_t* keys_in, const int32_t* keys_out, size_t n, int64_t minVal,

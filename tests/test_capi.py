@@ -48,7 +48,7 @@ def test_argument_errors_before_gpu(r):
     assert sort(P_IN, P_OUT, 10, -(2 ** 31) - 1, 0, None) == r.INVALID_VALUE
     assert sort(P_IN, P_OUT, 10, 0, 2 ** 31 + 1, None) == r.INVALID_VALUE
     assert sort(P_IN, P_OUT, 10, 0, (1 << 28) + 1, None) == r.RANGE_TOO_LARGE
-    assert sort(P_IN, P_OUT, 1 << 32, 0, 10, None) == r.SIZE_TOO_LARGE
+    assert sort(P_IN, P_OUT, (1 << 40) + 1, 0, 10, None) == r.SIZE_TOO_LARGE   # n >= 2^32 is taken up to 2^40
     assert sort(None, P_OUT, 10, 0, 10, None) == r.INVALID_VALUE
     assert sort(P_IN, None, 10, 0, 10, None) == r.INVALID_VALUE
     assert sort(ctypes.c_void_p((1 << 20) + 2), P_OUT, 10, 0, 10, None) == r.INVALID_VALUE  # not 4-byte aligned
@@ -64,7 +64,7 @@ def test_checked_mode_argument_errors(r):
     assert L.rtcdf_count_out_of_range(P_IN, 10, 0, 10, ctypes.c_void_p((1 << 24) + 4), None) == r.INVALID_VALUE
     assert L.rtcdf_count_out_of_range(P_IN, 10, 5, 5, cnt, None) == r.INVALID_VALUE
     assert L.rtcdf_count_out_of_range(None, 10, 0, 10, cnt, None) == r.INVALID_VALUE
-    assert L.rtcdf_count_out_of_range(P_IN, 1 << 32, 0, 10, cnt, None) == r.SIZE_TOO_LARGE
+    assert L.rtcdf_count_out_of_range(P_IN, (1 << 40) + 1, 0, 10, cnt, None) == r.SIZE_TOO_LARGE
     sc = L.rtcdf_sort_checked
     assert sc(P_IN, P_OUT, 0, 0, 10, None, None) == r.SUCCESS                # n = 0 is a no-op
     assert sc(P_IN, P_OUT, 10, 0, (1 << 28) + 1, None, None) == r.RANGE_TOO_LARGE
@@ -174,7 +174,7 @@ def test_sort_keys_argument_errors(r):
     assert sk(r.KEY_INT8, -129, 0) == r.INVALID_VALUE
     assert sk(r.KEY_UINT8, 0, 257) == r.INVALID_VALUE
     assert sk(r.KEY_UINT8, 5, 5) == r.INVALID_VALUE
-    assert sk(r.KEY_INT16, -32768, 32768, n=1 << 32) == r.SIZE_TOO_LARGE
+    assert sk(r.KEY_INT16, -32768, 32768, n=(1 << 40) + 1) == r.SIZE_TOO_LARGE
     assert sk(r.KEY_INT16, -32768, 32768, n=0) == r.SUCCESS                  # no-op
     assert sk(r.KEY_INT16, 0, 10, a=None) == r.INVALID_VALUE
     assert sk(r.KEY_INT16, 0, 10, a=ctypes.c_void_p((1 << 20) + 1)) == r.INVALID_VALUE   # odd address
@@ -184,13 +184,30 @@ def test_sort_keys_argument_errors(r):
     assert sk(r.KEY_INT16, 0, 10, cfg=ctypes.byref(pm)) == r.INVALID_VALUE
     bad = r.Config(100, 16, 1, 0)
     assert sk(r.KEY_UINT8, 0, 10, cfg=ctypes.byref(bad)) == r.INVALID_VALUE
-    assert sk(r.KEY_INT32, 0, 10, n=1 << 32) == r.SIZE_TOO_LARGE             # the int32 entry's checks
+    assert sk(r.KEY_INT32, 0, 10, n=(1 << 40) + 1) == r.SIZE_TOO_LARGE       # the int32 entry's checks
     # int64 keys: any window of at most RTCDF_MAX_RANGE values below INT64_MAX
     i64min, i64max = -(1 << 63), (1 << 63) - 1
     assert sk(r.KEY_INT64, i64min, i64min + (1 << 28) + 1) == r.RANGE_TOO_LARGE
     assert sk(r.KEY_INT64, i64min, i64max) == r.RANGE_TOO_LARGE
     assert sk(r.KEY_INT64, 5, 5) == r.INVALID_VALUE
-    assert sk(r.KEY_INT64, 0, 10, n=1 << 32) == r.SIZE_TOO_LARGE
+    assert sk(r.KEY_INT64, 0, 10, n=(1 << 40) + 1) == r.SIZE_TOO_LARGE
     assert sk(r.KEY_INT64, 0, 10, a=ctypes.c_void_p((1 << 20) + 4)) == r.INVALID_VALUE   # 8-byte alignment
     assert sk(r.KEY_INT64, 0, 10, b=ctypes.c_void_p((1 << 20) + 72)) == r.OVERLAP        # 80 bytes from 2^20
     assert sk(r.KEY_INT64, 0, 10, cfg=ctypes.byref(pm)) == r.INVALID_VALUE
+
+
+def test_wide_sorts_limits(r):
+    """n >= 2^32 is sorted (64-bit counts) up to 2^40 keys; the calls that
+    describe one plain plan (plan info, intermediates) stay below 2^32."""
+    L = r.lib
+    info = r.PlanInfo()
+    assert L.rtcdf_plan_info(1 << 32, 0, 10, None, None, None, ctypes.byref(info)) == r.SIZE_TOO_LARGE
+    assert L.rtcdf_debug_intermediates(P_IN, 1 << 32, 0, 10, None, None, None, None, None) == r.SIZE_TOO_LARGE
+    size = ctypes.c_size_t(0)
+    assert L.rtcdf_workspace_bytes((1 << 40) + 1, 0, 10, None, None, ctypes.byref(size)) == r.SIZE_TOO_LARGE
+    assert L.rtcdf_sort_ws(P_IN, P_IN, (1 << 40) + 1, 0, 10, None, ctypes.c_void_p(1 << 24), 1 << 20,
+                           None) == r.SIZE_TOO_LARGE
+    # above 2^32 the argument checks still come first: overlap, alignment
+    assert L.rtcdf_sort(P_IN, P_OUT, 1 << 32, 0, 10, None) == r.OVERLAP
+    assert L.rtcdf_sort(ctypes.c_void_p((1 << 20) + 2), ctypes.c_void_p(1 << 40), 1 << 32, 0, 10,
+                        None) == r.INVALID_VALUE

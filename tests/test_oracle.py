@@ -177,6 +177,32 @@ def test_streaming_verifier():
         v.chunk(np.concatenate([B, B[-1:]]))
 
 
+def test_streaming_verifier_counts_over_2pow32():
+    """The verifier's cursor is 64-bit (sorts of n >= 2^32 keys): one value
+    held 2^32 + 5 times, then three copies of the next, fed in chunks of one
+    reused 2^24-key array.  A wrong element at position 2^32 + 4 (the last
+    copy of the first value) is reported at that position, which neither a
+    32-bit count nor a 32-bit position could hold."""
+    minVal, big = -3, (1 << 32) + 5
+    cnt = np.array([big, 3], dtype=np.uint64)
+    run = np.full(1 << 24, minVal, dtype=np.int32)
+
+    def feed(v, upto):
+        for _ in range(upto >> 24):
+            v.chunk(run)
+        v.chunk(run[:upto & ((1 << 24) - 1)])
+
+    v = oracle.StreamingVerifier(cnt, minVal)
+    feed(v, big)
+    v.chunk(np.full(3, minVal + 1, dtype=np.int32))
+    v.end(big + 3)
+    assert v.position == big + 3
+    v = oracle.StreamingVerifier(cnt, minVal)
+    feed(v, big - 1)
+    with pytest.raises(oracle.OracleError, match=f"position {big - 1}"):
+        v.chunk(np.array([minVal + 1], dtype=np.int32))
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_sparse_and_offset_keys(seed):
     """Keys that avoid the low and high ends of the declared range, with long runs
