@@ -517,6 +517,67 @@ def bench_scale(torch, rtcdf, inputs, steps):
     return {"workload": "n=1e9 int32 keys, minVal=0, R=2^18", "cases": rows}
 
 
+WIDE_N = (1 << 32) + (1 << 30)
+
+
+def _wide_input(torch, n, R, seed):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    a = torch.empty(n, dtype=torch.int32, device="cuda")
+    for s in range(0, n, 1 << 28):
+        e = min(n, s + (1 << 28))
+        a[s:e] = torch.randint(0, R, (e - s,), generator=g, device="cuda", dtype=torch.int32)
+    return a
+
+
+def bench_wide(torch, rtcdf, steps):
+    """n = 2^32 + 2^30 int32 keys (per-value counts in 64 bits: three pieces
+    and output windows of 2^31, 2^31 and 2^30 keys), uniform over R = 2^16 at
+    minVal 0; warm, HIP events, mean.  The output is checked to be
+    nondecreasing with the input's value counts (bincount on the GPU, in
+    chunks); element-by-element parity at this size is the streaming
+    verifier's, in the GPU tests."""
+    n, R = WIDE_N, 1 << 16
+    stream = torch.cuda.current_stream()
+    a = _wide_input(torch, n, R, 4242)
+    b = torch.empty_like(a)
+    ms = timed_sorts(torch, rtcdf, a, b, 0, R, max(3, min(steps, 10)), stream)
+    ca = torch.zeros(R, dtype=torch.int64, device="cuda")
+    cb = torch.zeros(R, dtype=torch.int64, device="cuda")
+    ok = True
+    for s in range(0, n, 1 << 28):
+        e = min(n, s + (1 << 28))
+        ca += torch.bincount(a[s:e], minlength=R)
+        cb += torch.bincount(b[s:e], minlength=R)
+        ok = ok and bool((b[s + 1:min(n, e + 1)] >= b[s:min(n, e + 1) - 1]).all())
+    ok = ok and bool(torch.equal(ca, cb))
+    del a, b
+    torch.cuda.empty_cache()
+    log(f"[bench] n=2^32+2^30 R=2^16 uniform: {ms:.3f} ms, {n / (ms * 1e-3) / 1e9:.1f} Gkeys/s, checked {ok}")
+    return {"workload": "n=2^32+2^30 int32 keys (64-bit counts), minVal=0, R=2^16, uniform",
+            "n": n, "ms": round(ms, 4), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 2),
+            "frac_8B_roofline": round(8.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "checked": ok,
+            "timing": "warm, HIP events, mean"}
+
+
+def profile_wide(torch, rtcdf, steps, warmup):
+    """Profiling mode: the array of bench_wide sorted once per step."""
+    n, R = WIDE_N, 1 << 16
+    stream = torch.cuda.current_stream()
+    a = _wide_input(torch, n, R, 4242)
+    b = torch.empty_like(a)
+    for _ in range(warmup):
+        rtcdf.sort(a, 0, R, keys_out=b, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        rtcdf.sort(a, 0, R, keys_out=b, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    print(json.dumps({"ms_per_step": e0.elapsed_time(e1) / steps, "keys_per_step": n}))
+
+
 def bench_learned(torch, rtcdf, cases, ins, outs, steps):
     """The learned-tuned form against the plain form (DEFAULT mode, the static
     table), measured end to end in this run:
@@ -653,6 +714,8 @@ def main():
                          "normal sd R/64) instead of the range sweep")
     ap.add_argument("--picker", action="store_true",
                     help="with --profile-only: run the learned picker's decision and training kernels")
+    ap.add_argument("--wide-n", action="store_true",
+                    help="with --profile-only: sort n = 2^32 + 2^30 keys (64-bit counts) once per step")
     ap.add_argument("--flags", type=lambda x: int(x, 0), default=0,
                     help="with --profile-only: sort with the static knobs and these option flags "
                          "(e.g. 0x40: 4-bit counters) instead of the library's choice")
@@ -666,8 +729,8 @@ def main():
         ap.error("--wide-ranges is a profiling mode; it needs --profile-only")
     if args.key_widths and not args.profile_only:
         ap.error("--key-widths is a profiling mode; it needs --profile-only")
-    if (args.large_n or args.picker or args.flags) and not args.profile_only:
-        ap.error("--large-n, --picker and --flags are profiling modes; they need --profile-only")
+    if (args.large_n or args.picker or args.flags or args.wide_n) and not args.profile_only:
+        ap.error("--large-n, --wide-n, --picker and --flags are profiling modes; they need --profile-only")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
               f"drives one GPU (the sort would shard by one 4R-byte histogram all-reduce)", file=sys.stderr)
@@ -682,6 +745,9 @@ def main():
         return
     if args.large_n:
         profile_large_n(torch, rtcdf, inputs, args.steps, args.warmup, args.flags)
+        return
+    if args.wide_n:
+        profile_wide(torch, rtcdf, args.steps, args.warmup)
         return
     if args.picker:
         profile_picker(torch, rtcdf, inputs, args.steps, args.warmup)
@@ -931,11 +997,12 @@ def main():
                 f"{batched['speedup_vs_plain_calls']}x plain calls, {batched['speedup_vs_plain_graph']}x "
                 f"plain graph; parity {batched['parity']}")
 
-    small = large = methods = wide = narrow = None
+    small = large = wide_n = methods = wide = narrow = None
     if not args.no_extra:
         log("[bench] n=1e6 and n=1e9 timings")
         small = section("n=1e6", lambda: bench_small(torch, rtcdf, inputs, args.steps))
         large = section("n=1e9", lambda: bench_scale(torch, rtcdf, inputs, args.steps))
+        wide_n = section("n=2^32+2^30", lambda: bench_wide(torch, rtcdf, args.steps))
         log("[bench] output methods: local-CDF search vs prefix maximum")
         methods = section("output methods", lambda: bench_output_methods(torch, rtcdf, inputs, args.steps))
         if "error" not in methods:
@@ -991,6 +1058,7 @@ def main():
         "wide_ranges": wide,
         "key_widths": narrow,
         "large_n": large,
+        "wide_n": wide_n,
     }
     print(json.dumps(rec))
 
