@@ -321,16 +321,18 @@ def test_empty_and_errors(r):
 
 
 def test_fast_path_plan(r):
-    """One tile, one pass of 32-bit counters and R <= 2048 take the fast path
-    (histogram and output stage only: no local-CDF workgroups); other plans
-    keep every stage."""
-    for R in (1, 128, 1000, 2048, 2049, 5000, 1 << 16):
-        info = r.plan_info(10_000_000, 0, R)
-        _say(f"plan R={R} {info}")
-        fast = info["tiles"] == 1 and info["counter_bits"] == 32 and info["passes"] == 1 and R <= 2048
-        assert (info["scan_workgroups"] == 0) == fast
-        if R <= 128:
-            assert fast
+    """One tile, one pass of 32-bit counters, R <= 2048 and n < 2^26 take the
+    fast path (histogram and output stage only: no local-CDF workgroups);
+    other plans keep every stage."""
+    for n in (10_000_000, (1 << 26) - 1, 1 << 26, 100_000_000):
+        for R in (1, 128, 1000, 2048, 2049, 5000, 1 << 16):
+            info = r.plan_info(n, 0, R)
+            _say(f"plan n={n} R={R} {info}")
+            fast = (info["tiles"] == 1 and info["counter_bits"] == 32 and info["passes"] == 1 and R <= 2048
+                    and n < (1 << 26))
+            assert (info["scan_workgroups"] == 0) == fast
+            if R <= 128:
+                assert fast == (n < (1 << 26))
 
 
 def test_fast_path_sequence(r):
