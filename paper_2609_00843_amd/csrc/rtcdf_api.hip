@@ -310,7 +310,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   }
 
   // Single-tile fast path: one tile, one pass of 32-bit counters, at most
-  // kFastMaxRange bins and fewer than kFastMaxKeys keys.  The histogram adds into accumulation rows of the
+  // kFastMaxRange bins and fewer than kFastMaxBytes bytes of keys.  The histogram adds into accumulation rows of the
   // fast-path area and the output stage sums and scans them itself.  Rows
   // spread the atomics of the histogram workgroups over more addresses; every
   // output workgroup reads rows * stride <= kFastRegionWords words.
@@ -325,7 +325,7 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
     p->pm_init_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n4 + 255) / 256,
                                                                          (uint64_t)dev.cus * 8));
   }
-  p->fast = p->m == 1 && p->bits == 32 && p->passes == 1 && R <= kFastMaxRange && n < kFastMaxKeys &&
+  p->fast = p->m == 1 && p->bits == 32 && p->passes == 1 && R <= kFastMaxRange && (uint64_t)n * kb < kFastMaxBytes &&
             !p->pmax && role == PlanRole::kSort && env_int("RTCDF_DEV_FAST", 1) != 0;
   if (p->fast) {
     p->fast_stride = Rr;

@@ -28,12 +28,12 @@ constexpr uint32_t kWrapSlotsMax = 4096;    // most slots (the LDS left by the c
 // kernel's workgroups read it, and all state is on the device, so a captured
 // graph replays correctly.
 constexpr uint32_t kFastMaxRange = 2048;
-// ... and fewer than kFastMaxKeys keys.  The fast path saves the reduction and
-// local-CDF launches (~13 us), but its output stage writes more slowly than the
-// staged k_fill at large n (measured on MI355X, R = 2^7 and 2^11: fast path
-// 7-11 % faster at n = 3 x 10^7, staged path 4-5 % faster at 10^8 and 10 % at
-// 3 x 10^8).
-constexpr uint64_t kFastMaxKeys = 1ull << 26;
+// ... and fewer than kFastMaxBytes bytes of keys (2^26 int32 keys).  The fast
+// path saves the reduction and local-CDF launches (~13 us), but its output
+// stage writes more slowly than the staged k_fill at large sizes (measured on
+// MI355X, int32 keys, R = 2^7 and 2^11: fast path 7-11 % faster at
+// n = 3 x 10^7, staged path 4-5 % faster at 10^8 and 10 % at 3 x 10^8).
+constexpr uint64_t kFastMaxBytes = 1ull << 28;
 constexpr uint32_t kFastRegionWords = 4096;
 constexpr uint32_t kFastPar = 2 * kFastRegionWords;        // word read by the histogram
 constexpr uint32_t kFastCur = 2 * kFastRegionWords + 32;   // word read by the output stage

@@ -68,7 +68,7 @@ def _verify(b, cnt, lo, n):
 
 @pytest.mark.parametrize("n,lo,R,skip,gap,tail", [
     # one tile of 128 values (the staged path: the single-tile fast path
-    # stops at 2^26 keys), dense output walk over the last step
+    # stops at 2^28 bytes of keys), dense output walk over the last step
     (N32, -1000, 1 << 7, 0, 8, [(-1000 + 120, 3), (-1000 + 122, 1), (-1000 + 123, 60), (-1000 + 127, 100)]),
     # staged path, 8-bit counters.  200 rare values at the bottom make the
     # first output chunk's window sparse, which switches the output stage to

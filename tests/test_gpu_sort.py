@@ -321,8 +321,8 @@ def test_empty_and_errors(r):
 
 
 def test_fast_path_plan(r):
-    """One tile, one pass of 32-bit counters, R <= 2048 and n < 2^26 take the
-    fast path (histogram and output stage only: no local-CDF workgroups);
+    """One tile, one pass of 32-bit counters, R <= 2048 and fewer than 2^26
+    int32 keys (2^28 bytes) take the fast path (histogram and output stage only: no local-CDF workgroups);
     other plans keep every stage."""
     for n in (10_000_000, (1 << 26) - 1, 1 << 26, 100_000_000):
         for R in (1, 128, 1000, 2048, 2049, 5000, 1 << 16):
