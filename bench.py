@@ -281,9 +281,10 @@ def bench_output_methods(torch, rtcdf, inputs, steps):
 
 
 def bench_wide_ranges(torch, rtcdf, inputs, steps):
-    """n = 10^8 uniform and normal keys over R = 2^20, 2^22, 2^24 (beyond the
-    paper's ranges): the library's choice (the partition by pass from 9
-    passes on) against the histogram that reads every key once per pass
+    """n = 10^8 uniform, normal (sd R/6), Zipf(1.1) and all-equal keys over
+    R = 2^20, 2^22, 2^24 (beyond the paper's ranges; Zipf and all-equal keys
+    put nearly every key in one LDS pass): the library's choice (the
+    partition by pass from 9 passes on) against the histogram that reads every key once per pass
     (RTCDF_DEV_PARTITION=0), and the LEARNED mode (these ranges lie outside
     the network's trusted range, so its decision is the exhaustive autotune
     of the grid, made once and cached; timed after it), warm, HIP events;
@@ -295,7 +296,7 @@ def bench_wide_ranges(torch, rtcdf, inputs, steps):
     try:
         for logR in WIDE_LOG_R:
             R = 1 << logR
-            for dist in ("uniform", "normal"):
+            for dist in ("uniform", "normal", "zipf", "all_equal"):
                 a = inputs.make_device(dist, n, 0, R, inputs.case_seed(7, logR))
                 b = torch.empty_like(a)
                 c = torch.empty_like(a)
@@ -333,7 +334,8 @@ def bench_wide_ranges(torch, rtcdf, inputs, steps):
                 del a, b, c
     finally:
         os.environ.pop("RTCDF_DEV_PARTITION", None)
-    return {"workload": "n=1e8 int32 keys, minVal=0, R in {2^20, 2^22, 2^24}", "rows": rows,
+    return {"workload": "n=1e8 int32 keys, minVal=0, R in {2^20, 2^22, 2^24}, uniform / normal / zipf / all-equal",
+            "rows": rows,
             "outputs_identical": same, "timing": "warm, HIP events, mean"}
 
 

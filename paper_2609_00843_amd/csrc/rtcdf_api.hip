@@ -337,8 +337,11 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
 
   // Workspace layout.
   size_t off = 0;
+  // Partial rows: one per histogram workgroup; with the partition by pass
+  // one per piece of a bucket in a workgroup's range, numbered workgroup +
+  // bucket (at most passes more).
   p->off_partial = off;
-  off = align256(off + (size_t)p->passes * p->G * p->row_words * 4);
+  off = align256(off + ((size_t)p->passes * p->G + (p->part ? p->passes : 0)) * p->row_words * 4);
   p->off_hist = off;
   off = align256(off + (size_t)R * 4);
   p->off_cdf = off;
@@ -363,6 +366,8 @@ void make_plan(size_t n, int64_t minVal, int64_t maxVal, const rtcdf_config_t& c
   off = align256(off + P * 4);
   p->off_pbound = off;
   off = align256(off + (p->part ? (P + 1) * 4 : 0));
+  p->off_prow = off;                        // each bucket's first partial row and their number
+  off = align256(off + P * 8);
   // Carry entries cover every bin of every pass (plus the partner of the last
   // bin), so even keys outside the declared range stay in bounds.
   p->carry_words = p->bits < 32 ? (size_t)p->passes * p->W + 4 : 0;

@@ -122,7 +122,7 @@ struct Plan {
   uint32_t scan_grid;    // workgroups of the local-CDF stage; > m: split by chunk counts
   // workspace layout
   size_t off_partial, off_hist, off_cdf, off_rsum, off_O, off_split, off_flags, off_pm, ws_bytes;
-  size_t off_pkeys, off_pcnt, off_ptot, off_pbound;
+  size_t off_pkeys, off_pcnt, off_ptot, off_pbound, off_prow;
   size_t off_carry;      // carry array inside a caller-owned workspace (rtcdf_sort_ws)
   size_t carry_words;    // 0 for 32-bit counters; the fast-path area on the fast path
 };

@@ -120,6 +120,104 @@ __device__ __forceinline__ int32_t load_key(const int32_t* keys, size_t i, uint3
   else return (int32_t)(reinterpret_cast<const uint8_t*>(keys)[i] ^ flip);
 }
 
+// Counts the vectors body[t, end) of one pass, t = t0 + k * step for the
+// workgroup's tiles of BLOCK * ITEMS / 4 vectors, into the LDS counters S.
+// Software pipelined: the loads of the next tile are in flight while the
+// current one is counted.  Every load is issued unconditionally from an
+// index clamped into [0, end), so that the compiler can wait for the current
+// tile's loads alone rather than for all loads in flight; in the workgroup's
+// last, partial tile the lanes past the end count `outside`.
+template <int ITEMS, int BITS, int BLOCK, int KB, bool DEDUPE>
+__device__ __forceinline__ void count_tiles(const HistArgs& a, uint32_t* S, uint32_t* tab, HotBin& hot,
+                                            const v4i* body, uint32_t t0, uint32_t step, uint32_t end,
+                                            uint32_t base, uint32_t pass_lo, v4i outside) {
+  constexpr int V = ITEMS / 4;
+  const uint32_t W = a.W;
+  if (end == 0) return;
+  const uint32_t last = end - 1;
+  // first vector of the workgroup's tile (uniform: kept in a scalar register)
+  uint32_t tb = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t0 - threadIdx.x));
+  v4i cur[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) cur[j] = __builtin_nontemporal_load(&body[min(t0 + j * BLOCK, last)]);
+  while (tb < end) {
+    const uint32_t t1 = t0 + step;
+    v4i nxt[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) nxt[j] = __builtin_nontemporal_load(&body[min(t1 + j * BLOCK, last)]);
+    if (tb + V * BLOCK <= end) {
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        count_vec<BITS, KB, DEDUPE>(S, cur[j], true, outside, a.flip, base, W, a.carry, pass_lo, tab, hot,
+                                    a.min64, a.R);
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        count_vec<BITS, KB, DEDUPE>(S, cur[j], t0 + j * BLOCK < end, outside, a.flip, base, W, a.carry,
+                                    pass_lo, tab, hot, a.min64, a.R);
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) cur[j] = nxt[j];
+    t0 = t1;
+    tb += step;
+  }
+}
+
+// Zero LDS counters and (narrow forms) an empty wrap table: its slot mask,
+// its bins and its amounts.
+template <int BITS, int BLOCK>
+__device__ __forceinline__ void init_counters(const HistArgs& a, uint32_t* S, uint32_t* tab) {
+  for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) S[i] = 0u;
+  if constexpr (BITS < 32) {
+    if (threadIdx.x == 0) tab[-1] = a.wrap_slots - 1u;
+    for (uint32_t i = threadIdx.x; i < 2 * a.wrap_slots; i += BLOCK) tab[i] = i < a.wrap_slots ? kWrapEmpty : 0u;
+  }
+  __syncthreads();
+}
+
+// Partition by pass: the padded copy holds the keys grouped by bucket (bucket
+// b, the keys of pass b, at pbound[b], a multiple of 4 keys; padding counts
+// nowhere).  The grid cuts the whole copy into equal ranges of vectors,
+// whatever the bucket sizes (a skewed input puts nearly every key in one
+// bucket), and a workgroup counts each bucket its range overlaps in turn.
+// The piece of bucket b in workgroup j's range goes to partial row j + b:
+// the pieces of one bucket belong to consecutive workgroups, and no two
+// nonempty pieces share a row (a later bucket starts after an earlier one
+// ends), so the reduction finds bucket b's rows from its bounds alone.
+template <int ITEMS, int BITS, int BLOCK, int KB, bool DEDUPE>
+__device__ __forceinline__ void hist_partitioned(const HistArgs& a, uint32_t* S, uint32_t* tab) {
+  constexpr int V = ITEMS / 4;
+  const uint32_t* pb = a.pbound;
+  const uint32_t total4 = pb[a.passes] / 4;
+  const uint32_t per4 = (total4 + gridDim.x - 1) / gridDim.x;
+  const uint32_t r0 = min(blockIdx.x * per4, total4), r1 = min(r0 + per4, total4);
+  // first bucket that ends after r0
+  uint32_t b = 0, hi = a.passes;
+  while (b < hi) {
+    const uint32_t mid = (b + hi) >> 1;
+    if (pb[mid + 1] / 4 <= r0) b = mid + 1; else hi = mid;
+  }
+  const v4i* all = reinterpret_cast<const v4i*>(a.keys);
+  for (; b < a.passes; ++b) {
+    const uint32_t b0 = pb[b] / 4, b1 = pb[b + 1] / 4;
+    if (b0 >= r1) break;
+    const uint32_t s0 = max(r0, b0), s1 = min(r1, b1);
+    if (s0 >= s1) continue;
+    init_counters<BITS, BLOCK>(a, S, tab);
+    const uint32_t pass_lo = b * a.W;
+    const uint32_t base = a.min_u + pass_lo;
+    HotBin hot;
+    count_tiles<ITEMS, BITS, BLOCK, KB, DEDUPE>(a, S, tab, hot, all + s0, threadIdx.x, BLOCK * V, s1 - s0, base,
+                                                pass_lo, (v4i)(int)(base - 1u));
+    if constexpr (BITS < 32 || DEDUPE) hot_flush_any<BITS, false>(hot, S, tab, a.carry, pass_lo);
+    __syncthreads();
+    if constexpr (BITS < 32) wrap_flush(tab, a.carry, pass_lo, threadIdx.x);
+    uint32_t* row = a.partial + ((size_t)blockIdx.x + b) * a.row_words;
+    for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) row[i] = S[i];
+    __syncthreads();   // S is zeroed again for the next bucket
+  }
+}
+
 // DEDUPE: wave-level aggregation of frequent values (RTCDF_FLAG_WAVE_DEDUPE,
 // int32 keys only), a separate instantiation so that the default counting
 // loop carries none of its instructions.
@@ -138,28 +236,19 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   // LDS: the counters, then (narrow forms) the wrap table: its slot mask, its
   // bins and its amounts.
   uint32_t* tab = S + a.row_words + 1;
-  for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) S[i] = 0u;
-  if constexpr (BITS < 32) {
-    if (threadIdx.x == 0) tab[-1] = a.wrap_slots - 1u;
-    for (uint32_t i = threadIdx.x; i < 2 * a.wrap_slots; i += BLOCK) tab[i] = i < a.wrap_slots ? kWrapEmpty : 0u;
+  if (a.pbound != nullptr) {
+    hist_partitioned<ITEMS, BITS, BLOCK, KB, DEDUPE>(a, S, tab);
+    return;
   }
-  __syncthreads();
+  init_counters<BITS, BLOCK>(a, S, tab);
 
   const uint32_t pass_lo = pass * a.W;
   const uint32_t base = a.min_u + pass_lo;   // key (as uint32) of bin 0 of this pass
   const uint32_t W = a.W;
 
-  // this pass's input: the whole array, or its bucket of the partitioned copy
+  // this pass's input: the whole array
   const int32_t* keys = a.keys;
-  uint32_t in_n4 = a.in_n4, in_per = a.in_per, in_head = a.in_head, in_tail = a.in_tail;
-  if (a.pbound != nullptr) {
-    const uint32_t b0 = a.pbound[pass], b1 = a.pbound[pass + 1];
-    keys = a.keys + b0;
-    in_n4 = (b1 - b0) / 4;
-    in_per = (in_n4 + a.G - 1) / a.G;
-    in_head = 0;
-    in_tail = 0;
-  }
+  const uint32_t in_n4 = a.in_n4, in_per = a.in_per, in_head = a.in_head, in_tail = a.in_tail;
 
   constexpr int V = ITEMS / 4;
   constexpr uint32_t VK = 16 / KB;   // keys per 16-byte vector
@@ -179,40 +268,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
     step = BLOCK * V;
     end = c0 + in_per < in_n4 ? c0 + in_per : in_n4;
   }
-  // Software pipelined: the loads of the next tile are in flight while the
-  // current one is counted.  Every load is issued unconditionally from an
-  // index clamped into [0, end), so that the compiler can wait for the
-  // current tile's loads alone rather than for all loads in flight; in the
-  // workgroup's last, partial tile the lanes past the end count `outside`.
-  if (end > 0) {
-    const uint32_t last = end - 1;
-    // first vector of the workgroup's tile (uniform: kept in a scalar register)
-    uint32_t tb = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t0 - threadIdx.x));
-    v4i cur[V];
-#pragma unroll
-    for (int j = 0; j < V; ++j) cur[j] = __builtin_nontemporal_load(&body[min(t0 + j * BLOCK, last)]);
-    while (tb < end) {
-      const uint32_t t1 = t0 + step;
-      v4i nxt[V];
-#pragma unroll
-      for (int j = 0; j < V; ++j) nxt[j] = __builtin_nontemporal_load(&body[min(t1 + j * BLOCK, last)]);
-      if (tb + V * BLOCK <= end) {
-#pragma unroll
-        for (int j = 0; j < V; ++j)
-          count_vec<BITS, KB, DEDUPE>(S, cur[j], true, outside, a.flip, base, W, a.carry, pass_lo, tab, hot,
-                                      a.min64, a.R);
-      } else {
-#pragma unroll
-        for (int j = 0; j < V; ++j)
-          count_vec<BITS, KB, DEDUPE>(S, cur[j], t0 + j * BLOCK < end, outside, a.flip, base, W, a.carry,
-                                      pass_lo, tab, hot, a.min64, a.R);
-      }
-#pragma unroll
-      for (int j = 0; j < V; ++j) cur[j] = nxt[j];
-      t0 = t1;
-      tb += step;
-    }
-  }
+  count_tiles<ITEMS, BITS, BLOCK, KB, DEDUPE>(a, S, tab, hot, body, t0, step, end, base, pass_lo, outside);
   // scalar head and tail keys (at most VK - 1 each), counted by chunk 0 / chunk G-1
   v4i e = outside;
   if (chunk == 0 && threadIdx.x < in_head) e.x = load_key<KB>(keys, threadIdx.x, a.flip, a.min64, a.R);
@@ -251,6 +307,10 @@ struct ReduceArgs {
   uint32_t* rsum;
   uint32_t* flags;   // cleared here for the local-CDF stage
   uint32_t R, W, G, row_words, carry_words, bits;
+  // Partition by pass (non-null): pass p's partial rows are prow[2p] and the
+  // prow[2p + 1] rows after it (the pieces of bucket p in the histogram
+  // workgroups' ranges, hist_partitioned), written by the partition.
+  const uint32_t* prow;
   // Prefix-maximum output (Alg. 3): workgroups nred and up write the initial
   // B[0, pm_n) = pm_fill and clear the pm_nck chunk maxima pm_M.  pm_out is
   // null otherwise.
@@ -296,7 +356,13 @@ __device__ __forceinline__ void reduce_block(const ReduceArgs& a, uint32_t (*red
   const uint32_t r0 = blockIdx.x * kReduceBins;   // first bin (passes hold W bins, W % 128 == 0)
   const uint32_t pass = r0 / a.W, w0 = (r0 - pass * a.W) / per;
   const size_t rs4 = a.row_words / 4;
-  const v4u* src = reinterpret_cast<const v4u*>(a.partial + (size_t)pass * a.G * a.row_words + w0) + q;
+  size_t row0 = (size_t)pass * a.G;
+  uint32_t G = a.G;   // rows of the pass
+  if (a.prow != nullptr) {
+    row0 = a.prow[2 * pass];
+    G = a.prow[2 * pass + 1];
+  }
+  const v4u* src = reinterpret_cast<const v4u*>(a.partial + row0 * a.row_words + w0) + q;
   uint32_t acc[4 * per];
 #pragma unroll
   for (uint32_t k = 0; k < 4 * per; ++k) acc[k] = 0;
@@ -321,7 +387,7 @@ __device__ __forceinline__ void reduce_block(const ReduceArgs& a, uint32_t (*red
     }
   };
   uint32_t g = rg;
-  const uint32_t G = a.G, NG = RG;
+  const uint32_t NG = RG;
   for (; g + 3 * NG < G; g += 4 * NG) {
     const v4u x0 = src[(size_t)g * rs4], x1 = src[(size_t)(g + NG) * rs4];
     const v4u x2 = src[(size_t)(g + 2 * NG) * rs4], x3 = src[(size_t)(g + 3 * NG) * rs4];
@@ -1192,6 +1258,7 @@ hipError_t launch_reduce(const Plan& p, uint8_t* ws, uint32_t* carry, int32_t* p
   a.row_words = p.row_words;
   a.carry_words = (uint32_t)p.carry_words;
   a.bits = p.bits;
+  a.prow = p.part ? reinterpret_cast<const uint32_t*>(ws + p.off_prow) : nullptr;
   // 128-bin blocks never straddle passes (W % 128 == 0), and a block's words
   // are whole 16-byte quads of 16-byte aligned rows
   if (p.W % kReduceBins != 0 || p.row_words % 4 != 0) return hipErrorInvalidValue;

@@ -50,6 +50,11 @@ struct PartArgs {
   uint32_t* tot;            // P
   uint32_t* bound;          // P + 1 padded bucket starts
   int32_t* part;            // the partitioned keys
+  // The histogram's partial rows of each bucket (its first row and their
+  // number, 2 words per bucket), for hist_grid histogram workgroups that cut
+  // the padded copy into equal ranges of 16-byte vectors (k_hist).
+  uint32_t hist_grid;
+  uint32_t* prow;
 };
 
 // Bucket of key k, or P for a key outside the range.
@@ -140,6 +145,13 @@ __global__ __launch_bounds__(kPartBlock) void k_part_scatter(PartArgs a) {
       a.bound[b] = start;
       const int32_t pad = (int32_t)(a.min_u - 1u);   // normalised value 2^32 - 1: outside every pass
       for (uint32_t q = len; q < ((len + 3u) & ~3u); ++q) a.part[start + q] = pad;
+      // workgroups j0..j1 of the histogram hold the bucket's vectors
+      // [s4, e4); their pieces are rows j + b
+      const uint32_t per4 = (total / 4 + a.hist_grid - 1) / a.hist_grid;
+      const uint32_t s4 = start / 4, e4 = (start + ((len + 3u) & ~3u)) / 4;
+      const uint32_t j0 = e4 > s4 ? s4 / per4 : 0u, j1 = e4 > s4 ? (e4 - 1) / per4 : 0u;
+      a.prow[2 * b] = j0 + b;
+      a.prow[2 * b + 1] = e4 > s4 ? j1 - j0 + 1 : 0u;
     }
     start += (len + 3u) & ~3u;
   }
@@ -226,6 +238,8 @@ hipError_t launch_partition(const Plan& p, const int32_t* keys, uint8_t* ws, hip
   a.tot = reinterpret_cast<uint32_t*>(ws + p.off_ptot);
   a.bound = reinterpret_cast<uint32_t*>(ws + p.off_pbound);
   a.part = reinterpret_cast<int32_t*>(ws + p.off_pkeys);
+  a.hist_grid = p.passes * p.G;
+  a.prow = reinterpret_cast<uint32_t*>(ws + p.off_prow);
   hipLaunchKernelGGL(k_part_count, dim3(a.G), dim3(kPartBlock), (size_t)a.P * a.SUB * 4, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

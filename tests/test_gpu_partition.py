@@ -155,10 +155,12 @@ def test_caller_workspace_graph_replay(r, forced):
         assert np.array_equal(out.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("dist", ["uniform", "normal"])
+@pytest.mark.parametrize("dist", ["uniform", "normal", "zipf", "all_equal"])
 def test_library_choice_full_size(r, dist):
     """n = 10^8, R = 2^22 (26 passes): the library partitions; every key is
-    checked against the oracle's counts by the streaming verifier."""
+    checked against the oracle's counts by the streaming verifier.  Zipf and
+    all-equal keys put nearly every key in one bucket, whose pieces then span
+    most of the histogram workgroups."""
     n, R = 10 ** 8, 1 << 22
     assert r.plan_info(n, 0, R)["partition_buckets"] > 0
     a = inputs.make_device(dist, n, 0, R, 13)
