@@ -3,10 +3,12 @@
 // When the range needs several LDS passes (R above the ~161792 bins of one
 // pass of 8-bit counters), the histogram of Alg. 5 as built here reads every
 // key once per pass.  The partition sorts the keys once by pass (bucket
-// b = x / W of the normalised value x) into a workspace copy, so that pass b's
-// histogram workgroups read bucket b alone: about 12 more bytes per key once
-// (read for the counts, read and write for the scatter) instead of 4 bytes per
-// key per extra pass.  It is a counting sort by bucket, in three launches:
+// b = x / W of the normalised value x) into a workspace copy, so that each key
+// is read once by the histogram, in its own pass: about 12 more bytes per key
+// once (read for the counts, read and write for the scatter) instead of 4
+// bytes per key per extra pass.  The histogram's workgroups cut the copy into
+// equal ranges whatever the bucket sizes (k_hist).  It is a counting sort by
+// bucket, in three launches:
 //   k_part_count    workgroup g counts the keys of its slice of the input per
 //                   bucket in LDS and writes the column cnt[b * G + g].
 //   k_part_scan     one workgroup per bucket: exclusive scan of cnt[b * G + .]
@@ -17,8 +19,9 @@
 //                   grouped by bucket in LDS and written as runs at
 //                   start[b] + cnt[b * G + g] + (keys of the bucket in earlier
 //                   tiles).  Workgroup 0 writes the bucket starts for the
-//                   histogram and fills the padding with a key that lies
-//                   outside every pass.
+//                   histogram, fills the padding with a key that lies
+//                   outside every pass, and writes each pass's partial-row
+//                   range for the reduction.
 // Keys outside [minVal, maxVal) go to no bucket (their output is unspecified,
 // as on every path) and never index memory out of bounds.
 #include <hip/hip_runtime.h>
