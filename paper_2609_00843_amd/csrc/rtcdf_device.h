@@ -301,9 +301,15 @@ __device__ __forceinline__ uint32_t shl1(uint32_t s) {
 // if it has kDedupeMin or more copies they are added to the hot-bin register
 // at once and skip their LDS atomics (a frequent value would otherwise put
 // many lanes of one atomic on one LDS word, and wrap 8-bit counters).
-template <int BITS, bool PAD = false, bool DEDUPE = false>
+// SPREAD (32-bit counters, few bins): bin x has 2^sub_log copies at words
+// (x << sub_log) + c, and lane l adds into copy l mod 2^sub_log, so lanes
+// that hit one bin in the same atomic mostly hit different words; the copies
+// are summed when the counters are written out.
+template <int BITS, bool PAD = false, bool DEDUPE = false, bool SPREAD = false>
 __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32_t W,
-                                       uint32_t* carry, uint32_t pass_lo, uint32_t* tab, HotBin& hot) {
+                                       uint32_t* carry, uint32_t pass_lo, uint32_t* tab, HotBin& hot,
+                                       uint32_t sub_log = 0) {
+  static_assert(!SPREAD || (BITS == 32 && !PAD && !DEDUPE), "copies of 32-bit unpadded counters only");
   uint32_t x0 = (uint32_t)k.x - base, x1 = (uint32_t)k.y - base;
   uint32_t x2 = (uint32_t)k.z - base, x3 = (uint32_t)k.w - base;
   const uint32_t lead = (uint32_t)__builtin_amdgcn_readfirstlane((int)x0);
@@ -325,7 +331,7 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
           add_u16(S, lead, c, carry, pass_lo);   // 16-bit form without a wrap table
         }
       } else if (lane_id() == (uint32_t)(__ffsll((unsigned long long)active) - 1)) {
-        atomicAdd(&S[PAD ? pad32(lead) : lead], c);
+        atomicAdd(&S[PAD ? pad32(lead) : (SPREAD ? lead << sub_log : lead)], c);
       }
     }
     return;
@@ -385,6 +391,12 @@ __device__ __forceinline__ void count4(uint32_t* S, v4i k, uint32_t base, uint32
         if (w3) fix_packed<BITS>(o3, x3, 1u, tab, carry, pass_lo);
       }
     }
+  } else if constexpr (SPREAD) {
+    const uint32_t c = lane_id() & ((1u << sub_log) - 1u);
+    if (x0 < W) atomicAdd(&S[(x0 << sub_log) | c], 1u);
+    if (x1 < W) atomicAdd(&S[(x1 << sub_log) | c], 1u);
+    if (x2 < W) atomicAdd(&S[(x2 << sub_log) | c], 1u);
+    if (x3 < W) atomicAdd(&S[(x3 << sub_log) | c], 1u);
   } else {
     const uint32_t y0 = PAD ? pad32(x0) : x0, y1 = PAD ? pad32(x1) : x1;
     const uint32_t y2 = PAD ? pad32(x2) : x2, y3 = PAD ? pad32(x3) : x3;

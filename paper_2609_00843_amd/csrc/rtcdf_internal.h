@@ -90,6 +90,7 @@ struct Plan {
   uint32_t G;            // workgroups (input chunks) per pass, multiple of 8
   uint32_t row_words;    // 32-bit words per partial row (W * bits / 32)
   uint32_t wrap_slots;   // narrow counters: slots of the histogram's LDS wrap table
+  uint32_t sub_log;      // 32-bit counters: 2^sub_log LDS copies of each bin (0: one)
   uint32_t hist_block;   // threads per histogram workgroup
   uint32_t hist_interleave;  // 1: tiles dealt round-robin to chunks; 0: contiguous chunks
   uint32_t in_head;      // keys before the 16-byte aligned input body

@@ -48,6 +48,7 @@ struct HistArgs {
   uint32_t min_u, W, passes, G, row_words, R;
   int64_t min64;         // int64 keys: normalised value x = key - min64 (min_u is 0)
   uint32_t wrap_slots;   // narrow forms: slots of the LDS wrap table (a power of two)
+  uint32_t sub_log;      // 32-bit counters: 2^sub_log LDS copies per bin (count4's SPREAD)
   uint32_t interleave;
   uint32_t* partial;
   uint32_t* carry;
@@ -76,16 +77,17 @@ __device__ __forceinline__ uint32_t norm64(uint32_t lo, uint32_t hi, int64_t min
 // pass's first bin) and padded with two keys outside every pass.  Lanes
 // without a valid vector count `outside` (every group, so that the wave-wide
 // ballots inside count4 see every lane).
-template <int BITS, int KB, bool DEDUPE = false>
+template <int BITS, int KB, bool DEDUPE = false, bool SPREAD = false>
 __device__ __forceinline__ void count_vec(uint32_t* S, v4i v, bool valid, v4i outside, uint32_t flip,
                                           uint32_t base, uint32_t W, uint32_t* carry, uint32_t pass_lo,
-                                          uint32_t* tab, HotBin& hot, int64_t min64 = 0, uint32_t R = 0) {
+                                          uint32_t* tab, HotBin& hot, int64_t min64 = 0, uint32_t R = 0,
+                                          uint32_t sub_log = 0) {
   if constexpr (KB == 8) {
     const v4i g = {(int)norm64((uint32_t)v.x, (uint32_t)v.y, min64, R),
                    (int)norm64((uint32_t)v.z, (uint32_t)v.w, min64, R), outside.x, outside.x};
-    count4<BITS>(S, valid ? g : outside, base, W, carry, pass_lo, tab, hot);
+    count4<BITS, false, false, SPREAD>(S, valid ? g : outside, base, W, carry, pass_lo, tab, hot, sub_log);
   } else if constexpr (KB == 4) {
-    count4<BITS, false, DEDUPE>(S, valid ? v : outside, base, W, carry, pass_lo, tab, hot);
+    count4<BITS, false, DEDUPE, SPREAD>(S, valid ? v : outside, base, W, carry, pass_lo, tab, hot, sub_log);
   } else if constexpr (KB == 2) {
     const uint32_t f = flip | (flip << 16);
     const uint32_t w[4] = {(uint32_t)v.x ^ f, (uint32_t)v.y ^ f, (uint32_t)v.z ^ f, (uint32_t)v.w ^ f};
@@ -93,7 +95,7 @@ __device__ __forceinline__ void count_vec(uint32_t* S, v4i v, bool valid, v4i ou
     for (int h = 0; h < 2; ++h) {
       const v4i g = {(int)(w[2 * h] & 0xffffu), (int)(w[2 * h] >> 16), (int)(w[2 * h + 1] & 0xffffu),
                      (int)(w[2 * h + 1] >> 16)};
-      count4<BITS>(S, valid ? g : outside, base, W, carry, pass_lo, tab, hot);
+      count4<BITS, false, false, SPREAD>(S, valid ? g : outside, base, W, carry, pass_lo, tab, hot, sub_log);
     }
   } else {
     const uint32_t f = flip * 0x01010101u;
@@ -102,7 +104,7 @@ __device__ __forceinline__ void count_vec(uint32_t* S, v4i v, bool valid, v4i ou
     for (int h = 0; h < 4; ++h) {
       const v4i g = {(int)(w[h] & 0xffu), (int)((w[h] >> 8) & 0xffu), (int)((w[h] >> 16) & 0xffu),
                      (int)(w[h] >> 24)};
-      count4<BITS>(S, valid ? g : outside, base, W, carry, pass_lo, tab, hot);
+      count4<BITS, false, false, SPREAD>(S, valid ? g : outside, base, W, carry, pass_lo, tab, hot, sub_log);
     }
   }
 }
@@ -127,7 +129,7 @@ __device__ __forceinline__ int32_t load_key(const int32_t* keys, size_t i, uint3
 // index clamped into [0, end), so that the compiler can wait for the current
 // tile's loads alone rather than for all loads in flight; in the workgroup's
 // last, partial tile the lanes past the end count `outside`.
-template <int ITEMS, int BITS, int BLOCK, int KB, bool DEDUPE>
+template <int ITEMS, int BITS, int BLOCK, int KB, bool DEDUPE, bool SPREAD = false>
 __device__ __forceinline__ void count_tiles(const HistArgs& a, uint32_t* S, uint32_t* tab, HotBin& hot,
                                             const v4i* body, uint32_t t0, uint32_t step, uint32_t end,
                                             uint32_t base, uint32_t pass_lo, v4i outside) {
@@ -148,13 +150,13 @@ __device__ __forceinline__ void count_tiles(const HistArgs& a, uint32_t* S, uint
     if (tb + V * BLOCK <= end) {
 #pragma unroll
       for (int j = 0; j < V; ++j)
-        count_vec<BITS, KB, DEDUPE>(S, cur[j], true, outside, a.flip, base, W, a.carry, pass_lo, tab, hot,
-                                    a.min64, a.R);
+        count_vec<BITS, KB, DEDUPE, SPREAD>(S, cur[j], true, outside, a.flip, base, W, a.carry, pass_lo, tab,
+                                            hot, a.min64, a.R, a.sub_log);
     } else {
 #pragma unroll
       for (int j = 0; j < V; ++j)
-        count_vec<BITS, KB, DEDUPE>(S, cur[j], t0 + j * BLOCK < end, outside, a.flip, base, W, a.carry,
-                                    pass_lo, tab, hot, a.min64, a.R);
+        count_vec<BITS, KB, DEDUPE, SPREAD>(S, cur[j], t0 + j * BLOCK < end, outside, a.flip, base, W, a.carry,
+                                            pass_lo, tab, hot, a.min64, a.R, a.sub_log);
     }
 #pragma unroll
     for (int j = 0; j < V; ++j) cur[j] = nxt[j];
@@ -163,11 +165,12 @@ __device__ __forceinline__ void count_tiles(const HistArgs& a, uint32_t* S, uint
   }
 }
 
-// Zero LDS counters and (narrow forms) an empty wrap table: its slot mask,
-// its bins and its amounts.
-template <int BITS, int BLOCK>
+// Zero LDS counters (all copies with SPREAD) and (narrow forms) an empty wrap
+// table: its slot mask, its bins and its amounts.
+template <int BITS, int BLOCK, bool SPREAD = false>
 __device__ __forceinline__ void init_counters(const HistArgs& a, uint32_t* S, uint32_t* tab) {
-  for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) S[i] = 0u;
+  const uint32_t words = SPREAD ? a.row_words << a.sub_log : a.row_words;
+  for (uint32_t i = threadIdx.x; i < words; i += BLOCK) S[i] = 0u;
   if constexpr (BITS < 32) {
     if (threadIdx.x == 0) tab[-1] = a.wrap_slots - 1u;
     for (uint32_t i = threadIdx.x; i < 2 * a.wrap_slots; i += BLOCK) tab[i] = i < a.wrap_slots ? kWrapEmpty : 0u;
@@ -218,10 +221,24 @@ __device__ __forceinline__ void hist_partitioned(const HistArgs& a, uint32_t* S,
   }
 }
 
+// Counter i of the workgroup's LDS histogram: the sum of its copies with
+// SPREAD, else the word itself.
+template <bool SPREAD>
+__device__ __forceinline__ uint32_t counter_sum(const HistArgs& a, const uint32_t* S, uint32_t i) {
+  if constexpr (SPREAD) {
+    uint32_t t = 0;
+    for (uint32_t c = 0; c < (1u << a.sub_log); ++c) t += S[(i << a.sub_log) + c];
+    return t;
+  } else {
+    return S[i];
+  }
+}
+
 // DEDUPE: wave-level aggregation of frequent values (RTCDF_FLAG_WAVE_DEDUPE,
 // int32 keys only), a separate instantiation so that the default counting
-// loop carries none of its instructions.
-template <int ITEMS, int BITS, int BLOCK, int KB = 4, bool DEDUPE = false>
+// loop carries none of its instructions.  SPREAD: LDS copies of the 32-bit
+// counters (count4), summed into the partial row or the merge rows.
+template <int ITEMS, int BITS, int BLOCK, int KB = 4, bool DEDUPE = false, bool SPREAD = false>
 __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   // The planner's LDS budget: kLdsBytes per 1024 threads (one workgroup per
   // compute unit at 1024 threads, two at 512, four at 256).  A static array
@@ -236,11 +253,13 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
   // LDS: the counters, then (narrow forms) the wrap table: its slot mask, its
   // bins and its amounts.
   uint32_t* tab = S + a.row_words + 1;
-  if (a.pbound != nullptr) {
-    hist_partitioned<ITEMS, BITS, BLOCK, KB, DEDUPE>(a, S, tab);
-    return;
+  if constexpr (!SPREAD) {
+    if (a.pbound != nullptr) {
+      hist_partitioned<ITEMS, BITS, BLOCK, KB, DEDUPE>(a, S, tab);
+      return;
+    }
   }
-  init_counters<BITS, BLOCK>(a, S, tab);
+  init_counters<BITS, BLOCK, SPREAD>(a, S, tab);
 
   const uint32_t pass_lo = pass * a.W;
   const uint32_t base = a.min_u + pass_lo;   // key (as uint32) of bin 0 of this pass
@@ -268,13 +287,14 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
     step = BLOCK * V;
     end = c0 + in_per < in_n4 ? c0 + in_per : in_n4;
   }
-  count_tiles<ITEMS, BITS, BLOCK, KB, DEDUPE>(a, S, tab, hot, body, t0, step, end, base, pass_lo, outside);
+  count_tiles<ITEMS, BITS, BLOCK, KB, DEDUPE, SPREAD>(a, S, tab, hot, body, t0, step, end, base, pass_lo,
+                                                      outside);
   // scalar head and tail keys (at most VK - 1 each), counted by chunk 0 / chunk G-1
   v4i e = outside;
   if (chunk == 0 && threadIdx.x < in_head) e.x = load_key<KB>(keys, threadIdx.x, a.flip, a.min64, a.R);
   if (chunk == a.G - 1 && threadIdx.x < in_tail)
     e.y = load_key<KB>(keys, in_head + VK * (size_t)in_n4 + threadIdx.x, a.flip, a.min64, a.R);
-  if (threadIdx.x < 64) count4<BITS>(S, e, base, W, a.carry, pass_lo, tab, hot);
+  if (threadIdx.x < 64) count4<BITS, false, false, SPREAD>(S, e, base, W, a.carry, pass_lo, tab, hot, a.sub_log);
   if constexpr (BITS < 32 || DEDUPE) hot_flush_any<BITS, false>(hot, S, tab, a.carry, pass_lo);
   __syncthreads();
   if constexpr (BITS < 32) wrap_flush(tab, a.carry, pass_lo, threadIdx.x);
@@ -285,8 +305,10 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
     // partial row; the rows spread the atomics over more addresses.
     const uint32_t par = a.carry[kFastPar] & 1u;
     uint32_t* acc = a.carry + par * kFastRegionWords + (blockIdx.x % a.merge) * a.merge_stride;
-    for (uint32_t i = threadIdx.x; i < a.R; i += BLOCK)
-      if (S[i] != 0u) atomicAdd(&acc[i], S[i]);
+    for (uint32_t i = threadIdx.x; i < a.R; i += BLOCK) {
+      const uint32_t v = counter_sum<SPREAD>(a, S, i);
+      if (v != 0u) atomicAdd(&acc[i], v);
+    }
     if (blockIdx.x == 0) {   // the previous sort's region: zero for the next sort
       uint32_t* other = a.carry + (par ^ 1u) * kFastRegionWords;
       for (uint32_t i = threadIdx.x; i < kFastRegionWords; i += BLOCK) other[i] = 0u;
@@ -295,7 +317,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist(HistArgs a) {
     return;
   }
   uint32_t* row = a.partial + ((size_t)pass * a.G + chunk) * a.row_words;
-  for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) row[i] = S[i];
+  for (uint32_t i = threadIdx.x; i < a.row_words; i += BLOCK) row[i] = counter_sum<SPREAD>(a, S, i);
 }
 
 // ------------------------------------------------------------------ reduction
@@ -1134,12 +1156,15 @@ __global__ void k_clear(uint32_t* p, size_t words) {
     p[i] = 0u;
 }
 
-template <int ITEMS, int BITS, int BLOCK, int KB = 4, bool DEDUPE = false>
+template <int ITEMS, int BITS, int BLOCK, int KB = 4, bool DEDUPE = false, bool SPREAD = false>
 hipError_t launch_hist_t(const Plan& p, const HistArgs& a, hipStream_t s) {
-  // the counters (and the narrow forms' wrap table) fit the static LDS array
-  const size_t lds = ((size_t)p.row_words + (BITS < 32 ? 1 + 2 * (size_t)p.wrap_slots : 0)) * 4;
+  // the counters (their copies with SPREAD; the narrow forms' wrap table) fit
+  // the static LDS array
+  const size_t words = SPREAD ? (size_t)p.row_words << p.sub_log : (size_t)p.row_words;
+  const size_t lds = (words + (BITS < 32 ? 1 + 2 * (size_t)p.wrap_slots : 0)) * 4;
   if (lds > kLdsBytes / (1024 / BLOCK)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_hist<ITEMS, BITS, BLOCK, KB, DEDUPE>), dim3(p.passes * p.G), dim3(BLOCK), 0, s, a);
+  if (SPREAD && (p.part || p.sub_log > 4)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_hist<ITEMS, BITS, BLOCK, KB, DEDUPE, SPREAD>), dim3(p.passes * p.G), dim3(BLOCK), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1148,6 +1173,18 @@ hipError_t launch_hist_items(const Plan& p, const HistArgs& a, hipStream_t s) {
   // 8- and 16-bit keys: one 16-byte vector (16 or 8 keys) per thread per step
   // (4-bit counters serve int32 keys only)
   // (int64 keys: two 16-byte vectors, four keys, per thread per step)
+  if constexpr (BITS == 32) {
+    if (p.sub_log > 0 && !p.dedupe) {   // LDS copies of the counters
+      if (p.kb == 2) return launch_hist_t<4, 32, BLOCK, 2, false, true>(p, a, s);
+      if (p.kb == 1) return launch_hist_t<4, 32, BLOCK, 1, false, true>(p, a, s);
+      if (p.kb == 8) return launch_hist_t<8, 32, BLOCK, 8, false, true>(p, a, s);
+      switch (p.items) {
+        case 4: return launch_hist_t<4, 32, BLOCK, 4, false, true>(p, a, s);
+        case 8: return launch_hist_t<8, 32, BLOCK, 4, false, true>(p, a, s);
+        default: return launch_hist_t<16, 32, BLOCK, 4, false, true>(p, a, s);
+      }
+    }
+  }
   if constexpr (BITS == 4) {
     if (p.kb != 4) return hipErrorInvalidValue;
   } else {
@@ -1216,6 +1253,7 @@ hipError_t launch_hist(const Plan& p, const int32_t* keys, uint8_t* ws, uint32_t
   a.G = p.G;
   a.row_words = p.row_words;
   a.wrap_slots = p.wrap_slots;
+  a.sub_log = p.sub_log;
   a.R = p.R;
   a.partial = reinterpret_cast<uint32_t*>(ws + p.off_partial);
   a.carry = carry;

@@ -120,6 +120,24 @@ def test_full_size(r, name):
     v.end(n)
 
 
+@pytest.mark.parametrize("sub", [0, 1, 4])
+@pytest.mark.parametrize("name,lo,hi", [("uint8", 0, 256), ("int8", -128, 128), ("int16", -1000, 1048),
+                                        ("uint16", 7, 1500)])
+def test_counter_copies(r, monkeypatch, sub, name, lo, hi):
+    """LDS copies of the 32-bit counters (none, 2 or 16 per bin; 8-bit keys
+    take 8 by default) on narrow keys: single-tile fast path and staged path,
+    ragged n with head and tail keys, skewed and uniform values."""
+    npt = TYPES[name][0]
+    monkeypatch.setenv("RTCDF_DEV_HIST_SPREAD", str(sub))
+    rng = np.random.default_rng(sub * 7 + len(name))
+    for fast in ("1", "0"):
+        monkeypatch.setenv("RTCDF_DEV_FAST", fast)
+        for n in (300_007, 1_000_001):
+            x = rng.integers(lo, hi, size=n)
+            x[: n // 3] = lo + (hi - lo) // 3            # a third of the keys on one value
+            _check(r, x.astype(npt), npt, lo, hi, pin=3, pout=5)
+
+
 def test_sort_dispatches_by_dtype(r):
     """rtcdf.sort takes narrow key tensors too (through rtcdf_sort_keys)."""
     rng = np.random.default_rng(2)
@@ -199,6 +217,19 @@ def test_int64_in_place_and_configs(r):
     _check64(r, A, lo, lo + (1 << 17), inplace=True)
     for T, items, bpt in ((128, 4, 4), (1024, 8, 2), (8192, 16, 1), (32768, 4, 1)):
         _check64(r, A, lo, lo + (1 << 17), cfg=r.make_config(T, items, bpt), pin=1, pout=0)
+
+
+@pytest.mark.parametrize("sub", [1, 4])
+def test_int64_counter_copies(r, monkeypatch, sub):
+    """LDS copies of the 32-bit counters with int64 keys (two keys per
+    16-byte vector), fast and staged paths."""
+    monkeypatch.setenv("RTCDF_DEV_HIST_SPREAD", str(sub))
+    rng = np.random.default_rng(sub)
+    lo, R = -(1 << 40) + 11, 1000
+    for fast in ("1", "0"):
+        monkeypatch.setenv("RTCDF_DEV_FAST", fast)
+        A = rng.integers(0, R, size=500_003).astype(np.int64) + np.int64(lo)
+        _check64(r, A, lo, lo + R, pin=1, pout=0)
 
 
 def test_int64_full_size(r):

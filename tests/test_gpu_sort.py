@@ -188,6 +188,20 @@ def test_forced_counter_width(r, monkeypatch, bits, dist, R):
     _run(r, A, 9, 9 + R)
 
 
+@pytest.mark.parametrize("sub", [1, 4])
+@pytest.mark.parametrize("fast", [1, 0])
+@pytest.mark.parametrize("dist,R", [("uniform", 100), ("all_equal", 2048), ("zipf", 1500), ("normal", 5000)])
+def test_counter_copies(r, monkeypatch, sub, fast, dist, R):
+    """LDS copies of the 32-bit counters (2^sub per bin, lane-selected, summed
+    when written out) give the same output on the single-tile fast path (the
+    merge rows) and the staged path (partial rows), ragged n, input and output
+    off their 16-byte alignment."""
+    monkeypatch.setenv("RTCDF_DEV_HIST_SPREAD", str(sub))
+    monkeypatch.setenv("RTCDF_DEV_FAST", str(fast))
+    A = inputs.make(dist, 1_000_003, -5, -5 + R, inputs.case_seed(5, R))
+    _run(r, A, -5, -5 + R, pin=1, pout=2)
+
+
 def test_plan_counter_width_choice(r):
     """The plan takes 32-bit counters where they need no more passes, else
     8-bit ones."""
