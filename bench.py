@@ -863,9 +863,10 @@ def main():
     for (lr, d), a, b in zip(cases, ins, outs):
         R = 1 << lr
         info = rtcdf.plan_info(N, MIN_VAL, MIN_VAL + R, keys_in=a, keys_out=b)
-        # instantiation names: the key width (4 bytes), then the wave-aggregation switch
+        # instantiation names: the key width (4 bytes), the wave-aggregation
+        # switch, then the LDS-copies switch (int32 keys keep one copy)
         hist_name = (f"k_hist<{info['items_per_thread']}, {info['counter_bits']}, {info['hist_threads']}, 4, "
-                     f"{'true' if info['hist_dedupe'] else 'false'}>")
+                     f"{'true' if info['hist_dedupe'] else 'false'}, false>")
         rtcdf.profile_collect()
         rtcdf.profile_enable(True)
         for _ in range(args.steps):
