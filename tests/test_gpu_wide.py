@@ -134,7 +134,7 @@ def test_int32_wide_workspace_in_place(r):
     need = r.workspace_bytes(n, lo, lo + R, keys_out=a)
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     with pytest.raises(r.RtcdfError) as e:
-        r.sort_ws(a, a, lo, lo + R, ws[:need - 256])
+        r.sort_ws(a, a, lo, lo + R, ws[:need - 1])
     assert e.value.status == r.WORKSPACE_TOO_SMALL
     r.sort_ws(a, a, lo, lo + R, ws)
     torch.cuda.synchronize()
