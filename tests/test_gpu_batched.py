@@ -193,8 +193,9 @@ def test_skipped_descriptors(r):
 
 
 def test_graph_replay(r):
-    """Replays reproduce the eager result, chunked segments included (their
-    per-tile state is reset by every launch)."""
+    """Replays reproduce the eager result, with two segments far above their
+    share of the batch among 64 ordinary ones (the ordering kernel resets
+    the queue at every launch)."""
     segs = inputs.batched_segments(64, seed=77)
     specs = [(s["n"], s["minVal"], s["maxVal"] - s["minVal"], s["dist"]) for s in segs]
     specs += [(1_500_000, -40, 65536, "uniform"), (900_001, 9, 300, "all_equal")]

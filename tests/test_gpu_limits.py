@@ -109,8 +109,9 @@ def test_uint8_near_2pow32(r):
 
 
 def test_batched_segment_near_2pow32(r):
-    """One batch segment of 2^32 - 1 keys (two range tiles, each split into
-    512 chunks over the workgroups) beside a small one."""
+    """One batch segment of 2^32 - 1 keys (two range tiles, each one
+    workgroup's item end to end: segments are not split over workgroups)
+    beside a small one; the error word of timed-out waits stays zero."""
     n, lo, R = N32, -77, 40000
     tail = [(lo + R - 30, 2), (lo + R - 29, 1), (lo + R - 1, 80)]
     _say(f"batched segment n={n} R={R}")
