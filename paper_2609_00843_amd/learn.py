@@ -286,7 +286,7 @@ def evaluate_retimed(specs, model_path: str, warmup: int = 10, reps: int = 30, r
                      tune_reps: int = 5, log=print):
     """Held-out evaluation with every time measured in this run, on the GPU.
     Per array (generated on the device from its spec):
-      1. exhaustive autotuning of the whole grid (the judge of regret);
+      1. exhaustive autotuning of the whole grid (the reference that regret is measured against);
       2. the library's LEARNED decision from a cold decision cache (its pick
          time measured, including any exhaustive fallback), and the time of
          the same call once the decision is cached;
