@@ -324,6 +324,51 @@ def test_two_streams(r):
         assert np.array_equal(ob.cpu().numpy(), wb)
 
 
+def test_host_threads(r):
+    """Four host threads, each sorting on a stream of its own (the library's
+    per-(device, stream) workspaces and fast-path areas, and its device and
+    kernel-attribute caches, under concurrent calls; the binding releases
+    the interpreter lock in every library call): the single-tile fast path,
+    the staged path with 8-bit counters, two LDS passes and the partition by
+    pass, each thread in its own order, three rounds.  Every output equals
+    the oracle's."""
+    import threading
+    specs = [("uniform", 1_000_003, 0, 1000, 11), ("normal", 2_000_001, -5, 70_000, 12),
+             ("uniform", 1_500_000, 7, 7 + (1 << 18), 13), ("uniform", 3_000_000, 0, 1 << 22, 14)]
+    cases = []
+    for dist, n, lo, hi, seed in specs:
+        A = inputs.make(dist, n, lo, hi, seed)
+        _, t = _to_dev(A)
+        cases.append((t, lo, hi, oracle.sort(A, lo, hi)))
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream()
+            order = [(k + j) % len(cases) for j in range(len(cases))]
+            for _ in range(3):
+                outs = []
+                with torch.cuda.stream(s):
+                    for i in order:
+                        t, lo, hi, _ = cases[i]
+                        outs.append((i, r.sort(t, lo, hi)))
+                s.synchronize()
+                for i, o in outs:
+                    if not np.array_equal(o.cpu().numpy(), cases[i][3]):
+                        errors.append((k, i))
+        except Exception as e:   # reported by the main thread
+            errors.append((k, repr(e)))
+
+    _say("four host threads, one stream each")
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+
+
 def test_empty_and_errors(r):
     t = torch.empty(0, dtype=torch.int32, device="cuda")
     assert r.sort(t, 0, 10).numel() == 0
