@@ -112,6 +112,61 @@ def test_learned_sorts_do_not_wait_for_the_pick(r):
         r.clear_pick_cache()
 
 
+def test_learned_host_threads(r):
+    """LEARNED mode under four host threads, each on a stream of its own,
+    sorting the same four buffers in different orders (so that threads meet
+    on one pick-cache entry: a pick in flight, a decision being made by
+    another thread, the exhaustive fallback for the Zipf keys, which the
+    network does not judge), three rounds each.  Every output equals the
+    oracle's, whichever configuration each sort ran with."""
+    import threading
+    if not os.path.exists(MODEL):
+        pytest.skip("no shipped model")
+    specs = [("uniform", 2_000_003, -5, 1 << 13), ("zipf", 1_000_001, 0, 1 << 16),
+             ("normal", 1_500_000, 3, 5000), ("all_equal", 1_048_576, 0, 200)]
+    cases = []
+    for i, (dist, n, lo, R) in enumerate(specs):
+        A = inputs.make(dist, n, lo, lo + R, inputs.case_seed(73, i))
+        cases.append((torch.from_numpy(A).cuda(), lo, lo + R, oracle.sort(A, lo, lo + R)))
+    torch.cuda.synchronize()
+    r.load_model(MODEL)
+    old = r.get_config_mode()
+    errors = []
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream()
+            order = [(k + j) % len(cases) for j in range(len(cases))]
+            for _ in range(3):
+                outs = []
+                with torch.cuda.stream(s):
+                    for i in order:
+                        a, lo, hi, _ = cases[i]
+                        outs.append((i, r.sort(a, lo, hi)))
+                s.synchronize()
+                for i, o in outs:
+                    if not np.array_equal(o.cpu().numpy(), cases[i][3]):
+                        errors.append((k, i))
+        except Exception as e:   # reported by the main thread
+            errors.append((k, repr(e)))
+
+    try:
+        r.set_config_mode(r.CONFIG_LEARNED)
+        r.clear_pick_cache()
+        _say("learned mode, four host threads")
+        threads = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        torch.cuda.synchronize()
+    finally:
+        r.set_config_mode(old)
+        r.unload_model()
+        r.clear_pick_cache()
+    assert not errors, errors
+
+
 def test_learned_gain_over_static(r):
     """What the trained network (with its exhaustive fallback for sketches it
     does not trust) gains over the method without it: the first 60 arrays of
