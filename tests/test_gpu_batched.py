@@ -170,6 +170,45 @@ def test_segment_configs(r):
         _check(arrays, specs, pairs, dout, offs)
 
 
+def test_two_host_threads(r):
+    """Two host threads, each launching a batch of its own three times on a
+    stream and with a workspace of its own (two persistent launches that may
+    share the GPU; neither waits for the other's work items): both batches
+    equal the oracle's sorts, guard words untouched, error words zero."""
+    import threading
+    batches = []
+    for seed in (5, 6):
+        segs = inputs.batched_segments(48, seed=100 + seed)
+        specs = [(s["n"], s["minVal"], s["maxVal"] - s["minVal"], s["dist"]) for s in segs]
+        arrays, pairs, din, dout, offs = _build(specs, seed)
+        d, bounds, k = r.make_segments(pairs)
+        ws = torch.empty(r.batched_workspace_bytes(k, bounds), dtype=torch.uint8, device="cuda")
+        batches.append((arrays, specs, pairs, din, dout, offs, d, bounds, k, ws))
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(j):
+        try:
+            _, _, _, _, _, _, d, bounds, k, ws = batches[j]
+            s = torch.cuda.Stream()
+            for _ in range(3):
+                r.sort_batched(d, k, bounds, ws, stream=s)
+            s.synchronize()
+        except Exception as e:   # reported by the main thread
+            errors.append((j, repr(e)))
+
+    _say("two host threads, one batch each")
+    threads = [threading.Thread(target=work, args=(j,)) for j in range(2)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for arrays, specs, pairs, din, dout, offs, d, bounds, k, ws in batches:
+        assert _error_word(ws) == 0
+        _check(arrays, specs, pairs, dout, offs)
+
+
 def test_skipped_descriptors(r):
     """range 0 or above the bounds, and NULL pointers, are skipped."""
     import ctypes
