@@ -369,6 +369,45 @@ def test_host_threads(r):
     assert not errors, errors
 
 
+def test_host_threads_one_stream(r):
+    """Three host threads sorting on one stream (the current stream of each,
+    the device's default one), so that their sorts share one cached workspace
+    and fast-path area: problems of growing workspace size in different
+    orders, so the workspace grows (after a wait for that stream) while
+    another thread's sorts are queued on it.  Every output equals the
+    oracle's."""
+    import threading
+    r.release_workspaces()
+    specs = [("uniform", 300_001, 0, 1000, 21), ("normal", 1_000_003, -9, 1 << 16, 22),
+             ("uniform", 2_000_000, 5, 5 + (1 << 18), 23), ("uniform", 4_000_000, 0, 1 << 22, 24)]
+    cases = []
+    for dist, n, lo, hi, seed in specs:
+        A = inputs.make(dist, n, lo, hi, seed)
+        _, t = _to_dev(A)
+        cases.append((t, lo, hi, oracle.sort(A, lo, hi)))
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(k):
+        try:
+            order = list(range(len(cases))) if k == 0 else [(k + j) % len(cases) for j in range(len(cases))][::-1]
+            outs = [(i, r.sort(cases[i][0], cases[i][1], cases[i][2])) for _ in range(2) for i in order]
+            torch.cuda.current_stream().synchronize()
+            for i, o in outs:
+                if not np.array_equal(o.cpu().numpy(), cases[i][3]):
+                    errors.append((k, i))
+        except Exception as e:   # reported by the main thread
+            errors.append((k, repr(e)))
+
+    _say("three host threads, one stream")
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(3)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+
+
 def test_empty_and_errors(r):
     t = torch.empty(0, dtype=torch.int32, device="cuda")
     assert r.sort(t, 0, 10).numel() == 0
