@@ -532,15 +532,17 @@ __global__ __launch_bounds__(kScanBlock) void k_tilescan(ScanArgs a) {
     // workgroup derives the same assignment of the grid to tiles, one
     // workgroup per tile plus the spare ones in proportion to the number of
     // output chunks that start inside each tile (all-equal keys put every
-    // chunk in one tile).  Tile totals first (nb, a power of two, block totals
-    // per tile), then thread i handles tile i.
+    // chunk in one tile).  Tile totals first (nb block totals per tile), then
+    // thread i handles tile i.
     const uint32_t nb = a.T / kReduceBins, nred = (a.R + kReduceBins - 1) / kReduceBins;
     tiles[tid] = 0u;
     __syncthreads();
     for (uint32_t k0 = 0; k0 < nred; k0 += kScanBlock) {
       const uint32_t k = k0 + tid;
       const uint32_t v = k < nred ? a.rsum[k] : 0u;
-      if (nb >= 64) {   // a wave's 64 totals belong to one tile
+      if ((nb & 63u) == 0u) {   // a wave's 64 totals then belong to one tile
+        // (T a multiple of 8192; any other multiple of 128 puts tile
+        // boundaries inside waves, so each total is added on its own)
         const uint32_t ws = wave_sum(v);
         if (lane_id() == 0 && k < nred) atomicAdd(&tiles[k / nb], ws);
       } else if (k < nred) {

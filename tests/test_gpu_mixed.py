@@ -1,0 +1,162 @@
+"""GPU parity over a seeded random mix of problems: each case draws every axis
+at once -- key type (int32, int64, 16- and 8-bit, signed or not), n (1 to
+5 x 10^5), the range R (1 to 2^23 for int32 and int64 keys, any window of a
+narrow type), minVal anywhere in the type (its extremes included), the key
+distribution, the input and output offsets inside a 16-byte vector, in place
+or not, the configuration (the library's choice, flags alone, or explicit
+knobs with any tile width that is a multiple of 128; flags for int32 keys
+only, as the boundary requires) and, for int32 keys, the entry point
+(rtcdf_sort, rtcdf_sort_with_config, rtcdf_sort_ws, rtcdf_sort_noalloc,
+rtcdf_sort_checked).  The structured tests cover each axis on its own; this
+one covers their combinations.
+
+Every output is compared element by element with the oracle's sort of the
+normalised values (Sec. 2.1: the counting sort over [0, R), minVal added
+back), and the words around the output and the input are checked unchanged.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_00843_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N_CASES = 240
+TYPES = {"int32": (np.int32, -(1 << 31), 1 << 31), "int64": (np.int64, -(1 << 63), (1 << 63) - 1),
+         "int16": (np.int16, -32768, 32768), "uint16": (np.uint16, 0, 65536),
+         "int8": (np.int8, -128, 128), "uint8": (np.uint8, 0, 256)}
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def r():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_00843_amd import rtcdf
+    return rtcdf
+
+
+def _to_dev(A, npt, pad, fill):
+    """Device buffer holding A at element offset pad, `fill` around it."""
+    buf = np.full(A.size + pad + 16, fill, dtype=npt)
+    buf[pad:pad + A.size] = A
+    if npt is np.uint16:
+        t = torch.from_numpy(buf.view(np.int16)).cuda().view(torch.uint16)
+    else:
+        t = torch.from_numpy(buf).cuda()
+    return t, t[pad:pad + A.size]
+
+
+def _to_host(t, npt):
+    if npt is np.uint16:
+        return t.view(torch.int16).cpu().numpy().view(np.uint16)
+    return t.cpu().numpy()
+
+
+def _offsets(rng, dist, n, R, seed):
+    """n values in [0, R) (int64) with the named distribution."""
+    if dist == "few":
+        vals = rng.integers(0, R, size=int(rng.integers(1, 6)))
+        return vals[rng.integers(0, vals.size, size=n)].astype(np.int64)
+    if dist == "normal64":
+        return inputs.make("normal", n, 0, R, seed, sd_div=64.0).astype(np.int64)
+    return inputs.make(dist, n, 0, R, seed).astype(np.int64)
+
+
+def _rand_config(rng, r, int32_keys):
+    """None (the library's choice), flags alone, or explicit knobs; the flags
+    are offered for int32 keys only (other key types take none)."""
+    u = rng.random()
+    if u < 0.4:
+        return None
+    flags = 0
+    if rng.random() < 0.3:
+        flags |= r.FLAG_OUTPUT_PREFIX_MAX
+    flags |= int(rng.choice([0, 0, r.FLAG_COUNTERS_16, r.FLAG_COUNTERS_32, r.FLAG_COUNTERS_4]))
+    if rng.random() < 0.25:
+        flags |= r.FLAG_WAVE_DEDUPE
+    if rng.random() < 0.25:
+        flags |= r.FLAG_CHUNK_4096
+    if not int32_keys:
+        flags = 0
+    if u < 0.55 and flags:
+        return r.make_config(0, 0, 0, flags)
+    bpt = int(rng.choice([1, 2, 4]))
+    tiles_max = min(256, 163840 // (4 * bpt) // 128)
+    T = 128 * int(rng.integers(1, tiles_max + 1))
+    return r.make_config(T, int(rng.choice([4, 8, 16])), bpt, flags)
+
+
+def _case(k):
+    rng = np.random.default_rng(inputs.case_seed(91, k))
+    name = str(rng.choice(list(TYPES), p=[0.45, 0.15, 0.1, 0.1, 0.1, 0.1]))
+    npt, tlo, thi = TYPES[name]
+    n = int(rng.integers(1, 24)) if rng.random() < 0.15 else int(round(10 ** rng.uniform(0, 5.7)))
+    if name in ("int32", "int64"):
+        R = max(1, int(round(2 ** rng.uniform(0, 23))))
+        if rng.random() < 0.2:
+            R = max(1, (1 << int(rng.integers(0, 23))) + int(rng.integers(-1, 2)))
+    else:
+        R = int(rng.integers(1, thi - tlo + 1)) if rng.random() < 0.6 else thi - tlo
+    u = rng.random()
+    if u < 0.15:
+        lo = tlo                      # the type's lowest value
+    elif u < 0.3:
+        lo = thi - R                  # the range ends at the type's top (INT64_MAX excluded)
+    elif name == "int64":
+        lo = min(max(2 * int(rng.integers(-(1 << 62), 1 << 62)), tlo), thi - R)
+    else:
+        lo = tlo + int(rng.integers(0, thi - R - tlo + 1))
+    dist = str(rng.choice(["uniform", "normal", "normal64", "all_equal", "zipf", "few"]))
+    return rng, name, npt, n, lo, R, dist
+
+
+@pytest.mark.parametrize("k", range(N_CASES))
+def test_mixed(r, k):
+    rng, name, npt, n, lo, R, dist = _case(k)
+    hi = lo + R
+    off = _offsets(rng, dist, n, R, inputs.case_seed(92, k))
+    A = (off + np.int64(lo)).astype(npt) if name != "int64" else off + np.int64(lo)
+    kb = np.dtype(npt).itemsize
+    pin, pout = int(rng.integers(0, 16 // kb)), int(rng.integers(0, 16 // kb))
+    inplace = rng.random() < 0.15
+    cfg = _rand_config(rng, r, name == "int32")
+    entry = str(rng.choice(["sort", "sort_ws", "noalloc", "checked"])) if name == "int32" else "sort_keys"
+    _say(f"mixed {k}: {name} n={n} [{lo},{hi}) R={R} {dist} pin={pin} pout={pout} inplace={inplace} "
+         f"cfg={None if cfg is None else cfg.as_tuple()} entry={entry}")
+    want = (oracle.sort(off.astype(np.int32), 0, R).astype(np.int64) + np.int64(lo)).astype(npt)
+    bin_, tin = _to_dev(A, npt, pin, 7)
+    if inplace:
+        bout, tout = bin_, tin
+    else:
+        bout, tout = _to_dev(np.zeros(n, dtype=npt), npt, pout, 0x5A)
+    if entry == "sort_keys":
+        r.sort_keys(tin, lo, hi, keys_out=tout, config=cfg)
+    elif entry == "sort":
+        r.sort(tin, lo, hi, keys_out=tout, config=cfg)
+    elif entry == "checked":
+        r.sort_checked(tin, lo, hi, keys_out=tout, config=cfg)
+    else:
+        need = r.workspace_bytes(n, lo, hi, config=cfg, keys_out=tout)
+        if entry == "noalloc" and need <= r.NOALLOC_MAX_WORKSPACE:
+            r.sort_noalloc(tin, tout, lo, hi, config=cfg)
+        else:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+            r.sort_ws(tin, tout, lo, hi, ws, config=cfg)
+    torch.cuda.synchronize()
+    got = _to_host(tout, npt)
+    assert np.array_equal(got, want), f"mismatch at {np.flatnonzero(got != want)[:8]}"
+    full = _to_host(bout, npt)
+    guard = np.array(7 if inplace else 0x5A, dtype=npt)
+    pad = pin if inplace else pout
+    assert np.all(full[:pad] == guard) and np.all(full[pad + n:] == guard), "words around the output changed"
+    if not inplace:
+        assert np.array_equal(_to_host(tin, npt), A), "the input changed"

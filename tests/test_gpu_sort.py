@@ -267,7 +267,10 @@ def test_option_flags_are_identical(r, dist, n, logR):
 
 @pytest.mark.parametrize("R,T", [(4, 128), (1000, 128), (1000, 1024), (70000, 1024),
                                  (70000, 32768), (262144, 8192), (300000, 32768),
-                                 ((1 << 21) + 77, 128)])   # 16385 tiles: offsets by k_tile_offsets
+                                 ((1 << 21) + 77, 128),    # 16385 tiles: offsets by k_tile_offsets
+                                 # tile widths that are multiples of 128 but not powers of two:
+                                 # 111, 96, 37 and 129 block totals of 128 bins per tile
+                                 (1005816, 14208), (300000, 12288), (70000, 4736), (2_000_003, 16512)])
 def test_intermediates_match_oracle(r, R, T):
     """Tile histograms (Alg. 5), local CDFs (Alg. 4) and tile offsets (Alg. 6)."""
     rng = np.random.default_rng(R + T)
@@ -284,6 +287,27 @@ def test_intermediates_match_oracle(r, R, T):
     assert np.array_equal(as_u(gh), h)
     assert np.array_equal(as_u(gc), c)
     assert np.array_equal(as_u(gO), O)
+
+
+@pytest.mark.parametrize("T,items,bpt", [(14208, 4, 1), (12288, 8, 2), (4736, 16, 4), (16512, 16, 1),
+                                         (128 * 255, 4, 1)])
+def test_tile_widths_not_powers_of_two(r, T, items, bpt):
+    """Any multiple of 128 is a valid tile width: explicit configurations whose
+    tiles hold a number of 128-bin blocks that is not a power of two (tile
+    boundaries inside a wave's 64 block totals), with the flags that change
+    the counters and the output, over several tiles and distributions."""
+    for dist, n, R in (("uniform", 121_774, 1_005_816), ("normal", 400_001, 300_000),
+                       ("zipf", 250_000, 70_000), ("all_equal", 100_000, 2 * T + 5)):
+        A = inputs.make(dist, n, -987, -987 + R, inputs.case_seed(93, T + R))
+        want = oracle.sort(A, -987, -987 + R)
+        _, tin = _to_dev(A, 1)
+        for flags in (0, 0x10, 0x04, 0x01, 0x20):
+            cfg = r.make_config(T, items, bpt, flags)
+            _say(f"tile width T={T} {dist} n={n} R={R} flags={flags:#x}")
+            out = r.sort(tin, -987, -987 + R, config=cfg)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            assert np.array_equal(got, want), (T, dist, flags, np.flatnonzero(got != want)[:5])
 
 
 def test_caller_workspace(r):
