@@ -1,7 +1,8 @@
 """GPU parity over a seeded random mix of problems: each case draws every axis
 at once -- key type (int32, int64, 16- and 8-bit, signed or not), n (1 to
-5 x 10^5), the range R (1 to 2^23 for int32 and int64 keys, any window of a
-narrow type), minVal anywhere in the type (its extremes included), the key
+5 x 10^5, and 5 x 10^5 to 4 x 10^6 in the large set), the range R (1 to 2^23
+for int32 and int64 keys, 2^25 in the large set; any window of a narrow
+type), minVal anywhere in the type (its extremes included), the key
 distribution, the input and output offsets inside a 16-byte vector, in place
 or not, the configuration (the library's choice, flags alone, or explicit
 knobs with any tile width that is a multiple of 128; flags for int32 keys
@@ -25,7 +26,8 @@ from paper_2609_00843_amd import inputs
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-N_CASES = 240
+N_CASES = 600
+N_LARGE = 120
 TYPES = {"int32": (np.int32, -(1 << 31), 1 << 31), "int64": (np.int64, -(1 << 63), (1 << 63) - 1),
          "int16": (np.int16, -32768, 32768), "uint16": (np.uint16, 0, 65536),
          "int8": (np.int8, -128, 128), "uint8": (np.uint8, 0, 256)}
@@ -95,13 +97,18 @@ def _rand_config(rng, r, int32_keys):
     return r.make_config(T, int(rng.choice([4, 8, 16])), bpt, flags)
 
 
-def _case(k):
-    rng = np.random.default_rng(inputs.case_seed(91, k))
+def _case(k, large=False):
+    """Case k's draws; `large`: n from 5 x 10^5 to 4 x 10^6 and R up to 2^25
+    (many output chunks and tiles, the partition by pass)."""
+    rng = np.random.default_rng(inputs.case_seed(94 if large else 91, k))
     name = str(rng.choice(list(TYPES), p=[0.45, 0.15, 0.1, 0.1, 0.1, 0.1]))
     npt, tlo, thi = TYPES[name]
-    n = int(rng.integers(1, 24)) if rng.random() < 0.15 else int(round(10 ** rng.uniform(0, 5.7)))
+    if large:
+        n = int(round(10 ** rng.uniform(5.7, 6.6)))
+    else:
+        n = int(rng.integers(1, 24)) if rng.random() < 0.15 else int(round(10 ** rng.uniform(0, 5.7)))
     if name in ("int32", "int64"):
-        R = max(1, int(round(2 ** rng.uniform(0, 23))))
+        R = max(1, int(round(2 ** rng.uniform(0, 25 if large else 23))))
         if rng.random() < 0.2:
             R = max(1, (1 << int(rng.integers(0, 23))) + int(rng.integers(-1, 2)))
     else:
@@ -121,16 +128,25 @@ def _case(k):
 
 @pytest.mark.parametrize("k", range(N_CASES))
 def test_mixed(r, k):
-    rng, name, npt, n, lo, R, dist = _case(k)
+    _run_case(r, k, False)
+
+
+@pytest.mark.parametrize("k", range(N_LARGE))
+def test_mixed_large(r, k):
+    _run_case(r, k, True)
+
+
+def _run_case(r, k, large):
+    rng, name, npt, n, lo, R, dist = _case(k, large)
     hi = lo + R
-    off = _offsets(rng, dist, n, R, inputs.case_seed(92, k))
+    off = _offsets(rng, dist, n, R, inputs.case_seed(95 if large else 92, k))
     A = (off + np.int64(lo)).astype(npt) if name != "int64" else off + np.int64(lo)
     kb = np.dtype(npt).itemsize
     pin, pout = int(rng.integers(0, 16 // kb)), int(rng.integers(0, 16 // kb))
     inplace = rng.random() < 0.15
     cfg = _rand_config(rng, r, name == "int32")
     entry = str(rng.choice(["sort", "sort_ws", "noalloc", "checked"])) if name == "int32" else "sort_keys"
-    _say(f"mixed {k}: {name} n={n} [{lo},{hi}) R={R} {dist} pin={pin} pout={pout} inplace={inplace} "
+    _say(f"mixed{' large' if large else ''} {k}: {name} n={n} [{lo},{hi}) R={R} {dist} pin={pin} pout={pout} inplace={inplace} "
          f"cfg={None if cfg is None else cfg.as_tuple()} entry={entry}")
     want = (oracle.sort(off.astype(np.int32), 0, R).astype(np.int64) + np.int64(lo)).astype(npt)
     bin_, tin = _to_dev(A, npt, pin, 7)
