@@ -308,7 +308,9 @@ rtcdf_status_t rtcdf_batched_workspace_bytes(uint32_t num_segments,
 /* Sort every segment of d_segments[num_segments] (a device array) in one
  * persistent launch (Alg. 4 of the paper per range tile of 32768 values: a
  * segment is one or two work items, each handled by one workgroup in LDS,
- * largest first), preceded by a one-workgroup ordering kernel.  Each
+ * largest first; an in-place segment wider than 32768 values is one item
+ * that counts both tiles before it writes any position), preceded by a
+ * one-workgroup ordering kernel.  Each
  * segment's output equals rtcdf_sort of that segment.
  * d_ws: caller-owned device workspace of ws_bytes bytes (>=
  * rtcdf_batched_workspace_bytes), 256-byte aligned, no initialisation

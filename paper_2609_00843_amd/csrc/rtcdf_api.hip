@@ -854,7 +854,7 @@ rtcdf_status_t rtcdf_debug_intermediates(const int32_t* keys_in, size_t n, int64
 // ---- batched
 
 struct BatchLayout {
-  size_t off_counters, off_order, off_slots, bytes;
+  size_t off_counters, off_order, off_slots, off_park, bytes;
   uint32_t grid;
   BatchPlan plan;
 };
@@ -865,13 +865,14 @@ static rtcdf_status_t batch_layout(uint32_t nseg, const rtcdf_batch_bounds_t* bo
   DeviceInfo dev;
   rtcdf_status_t st = device_info(&dev);
   if (st != RTCDF_SUCCESS) return st;
-  L->plan = batched_plan(nseg, bounds->total_keys, dev.cus);
+  L->plan = batched_plan(nseg, bounds->total_keys, dev.cus, bounds->max_range);
   // one persistent workgroup per compute unit, or one per work item
   L->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)dev.cus, L->plan.items_max));
   L->off_counters = 0;
   L->off_order = 256;
   L->off_slots = align256(L->off_order + L->plan.order_words * 4);
-  L->bytes = align256(L->off_slots + L->plan.slot_words * 4);
+  L->off_park = align256(L->off_slots + L->plan.slot_words * 4);
+  L->bytes = align256(L->off_park + L->plan.park_words * 4);
   return RTCDF_SUCCESS;
 }
 
@@ -900,7 +901,8 @@ rtcdf_status_t rtcdf_sort_batched(const rtcdf_segment_t* d_segments, uint32_t nu
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
   hipError_t e = launch_batched(d_segments, num_segments, L.plan, reinterpret_cast<uint32_t*>(ws + L.off_order),
                                 reinterpret_cast<uint32_t*>(ws + L.off_counters),
-                                reinterpret_cast<uint32_t*>(ws + L.off_slots), L.grid, stream);
+                                reinterpret_cast<uint32_t*>(ws + L.off_slots),
+                                reinterpret_cast<uint32_t*>(ws + L.off_park), L.grid, stream);
   return e == hipSuccess ? RTCDF_SUCCESS : hip_fail(e);
 }
 

@@ -3,7 +3,9 @@
 //
 // The work items are range tiles of the arrays ("segments"): a segment with
 // R <= 32768 is one item, a wider one (R <= 2^16) two, one per half of its
-// range.  Each workgroup (1024 threads, 1 per compute unit, 135 KiB of LDS)
+// range -- unless its output overlaps its input (in place): its two tiles are
+// then one item, since a tile's workgroup would otherwise overwrite keys the
+// other one has not yet counted.  Each workgroup (1024 threads, 1 per compute unit, 135 KiB of LDS)
 // takes items from a device work queue and runs every step of Alg. 4 of the
 // paper for it without touching another workgroup:
 //   Alg. 5  histogram of the keys that fall in the item's tile, in LDS (32-bit
@@ -60,8 +62,10 @@ constexpr uint32_t kBBuckets = 34;
 static_assert(RTCDF_BATCH_MAX_RANGE <= 2 * kBTile, "a segment is at most two tiles");
 
 // Work items in the queue: two words {x, y}.  y = tile | kind << 1 | chunk
-// << 3; x is the segment index (whole items) or the slot index.
+// << 3; x is the segment index (whole items) or the slot index.  A whole item
+// with kBothTiles set covers both range tiles of an in-place segment.
 enum ItemKind : uint32_t { kWhole = 0, kZero = 1, kCount = 2, kFill = 3 };
+constexpr uint32_t kBothTiles = 1u << 3;
 // Per-slot state: control words, then the tile's histogram / local CDF.
 constexpr uint32_t kSlotCtrl = 64;
 constexpr uint32_t kSlotWords = kSlotCtrl + kBTile;
@@ -79,16 +83,26 @@ struct BatchArgs {
   uint32_t K;              // keys (and output positions) per chunk, a multiple of 4096
   uint32_t max_slots;      // capacity of slots
   uint32_t max_chunks;     // capacity of count (and of fill) items
+  uint32_t max_range;      // the bounds' largest range: wider segments are skipped
+  uint32_t* park;          // kBTile words per workgroup (both-tile items), or null
 };
 
 // Whether a descriptor is sorted at all (others are skipped, output untouched).
-__device__ __forceinline__ bool seg_valid(const rtcdf_segment_t& d) {
-  return d.n != 0 && d.range != 0 && d.range <= RTCDF_BATCH_MAX_RANGE && d.keys_in != nullptr &&
-         d.keys_out != nullptr;
+__device__ __forceinline__ bool seg_valid(const rtcdf_segment_t& d, uint32_t max_range) {
+  return d.n != 0 && d.range != 0 && d.range <= RTCDF_BATCH_MAX_RANGE && d.range <= max_range &&
+         d.keys_in != nullptr && d.keys_out != nullptr;
 }
 
-__device__ __forceinline__ uint32_t seg_tiles(const rtcdf_segment_t& d) {
-  return seg_valid(d) ? (d.range > kBTile ? 2u : 1u) : 0u;
+__device__ __forceinline__ uint32_t seg_tiles(const rtcdf_segment_t& d, uint32_t max_range) {
+  return seg_valid(d, max_range) ? (d.range > kBTile ? 2u : 1u) : 0u;
+}
+
+// A two-tile segment whose output overlaps its input: one item for both tiles
+// (the workspace then holds a park slot per workgroup).
+__device__ __forceinline__ bool seg_both(const rtcdf_segment_t& d, const BatchArgs& a) {
+  if (a.park == nullptr || seg_tiles(d, a.max_range) != 2) return false;
+  const uintptr_t i = (uintptr_t)d.keys_in, o = (uintptr_t)d.keys_out, b = (uintptr_t)d.n * 4u;
+  return i < o + b && o < i + b;
 }
 
 __device__ __forceinline__ uint32_t seg_bucket(const rtcdf_segment_t& d) {
@@ -115,7 +129,7 @@ __global__ __launch_bounds__(1024) void k_batch_order(BatchArgs a) {
   uint64_t chunks = 0;
   for (uint32_t i = tid; i < a.nseg; i += 1024u) {
     const rtcdf_segment_t d = a.segs[i];
-    const uint32_t t = seg_tiles(d), c = seg_chunks(d, a.K);
+    const uint32_t t = seg_tiles(d, a.max_range), c = seg_both(d, a) ? 0u : seg_chunks(d, a.K);
     if (t != 0 && c != 0) {
       slots += t;
       chunks += (uint64_t)t * c;
@@ -130,8 +144,9 @@ __global__ __launch_bounds__(1024) void k_batch_order(BatchArgs a) {
   const bool chunked = tot_slots <= a.max_slots && tot_chunks <= a.max_chunks;
   for (uint32_t i = tid; i < a.nseg; i += 1024u) {
     const rtcdf_segment_t d = a.segs[i];
-    const uint32_t t = seg_tiles(d);
-    if (t != 0 && !(chunked && seg_chunks(d, a.K) != 0)) atomicAdd(&hist[seg_bucket(d)], t);
+    const uint32_t t = seg_tiles(d, a.max_range);
+    const bool both = seg_both(d, a);
+    if (t != 0 && !(chunked && !both && seg_chunks(d, a.K) != 0)) atomicAdd(&hist[seg_bucket(d)], both ? 1u : t);
   }
   __syncthreads();
   const uint32_t U = chunked ? tot_slots : 0u, LC = chunked ? tot_chunks : 0u;
@@ -151,9 +166,14 @@ __global__ __launch_bounds__(1024) void k_batch_order(BatchArgs a) {
   uint32_t slot = slot0, chunk = chunk0;
   for (uint32_t i = tid; i < a.nseg; i += 1024u) {
     const rtcdf_segment_t d = a.segs[i];
-    const uint32_t t = seg_tiles(d);
+    const uint32_t t = seg_tiles(d, a.max_range);
     if (t == 0) continue;
-    const uint32_t C = chunked ? seg_chunks(d, a.K) : 0u;
+    const bool both = seg_both(d, a);
+    const uint32_t C = chunked && !both ? seg_chunks(d, a.K) : 0u;
+    if (both) {
+      order[atomicAdd(&hist[seg_bucket(d)], 1u)] = make_uint2(i, kWhole << 1 | kBothTiles);
+      continue;
+    }
     if (C == 0) {
       const uint32_t at = atomicAdd(&hist[seg_bucket(d)], t);
       for (uint32_t k = 0; k < t; ++k) order[at + k] = make_uint2(i, k | (kWhole << 1));
@@ -396,6 +416,38 @@ __device__ void sort_item(const rtcdf_segment_t& d, uint32_t tile, uint32_t* S, 
   __syncthreads();   // LDS is reused by the next item
 }
 
+// Whole item over both range tiles of an in-place segment d: every key is
+// counted for both tiles before any position is written.  Tile 1's local CDF
+// waits in the workgroup's park slot (global memory) while tile 0 is counted
+// in LDS; then tile 0's positions are written, tile 1's CDF is loaded back and
+// its positions are written.  The fences order the park slot's stores before
+// its loads (the loads must not hit lines of an earlier item in L1).
+__device__ void sort_both_tiles(const rtcdf_segment_t& d, uint32_t* S, uint32_t* wsum, uint32_t* park) {
+  const TileGeom g0 = tile_geom(d, 0), g1 = tile_geom(d, 1);
+  const uint32_t nv = body_vectors(d.keys_in, d.n);
+  zero_lds(S, g1.w);
+  count_range(d, 0, nv, true, true, g1.base, g1.w, S);
+  __syncthreads();
+  const uint32_t N1 = scan_tile(S, g1.w, wsum);
+  for (uint32_t i = threadIdx.x; i < g1.w; i += kBBlock) park[i] = S[pad32(i)];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  zero_lds(S, g0.w);
+  count_range(d, 0, nv, true, true, g0.base, g0.w, S);
+  __syncthreads();
+  const uint32_t N0 = scan_tile(S, g0.w, wsum);   // every key has been read
+  if (N0) fill_tile((g_i32*)d.keys_out, S, g0.w, g0.base, 0, 0, N0, g0.body_lo, S + kBLdsWords);
+  __syncthreads();
+  if (N1) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (uint32_t i = threadIdx.x; i < g1.w; i += kBBlock) S[pad32(i)] = park[i];
+    __syncthreads();
+    const uint32_t P0 = tile_start(d, 1, N1);
+    fill_tile((g_i32*)d.keys_out, S, g1.w, g1.base, P0, P0, P0 + N1, g1.body_lo, S + kBLdsWords);
+  }
+  __syncthreads();   // LDS is reused by the next item
+}
+
 // Thread 0 waits (bounded) until *flag is nonzero; returns, in every thread,
 // whether it did, with the flag's release visible (agent-scope acquire).  The
 // polling loads are relaxed: an acquire per poll would invalidate the L2 of
@@ -509,7 +561,9 @@ __global__ __launch_bounds__(kBBlock) void k_batched(BatchArgs a) {
     const uint32_t tile = it.y & 1u, kind = (it.y >> 1) & 3u, chunk = it.y >> 3;
     if (kind == kWhole) {
       const rtcdf_segment_t d = a.segs[it.x];
-      if (seg_valid(d)) sort_item(d, tile, S, wsum);
+      if (!seg_valid(d, a.max_range)) continue;
+      if (it.y & kBothTiles) sort_both_tiles(d, S, wsum, a.park + (size_t)blockIdx.x * kBTile);
+      else sort_item(d, tile, S, wsum);
     } else {
       uint32_t* st = a.slots + (size_t)it.x * kSlotWords;
       if (kind == kZero) zero_item(a, st);
@@ -521,8 +575,12 @@ __global__ __launch_bounds__(kBBlock) void k_batched(BatchArgs a) {
 
 }  // namespace
 
-BatchPlan batched_plan(uint32_t nseg, uint64_t total_keys, uint32_t cus) {
+BatchPlan batched_plan(uint32_t nseg, uint64_t total_keys, uint32_t cus, uint32_t max_range) {
   BatchPlan P;
+  P.max_range = max_range;
+  // a park slot per persistent workgroup (at most one per compute unit) when
+  // a segment may have two range tiles
+  P.park_words = max_range > kBTile ? (uint64_t)cus * kBTile : 0;
   // chunks of at least 2^18 keys, and at least the batch's keys per two
   // workgroups, so that a chunked segment is longer than a fair share
   const uint64_t share = (total_keys + 2ull * cus - 1) / (2ull * cus);
@@ -543,7 +601,7 @@ BatchPlan batched_plan(uint32_t nseg, uint64_t total_keys, uint32_t cus) {
 }
 
 hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, const BatchPlan& P, uint32_t* order,
-                          uint32_t* counters, uint32_t* slots, uint32_t grid, hipStream_t s) {
+                          uint32_t* counters, uint32_t* slots, uint32_t* park, uint32_t grid, hipStream_t s) {
   BatchArgs a;
   a.segs = segs;
   a.nseg = nseg;
@@ -553,6 +611,8 @@ hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, const Batc
   a.K = P.K;
   a.max_slots = P.max_slots;
   a.max_chunks = P.max_chunks;
+  a.max_range = P.max_range;
+  a.park = P.park_words != 0 ? park : nullptr;
   hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

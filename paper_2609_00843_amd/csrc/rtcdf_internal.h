@@ -167,18 +167,22 @@ hipError_t launch_fill_fast(const Plan& p, int32_t* out, uint32_t* area, hipStre
 
 // Batched sort (rtcdf_batched.hip).  batched_plan sizes the workspace from
 // the host-side bounds: order_words words of work-item list, slot_words words
-// of chunked-tile state (counters: 3 words).
+// of chunked-tile state, park_words words of park slots for the items that
+// sort both range tiles of an in-place segment (counters: 3 words).
 struct BatchPlan {
   uint32_t K;            // keys (and output positions) per chunk of a chunked segment
   uint32_t max_slots;    // chunked tiles the workspace holds
   uint32_t max_chunks;   // count items (and fill items) it holds
+  uint32_t max_range;    // the bounds' largest range (wider segments are skipped)
   uint64_t items_max;    // work items it holds
   uint64_t order_words;
   uint64_t slot_words;
+  uint64_t park_words;
 };
-BatchPlan batched_plan(uint32_t nseg, uint64_t total_keys, uint32_t cus);
+BatchPlan batched_plan(uint32_t nseg, uint64_t total_keys, uint32_t cus, uint32_t max_range);
 hipError_t launch_batched(const rtcdf_segment_t* segs, uint32_t nseg, const BatchPlan& plan, uint32_t* order,
-                          uint32_t* counters, uint32_t* slots, uint32_t grid, hipStream_t stream);
+                          uint32_t* counters, uint32_t* slots, uint32_t* park, uint32_t grid,
+                          hipStream_t stream);
 
 // Learned picker (rtcdf_mlp.hip).
 hipError_t launch_sketch(const int32_t* keys, uint64_t n, int64_t minVal, uint64_t R, uint32_t samples,

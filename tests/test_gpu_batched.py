@@ -209,26 +209,72 @@ def test_two_host_threads(r):
         _check(arrays, specs, pairs, dout, offs)
 
 
+def test_in_place_two_tiles(r):
+    """Segments wider than one 32768-value tile sorted in place: their two
+    tiles are one work item that counts every key for both tiles before it
+    writes (as two items, one tile's workgroup could overwrite keys the other
+    had not counted yet).  Large and skewed segments, beside out-of-place
+    copies of the same keys and small ones, in two rounds (the park slots
+    hold the previous item's CDF)."""
+    specs = [(180_001, 2_147_483_648 - 41913, 41913, "zipf"), (300_000, -5, 65536, "uniform"),
+             (250_003, -(1 << 31), 32769, "all_equal"), (120_000, 77, 50_000, "normal"),
+             (1000, 3, 40_000, "uniform"), (5, 0, 65536, "zipf"), (200_000, 9, 60_000, "zipf")]
+    specs = specs + specs[::-1] + [(70_000, -1, 300, "uniform")]
+    _say(f"in-place two-tile segments: {len(specs)}")
+    for rnd in range(2):
+        arrays, pairs, din, dout, offs = _build(specs, 7 + rnd, inplace_every=1 + rnd)
+        _run(r, pairs, configs=[(4, 8, 16, 0)[i % 4] for i in range(len(specs))])
+        _check(arrays, specs, pairs, dout, offs)
+
+
+@pytest.mark.parametrize("k", range(24))
+def test_random_batches(r, k):
+    """A seeded random mix of batches: 1 to 400 segments each, n from 0 to
+    3 x 10^5 (tiny ones often), R from 1 to 2^16 (one or two range tiles;
+    32768 and its neighbours often), minVal anywhere in int32 (its ends
+    included), four distributions, some segments in place, and per-segment
+    config words of every kind (4, 8, 16 keys per thread, and values that
+    mean 16).  Every segment equals the oracle's sort; nothing outside the
+    outputs is written."""
+    rng = np.random.default_rng(inputs.case_seed(96, k))
+    specs = []
+    for _ in range(int(rng.integers(1, 401))):
+        u = rng.random()
+        n = 0 if u < 0.05 else (int(rng.integers(1, 21)) if u < 0.2 else int(round(10 ** rng.uniform(1.3, 5.5))))
+        R = int(rng.choice([32767, 32768, 32769, 65536])) if rng.random() < 0.15 else \
+            max(1, int(round(2 ** rng.uniform(0, 16))))
+        v = rng.random()
+        lo = -(1 << 31) if v < 0.1 else ((1 << 31) - R if v < 0.2 else int(rng.integers(-(1 << 31), (1 << 31) - R + 1)))
+        specs.append((n, lo, R, str(rng.choice(["uniform", "normal", "all_equal", "zipf"]))))
+    configs = [int(rng.choice([0, 4, 8, 16, 3, 1000])) for _ in specs]
+    _say(f"random batch {k}: {len(specs)} segments, {sum(s[0] for s in specs)} keys")
+    arrays, pairs, din, dout, offs = _build(specs, 200 + k, inplace_every=int(rng.integers(0, 8)))
+    _run(r, pairs, configs=configs)
+    _check(arrays, specs, pairs, dout, offs)
+
+
 def test_skipped_descriptors(r):
-    """range 0 or above the bounds, and NULL pointers, are skipped."""
+    """range 0, above RTCDF_BATCH_MAX_RANGE or above the bounds' max_range,
+    and NULL pointers, are skipped."""
     import ctypes
     A = inputs.uniform(1000, 0, 100, 5)
     din = torch.from_numpy(A).cuda()
-    dout = torch.full((4000,), GUARD, dtype=torch.int32, device="cuda")
-    segs = (r.Segment * 4)()
+    dout = torch.full((5000,), GUARD, dtype=torch.int32, device="cuda")
+    segs = (r.Segment * 5)()
     segs[0] = r.Segment(din.data_ptr(), dout.data_ptr(), 1000, 0, 0, 0)               # range 0
     segs[1] = r.Segment(din.data_ptr(), dout[1000:].data_ptr(), 1000, 0, 70000, 0)    # > max
     segs[2] = r.Segment(0, dout[2000:].data_ptr(), 1000, 0, 100, 0)                   # NULL input
-    segs[3] = r.Segment(din.data_ptr(), dout[3000:].data_ptr(), 1000, 0, 100, 0)      # valid
+    segs[3] = r.Segment(din.data_ptr(), dout[4000:].data_ptr(), 1000, 0, 5000, 0)     # > bounds
+    segs[4] = r.Segment(din.data_ptr(), dout[3000:].data_ptr(), 1000, 0, 100, 0)      # valid
     d = torch.frombuffer(bytearray(bytes(segs)), dtype=torch.uint8).cuda()
-    bounds = r.BatchBounds(4000, 1000, 100)
-    ws = torch.empty(r.batched_workspace_bytes(4, bounds), dtype=torch.uint8, device="cuda")
+    bounds = r.BatchBounds(5000, 1000, 100)
+    ws = torch.empty(r.batched_workspace_bytes(5, bounds), dtype=torch.uint8, device="cuda")
     _say("skipped descriptors")
-    r.sort_batched(d, 4, bounds, ws)
+    r.sort_batched(d, 5, bounds, ws)
     torch.cuda.synchronize()
     out = dout.cpu().numpy()
-    assert np.all(out[:3000] == GUARD)
-    assert np.array_equal(out[3000:], oracle.sort(A, 0, 100))
+    assert np.all(out[:3000] == GUARD) and np.all(out[4000:] == GUARD)
+    assert np.array_equal(out[3000:4000], oracle.sort(A, 0, 100))
 
 
 def test_graph_replay(r):
