@@ -404,48 +404,46 @@ __device__ __forceinline__ void zero_lds(uint32_t* S, uint32_t w) {
 }
 
 // Whole item: tile `tile` of segment d -- the tile's histogram, local CDF and
-// output interval (see the file comment).
-__device__ void sort_item(const rtcdf_segment_t& d, uint32_t tile, uint32_t* S, uint32_t* wsum) {
-  const TileGeom g = tile_geom(d, tile);
-  zero_lds(S, g.w);
-  count_range(d, 0, body_vectors(d.keys_in, d.n), true, true, g.base, g.w, S);
-  __syncthreads();
-  const uint32_t Nt = scan_tile(S, g.w, wsum);
-  const uint32_t P0 = tile_start(d, tile, Nt);
-  if (Nt) fill_tile((g_i32*)d.keys_out, S, g.w, g.base, P0, P0, P0 + Nt, g.body_lo, S + kBLdsWords);
-  __syncthreads();   // LDS is reused by the next item
-}
-
-// Whole item over both range tiles of an in-place segment d: every key is
-// counted for both tiles before any position is written.  Tile 1's local CDF
-// waits in the workgroup's park slot (global memory) while tile 0 is counted
-// in LDS; then tile 0's positions are written, tile 1's CDF is loaded back and
-// its positions are written.  The fences order the park slot's stores before
-// its loads (the loads must not hit lines of an earlier item in L1).
-__device__ void sort_both_tiles(const rtcdf_segment_t& d, uint32_t* S, uint32_t* wsum, uint32_t* park) {
-  const TileGeom g0 = tile_geom(d, 0), g1 = tile_geom(d, 1);
-  const uint32_t nv = body_vectors(d.keys_in, d.n);
-  zero_lds(S, g1.w);
-  count_range(d, 0, nv, true, true, g1.base, g1.w, S);
-  __syncthreads();
-  const uint32_t N1 = scan_tile(S, g1.w, wsum);
-  for (uint32_t i = threadIdx.x; i < g1.w; i += kBBlock) park[i] = S[pad32(i)];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  zero_lds(S, g0.w);
-  count_range(d, 0, nv, true, true, g0.base, g0.w, S);
-  __syncthreads();
-  const uint32_t N0 = scan_tile(S, g0.w, wsum);   // every key has been read
-  if (N0) fill_tile((g_i32*)d.keys_out, S, g0.w, g0.base, 0, 0, N0, g0.body_lo, S + kBLdsWords);
-  __syncthreads();
-  if (N1) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    for (uint32_t i = threadIdx.x; i < g1.w; i += kBBlock) S[pad32(i)] = park[i];
+// output interval (see the file comment).  With `park` (an in-place segment
+// of two range tiles, tile 0) the item covers both tiles and counts every key
+// for both before it writes any position: tile 1 is counted and scanned
+// first and its local CDF waits in the workgroup's park slot (global memory)
+// while tile 0 is counted in LDS; tile 0's positions are written, tile 1's
+// CDF is loaded back and its positions are written.  The fences order the
+// park slot's stores before its loads (which must not hit lines of an earlier
+// item in L1).  The two phases are loops so that the count and the output
+// code each keep one call site here.
+__device__ void sort_item(const rtcdf_segment_t& d, uint32_t tile, uint32_t* S, uint32_t* wsum,
+                          uint32_t* park) {
+  const uint32_t phases = park != nullptr ? 2u : 1u;
+  uint32_t N[2] = {0u, 0u};
+  for (uint32_t ph = 0; ph < phases; ++ph) {
+    const uint32_t t = park != nullptr ? 1u - ph : tile;
+    const TileGeom g = tile_geom(d, t);
+    zero_lds(S, g.w);
+    count_range(d, 0, body_vectors(d.keys_in, d.n), true, true, g.base, g.w, S);
     __syncthreads();
-    const uint32_t P0 = tile_start(d, 1, N1);
-    fill_tile((g_i32*)d.keys_out, S, g1.w, g1.base, P0, P0, P0 + N1, g1.body_lo, S + kBLdsWords);
+    N[t] = scan_tile(S, g.w, wsum);
+    if (ph + 1 < phases) {
+      for (uint32_t i = threadIdx.x; i < g.w; i += kBBlock) park[i] = S[pad32(i)];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+    }
   }
-  __syncthreads();   // LDS is reused by the next item
+  // every key has been read; the LDS holds the local CDF of `tile` (tile 0
+  // with park)
+  for (uint32_t ph = 0; ph < phases; ++ph) {
+    const uint32_t t = park != nullptr ? ph : tile;
+    const TileGeom g = tile_geom(d, t);
+    if (ph == 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      for (uint32_t i = threadIdx.x; i < g.w; i += kBBlock) S[pad32(i)] = park[i];
+      __syncthreads();
+    }
+    const uint32_t P0 = tile_start(d, t, N[t]);
+    if (N[t]) fill_tile((g_i32*)d.keys_out, S, g.w, g.base, P0, P0, P0 + N[t], g.body_lo, S + kBLdsWords);
+    __syncthreads();   // LDS is reused by the next phase or item
+  }
 }
 
 // Thread 0 waits (bounded) until *flag is nonzero; returns, in every thread,
@@ -562,8 +560,7 @@ __global__ __launch_bounds__(kBBlock) void k_batched(BatchArgs a) {
     if (kind == kWhole) {
       const rtcdf_segment_t d = a.segs[it.x];
       if (!seg_valid(d, a.max_range)) continue;
-      if (it.y & kBothTiles) sort_both_tiles(d, S, wsum, a.park + (size_t)blockIdx.x * kBTile);
-      else sort_item(d, tile, S, wsum);
+      sort_item(d, tile, S, wsum, (it.y & kBothTiles) ? a.park + (size_t)blockIdx.x * kBTile : nullptr);
     } else {
       uint32_t* st = a.slots + (size_t)it.x * kSlotWords;
       if (kind == kZero) zero_item(a, st);
