@@ -454,7 +454,9 @@ static rtcdf_status_t grow(Workspace& w, const Plan& p, hipStream_t s) {
       (void)hipGetLastError();
       return RTCDF_ERROR_OUT_OF_MEMORY;
     }
-    e = hipMemset(w.fast, 0, (size_t)kFastAreaWords * 4);
+    // cleared on the sort's stream: a hipMemset runs on the null stream,
+    // which a non-blocking stream's kernels do not wait for
+    e = launch_clear(w.fast, kFastAreaWords, s);
     if (e != hipSuccess) return hip_fail(e);
   }
   if (!p.fast && w.carry_words < p.carry_words) {
@@ -469,7 +471,7 @@ static rtcdf_status_t grow(Workspace& w, const Plan& p, hipStream_t s) {
       (void)hipGetLastError();
       return RTCDF_ERROR_OUT_OF_MEMORY;
     }
-    e = hipMemset(w.carry, 0, words * 4);
+    e = launch_clear(w.carry, words, s);   // on the sort's stream, as above
     if (e != hipSuccess) return hip_fail(e);
     w.carry_words = words;
   }

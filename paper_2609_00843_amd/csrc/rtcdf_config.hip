@@ -232,6 +232,9 @@ static rtcdf_status_t upload_model(int dev, DeviceModel** out) {
     if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&d.dev), d.host, 0);
     if (e == hipSuccess) e = hipMalloc(&d.acc, sizeof(uint32_t) * 64 * kPickSlots);
     if (e == hipSuccess) e = hipMemset(d.acc, 0, sizeof(uint32_t) * 64 * kPickSlots);
+    // the memset runs on the null stream, which the picks' (possibly
+    // non-blocking) streams do not wait for: wait for it here, once
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     for (int k = 0; k < kPickSlots && e == hipSuccess; ++k) {
       e = hipEventCreateWithFlags(&d.ev[k], hipEventDisableTiming);
       if (e == hipSuccess) d.free_slots.push_back(k);
@@ -247,6 +250,9 @@ static rtcdf_status_t upload_model(int dev, DeviceModel** out) {
     if (e == hipSuccess)
       e = hipMemcpy(d.norm, g_model.norm.data(), sizeof(float) * 2 * kMlpIn, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d.valid, g_model.valid.data(), kMlpOut, hipMemcpyHostToDevice);
+    // a copy from pageable memory may return before its transfer lands, and
+    // it runs on the null stream: wait for it before a pick reads the weights
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) return hip_fail(e);
     d.generation = g_model_generation;
   }
