@@ -176,3 +176,92 @@ def _run_case(r, k, large):
     assert np.all(full[:pad] == guard) and np.all(full[pad + n:] == guard), "words around the output changed"
     if not inplace:
         assert np.array_equal(_to_host(tin, npt), A), "the input changed"
+
+
+def _prepare(r, k, seed_base):
+    """Inputs, expected output and call of random case k (from the seed space
+    `seed_base`) for enqueueing without a wait: (name, run(stream), check())."""
+    rng = np.random.default_rng(inputs.case_seed(seed_base, k))
+    _, name, npt, n, lo, R, dist = _case(int(rng.integers(0, 1 << 30)))
+    hi = lo + R
+    off = _offsets(rng, dist, n, R, inputs.case_seed(seed_base + 1, k))
+    A = (off + np.int64(lo)).astype(npt) if name != "int64" else off + np.int64(lo)
+    kb = np.dtype(npt).itemsize
+    pin, pout = int(rng.integers(0, 16 // kb)), int(rng.integers(0, 16 // kb))
+    cfg = _rand_config(rng, r, name == "int32")
+    entry = str(rng.choice(["sort", "sort_ws", "noalloc"])) if name == "int32" else "sort_keys"
+    want = (oracle.sort(off.astype(np.int32), 0, R).astype(np.int64) + np.int64(lo)).astype(npt)
+    _, tin = _to_dev(A, npt, pin, 7)
+    bout, tout = _to_dev(np.zeros(n, dtype=npt), npt, pout, 0x5A)
+    ws = None
+    if entry in ("sort_ws", "noalloc"):
+        need = r.workspace_bytes(n, lo, hi, config=cfg, keys_out=tout)
+        if entry == "noalloc" and need > r.NOALLOC_MAX_WORKSPACE:
+            entry = "sort_ws"
+        if entry == "sort_ws":
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+
+    def run(stream):
+        if entry == "sort_keys":
+            r.sort_keys(tin, lo, hi, keys_out=tout, config=cfg, stream=stream)
+        elif entry == "sort":
+            r.sort(tin, lo, hi, keys_out=tout, config=cfg, stream=stream)
+        elif entry == "noalloc":
+            r.sort_noalloc(tin, tout, lo, hi, config=cfg, stream=stream)
+        else:
+            r.sort_ws(tin, tout, lo, hi, ws, config=cfg, stream=stream)
+
+    def check():
+        got = _to_host(tout, npt)
+        assert np.array_equal(got, want), (k, name, n, R, entry, np.flatnonzero(got != want)[:5])
+        tout.fill_(0)   # the next replay must write it again
+
+    return f"{name} n={n} R={R} {dist} {entry} cfg={None if cfg is None else cfg.as_tuple()}", run, check
+
+
+@pytest.mark.parametrize("seq", range(4))
+def test_random_sequence_one_stream(r, seq):
+    """40 random problems enqueued back to back on one stream with no wait
+    between them (the state one sort leaves for the next on a stream: the
+    fast path's accumulation area and its parity words, carry arrays, the
+    workspace growing between two sorts, the allocation-free array), then
+    every output checked."""
+    cases = [_prepare(r, 40 * seq + i, 97) for i in range(40)]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for desc, run, _ in cases:
+        _say(f"sequence {seq}: {desc}")
+        run(s)
+    s.synchronize()
+    for _, _, check in cases:
+        check()
+
+
+def test_random_sequence_graph_replays(r):
+    """A random sequence of caller-workspace and allocation-free sorts captured
+    in one HIP graph and replayed three times, with eager sorts of other
+    problems between the replays; every replay's outputs are checked."""
+    rng_cases = [_prepare(r, i, 99) for i in range(60)]
+    cases = [c for c in rng_cases if "sort_ws" in c[0] or "noalloc" in c[0]][:20]
+    others = [c for c in rng_cases if "sort_ws" not in c[0] and "noalloc" not in c[0]][:6]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for desc, run, check in cases:   # eager once (and warm-up before capture)
+        run(s)
+    s.synchronize()
+    for _, _, check in cases:
+        check()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _, run, _ in cases:
+            run(s)
+    for rep in range(3):
+        _say(f"graph replay {rep} of {len(cases)} sorts")
+        g.replay()
+        torch.cuda.synchronize()
+        for _, _, check in cases:
+            check()
+        for _, run, check in others:
+            run(s)
+            s.synchronize()
+            check()
