@@ -265,3 +265,39 @@ def test_random_sequence_graph_replays(r):
             run(s)
             s.synchronize()
             check()
+
+
+@pytest.mark.parametrize("k", range(60))
+def test_random_checked(r, k):
+    """rtcdf_sort_checked on random int32 problems: in half of them 1 to 3
+    keys anywhere in the array (head, body or tail of any alignment) lie
+    below minVal or at or above maxVal, down to INT32_MIN and up to
+    INT32_MAX; those return KEY_OUT_OF_RANGE with the output untouched, the
+    others sort exactly."""
+    rng = np.random.default_rng(inputs.case_seed(98, k))
+    n = int(round(10 ** rng.uniform(0, 6)))
+    R = max(1, int(round(2 ** rng.uniform(0, 20))))
+    lo = int(rng.integers(-(1 << 31) + 1, (1 << 31) - R))   # room below and above the range
+    off = _offsets(rng, str(rng.choice(["uniform", "normal", "all_equal", "zipf"])), n, R,
+                   inputs.case_seed(99, k))
+    A = (off + lo).astype(np.int32)
+    bad = rng.random() < 0.5
+    if bad:
+        for _ in range(int(rng.integers(1, 4))):
+            i = int(rng.integers(0, n))
+            A[i] = int(rng.choice([lo - 1, lo + R, -(1 << 31), (1 << 31) - 1,
+                                   int(rng.integers(-(1 << 31), lo)), int(rng.integers(lo + R, 1 << 31))]))
+    pin, pout = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+    _say(f"checked {k}: n={n} [{lo},{lo + R}) out_of_range={bad} pin={pin} pout={pout}")
+    _, tin = _to_dev(A, np.int32, pin, 7)
+    bout, tout = _to_dev(np.zeros(n, dtype=np.int32), np.int32, pout, 0x5A)
+    if bad:
+        with pytest.raises(r.RtcdfError) as e:
+            r.sort_checked(tin, lo, lo + R, keys_out=tout)
+        assert e.value.status == r.KEY_OUT_OF_RANGE
+        torch.cuda.synchronize()
+        assert np.all(_to_host(bout, np.int32)[pout:pout + n] == 0), "the output was written"
+    else:
+        r.sort_checked(tin, lo, lo + R, keys_out=tout)
+        torch.cuda.synchronize()
+        assert np.array_equal(_to_host(tout, np.int32), oracle.sort(A, lo, lo + R))
