@@ -301,3 +301,46 @@ def test_random_checked(r, k):
         r.sort_checked(tin, lo, lo + R, keys_out=tout)
         torch.cuda.synchronize()
         assert np.array_equal(_to_host(tout, np.int32), oracle.sort(A, lo, lo + R))
+
+
+def test_random_learned(r):
+    """LEARNED mode with the shipped model on 40 random int32 problems (the
+    network's picks, the exhaustive fallback for sketches it does not trust,
+    each problem sorted twice: the pick in flight, then the decision), and
+    rtcdf_autotune on 6 of them (every valid grid point times a sort into
+    the output): every output equals the oracle's."""
+    import os
+    model = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2609_00843_amd",
+                         "data", "model.bin")
+    if not os.path.exists(model):
+        pytest.skip("no shipped model")
+    r.load_model(model)
+    old = r.get_config_mode()
+    try:
+        r.set_config_mode(r.CONFIG_LEARNED)
+        r.clear_pick_cache()
+        for k in range(40):
+            rng = np.random.default_rng(inputs.case_seed(100, k))
+            n = int(round(10 ** rng.uniform(3, 6.3)))
+            R = max(1, int(round(2 ** rng.uniform(0, 22))))
+            lo = int(rng.integers(-(1 << 31), (1 << 31) - R + 1))
+            dist = str(rng.choice(["uniform", "normal", "normal64", "all_equal", "zipf", "few"]))
+            A = (_offsets(rng, dist, n, R, inputs.case_seed(101, k)) + lo).astype(np.int32)
+            want = oracle.sort(A, lo, lo + R)
+            _, tin = _to_dev(A, np.int32, int(rng.integers(0, 4)), 7)
+            _say(f"learned {k}: n={n} [{lo},{lo + R}) {dist}")
+            for _ in range(2):
+                out = r.sort(tin, lo, lo + R)
+                torch.cuda.synchronize()
+                assert np.array_equal(out.cpu().numpy(), want), (k, r.last_pick())
+            if k % 7 == 0:
+                b = torch.empty_like(tin)
+                _say(f"autotune {k}")
+                times, best = r.autotune(tin, lo, lo + R, keys_out=b, warmup=1, reps=2)
+                torch.cuda.synchronize()
+                assert np.array_equal(b.cpu().numpy(), want)
+                assert min(t for t in times if t > 0) > 0
+    finally:
+        r.set_config_mode(old)
+        r.unload_model()
+        r.clear_pick_cache()
