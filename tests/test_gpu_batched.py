@@ -280,11 +280,13 @@ def test_skipped_descriptors(r):
 def test_graph_replay(r):
     """Replays reproduce the eager result, with two segments far above their
     share of the batch among 64 ordinary ones (the ordering kernel resets
-    the queue at every launch)."""
+    the queue at every launch); every fourth segment is sorted in place, the
+    1.5 x 10^6-key two-tile one included (a replay re-sorts its sorted
+    output, through the workgroups' park slots)."""
     segs = inputs.batched_segments(64, seed=77)
     specs = [(s["n"], s["minVal"], s["maxVal"] - s["minVal"], s["dist"]) for s in segs]
     specs += [(1_500_000, -40, 65536, "uniform"), (900_001, 9, 300, "all_equal")]
-    arrays, pairs, din, dout, offs = _build(specs, 4)
+    arrays, pairs, din, dout, offs = _build(specs, 4, inplace_every=4)
     d, bounds, k = r.make_segments(pairs)
     ws = torch.empty(r.batched_workspace_bytes(k, bounds), dtype=torch.uint8, device="cuda")
     s = torch.cuda.Stream()
