@@ -178,9 +178,11 @@ def _run_case(r, k, large):
         assert np.array_equal(_to_host(tin, npt), A), "the input changed"
 
 
-def _prepare(r, k, seed_base):
+def _prepare(r, k, seed_base, noalloc=True):
     """Inputs, expected output and call of random case k (from the seed space
-    `seed_base`) for enqueueing without a wait: (name, run(stream), check())."""
+    `seed_base`) for enqueueing without a wait: (name, run(stream), check()).
+    noalloc=False keeps the allocation-free entry point out (its calls must
+    not overlap in time, as calls on several streams may)."""
     rng = np.random.default_rng(inputs.case_seed(seed_base, k))
     _, name, npt, n, lo, R, dist = _case(int(rng.integers(0, 1 << 30)))
     hi = lo + R
@@ -190,6 +192,8 @@ def _prepare(r, k, seed_base):
     pin, pout = int(rng.integers(0, 16 // kb)), int(rng.integers(0, 16 // kb))
     cfg = _rand_config(rng, r, name == "int32")
     entry = str(rng.choice(["sort", "sort_ws", "noalloc"])) if name == "int32" else "sort_keys"
+    if entry == "noalloc" and not noalloc:
+        entry = "sort_ws"
     want = (oracle.sort(off.astype(np.int32), 0, R).astype(np.int64) + np.int64(lo)).astype(npt)
     _, tin = _to_dev(A, npt, pin, 7)
     bout, tout = _to_dev(np.zeros(n, dtype=npt), npt, pout, 0x5A)
@@ -344,3 +348,19 @@ def test_random_learned(r):
         r.set_config_mode(old)
         r.unload_model()
         r.clear_pick_cache()
+
+
+def test_random_sequence_three_streams(r):
+    """60 random problems dealt round-robin to three streams and enqueued
+    with no wait (each stream's cached workspace, fast-path area and carry
+    array serve only its own sorts, whatever the others run meanwhile); every
+    output checked once all streams are done."""
+    cases = [_prepare(r, i, 102, noalloc=False) for i in range(60)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    torch.cuda.synchronize()
+    for i, (desc, run, _) in enumerate(cases):
+        _say(f"three streams, case {i} on stream {i % 3}: {desc}")
+        run(streams[i % 3])
+    torch.cuda.synchronize()
+    for _, _, check in cases:
+        check()
