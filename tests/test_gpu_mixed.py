@@ -364,3 +364,39 @@ def test_random_sequence_three_streams(r):
     torch.cuda.synchronize()
     for _, _, check in cases:
         check()
+
+
+@pytest.mark.parametrize("k", range(100))
+def test_random_partition_forced(r, k, monkeypatch):
+    """The partition by pass forced on (RTCDF_DEV_PARTITION=1: wherever a
+    sort needs two or more LDS passes) for random int32 problems over R from
+    2^14 to 2^24 with random configurations, offsets, in place or not, through
+    rtcdf_sort and rtcdf_sort_ws: the keys grouped by pass into the
+    workspace, each pass's rows counted over its own bucket."""
+    monkeypatch.setenv("RTCDF_DEV_PARTITION", "1")
+    rng = np.random.default_rng(inputs.case_seed(103, k))
+    n = int(round(10 ** rng.uniform(0, 6.3)))
+    R = int(round(2 ** rng.uniform(14, 24)))
+    u = rng.random()
+    lo = -(1 << 31) if u < 0.1 else ((1 << 31) - R if u < 0.2 else int(rng.integers(-(1 << 31), (1 << 31) - R + 1)))
+    dist = str(rng.choice(["uniform", "normal", "normal64", "all_equal", "zipf", "few"]))
+    off = _offsets(rng, dist, n, R, inputs.case_seed(104, k))
+    A = (off + lo).astype(np.int32)
+    pin, pout = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+    inplace = rng.random() < 0.15
+    cfg = _rand_config(rng, r, True)
+    entry = str(rng.choice(["sort", "sort_ws"]))
+    _say(f"partition forced {k}: n={n} [{lo},{lo + R}) {dist} pin={pin} pout={pout} inplace={inplace} "
+         f"cfg={None if cfg is None else cfg.as_tuple()} entry={entry}")
+    want = oracle.sort(A, lo, lo + R)
+    bin_, tin = _to_dev(A, np.int32, pin, 7)
+    tout = tin if inplace else _to_dev(np.zeros(n, dtype=np.int32), np.int32, pout, 0x5A)[1]
+    if entry == "sort":
+        r.sort(tin, lo, lo + R, keys_out=tout, config=cfg)
+    else:
+        ws = torch.empty(max(r.workspace_bytes(n, lo, lo + R, config=cfg, keys_out=tout), 256),
+                         dtype=torch.uint8, device="cuda")
+        r.sort_ws(tin, tout, lo, lo + R, ws, config=cfg)
+    torch.cuda.synchronize()
+    got = _to_host(tout, np.int32)
+    assert np.array_equal(got, want), f"mismatch at {np.flatnonzero(got != want)[:8]}"
