@@ -400,3 +400,29 @@ def test_random_partition_forced(r, k, monkeypatch):
     torch.cuda.synchronize()
     got = _to_host(tout, np.int32)
     assert np.array_equal(got, want), f"mismatch at {np.flatnonzero(got != want)[:8]}"
+
+
+DEV_SWITCHES = {"RTCDF_DEV_COUNTER_BITS": ["4", "8", "16", "32"], "RTCDF_DEV_FAST": ["0", "1"],
+                "RTCDF_DEV_HIST_SPREAD": ["0", "1", "2", "4"], "RTCDF_DEV_PARTITION": ["0", "1"],
+                "RTCDF_DEV_HIST_INTERLEAVE": ["0", "1"], "RTCDF_DEV_FILL_CHUNK": ["2048", "4096", "8192"],
+                "RTCDF_DEV_FILL_SPARSE_KEYS": ["16", "64", "256"], "RTCDF_DEV_FAST_ROWS": ["1", "4", "16"],
+                "RTCDF_DEV_HIST_GMUL": ["1", "2", "4"], "RTCDF_DEV_PART_WGS_PER_CU": ["2", "4", "8"],
+                "RTCDF_DEV_FILL_WGS_PER_CU": ["2", "3", "4", "8"]}
+
+
+@pytest.mark.parametrize("k", range(120))
+def test_random_dev_switches(r, k, monkeypatch):
+    """Random problems (every key type) with a random subset of the developer
+    overrides set, each to a value the measurements swept (counter width,
+    fast path, LDS counter copies, partition by pass, input interleave, output
+    chunk, sparse-form threshold, fast-path rows, histogram and partition and
+    output workgroups): they change launch shapes only, so every output must
+    still equal the oracle's."""
+    rng = np.random.default_rng(inputs.case_seed(105, k))
+    chosen = {}
+    for name, values in DEV_SWITCHES.items():
+        if rng.random() < 0.35:
+            chosen[name] = str(rng.choice(values))
+            monkeypatch.setenv(name, chosen[name])
+    _say(f"developer switches {k}: {chosen}")
+    _run_case(r, 20000 + k, bool(rng.random() < 0.2))
