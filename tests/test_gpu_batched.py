@@ -253,6 +253,46 @@ def test_random_batches(r, k):
     _check(arrays, specs, pairs, dout, offs)
 
 
+@pytest.mark.parametrize("k", range(12))
+def test_random_bounds(r, k):
+    """Random batches under bounds that overstate the batch (more keys, a
+    larger n or range: a larger workspace, the same outputs) or whose
+    max_range lies below some segments' ranges: those segments are skipped
+    with their outputs untouched, every other one is sorted."""
+    rng = np.random.default_rng(inputs.case_seed(107, k))
+    specs = []
+    for _ in range(int(rng.integers(1, 120))):
+        n = int(round(10 ** rng.uniform(0, 5)))
+        R = max(1, int(round(2 ** rng.uniform(0, 16))))
+        specs.append((n, int(rng.integers(-(1 << 31), (1 << 31) - R + 1)), R,
+                      str(rng.choice(["uniform", "normal", "all_equal", "zipf"]))))
+    arrays, pairs, din, dout, offs = _build(specs, 300 + k, inplace_every=int(rng.integers(0, 4)))
+    d, bounds, nseg = r.make_segments(pairs)
+    cap = int(bounds.max_range)
+    if rng.random() < 0.5:
+        bounds = r.BatchBounds(bounds.total_keys + int(rng.integers(0, 10 ** 6)),
+                               bounds.max_n + int(rng.integers(0, 10 ** 5)),
+                               min(65536, bounds.max_range + int(rng.integers(0, 40000))))
+    else:
+        cap = max(1, int(bounds.max_range * rng.uniform(0.2, 0.9)))
+        bounds = r.BatchBounds(bounds.total_keys, bounds.max_n, cap)
+    _say(f"random bounds {k}: {len(specs)} segments, bounds ({bounds.total_keys}, {bounds.max_n}, "
+         f"{bounds.max_range})")
+    ws = torch.empty(r.batched_workspace_bytes(nseg, bounds), dtype=torch.uint8, device="cuda")
+    r.sort_batched(d, nseg, bounds, ws)
+    torch.cuda.synchronize()
+    assert _error_word(ws) == 0
+    full = dout.cpu().numpy()
+    for A, (n, lo, R, _), (a, b, _, _), oo in zip(arrays, specs, pairs, offs):
+        got = b.cpu().numpy()
+        if R <= bounds.max_range:
+            assert np.array_equal(got, oracle.sort(A, lo, lo + R) if n else A), (n, R)
+        elif a.data_ptr() == b.data_ptr():
+            assert np.array_equal(got, A), ("skipped in-place segment changed", n, R)
+        else:
+            assert np.all(full[oo:oo + n] == GUARD), ("skipped segment written", n, R)
+
+
 def test_skipped_descriptors(r):
     """range 0, above RTCDF_BATCH_MAX_RANGE or above the bounds' max_range,
     and NULL pointers, are skipped."""
