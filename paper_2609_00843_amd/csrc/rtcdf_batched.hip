@@ -5,9 +5,9 @@
 // R <= 32768 is one item, a wider one (R <= 2^16) two, one per half of its
 // range -- unless its output overlaps its input (in place): its two tiles are
 // then one item, since a tile's workgroup would otherwise overwrite keys the
-// other one has not yet counted.  Each workgroup (1024 threads, 1 per compute unit, 135 KiB of LDS)
-// takes items from a device work queue and runs every step of Alg. 4 of the
-// paper for it without touching another workgroup:
+// other one has not yet counted.  Each workgroup (1024 threads, 1 per compute
+// unit, 135 KiB of LDS) takes items from a device work queue and runs every
+// step of Alg. 4 of the paper for it without touching another workgroup:
 //   Alg. 5  histogram of the keys that fall in the item's tile, in LDS (32-bit
 //           counters; keys outside the tile are not counted);
 //   Alg. 4  local CDF of the tile by a blocked LDS scan;
