@@ -117,10 +117,14 @@ def _magnitudes(p, X, T, Mk):
     return Ya, _flat(g)
 
 
-def test_forward_and_gradient(r):
+@pytest.mark.parametrize("B", [1, 2, 63, 64, 65, 300, 1000, 2500])
+def test_forward_and_gradient(r, B):
+    """Forward output, gradient and loss against the float64 reference within
+    the bound above, from one sample to more than the training sets hold (the
+    forward and delta kernels take one sample per workgroup; the weight
+    gradient sums every sample per parameter, so its rounding grows with B)."""
     p = {k: _f32(v) for k, v in _init(1).items()}
-    X, T, Mk = (_f32(a) for a in _batch(2, 300))
-    B = X.shape[0]
+    X, T, Mk = (_f32(a) for a in _batch(2, B))
     P = _dev(_flat(p))
     _say("forward")
     Y = r.mlp_forward(P, _dev(X)).cpu().numpy()
