@@ -91,6 +91,27 @@ def test_sketch(r, dist, n, R):
     assert np.array_equal(np.rint(got[2:] * S), np.rint(want[2:] * S))   # identical bin counts
 
 
+
+@pytest.mark.parametrize("k", range(30))
+def test_sketch_random(r, k):
+    """The sketch of random arrays (n from 1 to 3 x 10^6, R from 1 to 2^28,
+    minVal down to INT32_MIN and ranges up to 2^31): the same features as
+    the float64 reference and identical bin counts."""
+    rng = np.random.default_rng(inputs.case_seed(108, k))
+    n = int(round(10 ** rng.uniform(0, 6.5)))
+    R = max(1, int(round(2 ** rng.uniform(0, 28))))
+    u = rng.random()
+    lo = -(1 << 31) if u < 0.2 else ((1 << 31) - R if u < 0.4 else int(rng.integers(-(1 << 31), (1 << 31) - R + 1)))
+    dist = str(rng.choice(["uniform", "normal", "all_equal", "zipf"]))
+    A = inputs.make(dist, n, lo, lo + R, inputs.case_seed(109, k))
+    _say(f"sketch random {k}: {dist} n={n} [{lo},{lo + R})")
+    got = r.sketch(torch.from_numpy(A).cuda(), lo, lo + R).cpu().numpy().astype(np.float64)
+    want = M.sketch(A, lo, lo + R, samples=4096, bins=32)
+    assert np.allclose(got[:2], want[:2], rtol=1e-6, atol=0)
+    S = min(4096, n)
+    assert np.array_equal(np.rint(got[2:] * S), np.rint(want[2:] * S))
+
+
 U32 = 2.0 ** -24
 
 
