@@ -426,3 +426,35 @@ def test_random_dev_switches(r, k, monkeypatch):
             monkeypatch.setenv(name, chosen[name])
     _say(f"developer switches {k}: {chosen}")
     _run_case(r, 20000 + k, bool(rng.random() < 0.2))
+
+
+@pytest.mark.parametrize("k", range(40))
+def test_random_workspace_contract(r, k):
+    """rtcdf_workspace_bytes on random int32 problems, configurations and
+    input / output offsets: a caller workspace of exactly that many bytes
+    sorts (into an output at the offset the size was asked for, from an
+    input at any offset), one byte less is refused before any GPU work with
+    the output untouched."""
+    rng = np.random.default_rng(inputs.case_seed(110, k))
+    n = int(round(10 ** rng.uniform(0, 6.3)))
+    R = max(1, int(round(2 ** rng.uniform(0, 24))))
+    lo = int(rng.integers(-(1 << 31), (1 << 31) - R + 1))
+    off = _offsets(rng, str(rng.choice(["uniform", "normal", "all_equal", "zipf"])), n, R, inputs.case_seed(111, k))
+    A = (off + lo).astype(np.int32)
+    cfg = _rand_config(rng, r, True)
+    pin, pout = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+    _, tin = _to_dev(A, np.int32, pin, 7)
+    bout, tout = _to_dev(np.zeros(n, dtype=np.int32), np.int32, pout, 0x5A)
+    need = r.workspace_bytes(n, lo, lo + R, config=cfg, keys_out=tout)
+    _say(f"workspace contract {k}: n={n} R={R} cfg={None if cfg is None else cfg.as_tuple()} "
+         f"pin={pin} pout={pout} bytes={need}")
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    if need > 0:
+        with pytest.raises(r.RtcdfError) as e:
+            r.sort_ws(tin, tout, lo, lo + R, ws[:need - 1], config=cfg)
+        assert e.value.status == r.WORKSPACE_TOO_SMALL
+        torch.cuda.synchronize()
+        assert np.all(_to_host(tout, np.int32) == 0)
+    r.sort_ws(tin, tout, lo, lo + R, ws[:need], config=cfg)
+    torch.cuda.synchronize()
+    assert np.array_equal(_to_host(tout, np.int32), oracle.sort(A, lo, lo + R))
