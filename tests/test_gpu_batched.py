@@ -293,6 +293,32 @@ def test_random_bounds(r, k):
             assert np.all(full[oo:oo + n] == GUARD), ("skipped segment written", n, R)
 
 
+@pytest.mark.parametrize("k", range(10))
+def test_random_workspace_contract(r, k):
+    """rtcdf_batched_workspace_bytes on random batches (ranges up to 2^16,
+    some segments in place): exactly that many bytes sort the batch, one byte
+    less is refused before any GPU work."""
+    rng = np.random.default_rng(inputs.case_seed(112, k))
+    specs = []
+    for _ in range(int(rng.integers(1, 200))):
+        n = int(round(10 ** rng.uniform(0, 5)))
+        R = max(1, int(round(2 ** rng.uniform(0, 16))))
+        specs.append((n, int(rng.integers(-(1 << 31), (1 << 31) - R + 1)), R,
+                      str(rng.choice(["uniform", "normal", "all_equal", "zipf"]))))
+    arrays, pairs, din, dout, offs = _build(specs, 400 + k, inplace_every=int(rng.integers(0, 4)))
+    d, bounds, nseg = r.make_segments(pairs)
+    need = r.batched_workspace_bytes(nseg, bounds)
+    _say(f"batched workspace contract {k}: {nseg} segments, {need} bytes")
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    with pytest.raises(r.RtcdfError) as e:
+        r.sort_batched(d, nseg, bounds, ws[:need - 1])
+    assert e.value.status == r.WORKSPACE_TOO_SMALL
+    r.sort_batched(d, nseg, bounds, ws)
+    torch.cuda.synchronize()
+    assert _error_word(ws) == 0
+    _check(arrays, specs, pairs, dout, offs)
+
+
 def test_skipped_descriptors(r):
     """range 0, above RTCDF_BATCH_MAX_RANGE or above the bounds' max_range,
     and NULL pointers, are skipped."""
